@@ -1,0 +1,180 @@
+#!/usr/bin/env python
+"""Benchmark of the CTR-IBIM solve on one MI355X.
+
+One step = one complete solve on a device-resident problem: right-hand side,
+GMRES to the workload's tolerance (every iteration one application of the
+discrete operator: the dense pair kernel plus the sparse correction), the
+explicit residual check, and the polarisation energy.  The problem setup
+(signed distance on the host -> geometry, correction sets and weights on the
+device) is timed separately because it consumes host buffers.
+
+value = pair interactions evaluated in all operator applications of the timed
+steps / wall time of those steps (one pair = the four kernels for one
+(target, source)).  Also reported: solves/s and per-solve latency.
+
+Prints ONE JSON line.  ``--gpus`` above 1 is refused: this build runs on one
+GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "pair-interactions/s in IBIM matvec; solves/s + p50/p99 latency at fixed error"
+FLOPS_PER_PAIR = 60            # algorithmic flops of one pair (FMA = 2), see the design doc
+PEAK_FP64_VECTOR_TFLOPS = 78.6  # MI355X vector FP64
+
+
+def percentile(xs, p):
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    k = (len(xs) - 1) * p / 100.0
+    lo, hi = math.floor(k), math.ceil(k)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def cpu_baseline(wl, M, seconds):
+    """The FP64 oracle on a bounded, seeded sample of rows of the same operator."""
+    import numpy as np
+
+    import oracle
+    import workloads
+
+    rng = np.random.Generator(np.random.PCG64(4242))
+    # probe with a small sample, then size the timed sample to ~`seconds`
+    probe_rows = np.sort(rng.choice(M, size=min(M, 64), replace=False))
+    orc = oracle.Oracle.from_workload(wl, weight_rows=probe_rows)
+    u = workloads.random_vector(2 * M, 4243)
+    t = time.perf_counter()
+    orc.apply_rows(u, probe_rows)
+    rate = len(probe_rows) * M / max(time.perf_counter() - t, 1e-6)
+    n = int(min(M, max(64, seconds * rate / M)))
+    rows = np.sort(rng.choice(M, size=n, replace=False))
+    orc = oracle.Oracle.from_workload(wl, weight_rows=rows)
+    t = time.perf_counter()
+    orc.apply_rows(u, rows)
+    dt = time.perf_counter() - t
+    return {
+        "value": n * M / dt,
+        "unit": "pair-interactions/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"operator rows: {n} seeded target rows x all {M} sources "
+                  f"({n * M:.3e} pairs, {dt:.1f} s)",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="kirkwood")
+    ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2210_03699_amd import FP64, Problem
+
+    wl = workloads.by_name(args.workload)
+    dev = "cuda:0"
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prob = Problem.from_workload(wl, device=0, precision=FP64)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    M = prob.M
+    print(f"[bench] {wl.name}: M={M} nnz={prob.nnz} setup {setup_s:.2f}s", file=sys.stderr,
+          flush=True)
+
+    def step():
+        g = prob.rhs()
+        x, info = prob.solve(g, wl.tol)
+        G = prob.energy(x)  # synchronises the stream
+        return info, G
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    prob.pair_timing(True)
+    lat, applies, iters, G = [], 0, [], None
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        info, G = step()
+        lat.append(time.perf_counter() - ts)
+        applies += info["applies"]
+        iters.append(info["iters"])
+        print(f"[bench] step {i}: {lat[-1] * 1e3:.1f} ms iters={info['iters']} G_pol={G:.12e}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    n_launch, pair_ms = prob.pair_timing_read()
+    prob.pair_timing(False)
+
+    pairs = float(applies) * M * M
+    avg_pair_ms = pair_ms / max(n_launch, 1)
+    achieved_tflops = FLOPS_PER_PAIR * float(M) * M / (avg_pair_ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": pairs / elapsed,
+        "unit": "pair-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": wl.name, "M": M, "unknowns": 2 * M, "h": wl.h, "eps_tube": wl.eps_tube,
+            "tol": wl.tol, "n_charges": int(wl.charge_q.shape[0]), "gmres_restart": 60,
+            "pair_kernel": "fp64",
+        },
+        "solves_per_s": args.steps / elapsed,
+        "latency_ms": {"p50": percentile(lat, 50) * 1e3, "p99": percentile(lat, 99) * 1e3},
+        "gmres_iters": iters,
+        "applies_per_solve": applies / args.steps,
+        "pair_kernel_ms": avg_pair_ms,
+        "pair_kernel_pairs_per_s": float(M) * M / (avg_pair_ms * 1e-3),
+        "setup_s": setup_s,
+        "g_pol": G,
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved_tflops,
+            "peak": PEAK_FP64_VECTOR_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved_tflops / PEAK_FP64_VECTOR_TFLOPS,
+            "traffic": None,
+        },
+    }
+    golden = os.path.join(ROOT, "tests", "golden", "kirkwood_R10_h0.25.json")
+    if args.workload == "kirkwood" and os.path.exists(golden):
+        gold = json.load(open(golden))
+        out["g_pol_rel_err_vs_oracle"] = abs(G - gold["g_pol"]) / abs(gold["g_pol"])
+    if not args.no_cpu_baseline:
+        print("[bench] CPU baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(wl, M, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

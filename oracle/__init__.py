@@ -47,6 +47,8 @@ def _load():
     lib.oc_build.restype = ctypes.c_void_p
     lib.oc_build.argtypes = [_D, ctypes.c_int, ctypes.c_int, ctypes.c_int, _D, ctypes.c_double,
                              ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    lib.oc_build_rows.restype = ctypes.c_void_p
+    lib.oc_build_rows.argtypes = lib.oc_build.argtypes + [_I64, ctypes.c_int64]
     lib.oc_free.argtypes = [ctypes.c_void_p]
     lib.oc_last_error.restype = ctypes.c_char_p
     lib.oc_num_nodes.restype = ctypes.c_int64
@@ -96,7 +98,9 @@ def num_threads() -> int:
 class Oracle:
     """One discretised problem: tube nodes, geometry, correction sets, weights."""
 
-    def __init__(self, sdf, origin, h, eps_tube, eps_in, eps_out, kappa):
+    def __init__(self, sdf, origin, h, eps_tube, eps_in, eps_out, kappa, weight_rows=None):
+        """``weight_rows``: build correction weights only for these rows (the
+        others hold NaN, so only ``apply_rows`` on listed rows is meaningful)."""
         lib = _load()
         self._lib = lib
         sdf = _f64(sdf)
@@ -105,8 +109,14 @@ class Oracle:
         self.h, self.eps, self.eps_in, self.eps_out, self.kappa = (
             float(h), float(eps_tube), float(eps_in), float(eps_out), float(kappa))
         self._sdf = sdf
-        ptr = lib.oc_build(_dp(sdf), sdf.shape[0], sdf.shape[1], sdf.shape[2], _dp(origin),
-                           self.h, self.eps, self.eps_in, self.eps_out, self.kappa)
+        if weight_rows is None:
+            ptr = lib.oc_build(_dp(sdf), sdf.shape[0], sdf.shape[1], sdf.shape[2], _dp(origin),
+                               self.h, self.eps, self.eps_in, self.eps_out, self.kappa)
+        else:
+            wr = np.ascontiguousarray(weight_rows, dtype=np.int64)
+            ptr = lib.oc_build_rows(_dp(sdf), sdf.shape[0], sdf.shape[1], sdf.shape[2],
+                                    _dp(origin), self.h, self.eps, self.eps_in, self.eps_out,
+                                    self.kappa, wr.ctypes.data_as(_I64), wr.shape[0])
         if not ptr:
             raise ValueError("oracle setup failed: " + lib.oc_last_error().decode())
         self._c = ctypes.c_void_p(ptr)
@@ -114,8 +124,9 @@ class Oracle:
         self.nnz = int(lib.oc_num_corrections(self._c))
 
     @classmethod
-    def from_workload(cls, wl):
-        return cls(wl.sdf, wl.origin, wl.h, wl.eps_tube, wl.eps_in, wl.eps_out, wl.kappa)
+    def from_workload(cls, wl, weight_rows=None):
+        return cls(wl.sdf, wl.origin, wl.h, wl.eps_tube, wl.eps_in, wl.eps_out, wl.kappa,
+                   weight_rows=weight_rows)
 
     def __del__(self):
         c = getattr(self, "_c", None)

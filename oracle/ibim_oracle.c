@@ -21,8 +21,9 @@
  *  - Theorem 2.1 leading terms with the sign of s0^(11), s0^(22) flipped and
  *    the factor kappa^2 added to s0^(21) (derived from the kernels; pinned by
  *    the limit tests).
- *  - A plane is corrected iff its nearest node lies in the tube; eta is the
- *    signed distance of the line point, -s along the outward normal.
+ *  - A plane is corrected iff its line point L = x* + s n has |s| <= eps + h
+ *    and the nearest node of L lies in the tube; eta is the signed distance
+ *    of the line point, -s along the outward normal.
  *  - Dominant axis ties go to the lowest axis; in-plane axes (i+1, i+2) mod 3.
  *  - Weights are evaluated exactly (Ewald form of the lattice sum that the
  *    limit definition eq. single_correction_weight reduces to), not from a
@@ -298,8 +299,11 @@ static void eig2(double p, double q, double r, double* mu, double* v /* 2x2 cols
 /* ------------------------------------------------------------------------ */
 /* Build: tube nodes, geometry, correction sets and weights.                 */
 /* Returns NULL on error (message in oc_last_error()).                       */
-oc_ctx* oc_build(const double* sdf, int nx, int ny, int nz, const double* origin, double h,
-                 double eps, double eps_in, double eps_out, double kappa) {
+/* Weights are computed for every row, or only for the rows listed in
+ * weight_rows (other rows get NaN weights, so using them fails loudly). */
+oc_ctx* oc_build_rows(const double* sdf, int nx, int ny, int nz, const double* origin, double h,
+                      double eps, double eps_in, double eps_out, double kappa,
+                      const int64_t* weight_rows, int64_t n_weight_rows) {
   oc_err[0] = 0;
   if (!(h > 0) || !(eps > 0) || !(eps_in > 0) || !(eps_out > 0) || !(kappa >= 0)) {
     snprintf(oc_err, sizeof oc_err, "bad scalar parameter");
@@ -435,13 +439,20 @@ oc_ctx* oc_build(const double* sdf, int nx, int ny, int nz, const double* origin
     if (fabs(nv[1]) > fabs(nv[ia])) ia = 1;
     if (fabs(nv[2]) > fabs(nv[ia])) ia = 2;
     int aa = (ia + 1) % 3, bb = (ia + 2) % 3;
-    int lo = (int)ceil((xs[ia] - (eps + 2.0 * h) - origin[ia]) / h);
-    int hi = (int)floor((xs[ia] + (eps + 2.0 * h) - origin[ia]) / h);
+    /* Theorem 2.1 needs the line point in the tube around x*: only planes
+     * whose line point has |s| <= eps + h can have their nearest node in the
+     * tube (that node lies within h/sqrt(2) of the line point); farther
+     * crossings of the normal line with the tube (the far side of a thin
+     * body) are not singular and are not corrected. */
+    double reach = eps + h;
+    int lo = (int)floor((xs[ia] - reach - origin[ia]) / h) - 1;
+    int hi = (int)ceil((xs[ia] + reach - origin[ia]) / h) + 1;
     int own = 0;
     for (int p = lo; p <= hi; ++p) {
       if (p < 0 || p >= c->dims[ia]) continue;
       double t = origin[ia] + (double)p * h;
       double s = (t - xs[ia]) / nv[ia];
+      if (!(fabs(s) <= reach)) continue;
       double La = xs[aa] + s * nv[aa];
       double Lb = xs[bb] + s * nv[bb];
       double fa = (La - origin[aa]) / h;
@@ -478,8 +489,12 @@ oc_ctx* oc_build(const double* sdf, int nx, int ny, int nz, const double* origin
   c->nnz = nnz;
   c->om11 = (double*)xmalloc(sizeof(double) * (nnz ? nnz : 1));
   c->om21 = (double*)xmalloc(sizeof(double) * (nnz ? nnz : 1));
+  for (int64_t e = 0; e < nnz; ++e) c->om11[e] = c->om21[e] = NAN;
+  int64_t nrows = weight_rows ? n_weight_rows : M;
 #pragma omp parallel for schedule(dynamic, 16)
-  for (int64_t k = 0; k < M; ++k) {
+  for (int64_t r = 0; r < nrows; ++r) {
+    int64_t k = weight_rows ? weight_rows[r] : r;
+    if (k < 0 || k >= M) continue;
     for (int64_t e = c->crow[k]; e < c->crow[k + 1]; ++e) {
       int ia = c->cplane[e];
       plane_weights(&c->tau[6 * k], &c->tau[6 * k + 3], c->kap[2 * k], c->kap[2 * k + 1],
@@ -489,6 +504,11 @@ oc_ctx* oc_build(const double* sdf, int nx, int ny, int nz, const double* origin
   }
 #undef SDF
   return c;
+}
+
+oc_ctx* oc_build(const double* sdf, int nx, int ny, int nz, const double* origin, double h,
+                 double eps, double eps_in, double eps_out, double kappa) {
+  return oc_build_rows(sdf, nx, ny, nz, origin, h, eps, eps_in, eps_out, kappa, NULL, 0);
 }
 
 /* ------------------------------------------------------------------------ */

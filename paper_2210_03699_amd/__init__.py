@@ -1,0 +1,7 @@
+"""CTR-IBIM linearised Poisson-Boltzmann solver for AMD MI355X.
+
+The solver lives in ``libibim.so`` (hand-written HIP for gfx950 plus host C++
+setup) behind the C ABI of ``include/ibim.h``; :mod:`.ibim` is its ctypes
+binding.
+"""
+from .ibim import FP64, MIXED, IbimError, Problem, header_functions, load  # noqa: F401

@@ -1,0 +1,639 @@
+// C ABI of the CTR-IBIM solver: problem contexts, device uploads, the GMRES
+// driver (Section 2.5), the right-hand side (eq. PB-lambda-g) and the
+// polarisation energy (eq. pol-energy).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ibim.h"
+#include "ibim_internal.h"
+#include "krylov.h"
+#include "operator.h"
+#include "weights.h"
+
+using namespace ibim;
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(e == hipErrorOutOfMemory ? IBIM_ENOMEM : IBIM_EHIP,
+              std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, where)                    \
+  do {                                          \
+    hipError_t _e = (expr);                     \
+    if (_e != hipSuccess) return hip_fail(_e, where); \
+  } while (0)
+
+template <class T>
+hipError_t dalloc(T** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  return hipMalloc((void**)p, n * sizeof(T));
+}
+
+template <class T>
+hipError_t upload(T** p, const T* src, size_t n, hipStream_t s) {
+  hipError_t e = dalloc(p, n);
+  if (e != hipSuccess) return e;
+  if (n == 0) return hipSuccess;
+  return hipMemcpyAsync(*p, src, n * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+template <class T>
+void dfree(T*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+// Restores the caller's current device on scope exit.
+struct DeviceScope {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceScope(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (dev >= 0 && dev != prev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceScope() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+struct ibim_ctx {
+  HostPlan plan;
+  ibim_options opt{};
+  double eps_in = 1, eps_out = 1, kappa = 0;
+  std::vector<double> zq, q;  // charges (host)
+  // device state
+  DeviceProblem P;
+  PairPlan pair;
+  double* partial = nullptr;  // nsplit * 2M
+  double* om11 = nullptr;
+  double* om21 = nullptr;
+  double* d_zq = nullptr;
+  double* d_q = nullptr;
+  double* d_psi = nullptr;
+  Krylov kr;
+  bool kr_ready = false;
+  // pair-kernel timing (events bracket every pair launch while enabled)
+  bool timing = false;
+  std::vector<hipEvent_t> tev;  // 2 per launch
+  size_t tcount = 0;            // launches recorded
+  int applies = 0;              // operator applications of the current solve
+
+  bool on_device() const { return opt.device >= 0; }
+
+  void release() {
+    if (!on_device()) return;
+    DeviceScope ds(opt.device);
+    dfree(P.px); dfree(P.py); dfree(P.pz); dfree(P.nx); dfree(P.ny); dfree(P.nz); dfree(P.w);
+    dfree(P.px32); dfree(P.py32); dfree(P.pz32); dfree(P.nx32); dfree(P.ny32); dfree(P.nz32);
+    dfree(P.crow); dfree(P.ccol); dfree(P.blocks); dfree(P.nrow); dfree(P.ncol);
+    dfree(partial); dfree(om11); dfree(om21); dfree(d_zq); dfree(d_q); dfree(d_psi);
+    dfree(kr.V); dfree(kr.H); dfree(kr.cs); dfree(kr.sn); dfree(kr.g); dfree(kr.y);
+    dfree(kr.hcol); dfree(kr.hcol2); dfree(kr.scal); dfree(kr.status); dfree(kr.partial);
+    dfree(kr.tmp); dfree(kr.tmp2);
+    if (kr.host_status) (void)hipHostFree(kr.host_status);
+    kr.host_status = nullptr;
+    for (hipEvent_t e : tev) (void)hipEventDestroy(e);
+    tev.clear();
+  }
+};
+
+namespace {
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+__global__ void rhs_kernel(const double* px, const double* py, const double* pz, const double* nx,
+                           const double* ny, const double* nz, int32_t M, const double* zq,
+                           const double* q, int nc, double inv_eps_in, double* g) {
+  const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= M) return;
+  const double x = px[k], y = py[k], z = pz[k];
+  const double n0 = nx[k], n1 = ny[k], n2 = nz[k];
+  double g1 = 0.0, g2 = 0.0;
+  for (int j = 0; j < nc; ++j) {
+    const double rx = x - zq[3 * j], ry = y - zq[3 * j + 1], rz = z - zq[3 * j + 2];
+    const double R2 = rx * rx + ry * ry + rz * rz;
+    const double iR = 1.0 / sqrt(R2);
+    const double qj = q[j] * inv_eps_in;
+    g1 += qj * iR;
+    g2 -= qj * (rx * n0 + ry * n1 + rz * n2) * iR * iR * iR;
+  }
+  g[k] = g1 / (4.0 * kPiD);
+  g[M + k] = g2 / (4.0 * kPiD);
+}
+
+// psi[j] = h^3 sum_m f_j(m) w_m for charge j (one workgroup per charge,
+// fixed-order tree reduction).
+__global__ __launch_bounds__(256) void psi_rxn_kernel(const double* px, const double* py,
+                                                      const double* pz, const double* nx,
+                                                      const double* ny, const double* nz,
+                                                      const double* w, int32_t M, const double* x,
+                                                      const double* zq, double ratio,
+                                                      double kappa, double h3, double* psi) {
+  __shared__ double red[256];
+  const int j = blockIdx.x;
+  const double zx = zq[3 * j], zy = zq[3 * j + 1], zz = zq[3 * j + 2];
+  double acc = 0.0;
+  for (int32_t m = threadIdx.x; m < M; m += blockDim.x) {
+    const double rx = zx - px[m], ry = zy - py[m], rz = zz - pz[m];
+    const double R2 = rx * rx + ry * ry + rz * rz;
+    const double R = sqrt(R2);
+    const double iR = 1.0 / R;
+    const double kr = kappa * R;
+    const double e = exp(-kr);
+    const double rn = rx * nx[m] + ry * ny[m] + rz * nz[m];
+    const double dG0 = rn * iR * iR * iR;          // 4 pi dG0/dn_y
+    const double dGk = dG0 * (e + e * kr);          // 4 pi dGk/dn_y
+    const double G0mGk = -expm1(-kr) * iR;          // 4 pi (G0 - Gk)
+    acc += ((ratio * dGk - dG0) * x[m] + G0mGk * x[M + m]) * w[m];
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) psi[j] = h3 * red[0] / (4.0 * kPiD);
+}
+
+__global__ void fill_kernel(double* x, int64_t n, double v) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) x[r] = v;
+}
+
+__global__ void copy_kernel(const double* a, double* b, int64_t n) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) b[r] = a[r];
+}
+
+int check_ctx(const ibim_ctx* c) {
+  if (!c) return fail(IBIM_EINVAL, "null context");
+  return IBIM_OK;
+}
+
+int check_dev(const ibim_ctx* c) {
+  int r = check_ctx(c);
+  if (r) return r;
+  if (!c->on_device()) return fail(IBIM_ENODEV, "host-only context (options.device < 0)");
+  return IBIM_OK;
+}
+
+int apply_impl(ibim_ctx* c, const double* u, double* out, hipStream_t s) {
+  const int prec = c->opt.precision;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c->timing) {
+    if (2 * c->tcount + 2 > c->tev.size()) {
+      for (int i = 0; i < 2; ++i) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e), "hipEventCreate");
+        c->tev.push_back(e);
+      }
+    }
+    e0 = c->tev[2 * c->tcount];
+    e1 = c->tev[2 * c->tcount + 1];
+    HIP_TRY(hipEventRecord(e0, s), "hipEventRecord");
+  }
+  HIP_TRY(launch_pair(c->P, c->pair, prec, u, c->partial, s), "pair kernel launch");
+  if (c->timing) {
+    HIP_TRY(hipEventRecord(e1, s), "hipEventRecord");
+    ++c->tcount;
+  }
+  HIP_TRY(launch_finish(c->P, c->pair, prec, u, c->partial, out, s), "finish kernel launch");
+  ++c->applies;
+  return IBIM_OK;
+}
+
+int ensure_krylov(ibim_ctx* c) {
+  if (c->kr_ready) return IBIM_OK;
+  Krylov& k = c->kr;
+  k.m = c->opt.restart;
+  k.n = 2 * (int64_t)c->P.M;
+  const size_t m = (size_t)k.m;
+  HIP_TRY(dalloc(&k.V, (m + 1) * (size_t)k.n), "GMRES basis allocation");
+  HIP_TRY(dalloc(&k.H, (m + 1) * m), "alloc");
+  HIP_TRY(dalloc(&k.cs, m), "alloc");
+  HIP_TRY(dalloc(&k.sn, m), "alloc");
+  HIP_TRY(dalloc(&k.g, m + 1), "alloc");
+  HIP_TRY(dalloc(&k.y, m), "alloc");
+  HIP_TRY(dalloc(&k.hcol, m + 1), "alloc");
+  HIP_TRY(dalloc(&k.hcol2, m + 1), "alloc");
+  HIP_TRY(dalloc(&k.scal, 4), "alloc");
+  HIP_TRY(dalloc(&k.status, 2), "alloc");
+  HIP_TRY(dalloc(&k.partial, (m + 1) * 1024), "alloc");
+  HIP_TRY(dalloc(&k.tmp, (size_t)k.n), "alloc");
+  HIP_TRY(dalloc(&k.tmp2, (size_t)k.n), "alloc");
+  HIP_TRY(hipHostMalloc((void**)&k.host_status, 4 * sizeof(double), hipHostMallocDefault),
+          "pinned allocation");
+  c->kr_ready = true;
+  return IBIM_OK;
+}
+
+// Copies n device doubles to the pinned mirror and waits for them.
+int fetch(ibim_ctx* c, const double* d, int n, hipStream_t s, double* out) {
+  HIP_TRY(hipMemcpyAsync(c->kr.host_status, d, n * sizeof(double), hipMemcpyDeviceToHost, s),
+          "hipMemcpyAsync");
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  for (int i = 0; i < n; ++i) out[i] = c->kr.host_status[i];
+  return IBIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void ibim_default_options(ibim_options* opt) {
+  if (!opt) return;
+  opt->precision = IBIM_FP64;
+  opt->restart = 60;
+  opt->max_iter = 300;
+  opt->check_residual = 1;
+  opt->device = 0;
+  opt->r_near = 0.0;
+}
+
+const char* ibim_last_error(void) { return g_last_error.c_str(); }
+
+int ibim_setup(const double* sdf, int nx, int ny, int nz, const double origin[3], double h,
+               double eps_tube, double eps_in, double eps_out, double kappa,
+               const double* charge_xyz, const double* charge_q, int n_charges,
+               const ibim_options* opt, void* stream, ibim_ctx** out) {
+  if (!out) return fail(IBIM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!(eps_in > 0) || !(eps_out > 0) || !(kappa >= 0) || !std::isfinite(kappa))
+    return fail(IBIM_EINVAL, "eps_in, eps_out must be > 0 and kappa >= 0");
+  if (n_charges < 0 || (n_charges > 0 && (!charge_xyz || !charge_q)))
+    return fail(IBIM_EINVAL, "bad charge arrays");
+  ibim_options o;
+  ibim_default_options(&o);
+  if (opt) o = *opt;
+  if (o.precision != IBIM_FP64)
+    return fail(IBIM_EINVAL, "unknown or unsupported precision mode");
+  if (o.restart < 1 || o.restart > 1000 || o.max_iter < 1)
+    return fail(IBIM_EINVAL, "restart must be in [1, 1000] and max_iter >= 1");
+  ibim_ctx* c = new (std::nothrow) ibim_ctx();
+  if (!c) return fail(IBIM_ENOMEM, "host allocation failed");
+  c->opt = o;
+  c->eps_in = eps_in;
+  c->eps_out = eps_out;
+  c->kappa = kappa;
+  c->zq.assign(charge_xyz, charge_xyz + 3 * (size_t)n_charges);
+  c->q.assign(charge_q, charge_q + (size_t)n_charges);
+  std::string err;
+  int r = build_host_plan(sdf, nx, ny, nz, origin, h, eps_tube, &c->plan, &err);
+  if (r) {
+    delete c;
+    return fail(r, err);
+  }
+  if (!c->on_device()) {
+    *out = c;
+    return IBIM_OK;
+  }
+  DeviceScope ds(o.device);
+  if (!ds.ok) {
+    delete c;
+    return fail(IBIM_EHIP, "hipSetDevice failed");
+  }
+  hipStream_t s = as_stream(stream);
+  const HostPlan& pl = c->plan;
+  const int32_t M = (int32_t)pl.M;
+  const int64_t nnz = pl.crow[M];
+  DeviceProblem& P = c->P;
+  P.M = M;
+  P.nnz = nnz;
+  P.eps_in = eps_in;
+  P.eps_out = eps_out;
+  P.kappa = kappa;
+  P.h = h;
+  P.lam1 = 0.5 * (1.0 + eps_out / eps_in);
+  P.lam2 = 0.5 * (1.0 + eps_in / eps_out);
+  std::vector<int32_t> crow32(M + 1);
+  for (int32_t k = 0; k <= M; ++k) crow32[k] = (int32_t)pl.crow[k];
+
+  auto cleanup = [&](int code, const std::string& msg) {
+    c->release();
+    delete c;
+    return fail(code, msg);
+  };
+#define UP(dst, vec)                                                             \
+  do {                                                                           \
+    hipError_t _e = upload(&(dst), (vec).data(), (vec).size(), s);               \
+    if (_e != hipSuccess)                                                        \
+      return cleanup(_e == hipErrorOutOfMemory ? IBIM_ENOMEM : IBIM_EHIP,        \
+                     std::string("upload: ") + hipGetErrorString(_e));           \
+  } while (0)
+  UP(P.px, pl.px); UP(P.py, pl.py); UP(P.pz, pl.pz);
+  UP(P.nx, pl.nx); UP(P.ny, pl.ny); UP(P.nz, pl.nz);
+  UP(P.w, pl.w);
+  UP(P.crow, crow32);
+  UP(P.ccol, pl.ccol);
+  if (n_charges > 0) {
+    UP(c->d_zq, c->zq);
+    UP(c->d_q, c->q);
+  }
+  // correction weights, built on the device from temporary per-entry data
+  int32_t* d_rowid = nullptr;
+  int8_t* d_axis = nullptr;
+  double *d_alpha = nullptr, *d_beta = nullptr, *d_eta = nullptr, *d_tau = nullptr;
+  double *d_k1 = nullptr, *d_k2 = nullptr;
+  UP(d_rowid, pl.crowid); UP(d_axis, pl.caxis); UP(d_alpha, pl.calpha); UP(d_beta, pl.cbeta);
+  UP(d_eta, pl.ceta); UP(d_tau, pl.tau); UP(d_k1, pl.kap1); UP(d_k2, pl.kap2);
+#undef UP
+  hipError_t e = dalloc(&c->om11, (size_t)nnz);
+  if (e == hipSuccess) e = dalloc(&c->om21, (size_t)nnz);
+  if (e == hipSuccess) e = dalloc(&P.blocks, 4 * (size_t)nnz);
+  if (e == hipSuccess) {
+    WeightArgs wa;
+    wa.nnz = nnz;
+    wa.rowid = d_rowid;
+    wa.col = P.ccol;
+    wa.axis = d_axis;
+    wa.alpha = d_alpha;
+    wa.beta = d_beta;
+    wa.eta = d_eta;
+    wa.tau = d_tau;
+    wa.kap1 = d_k1;
+    wa.kap2 = d_k2;
+    wa.w = P.w;
+    wa.eps_in = eps_in;
+    wa.eps_out = eps_out;
+    wa.kappa = kappa;
+    wa.h = h;
+    wa.om11 = c->om11;
+    wa.om21 = c->om21;
+    wa.blocks = P.blocks;
+    e = launch_weights(wa, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  dfree(d_rowid); dfree(d_axis); dfree(d_alpha); dfree(d_beta); dfree(d_eta); dfree(d_tau);
+  dfree(d_k1); dfree(d_k2);
+  if (e != hipSuccess)
+    return cleanup(e == hipErrorOutOfMemory ? IBIM_ENOMEM : IBIM_EHIP,
+                   std::string("correction weights: ") + hipGetErrorString(e));
+  c->pair = make_pair_plan(M, o.precision);
+  e = dalloc(&c->partial, (size_t)c->pair.nsplit * 2 * (size_t)M);
+  if (e == hipSuccess) e = dalloc(&c->d_psi, (size_t)(n_charges > 0 ? n_charges : 1));
+  if (e != hipSuccess)
+    return cleanup(e == hipErrorOutOfMemory ? IBIM_ENOMEM : IBIM_EHIP,
+                   std::string("setup: ") + hipGetErrorString(e));
+  *out = c;
+  return IBIM_OK;
+}
+
+void ibim_destroy(ibim_ctx* ctx) {
+  if (!ctx) return;
+  ctx->release();
+  delete ctx;
+}
+
+int ibim_num_nodes(const ibim_ctx* ctx, int64_t* M) {
+  if (int r = check_ctx(ctx)) return r;
+  if (!M) return fail(IBIM_EINVAL, "M is NULL");
+  *M = ctx->plan.M;
+  return IBIM_OK;
+}
+
+int ibim_node_grid_index(const ibim_ctx* ctx, int64_t* idx) {
+  if (int r = check_ctx(ctx)) return r;
+  if (!idx) return fail(IBIM_EINVAL, "idx is NULL");
+  std::memcpy(idx, ctx->plan.grid_index.data(), sizeof(int64_t) * ctx->plan.M);
+  return IBIM_OK;
+}
+
+int ibim_node_geometry(const ibim_ctx* ctx, double* P, double* n, double* w) {
+  if (int r = check_ctx(ctx)) return r;
+  const HostPlan& pl = ctx->plan;
+  for (int64_t m = 0; m < pl.M; ++m) {
+    if (P) {
+      P[3 * m] = pl.px[m];
+      P[3 * m + 1] = pl.py[m];
+      P[3 * m + 2] = pl.pz[m];
+    }
+    if (n) {
+      n[3 * m] = pl.nx[m];
+      n[3 * m + 1] = pl.ny[m];
+      n[3 * m + 2] = pl.nz[m];
+    }
+    if (w) w[m] = pl.w[m];
+  }
+  return IBIM_OK;
+}
+
+int ibim_num_corrections(const ibim_ctx* ctx, int64_t* nnz) {
+  if (int r = check_ctx(ctx)) return r;
+  if (!nnz) return fail(IBIM_EINVAL, "nnz is NULL");
+  *nnz = ctx->plan.crow[ctx->plan.M];
+  return IBIM_OK;
+}
+
+int ibim_corrections(const ibim_ctx* ctx, int64_t* rowptr, int64_t* col, int32_t* axis,
+                     double* alpha, double* beta, double* eta) {
+  if (int r = check_ctx(ctx)) return r;
+  const HostPlan& pl = ctx->plan;
+  const int64_t nnz = pl.crow[pl.M];
+  if (rowptr) std::memcpy(rowptr, pl.crow.data(), sizeof(int64_t) * (pl.M + 1));
+  for (int64_t e = 0; e < nnz; ++e) {
+    if (col) col[e] = pl.ccol[e];
+    if (axis) axis[e] = pl.caxis[e];
+    if (alpha) alpha[e] = pl.calpha[e];
+    if (beta) beta[e] = pl.cbeta[e];
+    if (eta) eta[e] = pl.ceta[e];
+  }
+  return IBIM_OK;
+}
+
+int ibim_correction_weights(const ibim_ctx* ctx, double* om11, double* om21, void* stream) {
+  if (int r = check_dev(ctx)) return r;
+  DeviceScope ds(ctx->opt.device);
+  hipStream_t s = as_stream(stream);
+  const size_t nnz = (size_t)ctx->P.nnz;
+  if (om11) HIP_TRY(hipMemcpyAsync(om11, ctx->om11, nnz * 8, hipMemcpyDeviceToHost, s), "copy");
+  if (om21) HIP_TRY(hipMemcpyAsync(om21, ctx->om21, nnz * 8, hipMemcpyDeviceToHost, s), "copy");
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  return IBIM_OK;
+}
+
+int ibim_rhs(ibim_ctx* ctx, double* g, void* stream) {
+  if (int r = check_dev(ctx)) return r;
+  if (!g) return fail(IBIM_EINVAL, "g is NULL");
+  DeviceScope ds(ctx->opt.device);
+  hipStream_t s = as_stream(stream);
+  const DeviceProblem& P = ctx->P;
+  const int nc = (int)ctx->q.size();
+  hipLaunchKernelGGL(rhs_kernel, dim3((P.M + 255) / 256), dim3(256), 0, s, P.px, P.py, P.pz, P.nx,
+                     P.ny, P.nz, P.M, ctx->d_zq, ctx->d_q, nc, 1.0 / ctx->eps_in, g);
+  HIP_TRY(hipGetLastError(), "rhs kernel launch");
+  return IBIM_OK;
+}
+
+int ibim_apply(ibim_ctx* ctx, const double* u, double* out, void* stream) {
+  if (int r = check_dev(ctx)) return r;
+  if (!u || !out || u == out) return fail(IBIM_EINVAL, "u and out must be distinct device vectors");
+  DeviceScope ds(ctx->opt.device);
+  return apply_impl(ctx, u, out, as_stream(stream));
+}
+
+int ibim_solve(ibim_ctx* ctx, const double* rhs, double tol, double* x, ibim_solve_info* info,
+               void* stream) {
+  if (int r = check_dev(ctx)) return r;
+  if (!rhs || !x || rhs == x) return fail(IBIM_EINVAL, "rhs and x must be distinct device vectors");
+  if (!(tol > 0)) return fail(IBIM_EINVAL, "tol must be > 0");
+  DeviceScope ds(ctx->opt.device);
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = as_stream(stream);
+  if (int r = ensure_krylov(ctx)) return r;
+  ctx->applies = 0;
+  Krylov& K = ctx->kr;
+  const int64_t N = K.n;
+  const int m = K.m;
+  const unsigned nblk = (unsigned)((N + 255) / 256);
+  double hv[2];
+
+  HIP_TRY(K.dots(rhs, N, 1, rhs, N, K.scal + 1, 0, s), "dots");
+  if (int r = fetch(ctx, K.scal + 1, 1, s, hv)) return r;
+  const double bnorm = std::sqrt(hv[0]);
+  hipLaunchKernelGGL(fill_kernel, dim3(nblk), dim3(256), 0, s, x, N, 0.0);
+  HIP_TRY(hipGetLastError(), "fill");
+  int total = 0;
+  bool converged = false;
+  double resid = bnorm;
+  if (!std::isfinite(bnorm)) return fail(IBIM_ENAN, "right-hand side is not finite");
+  if (bnorm == 0.0) {
+    if (info) *info = ibim_solve_info{0, 0, 1, 0.0, 0.0, 0.0};
+    return IBIM_OK;
+  }
+  bool first = true;
+  while (total < ctx->opt.max_iter && !converged) {
+    // r = b - A x (x = 0 on the first cycle, where A x = 0 exactly)
+    if (first) {
+      hipLaunchKernelGGL(copy_kernel, dim3(nblk), dim3(256), 0, s, rhs, K.tmp, N);
+      HIP_TRY(hipGetLastError(), "copy");
+    } else {
+      if (int r = apply_impl(ctx, x, K.tmp2, s)) return r;
+      HIP_TRY(K.residual(rhs, K.tmp2, K.tmp, N, s), "residual");
+    }
+    first = false;
+    HIP_TRY(K.dots(K.tmp, N, 1, K.tmp, N, K.scal + 1, 0, s), "dots");
+    if (int r = fetch(ctx, K.scal + 1, 1, s, hv)) return r;
+    const double beta = std::sqrt(hv[0]);
+    if (!std::isfinite(beta)) return fail(IBIM_ENAN, "NaN in the GMRES residual");
+    if (beta <= tol * bnorm) {
+      converged = true;
+      resid = beta;
+      break;
+    }
+    HIP_TRY(K.normalize(K.tmp, K.scal + 1, K.V, N, s), "normalize");
+    HIP_TRY(K.init_g(K.scal + 1, s), "init_g");
+    int jend = 0;
+    for (int j = 0; j < m; ++j) {
+      double* vj = K.V + (int64_t)j * N;
+      double* w = K.V + (int64_t)(j + 1) * N;
+      if (int r = apply_impl(ctx, vj, w, s)) return r;
+      ++total;
+      // classical Gram-Schmidt, twice
+      HIP_TRY(K.dots(K.V, N, j + 1, w, N, K.hcol, 0, s), "dots");
+      HIP_TRY(K.sub(K.V, N, j + 1, K.hcol, w, N, s), "sub");
+      HIP_TRY(K.dots(K.V, N, j + 1, w, N, K.hcol2, 0, s), "dots");
+      HIP_TRY(K.sub(K.V, N, j + 1, K.hcol2, w, N, s), "sub");
+      HIP_TRY(K.dots(w, N, 1, w, N, K.scal, 0, s), "dots");
+      HIP_TRY(K.normalize(w, K.scal, w, N, s), "normalize");
+      HIP_TRY(K.givens(j, s), "givens");
+      if (int r = fetch(ctx, K.status, 2, s, hv)) return r;
+      resid = hv[0];
+      jend = j + 1;
+      if (!std::isfinite(resid)) return fail(IBIM_ENAN, "NaN in the GMRES recurrence");
+      if (resid <= tol * bnorm || hv[1] == 0.0) {
+        converged = true;
+        break;
+      }
+      if (total >= ctx->opt.max_iter) break;
+    }
+    HIP_TRY(K.backsolve(jend, s), "backsolve");
+    HIP_TRY(K.add(K.V, N, jend, K.y, x, N, s), "update");
+  }
+  double explicit_rel = -1.0;
+  if (ctx->opt.check_residual) {
+    if (int r = apply_impl(ctx, x, K.tmp2, s)) return r;
+    HIP_TRY(K.residual(rhs, K.tmp2, K.tmp, N, s), "residual");
+    HIP_TRY(K.dots(K.tmp, N, 1, K.tmp, N, K.scal + 2, 0, s), "dots");
+    if (int r = fetch(ctx, K.scal + 2, 1, s, hv)) return r;
+    explicit_rel = std::sqrt(hv[0]) / bnorm;
+    if (!std::isfinite(explicit_rel)) return fail(IBIM_ENAN, "NaN in the explicit residual");
+  } else {
+    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  }
+  const double secs =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (info)
+    *info = ibim_solve_info{total, ctx->applies, converged ? 1 : 0, resid / bnorm, explicit_rel, secs};
+  return converged ? IBIM_OK : IBIM_NOT_CONVERGED;
+}
+
+int ibim_energy(ibim_ctx* ctx, const double* x, double* g_pol, void* stream) {
+  if (int r = check_dev(ctx)) return r;
+  if (!x || !g_pol) return fail(IBIM_EINVAL, "x and g_pol must not be NULL");
+  DeviceScope ds(ctx->opt.device);
+  hipStream_t s = as_stream(stream);
+  const int nc = (int)ctx->q.size();
+  if (nc == 0) {
+    *g_pol = 0.0;
+    return IBIM_OK;
+  }
+  const DeviceProblem& P = ctx->P;
+  hipLaunchKernelGGL(psi_rxn_kernel, dim3(nc), dim3(256), 0, s, P.px, P.py, P.pz, P.nx, P.ny,
+                     P.nz, P.w, P.M, x, ctx->d_zq, ctx->eps_out / ctx->eps_in, ctx->kappa,
+                     P.h * P.h * P.h, ctx->d_psi);
+  HIP_TRY(hipGetLastError(), "energy kernel launch");
+  std::vector<double> psi(nc);
+  HIP_TRY(hipMemcpyAsync(psi.data(), ctx->d_psi, nc * sizeof(double), hipMemcpyDeviceToHost, s),
+          "copy");
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  double G = 0.0;
+  for (int j = 0; j < nc; ++j) G += 0.5 * ctx->q[j] * psi[j];
+  if (!std::isfinite(G)) return fail(IBIM_ENAN, "energy is not finite");
+  *g_pol = G;
+  return IBIM_OK;
+}
+
+int ibim_pair_timing(ibim_ctx* ctx, int enable) {
+  if (int r = check_dev(ctx)) return r;
+  ctx->timing = enable != 0;
+  if (enable) ctx->tcount = 0;
+  return IBIM_OK;
+}
+
+int ibim_pair_timing_read(ibim_ctx* ctx, int64_t* launches, double* total_ms) {
+  if (int r = check_dev(ctx)) return r;
+  if (!launches || !total_ms) return fail(IBIM_EINVAL, "NULL output");
+  DeviceScope ds(ctx->opt.device);
+  double tot = 0.0;
+  if (ctx->tcount > 0) HIP_TRY(hipEventSynchronize(ctx->tev[2 * ctx->tcount - 1]), "sync");
+  for (size_t i = 0; i < ctx->tcount; ++i) {
+    float t = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&t, ctx->tev[2 * i], ctx->tev[2 * i + 1]), "hipEventElapsedTime");
+    tot += t;
+  }
+  *launches = (int64_t)ctx->tcount;
+  *total_ms = tot;
+  return IBIM_OK;
+}
+
+}  // extern "C"

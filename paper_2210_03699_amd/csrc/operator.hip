@@ -1,0 +1,231 @@
+// Dense pair sum and sparse correction of the discrete CTR-IBIM operator.
+//
+// Row k of eq. (corr-trapz-rule-sys1/2):
+//   (A u)_1k = lambda1 u1_k + h^3 sum_{m not in N_k} [K11 a1_m - K12 a2_m]
+//            + sum_{m in N_k} [h^2 w11 a1_m - h^3 w12 a2_m]
+//   (A u)_2k = lambda2 u2_k + h^3 sum_{m not in N_k} [K21 a1_m - K22 a2_m]
+//            + sum_{m in N_k} [h^2 w21 a1_m - h^2 w22 a2_m],   a = w u,
+// with the kernels of eq. (Kij-kernels) at x = P(y_k), y = P(y_m).
+//
+// The pair sum is the hot loop (M^2 pairs, exp and rsqrt per pair, not a
+// dense contraction, so it runs on the vector ALUs).  Targets are tiled one
+// per thread; source tiles are staged in LDS as 64-byte records
+// (P, n, a1, a2) and read back as wavefront-uniform broadcasts.  Sources are
+// split into chunks across workgroups for small problems; the chunk partial
+// sums are reduced in a fixed order by the finishing kernel, so results do
+// not depend on scheduling.  Each thread walks its row's sorted correction
+// list alongside the source loop and skips exactly the pairs of N_k.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+
+#include "operator.h"
+#include "weights.h"
+
+namespace ibim {
+namespace {
+
+constexpr int kThreads = 256;  // targets per workgroup, one per thread
+constexpr int kTile = 256;     // sources staged per LDS tile
+constexpr int kXcd = 8;        // MI355X: workgroups are dealt round-robin to 8 XCDs
+
+struct PairArgs {
+  const double* px;
+  const double* py;
+  const double* pz;
+  const double* nx;
+  const double* ny;
+  const double* nz;
+  const double* w;
+  const double* u;
+  const int32_t* crow;
+  const int32_t* ccol;
+  int32_t M;
+  int nsplit;
+  int chunk_tiles;
+  double c1;     // eps_out / eps_in
+  double c2;     // eps_in / eps_out
+  double kappa;
+  double scale;  // h^3 / (4 pi)
+  double* partial;
+};
+
+// Workgroup b handles source chunk b % nsplit of target tile b / nsplit.
+__device__ inline void block_to_work(int b, int nsplit, int* split, int* tile) {
+  *split = b % nsplit;
+  *tile = b / nsplit;
+}
+
+__global__ __launch_bounds__(kThreads) void pair_fp64_kernel(PairArgs a) {
+  __shared__ double2 src[kTile * 4];  // per source: (px,py) (pz,nx) (ny,nz) (a1,a2)
+
+  const int tid = threadIdx.x;
+  int split, tile;
+  block_to_work(blockIdx.x, a.nsplit, &split, &tile);
+  const int32_t M = a.M;
+  const int32_t k = tile * kThreads + tid;
+  const int32_t kc = k < M ? k : M - 1;
+  const double xk = a.px[kc], yk = a.py[kc], zk = a.pz[kc];
+  const double nxk = a.nx[kc], nyk = a.ny[kc], nzk = a.nz[kc];
+  const int32_t s_begin = split * a.chunk_tiles * kTile;
+  const int32_t s_end = min(M, s_begin + a.chunk_tiles * kTile);
+
+  // next excluded source of this row (correction list is sorted by column)
+  int32_t p = a.crow[kc];
+  const int32_t pe = a.crow[kc + 1];
+  while (p < pe && a.ccol[p] < s_begin) ++p;
+  int32_t nxt = p < pe ? a.ccol[p] : INT_MAX;
+
+  const double c1 = a.c1, c2 = a.c2, kap = a.kappa;
+  double S1 = 0.0, S2 = 0.0;
+  for (int32_t s0 = s_begin; s0 < s_end; s0 += kTile) {
+    const int32_t m = s0 + tid;
+    if (m < s_end) {
+      const double wm = a.w[m];
+      src[4 * tid + 0] = make_double2(a.px[m], a.py[m]);
+      src[4 * tid + 1] = make_double2(a.pz[m], a.nx[m]);
+      src[4 * tid + 2] = make_double2(a.ny[m], a.nz[m]);
+      src[4 * tid + 3] = make_double2(wm * a.u[m], wm * a.u[M + m]);
+    }
+    __syncthreads();
+    const int n = min(kTile, s_end - s0);
+#pragma unroll 2
+    for (int j = 0; j < n; ++j) {
+      const double2 q0 = src[4 * j + 0];
+      const double2 q1 = src[4 * j + 1];
+      const double2 q2 = src[4 * j + 2];
+      const double2 q3 = src[4 * j + 3];
+      const double rx = xk - q0.x, ry = yk - q0.y, rz = zk - q1.x;
+      const double R2 = rx * rx + ry * ry + rz * rz;
+      const double iR = rsqrt(R2);
+      const double R = R2 * iR;
+      const double iR2 = iR * iR;
+      const double iR3 = iR2 * iR;
+      const double kr = kap * R;
+      const double e = exp(-kr);
+      const double t = e + e * kr;  // e (1 + kr)
+      const double rny = rx * q1.y + ry * q2.x + rz * q2.y;
+      const double rnx = rx * nxk + ry * nyk + rz * nzk;
+      const double nn = nxk * q1.y + nyk * q2.x + nzk * q2.y;
+      const double phi2 = 1.0 - t;
+      const double phi3 = phi2 - (1.0 / 3.0) * e * kr * kr;
+      const double k11 = rny * iR3 * (1.0 - c1 * t);
+      const double k12 = (1.0 - e) * iR;
+      const double k21 = (nn * phi2 - 3.0 * rnx * rny * phi3 * iR2) * iR3;
+      const double k22 = -rnx * iR3 * (1.0 - c2 * t);
+      const double t1 = k11 * q3.x - k12 * q3.y;
+      const double t2 = k21 * q3.x - k22 * q3.y;
+      const bool ex = (s0 + j == nxt);
+      if (ex) {
+        ++p;
+        nxt = p < pe ? a.ccol[p] : INT_MAX;
+      }
+      S1 += ex ? 0.0 : t1;
+      S2 += ex ? 0.0 : t2;
+    }
+    __syncthreads();
+  }
+  if (k < M) {
+    double* out = a.partial + (size_t)split * 2 * (size_t)M;
+    out[k] = a.scale * S1;
+    out[M + k] = a.scale * S2;
+  }
+}
+
+struct FinishArgs {
+  const double* u;
+  const double* partial;
+  const int32_t* crow;
+  const int32_t* ccol;
+  const double* blocks;
+  int32_t M;
+  int nsplit;
+  double lam1, lam2;
+  double* out;
+};
+
+__global__ __launch_bounds__(256) void finish_kernel(FinishArgs a) {
+  const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= a.M) return;
+  const int32_t M = a.M;
+  double s1 = 0.0, s2 = 0.0;
+  for (int s = 0; s < a.nsplit; ++s) {
+    const double* pp = a.partial + (size_t)s * 2 * (size_t)M;
+    s1 += pp[k];
+    s2 += pp[M + k];
+  }
+  double o1 = a.lam1 * a.u[k] + s1;
+  double o2 = a.lam2 * a.u[M + k] + s2;
+  for (int32_t e = a.crow[k]; e < a.crow[k + 1]; ++e) {
+    const int32_t m = a.ccol[e];
+    const double* B = a.blocks + 4 * (size_t)e;
+    const double v1 = a.u[m], v2 = a.u[M + m];
+    o1 += B[0] * v1 + B[1] * v2;
+    o2 += B[2] * v1 + B[3] * v2;
+  }
+  a.out[k] = o1;
+  a.out[M + k] = o2;
+}
+
+}  // namespace
+
+PairPlan make_pair_plan(int32_t M, int precision) {
+  (void)precision;
+  PairPlan pl;
+  pl.ntile = (M + kThreads - 1) / kThreads;
+  const int src_tiles = (M + kTile - 1) / kTile;
+  // aim for about 8192 workgroups so the tail of the grid is short
+  int want = (8192 + pl.ntile - 1) / pl.ntile;
+  want = ((want + kXcd - 1) / kXcd) * kXcd;
+  const int max_split = src_tiles / 4 > 0 ? src_tiles / 4 : 1;
+  int ns = want < max_split ? want : max_split;
+  if (ns < 1) ns = 1;
+  pl.chunk_tiles = (src_tiles + ns - 1) / ns;
+  pl.nsplit = (src_tiles + pl.chunk_tiles - 1) / pl.chunk_tiles;
+  return pl;
+}
+
+hipError_t launch_pair(const DeviceProblem& P, const PairPlan& plan, int precision,
+                       const double* u, double* partial, hipStream_t stream) {
+  (void)precision;
+  PairArgs a;
+  a.px = P.px; a.py = P.py; a.pz = P.pz;
+  a.nx = P.nx; a.ny = P.ny; a.nz = P.nz;
+  a.w = P.w;
+  a.u = u;
+  a.crow = P.crow;
+  a.ccol = P.ccol;
+  a.M = P.M;
+  a.nsplit = plan.nsplit;
+  a.chunk_tiles = plan.chunk_tiles;
+  a.c1 = P.eps_out / P.eps_in;
+  a.c2 = P.eps_in / P.eps_out;
+  a.kappa = P.kappa;
+  a.scale = P.h * P.h * P.h / (4.0 * kPiD);
+  a.partial = partial;
+  const unsigned blocks = (unsigned)plan.ntile * (unsigned)plan.nsplit;
+  hipLaunchKernelGGL(pair_fp64_kernel, dim3(blocks), dim3(kThreads), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish(const DeviceProblem& P, const PairPlan& plan, int precision,
+                         const double* u, const double* partial, double* out, hipStream_t stream) {
+  (void)precision;
+  FinishArgs f;
+  f.u = u;
+  f.partial = partial;
+  f.crow = P.crow;
+  f.ccol = P.ccol;
+  f.blocks = P.blocks;
+  f.M = P.M;
+  f.nsplit = plan.nsplit;
+  f.lam1 = P.lam1;
+  f.lam2 = P.lam2;
+  f.out = out;
+  const unsigned blocks = (unsigned)((P.M + 255) / 256);
+  hipLaunchKernelGGL(finish_kernel, dim3(blocks), dim3(256), 0, stream, f);
+  return hipGetLastError();
+}
+
+}  // namespace ibim

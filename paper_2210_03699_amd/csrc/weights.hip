@@ -1,0 +1,242 @@
+// Correction weights of the CTR2 rule, computed on the device.
+//
+// For a correction entry (target row k, grid plane with shift (alpha, beta)
+// and line-point signed distance eta) the weight of a kernel with leading
+// term s0(y) = l(y/|y|)/|y| (Theorem 2.1; with the signs of s0^(11), s0^(22)
+// and the factor kappa^2 of s0^(21) that the kernels' limits give) is
+//   omega[s0; alpha, beta] = sum_k a_k omega[cos(k psi)/|y|] + b_k omega[sin(k psi)/|y|]
+// (Section 2.4.2).  l is pi-periodic, so only even k occur.  Each basis weight
+// is the limit of eq. (single_correction_weight), i.e. minus the regularised
+// punctured lattice sum Z_k(alpha, beta) of e^{ik psi}/|y| over Z^2 - (alpha, beta),
+// which an Ewald split evaluates exactly:
+//   Z_k = sum_{n != 0} e^{ik psi(n-a)} Q(s, pi|n-a|^2)/|n-a|
+//       + (-i)^k sum_{m != 0} e^{ik psi(m)} e^{-2 pi i m.a} Q(s, pi|m|^2)/|m|
+//       - 2 [k = 0] - e^{ik psi(-a)} P(s, pi|a|^2)/|a|,        s = (k+1)/2,
+// Q, P the regularised incomplete gamma functions.  Instead of tabulating
+// basis weights and interpolating them, the GPU evaluates this for every
+// entry directly: one wavefront per entry, the lanes splitting the theta
+// samples, the Fourier modes and the lattice points.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "weights.h"
+
+namespace ibim {
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kModes = 41;    // even modes 0, 2, ..., 80
+constexpr int kSamples = 128; // samples of l on [0, pi)
+constexpr int kLat = 8;       // lattice half-width of both sums
+constexpr int kSide = 2 * kLat + 1;
+constexpr int kPts = kSide * kSide;  // includes the origin, skipped
+constexpr int kWavesPerBlock = 4;
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+__global__ __launch_bounds__(kWave* kWavesPerBlock) void weights_kernel(WeightArgs a) {
+  __shared__ double cos_t[kSamples], sin_t[kSamples];
+  __shared__ double l11s[kWavesPerBlock][kSamples], l21s[kWavesPerBlock][kSamples];
+  __shared__ double coef[kWavesPerBlock][4][kModes];
+  __shared__ int jmax_s[kWavesPerBlock];
+
+  const int lane = threadIdx.x % kWave;
+  const int wv = threadIdx.x / kWave;
+  for (int q = threadIdx.x; q < kSamples; q += blockDim.x) {
+    double ang = 2.0 * kPiD * q / kSamples;
+    cos_t[q] = cos(ang);
+    sin_t[q] = sin(ang);
+  }
+  __syncthreads();
+
+  // A wavefront past the last entry recomputes the last entry and discards
+  // it, so every wavefront reaches every block barrier.
+  const int64_t e_raw = (int64_t)blockIdx.x * kWavesPerBlock + wv;
+  const bool valid = e_raw < a.nnz;
+  const int64_t e = valid ? e_raw : a.nnz - 1;
+
+  const int32_t k = a.rowid[e];
+  const int ax = a.axis[e];
+  const int ia = (ax + 1) % 3, ib = (ax + 2) % 3;
+  const double al = a.alpha[e], be = a.beta[e], eta = a.eta[e];
+  const double* tau = a.tau + 6 * (int64_t)k;
+  const double t1a = tau[ia], t1b = tau[ib], t2a = tau[3 + ia], t2b = tau[3 + ib];
+  const double d1 = 1.0 / (1.0 - eta * a.kap1[k]);
+  const double d2 = 1.0 / (1.0 - eta * a.kap2[k]);
+  const double k1 = a.kap1[k], k2 = a.kap2[k];
+  const double c11 = (a.eps_out / a.eps_in - 1.0) / (8.0 * kPiD);
+  const double c21 = a.kappa * a.kappa / (8.0 * kPiD);
+
+  // 1. samples of l11, l21 at theta_p = pi p / kSamples
+  for (int p = lane; p < kSamples; p += kWave) {
+    // cos/sin of pi p / N from the 2 pi table: angle index p/2 on a 2N grid
+    double ang = kPiD * p / kSamples;
+    double c = cos(ang), s = sin(ang);
+    double v0 = (t1a * c + t1b * s) * d1;
+    double v1 = (t2a * c + t2b * s) * d2;
+    double vn2 = v0 * v0 + v1 * v1;
+    double vn = sqrt(vn2);
+    double qf = k1 * v0 * v0 + k2 * v1 * v1;
+    l11s[wv][p] = c11 * qf / (vn2 * vn);
+    l21s[wv][p] = c21 / vn;
+  }
+  __syncthreads();
+
+  // 2. Fourier coefficients of the even modes: lane j owns mode k = 2j.
+  //    cos(2j theta_p) = cos(2 pi (j p mod N) / N).
+  if (lane < kModes) {
+    const int j = lane;
+    double a11 = 0.0, b11 = 0.0, a21 = 0.0, b21 = 0.0;
+    for (int p = 0; p < kSamples; ++p) {
+      int q = (j * p) & (kSamples - 1);
+      double cq = cos_t[q], sq = sin_t[q];
+      a11 += l11s[wv][p] * cq;
+      b11 += l11s[wv][p] * sq;
+      a21 += l21s[wv][p] * cq;
+      b21 += l21s[wv][p] * sq;
+    }
+    double f = (j == 0) ? 1.0 / kSamples : 2.0 / kSamples;
+    coef[wv][0][j] = a11 * f;
+    coef[wv][1][j] = b11 * f;
+    coef[wv][2][j] = a21 * f;
+    coef[wv][3][j] = b21 * f;
+  }
+  __syncthreads();
+  // highest significant mode (wave-uniform)
+  if (lane == 0) {
+    double mx = 0.0;
+    for (int j = 0; j < kModes; ++j)
+      for (int c = 0; c < 4; ++c) mx = fmax(mx, fabs(coef[wv][c][j]));
+    int jm = 1;
+    for (int j = 0; j < kModes; ++j) {
+      double mj = 0.0;
+      for (int c = 0; c < 4; ++c) mj = fmax(mj, fabs(coef[wv][c][j]));
+      if (mj > 1e-18 * mx) jm = j + 1;
+    }
+    jmax_s[wv] = jm;
+  }
+  __syncthreads();
+  const int jmax = jmax_s[wv];
+
+  // 3. lattice sums, accumulated straight into the two weights
+  double acc11 = 0.0, acc21 = 0.0;
+  const double two_over_sqrtpi = 1.1283791670955126;
+  for (int idx = lane; idx < 2 * kPts; idx += kWave) {
+    const int recip = idx >= kPts;
+    const int q = recip ? idx - kPts : idx;
+    const int n1 = q / kSide - kLat, n2 = q % kSide - kLat;
+    if (n1 == 0 && n2 == 0) continue;
+    double y1, y2, pr, pi, sg;
+    if (!recip) {
+      y1 = n1 - al;
+      y2 = n2 - be;
+      pr = 1.0;
+      pi = 0.0;
+      sg = 1.0;
+    } else {
+      y1 = n1;
+      y2 = n2;
+      double arg = -2.0 * kPiD * (n1 * al + n2 * be);
+      pr = cos(arg);
+      pi = sin(arg);
+      sg = -1.0;  // (-i)^k = (-1)^(k/2) for even k
+    }
+    const double r2 = y1 * y1 + y2 * y2;
+    const double r = sqrt(r2);
+    const double x = kPiD * r2;
+    const double sx = sqrt(x);
+    double Q = erfc(sx);                        // Q(1/2, x)
+    double term = two_over_sqrtpi * sx * exp(-x);  // x^s e^-x / Gamma(s+1), s = 1/2
+    const double ir = 1.0 / r;
+    const double zr = y1 * ir, zi = y2 * ir;
+    const double z2r = zr * zr - zi * zi, z2i = 2.0 * zr * zi;
+    double wr = pr * ir, wi = pi * ir;  // phase * e^{ik psi} / r, k = 0
+    double s = 0.5;
+    for (int j = 0; j < jmax; ++j) {
+      const double cr = wr * Q, ci = wi * Q;
+      acc11 += coef[wv][0][j] * cr + coef[wv][1][j] * ci;
+      acc21 += coef[wv][2][j] * cr + coef[wv][3][j] * ci;
+      Q += term;
+      s += 1.0;
+      term *= x / s;
+      const double nr = (wr * z2r - wi * z2i) * sg;
+      const double ni = (wr * z2i + wi * z2r) * sg;
+      wr = nr;
+      wi = ni;
+    }
+  }
+
+  // 4. constant term and the punctured node (lane j owns mode 2j)
+  const double r0 = sqrt(al * al + be * be);
+  if (lane == 0) {
+    acc11 += coef[wv][0][0] * (-2.0);
+    acc21 += coef[wv][2][0] * (-2.0);
+  }
+  if (r0 == 0.0) {
+    if (lane == 0) {  // limit of -P(1/2, pi r^2)/r; higher modes vanish
+      acc11 += coef[wv][0][0] * (-2.0);
+      acc21 += coef[wv][2][0] * (-2.0);
+    }
+  } else if (lane < jmax) {
+    const int j = lane;
+    const double x0 = kPiD * r0 * r0;
+    double sj = 0.5;
+    double pref = two_over_sqrtpi * sqrt(x0) * exp(-x0);
+    for (int t = 0; t < j; ++t) {
+      pref *= x0 / (sj + 1.0);
+      sj += 1.0;
+    }
+    double sum = 0.0, tt = 1.0;
+    for (int l = 0; l < 200; ++l) {
+      sum += tt;
+      tt *= x0 / (sj + 1.0 + l);
+      if (tt < 1e-18 * sum) break;
+    }
+    const double Pv = pref * sum;
+    // e^{i 2j psi(-a)}
+    const double ur = -al / r0, ui = -be / r0;
+    const double u2r = ur * ur - ui * ui, u2i = 2.0 * ur * ui;
+    double zkr = 1.0, zki = 0.0;
+    for (int t = 0; t < j; ++t) {
+      double nr = zkr * u2r - zki * u2i;
+      double ni = zkr * u2i + zki * u2r;
+      zkr = nr;
+      zki = ni;
+    }
+    const double cr = -zkr * Pv / r0, ci = -zki * Pv / r0;
+    acc11 += coef[wv][0][j] * cr + coef[wv][1][j] * ci;
+    acc21 += coef[wv][2][j] * cr + coef[wv][3][j] * ci;
+  }
+
+  const double z11 = wave_sum(acc11);
+  const double z21 = wave_sum(acc21);
+  if (lane == 0 && valid) {
+    const double om11 = -z11, om21 = -z21;
+    a.om11[e] = om11;
+    a.om21[e] = om21;
+    const double wm = a.w[a.col[e]];
+    const double h2 = a.h * a.h, h3 = h2 * a.h;
+    double* B = a.blocks + 4 * e;
+    B[0] = h2 * om11 * wm;
+    B[1] = -h3 * (a.kappa / (4.0 * kPiD)) * wm;
+    B[2] = h2 * om21 * wm;
+    B[3] = h2 * (a.eps_in / a.eps_out) * om11 * wm;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_weights(const WeightArgs& a, hipStream_t stream) {
+  if (a.nnz == 0) return hipSuccess;
+  const int64_t blocks = (a.nnz + kWavesPerBlock - 1) / kWavesPerBlock;
+  hipLaunchKernelGGL(weights_kernel, dim3((unsigned)blocks), dim3(kWave * kWavesPerBlock), 0,
+                     stream, a);
+  return hipGetLastError();
+}
+
+}  // namespace ibim

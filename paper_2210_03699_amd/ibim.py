@@ -1,0 +1,264 @@
+"""Python binding of ``libibim.so`` (the C ABI declared in ``include/ibim.h``).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  Device vectors are ``torch`` float64 CUDA tensors (HIP on ROCm);
+the current torch stream is passed to the library unless a stream is given.
+The library is loaded from the package directory; if it is missing this
+module raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+LIB_PATH = os.path.join(PKG, "libibim.so")
+HEADER = os.path.join(ROOT, "include", "ibim.h")
+
+FP64 = 0
+MIXED = 1
+
+_ERRORS = {
+    -1: "IBIM_EINVAL", -2: "IBIM_EGEOM", -3: "IBIM_ENOMEM", -4: "IBIM_EHIP", -5: "IBIM_ENAN",
+    -6: "IBIM_ENODEV",
+}
+
+
+class IbimError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("restart", ctypes.c_int), ("max_iter", ctypes.c_int),
+                ("check_residual", ctypes.c_int), ("device", ctypes.c_int),
+                ("r_near", ctypes.c_double)]
+
+
+class _SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("applies", ctypes.c_int), ("converged", ctypes.c_int),
+                ("rel_resid", ctypes.c_double), ("explicit_rel_resid", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+
+_lib = None
+_D = ctypes.POINTER(ctypes.c_double)
+_I64 = ctypes.POINTER(ctypes.c_int64)
+_I32 = ctypes.POINTER(ctypes.c_int32)
+_VP = ctypes.c_void_p
+
+
+def header_functions() -> list[str]:
+    """Names of the functions declared in ``include/ibim.h``."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(ibim_[a-z0-9_]+)\s*\(", text)))
+
+
+def load():
+    """Load ``libibim.so``; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2210_03699_amd.build`")
+    # torch ships its own HIP runtime (soname libamdhip64.so.7) and opens it by
+    # an unversioned name; loading torch first makes this library bind to that
+    # same runtime, so torch streams and device pointers are valid here.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.ibim_default_options.argtypes = [ctypes.POINTER(_Options)]
+    lib.ibim_default_options.restype = None
+    lib.ibim_last_error.restype = ctypes.c_char_p
+    lib.ibim_setup.argtypes = [_D, ctypes.c_int, ctypes.c_int, ctypes.c_int, _D, ctypes.c_double,
+                               ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                               _D, _D, ctypes.c_int, ctypes.POINTER(_Options), _VP,
+                               ctypes.POINTER(_VP)]
+    lib.ibim_destroy.argtypes = [_VP]
+    lib.ibim_destroy.restype = None
+    lib.ibim_num_nodes.argtypes = [_VP, _I64]
+    lib.ibim_node_grid_index.argtypes = [_VP, _I64]
+    lib.ibim_node_geometry.argtypes = [_VP, _D, _D, _D]
+    lib.ibim_num_corrections.argtypes = [_VP, _I64]
+    lib.ibim_corrections.argtypes = [_VP, _I64, _I64, _I32, _D, _D, _D]
+    lib.ibim_correction_weights.argtypes = [_VP, _D, _D, _VP]
+    lib.ibim_rhs.argtypes = [_VP, _VP, _VP]
+    lib.ibim_apply.argtypes = [_VP, _VP, _VP, _VP]
+    lib.ibim_solve.argtypes = [_VP, _VP, ctypes.c_double, _VP, ctypes.POINTER(_SolveInfo), _VP]
+    lib.ibim_energy.argtypes = [_VP, _VP, _D, _VP]
+    lib.ibim_pair_timing.argtypes = [_VP, ctypes.c_int]
+    lib.ibim_pair_timing_read.argtypes = [_VP, _I64, _D]
+    _lib = lib
+    return lib
+
+
+def _check(code):
+    if code < 0:
+        raise IbimError(code, load().ibim_last_error().decode())
+    return code
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(_D)
+
+
+def _stream_ptr(stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    import torch
+    return ctypes.c_void_p(int(torch.cuda.current_stream().cuda_stream))
+
+
+def _dev_ptr(t, n=None):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+            and t.is_contiguous()):
+        raise TypeError("expected a contiguous float64 device tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Problem:
+    """One discretised problem (``ibim_setup``) and its solve entry points."""
+
+    def __init__(self, sdf, origin, h, eps_tube, eps_in, eps_out, kappa, charge_xyz=None,
+                 charge_q=None, precision=FP64, restart=60, max_iter=300, check_residual=True,
+                 device=0, r_near=0.0, stream=None):
+        lib = load()
+        self._lib = lib
+        sdf = np.ascontiguousarray(sdf, dtype=np.float64)
+        if sdf.ndim != 3:
+            raise ValueError("sdf must be a 3-D array")
+        origin = np.ascontiguousarray(origin, dtype=np.float64).reshape(3)
+        zq = np.ascontiguousarray(np.zeros((0, 3)) if charge_xyz is None else charge_xyz,
+                                  dtype=np.float64).reshape(-1, 3)
+        q = np.ascontiguousarray(np.zeros(0) if charge_q is None else charge_q, dtype=np.float64)
+        if q.shape[0] != zq.shape[0]:
+            raise ValueError("charge_xyz and charge_q disagree")
+        opt = _Options()
+        lib.ibim_default_options(ctypes.byref(opt))
+        opt.precision = int(precision)
+        opt.restart = int(restart)
+        opt.max_iter = int(max_iter)
+        opt.check_residual = int(bool(check_residual))
+        opt.device = int(device)
+        opt.r_near = float(r_near)
+        self.device = int(device)
+        self.h = float(h)
+        ctx = ctypes.c_void_p()
+        st = ctypes.c_void_p(0) if device < 0 else _stream_ptr(stream)
+        _check(lib.ibim_setup(_dp(sdf), sdf.shape[0], sdf.shape[1], sdf.shape[2], _dp(origin),
+                              float(h), float(eps_tube), float(eps_in), float(eps_out),
+                              float(kappa), _dp(zq), _dp(q), int(q.shape[0]), ctypes.byref(opt),
+                              st, ctypes.byref(ctx)))
+        self._ctx = ctx
+        M = ctypes.c_int64()
+        _check(lib.ibim_num_nodes(ctx, ctypes.byref(M)))
+        self.M = int(M.value)
+        nnz = ctypes.c_int64()
+        _check(lib.ibim_num_corrections(ctx, ctypes.byref(nnz)))
+        self.nnz = int(nnz.value)
+
+    @classmethod
+    def from_workload(cls, wl, **kw):
+        return cls(wl.sdf, wl.origin, wl.h, wl.eps_tube, wl.eps_in, wl.eps_out, wl.kappa,
+                   wl.charge_xyz, wl.charge_q, **kw)
+
+    def close(self):
+        ctx = getattr(self, "_ctx", None)
+        if ctx is not None and ctx.value:
+            self._lib.ibim_destroy(ctx)
+        self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- host inspection ----------------------------------------------------
+    def node_grid_index(self) -> np.ndarray:
+        out = np.empty(self.M, np.int64)
+        _check(self._lib.ibim_node_grid_index(self._ctx, out.ctypes.data_as(_I64)))
+        return out
+
+    def node_geometry(self):
+        P = np.empty((self.M, 3))
+        n = np.empty((self.M, 3))
+        w = np.empty(self.M)
+        _check(self._lib.ibim_node_geometry(self._ctx, _dp(P), _dp(n), _dp(w)))
+        return P, n, w
+
+    def corrections(self) -> dict:
+        out = {"row": np.empty(self.M + 1, np.int64), "col": np.empty(self.nnz, np.int64),
+               "axis": np.empty(self.nnz, np.int32), "alpha": np.empty(self.nnz),
+               "beta": np.empty(self.nnz), "eta": np.empty(self.nnz)}
+        _check(self._lib.ibim_corrections(self._ctx, out["row"].ctypes.data_as(_I64),
+                                          out["col"].ctypes.data_as(_I64),
+                                          out["axis"].ctypes.data_as(_I32), _dp(out["alpha"]),
+                                          _dp(out["beta"]), _dp(out["eta"])))
+        return out
+
+    def correction_weights(self, stream=None):
+        om11 = np.empty(self.nnz)
+        om21 = np.empty(self.nnz)
+        _check(self._lib.ibim_correction_weights(self._ctx, _dp(om11), _dp(om21),
+                                                 _stream_ptr(stream)))
+        return om11, om21
+
+    # -- device entry points ------------------------------------------------
+    def new_vector(self):
+        import torch
+        return torch.empty(2 * self.M, dtype=torch.float64, device=f"cuda:{self.device}")
+
+    def rhs(self, out=None, stream=None):
+        g = self.new_vector() if out is None else out
+        _check(self._lib.ibim_rhs(self._ctx, _dev_ptr(g, 2 * self.M), _stream_ptr(stream)))
+        return g
+
+    def apply(self, u, out=None, stream=None):
+        out = self.new_vector() if out is None else out
+        _check(self._lib.ibim_apply(self._ctx, _dev_ptr(u, 2 * self.M),
+                                    _dev_ptr(out, 2 * self.M), _stream_ptr(stream)))
+        return out
+
+    def solve(self, rhs, tol, x=None, stream=None):
+        x = self.new_vector() if x is None else x
+        info = _SolveInfo()
+        code = _check(self._lib.ibim_solve(self._ctx, _dev_ptr(rhs, 2 * self.M), float(tol),
+                                           _dev_ptr(x, 2 * self.M), ctypes.byref(info),
+                                           _stream_ptr(stream)))
+        return x, {"status": int(code), "iters": info.iters, "applies": info.applies,
+                   "converged": bool(info.converged),
+                   "rel_resid": info.rel_resid, "explicit_rel_resid": info.explicit_rel_resid,
+                   "seconds": info.seconds}
+
+    def energy(self, x, stream=None) -> float:
+        g = ctypes.c_double()
+        _check(self._lib.ibim_energy(self._ctx, _dev_ptr(x, 2 * self.M), ctypes.byref(g),
+                                     _stream_ptr(stream)))
+        return float(g.value)
+
+    def pair_timing(self, enable: bool):
+        _check(self._lib.ibim_pair_timing(self._ctx, int(bool(enable))))
+
+    def pair_timing_read(self):
+        """(launches, total milliseconds) of the pair kernels timed so far."""
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        _check(self._lib.ibim_pair_timing_read(self._ctx, ctypes.byref(n), ctypes.byref(ms)))
+        return int(n.value), float(ms.value)
+
+    def solve_energy(self, tol, stream=None):
+        g = self.rhs(stream=stream)
+        x, info = self.solve(g, tol, stream=stream)
+        info["g_pol"] = self.energy(x, stream=stream)
+        return x, info
