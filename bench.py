@@ -81,6 +81,9 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile", action="store_true",
+                    help="short run for rocprofv3: 3 operator applications and one plain "
+                         "256 MiB device copy (the reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
@@ -102,6 +105,17 @@ def main():
     M = prob.M
     print(f"[bench] {wl.name}: M={M} nnz={prob.nnz} setup {setup_s:.2f}s", file=sys.stderr,
           flush=True)
+
+    if args.profile:
+        u = torch.from_numpy(workloads.random_vector(2 * M, 1)).to(dev)
+        for _ in range(3):
+            prob.apply(u)
+        src = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile": True, "M": M, "copy_bytes": src.numel() * 8}), flush=True)
+        return
 
     def step():
         g = prob.rhs()

@@ -106,6 +106,7 @@ struct ibim_ctx {
     dfree(P.px); dfree(P.py); dfree(P.pz); dfree(P.nx); dfree(P.ny); dfree(P.nz); dfree(P.w);
     dfree(P.px32); dfree(P.py32); dfree(P.pz32); dfree(P.nx32); dfree(P.ny32); dfree(P.nz32);
     dfree(P.crow); dfree(P.ccol); dfree(P.blocks); dfree(P.nrow); dfree(P.ncol);
+    dfree(P.xrow); dfree(P.xtile);
     dfree(partial); dfree(om11); dfree(om21); dfree(d_zq); dfree(d_q); dfree(d_psi);
     dfree(kr.V); dfree(kr.H); dfree(kr.cs); dfree(kr.sn); dfree(kr.g); dfree(kr.y);
     dfree(kr.hcol); dfree(kr.hcol2); dfree(kr.scal); dfree(kr.status); dfree(kr.partial);
@@ -345,6 +346,10 @@ int ibim_setup(const double* sdf, int nx, int ny, int nz, const double origin[3]
   UP(P.w, pl.w);
   UP(P.crow, crow32);
   UP(P.ccol, pl.ccol);
+  std::vector<int32_t> xrow, xtile;
+  exclusion_tiles(M, pl.crow.data(), pl.ccol.data(), &xrow, &xtile);
+  UP(P.xrow, xrow);
+  UP(P.xtile, xtile);
   if (n_charges > 0) {
     UP(c->d_zq, c->zq);
     UP(c->d_q, c->q);

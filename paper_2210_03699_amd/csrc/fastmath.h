@@ -1,0 +1,64 @@
+// Elementary functions for the pair kernels, written for the value ranges
+// the kernels need (no special-value handling).
+#pragma once
+
+#if defined(__HIPCC__)
+#define IBIM_HD __host__ __device__
+#else
+#define IBIM_HD
+#endif
+
+#include <cmath>
+
+namespace ibim {
+
+// e^{-x} for finite x >= 0 (x = kappa R).  Cody-Waite reduction
+// -x = k ln2 + r, |r| <= ln2/2, then e^r by a degree-11 polynomial whose
+// coefficients interpolate e^r at the Chebyshev nodes of [-0.3466, 0.3466]
+// (relative error below 2e-17 before rounding), and 2^k by ldexp.  Underflow
+// for large x returns 0 through ldexp.
+IBIM_HD inline double exp_neg(double x) {
+  const double kLog2e = 1.4426950408889634;
+  const double kLn2Hi = 6.93147180369123816490e-01;  // ln 2, high 32 bits
+  const double kLn2Lo = 1.90821492927058770002e-10;  // ln 2 - kLn2Hi
+  const double k = rint(-x * kLog2e);
+  const double r = fma(-k, kLn2Lo, fma(-k, kLn2Hi, -x));
+  double p = 2.5110049204818658e-08;
+  p = fma(p, r, 2.763265472252779e-07);
+  p = fma(p, r, 2.755724088722987e-06);
+  p = fma(p, r, 2.4801485441561313e-05);
+  p = fma(p, r, 0.00019841269890076403);
+  p = fma(p, r, 0.0013888888952352863);
+  p = fma(p, r, 0.008333333333319589);
+  p = fma(p, r, 0.04166666666648795);
+  p = fma(p, r, 0.1666666666666668);
+  p = fma(p, r, 0.5000000000000019);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return ldexp(p, (int)k);
+}
+
+// e^{-x} in float32 for x >= 0, from the hardware base-2 exponential.
+IBIM_HD inline float exp_neg_f32(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_exp2f(-x * 1.44269504088896341f);
+#else
+  return std::exp2(-x * 1.44269504088896341f);
+#endif
+}
+
+#if defined(__HIPCC__)
+// 1/sqrt(x) for finite x > 0: hardware estimate and one third-order
+// correction y (1 + e/2 + 3 e^2/8), e = 1 - x y^2.
+__device__ inline double rsqrt_pos(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * y, y, 1.0);
+  return fma(y * e, fma(e, 0.375, 0.5), y);
+#else
+  return 1.0 / std::sqrt(x);
+#endif
+}
+#endif
+
+}  // namespace ibim

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 namespace ibim {
 
@@ -32,6 +33,9 @@ struct DeviceProblem {
   int32_t* crow = nullptr;  // M+1 (nnz < 2^31)
   int32_t* ccol = nullptr;  // nnz
   double* blocks = nullptr; // 4*nnz
+  // per target tile, the sorted source tiles that hold one of its corrected pairs
+  int32_t* xrow = nullptr;
+  int32_t* xtile = nullptr;
   // near list of the mixed path: CSR of (row, col) pairs with R < r_near
   int32_t* nrow = nullptr;
   int32_t* ncol = nullptr;
@@ -48,6 +52,11 @@ struct PairPlan {
 };
 
 PairPlan make_pair_plan(int32_t M, int precision);
+
+// Host: per target tile, the sorted list of source tiles containing one of
+// its corrected pairs (CSR: xrow has one entry per tile plus one).
+void exclusion_tiles(int32_t M, const int64_t* crow, const int32_t* ccol,
+                     std::vector<int32_t>* xrow, std::vector<int32_t>* xtile);
 
 // partial: nsplit * 2M float64 scratch.  Writes partial sums of
 // h^3 sum_m K(k, m) (w u)(m) over each source chunk, pairs in N_h(y_k) skipped.

@@ -13,13 +13,18 @@
 // (P, n, a1, a2) and read back as wavefront-uniform broadcasts.  Sources are
 // split into chunks across workgroups for small problems; the chunk partial
 // sums are reduced in a fixed order by the finishing kernel, so results do
-// not depend on scheduling.  Each thread walks its row's sorted correction
-// list alongside the source loop and skips exactly the pairs of N_k.
+// not depend on scheduling.  The pairs of N_k are skipped exactly: source
+// tiles that hold a corrected pair of the target tile (a few percent) run a
+// loop in which each thread walks its row's sorted correction list; all other
+// tiles run a loop without any test.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cstdint>
+#include <vector>
 
+#include "fastmath.h"
 #include "operator.h"
 #include "weights.h"
 
@@ -41,6 +46,8 @@ struct PairArgs {
   const double* u;
   const int32_t* crow;
   const int32_t* ccol;
+  const int32_t* xrow;   // per target tile: range in xtile
+  const int32_t* xtile;  // sorted source tiles holding a corrected pair of the tile
   int32_t M;
   int nsplit;
   int chunk_tiles;
@@ -51,10 +58,68 @@ struct PairArgs {
   double* partial;
 };
 
-// Workgroup b handles source chunk b % nsplit of target tile b / nsplit.
+// Workgroups are dealt round-robin to the 8 XCDs (workgroup b runs on XCD
+// b % 8), each with its own L2.  When nsplit is a multiple of 8, XCD x gets
+// the source chunks [x*nsplit/8, (x+1)*nsplit/8) of every target tile, so
+// each L2 holds only one eighth of the sources.
 __device__ inline void block_to_work(int b, int nsplit, int* split, int* tile) {
-  *split = b % nsplit;
-  *tile = b / nsplit;
+  if (nsplit % kXcd == 0) {
+    const int x = b % kXcd, j = b / kXcd, per = nsplit / kXcd;
+    *split = x * per + j % per;
+    *tile = j / per;
+  } else {
+    *split = b % nsplit;
+    *tile = b / nsplit;
+  }
+}
+
+struct Target {
+  double x, y, z, nx, ny, nz;
+};
+
+// Contribution of one source to the two rows of a target:
+//   d1 = K11 a1 - K12 a2,  d2 = K21 a1 - K22 a2   (without the 1/(4 pi)),
+// with e = e^{-kR}, t = e (1 + kR):
+//   K11 = (r.n_m)(1 - c1 t)/R^3,         K12 = (1 - e)/R,
+//   K21 = [n_k.n_m (1 - t) - 3 (r.n_k)(r.n_m) phi3 / R^2]/R^3,
+//   K22 = -(r.n_k)(1 - c2 t)/R^3,        phi3 = 1 - t - e (kR)^2/3;
+// since (kR)^2/R^2 = k^2, K21 R^3 = (1 - t)(n_k.n_m - 3 q/R^2) + k^2 e q with
+// q = (r.n_k)(r.n_m).
+// The source amplitudes are scaled by 1/R^3 once (A1, A2).
+// kAccumulate: add straight into (s1, s2) with fused multiply-adds;
+// otherwise return the contributions in (s1, s2) for a masked add.
+template <bool kAccumulate>
+__device__ __forceinline__ void pair_terms(const Target& t, const double2 q0, const double2 q1,
+                                           const double2 q2, const double2 q3, double c1,
+                                           double c2, double kap, double kap2, double& s1,
+                                           double& s2) {
+  const double rx = t.x - q0.x, ry = t.y - q0.y, rz = t.z - q1.x;
+  const double R2 = fma(rz, rz, fma(ry, ry, rx * rx));
+  const double iR = rsqrt_pos(R2);
+  const double R = R2 * iR;
+  const double iR2 = iR * iR;
+  const double iR3 = iR2 * iR;
+  const double kr = kap * R;
+  const double e = exp_neg(kr);
+  const double te = fma(e, kr, e);
+  const double rny = fma(rz, q2.y, fma(ry, q2.x, rx * q1.y));
+  const double rnx = fma(rz, t.nz, fma(ry, t.ny, rx * t.nx));
+  const double nn = fma(t.nz, q2.y, fma(t.ny, q2.x, t.nx * q1.y));
+  const double A1 = q3.x * iR3;
+  const double A2 = q3.y * iR3;
+  const double g11 = rny * fma(-c1, te, 1.0);
+  const double g12 = (1.0 - e) * R2;
+  const double phi2 = 1.0 - te;
+  const double q = rnx * rny;
+  const double g21 = fma(phi2, fma(q * iR2, -3.0, nn), kap2 * e * q);
+  const double g22 = rnx * fma(-c2, te, 1.0);
+  if (kAccumulate) {
+    s1 = fma(g11, A1, fma(-g12, A2, s1));
+    s2 = fma(g21, A1, fma(g22, A2, s2));
+  } else {
+    s1 = fma(g11, A1, -g12 * A2);
+    s2 = fma(g21, A1, g22 * A2);
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void pair_fp64_kernel(PairArgs a) {
@@ -66,8 +131,7 @@ __global__ __launch_bounds__(kThreads) void pair_fp64_kernel(PairArgs a) {
   const int32_t M = a.M;
   const int32_t k = tile * kThreads + tid;
   const int32_t kc = k < M ? k : M - 1;
-  const double xk = a.px[kc], yk = a.py[kc], zk = a.pz[kc];
-  const double nxk = a.nx[kc], nyk = a.ny[kc], nzk = a.nz[kc];
+  const Target tg{a.px[kc], a.py[kc], a.pz[kc], a.nx[kc], a.ny[kc], a.nz[kc]};
   const int32_t s_begin = split * a.chunk_tiles * kTile;
   const int32_t s_end = min(M, s_begin + a.chunk_tiles * kTile);
 
@@ -76,8 +140,12 @@ __global__ __launch_bounds__(kThreads) void pair_fp64_kernel(PairArgs a) {
   const int32_t pe = a.crow[kc + 1];
   while (p < pe && a.ccol[p] < s_begin) ++p;
   int32_t nxt = p < pe ? a.ccol[p] : INT_MAX;
+  // next source tile that holds an excluded pair of this target tile (uniform)
+  int32_t xp = a.xrow[tile];
+  const int32_t xe = a.xrow[tile + 1];
+  while (xp < xe && a.xtile[xp] * kTile < s_begin) ++xp;
 
-  const double c1 = a.c1, c2 = a.c2, kap = a.kappa;
+  const double c1 = a.c1, c2 = a.c2, kap = a.kappa, kap2 = a.kappa * a.kappa;
   double S1 = 0.0, S2 = 0.0;
   for (int32_t s0 = s_begin; s0 < s_end; s0 += kTile) {
     const int32_t m = s0 + tid;
@@ -90,39 +158,27 @@ __global__ __launch_bounds__(kThreads) void pair_fp64_kernel(PairArgs a) {
     }
     __syncthreads();
     const int n = min(kTile, s_end - s0);
+    const bool careful = xp < xe && a.xtile[xp] * kTile == s0;
+    if (!careful) {
+      // no corrected pair of this target tile among these sources
 #pragma unroll 2
-    for (int j = 0; j < n; ++j) {
-      const double2 q0 = src[4 * j + 0];
-      const double2 q1 = src[4 * j + 1];
-      const double2 q2 = src[4 * j + 2];
-      const double2 q3 = src[4 * j + 3];
-      const double rx = xk - q0.x, ry = yk - q0.y, rz = zk - q1.x;
-      const double R2 = rx * rx + ry * ry + rz * rz;
-      const double iR = rsqrt(R2);
-      const double R = R2 * iR;
-      const double iR2 = iR * iR;
-      const double iR3 = iR2 * iR;
-      const double kr = kap * R;
-      const double e = exp(-kr);
-      const double t = e + e * kr;  // e (1 + kr)
-      const double rny = rx * q1.y + ry * q2.x + rz * q2.y;
-      const double rnx = rx * nxk + ry * nyk + rz * nzk;
-      const double nn = nxk * q1.y + nyk * q2.x + nzk * q2.y;
-      const double phi2 = 1.0 - t;
-      const double phi3 = phi2 - (1.0 / 3.0) * e * kr * kr;
-      const double k11 = rny * iR3 * (1.0 - c1 * t);
-      const double k12 = (1.0 - e) * iR;
-      const double k21 = (nn * phi2 - 3.0 * rnx * rny * phi3 * iR2) * iR3;
-      const double k22 = -rnx * iR3 * (1.0 - c2 * t);
-      const double t1 = k11 * q3.x - k12 * q3.y;
-      const double t2 = k21 * q3.x - k22 * q3.y;
-      const bool ex = (s0 + j == nxt);
-      if (ex) {
-        ++p;
-        nxt = p < pe ? a.ccol[p] : INT_MAX;
+      for (int j = 0; j < n; ++j)
+        pair_terms<true>(tg, src[4 * j], src[4 * j + 1], src[4 * j + 2], src[4 * j + 3], c1, c2,
+                         kap, kap2, S1, S2);
+    } else {
+      ++xp;
+      for (int j = 0; j < n; ++j) {
+        double d1, d2;
+        pair_terms<false>(tg, src[4 * j], src[4 * j + 1], src[4 * j + 2], src[4 * j + 3], c1,
+                          c2, kap, kap2, d1, d2);
+        const bool ex = (s0 + j == nxt);
+        if (ex) {
+          ++p;
+          nxt = p < pe ? a.ccol[p] : INT_MAX;
+        }
+        S1 += ex ? 0.0 : d1;
+        S2 += ex ? 0.0 : d2;
       }
-      S1 += ex ? 0.0 : t1;
-      S2 += ex ? 0.0 : t2;
     }
     __syncthreads();
   }
@@ -170,13 +226,29 @@ __global__ __launch_bounds__(256) void finish_kernel(FinishArgs a) {
 
 }  // namespace
 
+void exclusion_tiles(int32_t M, const int64_t* crow, const int32_t* ccol,
+                     std::vector<int32_t>* xrow, std::vector<int32_t>* xtile) {
+  const int ntile = (M + kThreads - 1) / kThreads;
+  std::vector<std::vector<int32_t>> lists(ntile);
+  for (int32_t k = 0; k < M; ++k)
+    for (int64_t e = crow[k]; e < crow[k + 1]; ++e) lists[k / kThreads].push_back(ccol[e] / kTile);
+  xrow->assign(ntile + 1, 0);
+  xtile->clear();
+  for (int t = 0; t < ntile; ++t) {
+    std::sort(lists[t].begin(), lists[t].end());
+    lists[t].erase(std::unique(lists[t].begin(), lists[t].end()), lists[t].end());
+    xtile->insert(xtile->end(), lists[t].begin(), lists[t].end());
+    (*xrow)[t + 1] = (int32_t)xtile->size();
+  }
+}
+
 PairPlan make_pair_plan(int32_t M, int precision) {
   (void)precision;
   PairPlan pl;
   pl.ntile = (M + kThreads - 1) / kThreads;
   const int src_tiles = (M + kTile - 1) / kTile;
-  // aim for about 8192 workgroups so the tail of the grid is short
-  int want = (8192 + pl.ntile - 1) / pl.ntile;
+  // aim for about 16384 workgroups so the tail of the grid is short
+  int want = (16384 + pl.ntile - 1) / pl.ntile;
   want = ((want + kXcd - 1) / kXcd) * kXcd;
   const int max_split = src_tiles / 4 > 0 ? src_tiles / 4 : 1;
   int ns = want < max_split ? want : max_split;
@@ -196,6 +268,8 @@ hipError_t launch_pair(const DeviceProblem& P, const PairPlan& plan, int precisi
   a.u = u;
   a.crow = P.crow;
   a.ccol = P.ccol;
+  a.xrow = P.xrow;
+  a.xtile = P.xtile;
   a.M = P.M;
   a.nsplit = plan.nsplit;
   a.chunk_tiles = plan.chunk_tiles;
