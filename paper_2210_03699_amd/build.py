@@ -16,7 +16,10 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libibim.so")
 
-HIP_SOURCES = ["weights.hip", "operator.hip", "krylov.hip", "capi.hip"]
+HIP_SOURCES = ["weights.hip", "operator.hip", "mixed.hip", "krylov.hip", "capi.hip"]
+# The mixed-precision file needs bit-reproducible float32 evaluations in two
+# kernels: no automatic contraction there (its fused multiply-adds are explicit).
+PER_FILE_FLAGS = {"mixed.hip": ["-ffp-contract=off"]}
 HOST_SOURCES = ["setup_host.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -45,7 +48,8 @@ def build(verbose: bool = False) -> str:
     for src in HIP_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
         objs.append(obj)
-        jobs.append([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+        jobs.append([HIPCC, *HIP_FLAGS, *PER_FILE_FLAGS.get(src, []), "-c",
+                     os.path.join(CSRC, src), "-o", obj])
     for src in HOST_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
         objs.append(obj)

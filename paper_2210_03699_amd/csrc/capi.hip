@@ -213,12 +213,18 @@ int apply_impl(ibim_ctx* c, const double* u, double* out, hipStream_t s) {
     e1 = c->tev[2 * c->tcount + 1];
     HIP_TRY(hipEventRecord(e0, s), "hipEventRecord");
   }
-  HIP_TRY(launch_pair(c->P, c->pair, prec, u, c->partial, s), "pair kernel launch");
+  if (prec == IBIM_MIXED)
+    HIP_TRY(launch_pair_mixed(c->P, c->pair, u, c->partial, s), "pair kernel launch");
+  else
+    HIP_TRY(launch_pair(c->P, c->pair, prec, u, c->partial, s), "pair kernel launch");
   if (c->timing) {
     HIP_TRY(hipEventRecord(e1, s), "hipEventRecord");
     ++c->tcount;
   }
-  HIP_TRY(launch_finish(c->P, c->pair, prec, u, c->partial, out, s), "finish kernel launch");
+  if (prec == IBIM_MIXED)
+    HIP_TRY(launch_finish_mixed(c->P, c->pair, u, c->partial, out, s), "finish kernel launch");
+  else
+    HIP_TRY(launch_finish(c->P, c->pair, prec, u, c->partial, out, s), "finish kernel launch");
   ++c->applies;
   return IBIM_OK;
 }
@@ -286,8 +292,10 @@ int ibim_setup(const double* sdf, int nx, int ny, int nz, const double origin[3]
   ibim_options o;
   ibim_default_options(&o);
   if (opt) o = *opt;
-  if (o.precision != IBIM_FP64)
-    return fail(IBIM_EINVAL, "unknown or unsupported precision mode");
+  if (o.precision != IBIM_FP64 && o.precision != IBIM_MIXED)
+    return fail(IBIM_EINVAL, "unknown precision mode");
+  if (!(o.r_near >= 0.0) || !std::isfinite(o.r_near))
+    return fail(IBIM_EINVAL, "r_near must be >= 0");
   if (o.restart < 1 || o.restart > 1000 || o.max_iter < 1)
     return fail(IBIM_EINVAL, "restart must be in [1, 1000] and max_iter >= 1");
   ibim_ctx* c = new (std::nothrow) ibim_ctx();
@@ -393,6 +401,46 @@ int ibim_setup(const double* sdf, int nx, int ny, int nz, const double origin[3]
   if (e != hipSuccess)
     return cleanup(e == hipErrorOutOfMemory ? IBIM_ENOMEM : IBIM_EHIP,
                    std::string("correction weights: ") + hipGetErrorString(e));
+  if (o.precision == IBIM_MIXED) {
+    // float32 geometry relative to the centroid, and the near list
+    double cen[3] = {0, 0, 0};
+    for (int32_t m = 0; m < M; ++m) {
+      cen[0] += pl.px[m];
+      cen[1] += pl.py[m];
+      cen[2] += pl.pz[m];
+    }
+    for (int a = 0; a < 3; ++a) P.centre[a] = cen[a] / M;
+    std::vector<float> f(M);
+    auto up32 = [&](float** dst, const std::vector<double>& v, double shift) {
+      for (int32_t m = 0; m < M; ++m) f[m] = (float)(v[m] - shift);
+      hipError_t e2 = upload(dst, f.data(), f.size(), s);
+      if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);  // f is reused
+      return e2;
+    };
+    e = up32(&P.px32, pl.px, P.centre[0]);
+    if (e == hipSuccess) e = up32(&P.py32, pl.py, P.centre[1]);
+    if (e == hipSuccess) e = up32(&P.pz32, pl.pz, P.centre[2]);
+    if (e == hipSuccess) e = up32(&P.nx32, pl.nx, 0.0);
+    if (e == hipSuccess) e = up32(&P.ny32, pl.ny, 0.0);
+    if (e == hipSuccess) e = up32(&P.nz32, pl.nz, 0.0);
+    int32_t* d_node_of = nullptr;
+    int64_t* d_gidx = nullptr;
+    if (e == hipSuccess) {
+      std::vector<int32_t> node_of((size_t)nx * ny * nz, -1);
+      for (int32_t m = 0; m < M; ++m) node_of[pl.grid_index[m]] = m;
+      e = upload(&d_node_of, node_of.data(), node_of.size(), s);
+      if (e == hipSuccess) e = upload(&d_gidx, pl.grid_index.data(), pl.grid_index.size(), s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+    const double r_near = o.r_near > 0.0 ? o.r_near : 4.0 * h;
+    if (e == hipSuccess)
+      e = build_near_list(P, d_node_of, d_gidx, nx, ny, nz, r_near, eps_tube, s);
+    dfree(d_node_of);
+    dfree(d_gidx);
+    if (e != hipSuccess)
+      return cleanup(e == hipErrorOutOfMemory ? IBIM_ENOMEM : IBIM_EHIP,
+                     std::string("mixed-precision setup: ") + hipGetErrorString(e));
+  }
   c->pair = make_pair_plan(M, o.precision);
   e = dalloc(&c->partial, (size_t)c->pair.nsplit * 2 * (size_t)M);
   if (e == hipSuccess) e = dalloc(&c->d_psi, (size_t)(n_charges > 0 ? n_charges : 1));

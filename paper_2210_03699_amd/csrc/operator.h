@@ -8,6 +8,25 @@
 
 namespace ibim {
 
+constexpr int kPairThreads = 256;  // targets per workgroup of the pair kernels (one per lane)
+constexpr int kPairTile = 256;     // sources staged per LDS tile
+constexpr int kXcdCount = 8;       // MI355X: workgroup b runs on XCD b % 8
+
+// Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.  When
+// nsplit is a multiple of 8, XCD x gets the source chunks
+// [x*nsplit/8, (x+1)*nsplit/8) of every target tile, so each L2 holds only
+// one eighth of the sources; otherwise chunk b % nsplit of tile b / nsplit.
+__device__ inline void pair_block_to_work(int b, int nsplit, int* split, int* tile) {
+  if (nsplit % kXcdCount == 0) {
+    const int x = b % kXcdCount, j = b / kXcdCount, per = nsplit / kXcdCount;
+    *split = x * per + j % per;
+    *tile = j / per;
+  } else {
+    *split = b % nsplit;
+    *tile = b / nsplit;
+  }
+}
+
 // Geometry and correction structure resident on the device for one problem.
 struct DeviceProblem {
   int32_t M = 0;
@@ -37,7 +56,8 @@ struct DeviceProblem {
   int32_t* xrow = nullptr;
   int32_t* xtile = nullptr;
   // near list of the mixed path: CSR of (row, col) pairs with R < r_near
-  int32_t* nrow = nullptr;
+  // (float64 distance), pairs of N_k excluded
+  int64_t* nrow = nullptr;
   int32_t* ncol = nullptr;
   int64_t nnear = 0;
   double eps_in = 1, eps_out = 1, kappa = 0, h = 0;
@@ -67,5 +87,20 @@ hipError_t launch_pair(const DeviceProblem& P, const PairPlan& plan, int precisi
 // for the mixed path).
 hipError_t launch_finish(const DeviceProblem& P, const PairPlan& plan, int precision,
                          const double* u, const double* partial, double* out, hipStream_t stream);
+
+// Mixed-precision pair sum (float32 pairs, float64 sums) and its finishing
+// kernel (adds float64 minus float32 values of the near pairs).
+hipError_t launch_pair_mixed(const DeviceProblem& P, const PairPlan& plan, const double* u,
+                             double* partial, hipStream_t stream);
+hipError_t launch_finish_mixed(const DeviceProblem& P, const PairPlan& plan, const double* u,
+                               const double* partial, double* out, hipStream_t stream);
+
+// Builds P.nrow / P.ncol: for every node, the nodes m not in N_k with
+// |P_k - P_m| < r_near, found by scanning grid offsets within
+// (r_near + 2 eps)/h.  node_of: device grid -> node map (-1 off the tube);
+// grid_index: device node -> linear grid index.  Synchronises the stream.
+hipError_t build_near_list(DeviceProblem& P, const int32_t* node_of, const int64_t* grid_index,
+                           int nx, int ny, int nz, double r_near, double eps,
+                           hipStream_t stream);
 
 }  // namespace ibim

@@ -24,16 +24,16 @@
 #include <cstdint>
 #include <vector>
 
-#include "fastmath.h"
 #include "operator.h"
+#include "pair_math.h"
 #include "weights.h"
 
 namespace ibim {
 namespace {
 
-constexpr int kThreads = 256;  // targets per workgroup, one per thread
-constexpr int kTile = 256;     // sources staged per LDS tile
-constexpr int kXcd = 8;        // MI355X: workgroups are dealt round-robin to 8 XCDs
+constexpr int kThreads = kPairThreads;
+constexpr int kTile = kPairTile;
+constexpr int kXcd = kXcdCount;
 
 struct PairArgs {
   const double* px;
@@ -58,80 +58,17 @@ struct PairArgs {
   double* partial;
 };
 
-// Workgroups are dealt round-robin to the 8 XCDs (workgroup b runs on XCD
-// b % 8), each with its own L2.  When nsplit is a multiple of 8, XCD x gets
-// the source chunks [x*nsplit/8, (x+1)*nsplit/8) of every target tile, so
-// each L2 holds only one eighth of the sources.
-__device__ inline void block_to_work(int b, int nsplit, int* split, int* tile) {
-  if (nsplit % kXcd == 0) {
-    const int x = b % kXcd, j = b / kXcd, per = nsplit / kXcd;
-    *split = x * per + j % per;
-    *tile = j / per;
-  } else {
-    *split = b % nsplit;
-    *tile = b / nsplit;
-  }
-}
-
-struct Target {
-  double x, y, z, nx, ny, nz;
-};
-
-// Contribution of one source to the two rows of a target:
-//   d1 = K11 a1 - K12 a2,  d2 = K21 a1 - K22 a2   (without the 1/(4 pi)),
-// with e = e^{-kR}, t = e (1 + kR):
-//   K11 = (r.n_m)(1 - c1 t)/R^3,         K12 = (1 - e)/R,
-//   K21 = [n_k.n_m (1 - t) - 3 (r.n_k)(r.n_m) phi3 / R^2]/R^3,
-//   K22 = -(r.n_k)(1 - c2 t)/R^3,        phi3 = 1 - t - e (kR)^2/3;
-// since (kR)^2/R^2 = k^2, K21 R^3 = (1 - t)(n_k.n_m - 3 q/R^2) + k^2 e q with
-// q = (r.n_k)(r.n_m).
-// The source amplitudes are scaled by 1/R^3 once (A1, A2).
-// kAccumulate: add straight into (s1, s2) with fused multiply-adds;
-// otherwise return the contributions in (s1, s2) for a masked add.
-template <bool kAccumulate>
-__device__ __forceinline__ void pair_terms(const Target& t, const double2 q0, const double2 q1,
-                                           const double2 q2, const double2 q3, double c1,
-                                           double c2, double kap, double kap2, double& s1,
-                                           double& s2) {
-  const double rx = t.x - q0.x, ry = t.y - q0.y, rz = t.z - q1.x;
-  const double R2 = fma(rz, rz, fma(ry, ry, rx * rx));
-  const double iR = rsqrt_pos(R2);
-  const double R = R2 * iR;
-  const double iR2 = iR * iR;
-  const double iR3 = iR2 * iR;
-  const double kr = kap * R;
-  const double e = exp_neg(kr);
-  const double te = fma(e, kr, e);
-  const double rny = fma(rz, q2.y, fma(ry, q2.x, rx * q1.y));
-  const double rnx = fma(rz, t.nz, fma(ry, t.ny, rx * t.nx));
-  const double nn = fma(t.nz, q2.y, fma(t.ny, q2.x, t.nx * q1.y));
-  const double A1 = q3.x * iR3;
-  const double A2 = q3.y * iR3;
-  const double g11 = rny * fma(-c1, te, 1.0);
-  const double g12 = (1.0 - e) * R2;
-  const double phi2 = 1.0 - te;
-  const double q = rnx * rny;
-  const double g21 = fma(phi2, fma(q * iR2, -3.0, nn), kap2 * e * q);
-  const double g22 = rnx * fma(-c2, te, 1.0);
-  if (kAccumulate) {
-    s1 = fma(g11, A1, fma(-g12, A2, s1));
-    s2 = fma(g21, A1, fma(g22, A2, s2));
-  } else {
-    s1 = fma(g11, A1, -g12 * A2);
-    s2 = fma(g21, A1, g22 * A2);
-  }
-}
-
 __global__ __launch_bounds__(kThreads) void pair_fp64_kernel(PairArgs a) {
   __shared__ double2 src[kTile * 4];  // per source: (px,py) (pz,nx) (ny,nz) (a1,a2)
 
   const int tid = threadIdx.x;
   int split, tile;
-  block_to_work(blockIdx.x, a.nsplit, &split, &tile);
+  pair_block_to_work(blockIdx.x, a.nsplit, &split, &tile);
   const int32_t M = a.M;
   const int32_t k = tile * kThreads + tid;
   const int32_t kc = k < M ? k : M - 1;
-  const Target tg{a.px[kc], a.py[kc], a.pz[kc], a.nx[kc], a.ny[kc], a.nz[kc]};
+  const double tx = a.px[kc], ty = a.py[kc], tz = a.pz[kc];
+  const double tnx = a.nx[kc], tny = a.ny[kc], tnz = a.nz[kc];
   const int32_t s_begin = split * a.chunk_tiles * kTile;
   const int32_t s_end = min(M, s_begin + a.chunk_tiles * kTile);
 
@@ -145,7 +82,7 @@ __global__ __launch_bounds__(kThreads) void pair_fp64_kernel(PairArgs a) {
   const int32_t xe = a.xrow[tile + 1];
   while (xp < xe && a.xtile[xp] * kTile < s_begin) ++xp;
 
-  const double c1 = a.c1, c2 = a.c2, kap = a.kappa, kap2 = a.kappa * a.kappa;
+  const PairConsts pc{a.c1, a.c2, a.kappa, a.kappa * a.kappa};
   double S1 = 0.0, S2 = 0.0;
   for (int32_t s0 = s_begin; s0 < s_end; s0 += kTile) {
     const int32_t m = s0 + tid;
@@ -162,15 +99,18 @@ __global__ __launch_bounds__(kThreads) void pair_fp64_kernel(PairArgs a) {
     if (!careful) {
       // no corrected pair of this target tile among these sources
 #pragma unroll 2
-      for (int j = 0; j < n; ++j)
-        pair_terms<true>(tg, src[4 * j], src[4 * j + 1], src[4 * j + 2], src[4 * j + 3], c1, c2,
-                         kap, kap2, S1, S2);
+      for (int j = 0; j < n; ++j) {
+        const double2 q0 = src[4 * j], q1 = src[4 * j + 1], q2 = src[4 * j + 2], q3 = src[4 * j + 3];
+        pair_f64<true>(tx, ty, tz, tnx, tny, tnz, q0.x, q0.y, q1.x, q1.y, q2.x, q2.y, q3.x, q3.y,
+                       pc, S1, S2);
+      }
     } else {
       ++xp;
       for (int j = 0; j < n; ++j) {
         double d1, d2;
-        pair_terms<false>(tg, src[4 * j], src[4 * j + 1], src[4 * j + 2], src[4 * j + 3], c1,
-                          c2, kap, kap2, d1, d2);
+        const double2 q0 = src[4 * j], q1 = src[4 * j + 1], q2 = src[4 * j + 2], q3 = src[4 * j + 3];
+        pair_f64<false>(tx, ty, tz, tnx, tny, tnz, q0.x, q0.y, q1.x, q1.y, q2.x, q2.y, q3.x, q3.y,
+                        pc, d1, d2);
         const bool ex = (s0 + j == nxt);
         if (ex) {
           ++p;

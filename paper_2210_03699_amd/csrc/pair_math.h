@@ -1,0 +1,96 @@
+// Per-pair kernel evaluations shared by the float64 and mixed-precision
+// pair kernels and by the near-pair fix-up.
+//
+// For target x = P(y_k) with normal n_k and source P(y_m) with normal n_m,
+// r = x - P(y_m), e = e^{-kR}, t = e (1 + kR), the kernels of
+// eq. (Kij-kernels) times 4 pi are
+//   K11 = (r.n_m)(1 - c1 t)/R^3,   K12 = (1 - e)/R,
+//   K21 = [(1 - t)(n_k.n_m - 3 q/R^2) + k^2 e q]/R^3,  q = (r.n_k)(r.n_m),
+//   K22 = -(r.n_k)(1 - c2 t)/R^3,
+// (K21 uses (kR)^2/R^2 = k^2 to fold the cubic term of 1 - e(1 + kR + (kR)^2/3)),
+// and the contributions of one source with amplitudes (a1, a2) = w (u1, u2)
+// to the two rows are d1 = K11 a1 - K12 a2, d2 = K21 a1 - K22 a2.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fastmath.h"
+
+namespace ibim {
+
+struct PairConsts {
+  double c1, c2, kappa, kappa2;
+};
+
+struct PairConstsF {
+  float c1, c2, kappa, kappa2;
+};
+
+// float64.  kAccumulate: add the contributions straight into (s1, s2) with
+// fused multiply-adds; otherwise write them to (s1, s2).
+template <bool kAccumulate>
+__device__ __forceinline__ void pair_f64(double x, double y, double z, double nxk, double nyk,
+                                         double nzk, double px, double py, double pz, double nxm,
+                                         double nym, double nzm, double a1, double a2,
+                                         const PairConsts& c, double& s1, double& s2) {
+  const double rx = x - px, ry = y - py, rz = z - pz;
+  const double R2 = fma(rz, rz, fma(ry, ry, rx * rx));
+  const double iR = rsqrt_pos(R2);
+  const double R = R2 * iR;
+  const double iR2 = iR * iR;
+  const double iR3 = iR2 * iR;
+  const double kr = c.kappa * R;
+  const double e = exp_neg(kr);
+  const double te = fma(e, kr, e);
+  const double rny = fma(rz, nzm, fma(ry, nym, rx * nxm));
+  const double rnx = fma(rz, nzk, fma(ry, nyk, rx * nxk));
+  const double nn = fma(nzk, nzm, fma(nyk, nym, nxk * nxm));
+  const double A1 = a1 * iR3;
+  const double A2 = a2 * iR3;
+  const double g11 = rny * fma(-c.c1, te, 1.0);
+  const double g12 = (1.0 - e) * R2;
+  const double phi2 = 1.0 - te;
+  const double q = rnx * rny;
+  const double g21 = fma(phi2, fma(q * iR2, -3.0, nn), c.kappa2 * e * q);
+  const double g22 = rnx * fma(-c.c2, te, 1.0);
+  if (kAccumulate) {
+    s1 = fma(g11, A1, fma(-g12, A2, s1));
+    s2 = fma(g21, A1, fma(g22, A2, s2));
+  } else {
+    s1 = fma(g11, A1, -g12 * A2);
+    s2 = fma(g21, A1, g22 * A2);
+  }
+}
+
+// float32, every operation explicit (fused multiply-adds written out), so
+// that every kernel including this header computes bit-identical values
+// when its translation unit is compiled without automatic contraction.
+__device__ __forceinline__ void pair_f32(float x, float y, float z, float nxk, float nyk,
+                                         float nzk, float px, float py, float pz, float nxm,
+                                         float nym, float nzm, float a1, float a2,
+                                         const PairConstsF& c, float& d1, float& d2) {
+  const float rx = x - px, ry = y - py, rz = z - pz;
+  const float R2 = __fmaf_rn(rz, rz, __fmaf_rn(ry, ry, rx * rx));
+  const float iR = __builtin_amdgcn_rsqf(R2);
+  const float R = R2 * iR;
+  const float iR2 = iR * iR;
+  const float iR3 = iR2 * iR;
+  const float kr = c.kappa * R;
+  const float e = exp_neg_f32(kr);
+  const float te = __fmaf_rn(e, kr, e);
+  const float rny = __fmaf_rn(rz, nzm, __fmaf_rn(ry, nym, rx * nxm));
+  const float rnx = __fmaf_rn(rz, nzk, __fmaf_rn(ry, nyk, rx * nxk));
+  const float nn = __fmaf_rn(nzk, nzm, __fmaf_rn(nyk, nym, nxk * nxm));
+  const float A1 = a1 * iR3;
+  const float A2 = a2 * iR3;
+  const float g11 = rny * __fmaf_rn(-c.c1, te, 1.0f);
+  const float g12 = (1.0f - e) * R2;
+  const float phi2 = 1.0f - te;
+  const float q = rnx * rny;
+  const float g21 = __fmaf_rn(phi2, __fmaf_rn(q * iR2, -3.0f, nn), (c.kappa2 * e) * q);
+  const float g22 = rnx * __fmaf_rn(-c.c2, te, 1.0f);
+  d1 = __fmaf_rn(g11, A1, -(g12 * A2));
+  d2 = __fmaf_rn(g21, A1, g22 * A2);
+}
+
+}  // namespace ibim
