@@ -54,6 +54,7 @@ CASES = {
     "torus": lambda: workloads.torus_case(h=0.1),
     "kirkwood_small": lambda: workloads.kirkwood_sphere(h=0.3, radius=3.0, r_charges=2.0,
                                                         n_charges=5, seed=7, tol=1e-10),
+    "ses_molecule": lambda: workloads.ses_molecule(20, 9.0, 0.35, 2.0, seed=11, tol=1e-10),
 }
 
 

@@ -65,6 +65,10 @@ def test_host_setup_matches_oracle_wide_tube():
     _compare(workloads.kirkwood_sphere(h=0.3, radius=3.0, r_charges=2.0, n_charges=3))
 
 
+def test_host_setup_matches_oracle_ses_molecule():
+    _compare(workloads.ses_molecule(20, 9.0, 0.35, 2.0, seed=11))
+
+
 def test_every_row_corrects_its_own_node():
     lib = ibim.Problem.from_workload(workloads.born_sphere(h=0.2), device=-1)
     c = lib.corrections()

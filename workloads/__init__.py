@@ -29,6 +29,7 @@ __all__ = [
     "kirkwood_sphere",
     "torus_case",
     "by_name",
+    "ses_molecule",
     "random_vector",
 ]
 
@@ -186,16 +187,42 @@ def torus_case(h=0.1, r_major=1.0, r_minor=0.5, eps_factor=2.0, kappa=KAPPA,
     )
 
 
+def ses_molecule(n_atoms=500, box=25.0, h=0.3, eps_factor=2.0, seed=3, probe=1.4,
+                 tol=1e-6) -> Workload:
+    """Random-walk molecule (see ``workloads.ses``) with its SES signed distance."""
+    from . import ses
+    xyz, radii, q = ses.random_walk_molecule(n_atoms, box, seed)
+    eps_tube = eps_factor * h
+    sdf, origin = ses.ses_grid(xyz, radii, h, eps_tube, probe=probe, pad_nodes=PAD_NODES)
+    return Workload(
+        name=f"ses_molecule_{n_atoms}at_box{box:g}_h{h:g}_eps{eps_factor:g}h",
+        sdf=sdf, origin=origin, h=h, eps_tube=eps_tube, eps_in=EPS_IN, eps_out=EPS_OUT,
+        kappa=KAPPA, charge_xyz=xyz, charge_q=q, tol=tol,
+        meta={"geometry": "ses", "n_atoms": n_atoms, "box": box, "seed": seed, "probe": probe},
+    )
+
+
 def by_name(name: str) -> Workload:
     """Named workloads.
 
     ``born``      Born ion: sphere R = 2 A, +1e at the centre, h = 0.2, eps = 2h.
     ``kirkwood``  Kirkwood sphere R = 10 A, 20 charges in r <= 8 A, h = 0.25, eps = 3h.
+    ``ses500``    500-atom random-walk molecule, 25 A box, SES (probe 1.4 A), h = 0.3,
+                  eps = 2h, tol 1e-6.
+    ``ses2000``   2000 atoms, 40 A box, h = 0.35, eps = 2h, tol 1e-6.
+    ``ses2000_twin`` the same molecule at h = 0.7 with eps = 1.5h (within the
+                  re-entrant reach of the 1.4 A probe).
     """
     if name == "born":
         return born_sphere()
     if name == "kirkwood":
         return kirkwood_sphere()
+    if name == "ses500":
+        return ses_molecule(500, 25.0, 0.3, 2.0, seed=3)
+    if name == "ses2000":
+        return ses_molecule(2000, 40.0, 0.35, 2.0, seed=5)
+    if name == "ses2000_twin":
+        return ses_molecule(2000, 40.0, 0.7, 1.5, seed=5)
     raise KeyError(name)
 
 

@@ -1,0 +1,410 @@
+/*
+ * Signed distance (positive inside) to the solvent-excluded surface of a set
+ * of atoms, sampled on a uniform grid.  Input generation only.
+ *
+ * With R_i = r_i + r_p, let B = union of the balls B(c_i, R_i) and A the
+ * complement of B (probe centres).  The solvent region is A dilated by r_p,
+ * the molecule its complement, and near the surface
+ *     d(x) = dist(x, boundary of A) - r_p.
+ * The nearest boundary point of A lies on an exposed sphere patch (radial
+ * projection of x onto a sphere), an exposed circle arc of two spheres
+ * (nearest point of the circle) or an exposed vertex of three spheres; a
+ * candidate counts only if no other ball contains it.  Enclosed cavities are
+ * removed in a second pass: solvent bubbles (grid nodes with d < 0 that a
+ * flood fill from the grid boundary does not reach) are at least a probe
+ * ball across and so resolved by the grid; the second pass rejects every
+ * candidate whose nearest grid node lies in a bubble (a probe centre's own
+ * ball lies in its bubble) and treats bubble nodes as interior.  Points
+ * farther than `band` from the surface get a cheap bound with the right sign
+ * instead.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+  double c[3];
+  double R;
+} Ball;
+
+typedef struct {
+  double C[3], u[3], rho; /* centre, unit axis, radius */
+  int i, j;
+} Circle;
+
+typedef struct {
+  double p[3];
+  int i, j, k;
+} Vertex;
+
+static double dist3(const double* a, const double* b) {
+  double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+  return sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+/* cell list over atom centres */
+typedef struct {
+  double lo[3], cs;
+  int n[3];
+  int* start; /* ncell + 1 */
+  int* idx;
+} Cells;
+
+static int cell_of(const Cells* cl, const double* p, int a) {
+  int v = (int)floor((p[a] - cl->lo[a]) / cl->cs);
+  if (v < 0) v = 0;
+  if (v >= cl->n[a]) v = cl->n[a] - 1;
+  return v;
+}
+
+static void cells_build(Cells* cl, const Ball* b, int n, double cs) {
+  for (int a = 0; a < 3; ++a) {
+    double lo = 1e300, hi = -1e300;
+    for (int i = 0; i < n; ++i) {
+      if (b[i].c[a] < lo) lo = b[i].c[a];
+      if (b[i].c[a] > hi) hi = b[i].c[a];
+    }
+    cl->lo[a] = lo - cs;
+    cl->n[a] = (int)((hi - lo) / cs) + 3;
+  }
+  cl->cs = cs;
+  int nc = cl->n[0] * cl->n[1] * cl->n[2];
+  int* cnt = (int*)calloc(nc + 1, sizeof(int));
+  int* cid = (int*)malloc(sizeof(int) * n);
+  for (int i = 0; i < n; ++i) {
+    int ci = (cell_of(cl, b[i].c, 0) * cl->n[1] + cell_of(cl, b[i].c, 1)) * cl->n[2] +
+             cell_of(cl, b[i].c, 2);
+    cid[i] = ci;
+    cnt[ci + 1]++;
+  }
+  for (int q = 0; q < nc; ++q) cnt[q + 1] += cnt[q];
+  cl->start = cnt;
+  cl->idx = (int*)malloc(sizeof(int) * n);
+  int* fill = (int*)calloc((size_t)nc, sizeof(int));
+  for (int i = 0; i < n; ++i) cl->idx[cnt[cid[i]] + fill[cid[i]]++] = i;
+  free(fill);
+  free(cid);
+}
+
+/* atoms with centre within `rad` of p (rad <= cs * reach) -> out, returns count */
+static int cells_query(const Cells* cl, const Ball* b, const double* p, double rad, int* out,
+                       int cap) {
+  int lo[3], hi[3], m = 0;
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = (int)floor((p[a] - rad - cl->lo[a]) / cl->cs);
+    hi[a] = (int)floor((p[a] + rad - cl->lo[a]) / cl->cs);
+    if (lo[a] < 0) lo[a] = 0;
+    if (hi[a] >= cl->n[a]) hi[a] = cl->n[a] - 1;
+  }
+  for (int x = lo[0]; x <= hi[0]; ++x)
+    for (int y = lo[1]; y <= hi[1]; ++y)
+      for (int z = lo[2]; z <= hi[2]; ++z) {
+        int q = (x * cl->n[1] + y) * cl->n[2] + z;
+        for (int t = cl->start[q]; t < cl->start[q + 1]; ++t) {
+          int i = cl->idx[t];
+          if (dist3(b[i].c, p) < rad && m < cap) out[m++] = i;
+        }
+      }
+  return m;
+}
+
+typedef struct {
+  const uint8_t* bubble; /* grid flag: enclosed solvent (NULL in the first pass) */
+  const double* origin;
+  int nx, ny, nz;
+  double h;
+} GridInfo;
+
+static int buried(const Ball* b, const int* nb, int nn, const double* p, int e1, int e2, int e3) {
+  for (int t = 0; t < nn; ++t) {
+    int k = nb[t];
+    if (k == e1 || k == e2 || k == e3) continue;
+    if (dist3(b[k].c, p) < b[k].R * (1.0 - 1e-12)) return 1;
+  }
+  return 0;
+}
+
+/* 1 if the probe centre p belongs to an enclosed cavity: its nearest grid
+ * node is a bubble node. */
+static int in_bubble(const GridInfo* g, const double* p) {
+  if (!g->bubble) return 0;
+  int ii = (int)floor((p[0] - g->origin[0]) / g->h + 0.5);
+  int jj = (int)floor((p[1] - g->origin[1]) / g->h + 0.5);
+  int kk = (int)floor((p[2] - g->origin[2]) / g->h + 0.5);
+  if (ii < 0 || jj < 0 || kk < 0 || ii >= g->nx || jj >= g->ny || kk >= g->nz) return 0;
+  return g->bubble[((int64_t)ii * g->ny + jj) * g->nz + kk];
+}
+
+/*
+ * xyz (3n), radii (n), probe; grid (nx, ny, nz) at origin + h*(i,j,k);
+ * band: points with |d| below about band get the exact value.  Returns 0.
+ */
+int ses_sdf(const double* xyz, const double* radii, int n, double probe, const double* origin,
+            int nx, int ny, int nz, double h, double band, double* out) {
+  Ball* b = (Ball*)malloc(sizeof(Ball) * n);
+  double Rmax = 0.0;
+  for (int i = 0; i < n; ++i) {
+    for (int a = 0; a < 3; ++a) b[i].c[a] = xyz[3 * i + a];
+    b[i].R = radii[i] + probe;
+    if (b[i].R > Rmax) Rmax = b[i].R;
+  }
+  Cells cl;
+  cells_build(&cl, b, n, 2.0 * Rmax);
+  const int64_t ng = (int64_t)nx * ny * nz;
+
+  /* 1. s(x) = min_i |x - c_i| - R_i (>= 0 in A), inner(x) = max_i R_i - |x - c_i| */
+  double* s = (double*)malloc(sizeof(double) * ng);
+  double* inner = (double*)malloc(sizeof(double) * ng);
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int i = 0; i < nx; ++i) {
+    int nb[4096];
+    for (int j = 0; j < ny; ++j)
+      for (int k = 0; k < nz; ++k) {
+        double x[3] = {origin[0] + i * h, origin[1] + j * h, origin[2] + k * h};
+        int m = cells_query(&cl, b, x, 2.0 * Rmax + band + probe, nb, 4096);
+        double sm = 1e300, im = -1e300;
+        for (int t = 0; t < m; ++t) {
+          double dd = dist3(x, b[nb[t]].c) - b[nb[t]].R;
+          if (dd < sm) sm = dd;
+          if (-dd > im) im = -dd;
+        }
+        if (m == 0) sm = 1e300;
+        int64_t q = ((int64_t)i * ny + j) * nz + k;
+        s[q] = sm;
+        inner[q] = im;
+      }
+  }
+
+  /* 2. circles of intersecting sphere pairs */
+  int ccap = 64 * n + 64, nc = 0;
+  Circle* circ = (Circle*)malloc(sizeof(Circle) * ccap);
+  {
+    int nb[4096];
+    for (int i = 0; i < n; ++i) {
+      int m = cells_query(&cl, b, b[i].c, 2.0 * Rmax, nb, 4096);
+      for (int t = 0; t < m; ++t) {
+        int j = nb[t];
+        if (j <= i) continue;
+        double D = dist3(b[i].c, b[j].c);
+        if (D >= b[i].R + b[j].R || D <= fabs(b[i].R - b[j].R) || D == 0.0) continue;
+        double a = (D * D + b[i].R * b[i].R - b[j].R * b[j].R) / (2.0 * D);
+        double rho2 = b[i].R * b[i].R - a * a;
+        if (rho2 <= 0.0) continue;
+        if (nc >= ccap) {
+          ccap *= 2;
+          circ = (Circle*)realloc(circ, sizeof(Circle) * ccap);
+        }
+        Circle* C = &circ[nc++];
+        for (int q = 0; q < 3; ++q) {
+          C->u[q] = (b[j].c[q] - b[i].c[q]) / D;
+          C->C[q] = b[i].c[q] + a * C->u[q];
+        }
+        C->rho = sqrt(rho2);
+        C->i = i;
+        C->j = j;
+      }
+    }
+  }
+  /* 3. exposed vertices of sphere triples */
+  int vcap = 64 * n + 64, nv = 0;
+  Vertex* vert = (Vertex*)malloc(sizeof(Vertex) * vcap);
+  {
+    int nb[4096];
+    for (int ci = 0; ci < nc; ++ci) {
+      const Circle* C = &circ[ci];
+      int m = cells_query(&cl, b, C->C, C->rho + Rmax, nb, 4096);
+      for (int t = 0; t < m; ++t) {
+        int k = nb[t];
+        if (k <= C->j) continue; /* i < j < k once */
+        /* intersect circle with sphere k: points p = C + rho (cos t e1 + sin t e2) */
+        double w[3] = {b[k].c[0] - C->C[0], b[k].c[1] - C->C[1], b[k].c[2] - C->C[2]};
+        double wu = w[0] * C->u[0] + w[1] * C->u[1] + w[2] * C->u[2];
+        double wp[3] = {w[0] - wu * C->u[0], w[1] - wu * C->u[1], w[2] - wu * C->u[2]};
+        double L = sqrt(wp[0] * wp[0] + wp[1] * wp[1] + wp[2] * wp[2]);
+        if (L == 0.0) continue;
+        /* |p - c_k|^2 = rho^2 + |w|^2 - 2 rho L cos(phi) = R_k^2 */
+        double ww = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+        double cph = (C->rho * C->rho + ww - b[k].R * b[k].R) / (2.0 * C->rho * L);
+        if (cph <= -1.0 || cph >= 1.0) continue;
+        double sph = sqrt(1.0 - cph * cph);
+        double e1[3] = {wp[0] / L, wp[1] / L, wp[2] / L};
+        double e2[3] = {C->u[1] * e1[2] - C->u[2] * e1[1], C->u[2] * e1[0] - C->u[0] * e1[2],
+                        C->u[0] * e1[1] - C->u[1] * e1[0]};
+        for (int sg = -1; sg <= 1; sg += 2) {
+          double p[3];
+          for (int q = 0; q < 3; ++q) p[q] = C->C[q] + C->rho * (cph * e1[q] + sg * sph * e2[q]);
+          int nb2[4096];
+          int m2 = cells_query(&cl, b, p, Rmax, nb2, 4096);
+          if (buried(b, nb2, m2, p, C->i, C->j, k)) continue;
+          if (nv >= vcap) {
+            vcap *= 2;
+            vert = (Vertex*)realloc(vert, sizeof(Vertex) * vcap);
+          }
+          Vertex* V = &vert[nv++];
+          for (int q = 0; q < 3; ++q) V->p[q] = p[q];
+          V->i = C->i;
+          V->j = C->j;
+          V->k = k;
+        }
+      }
+    }
+  }
+  /* cell lists over circle centres and vertices (reuse the Ball layout) */
+  Ball* cb = (Ball*)malloc(sizeof(Ball) * (nc > 0 ? nc : 1));
+  for (int q = 0; q < nc; ++q) {
+    for (int a = 0; a < 3; ++a) cb[q].c[a] = circ[q].C[a];
+    cb[q].R = circ[q].rho;
+  }
+  Ball* vb = (Ball*)malloc(sizeof(Ball) * (nv > 0 ? nv : 1));
+  for (int q = 0; q < nv; ++q) {
+    for (int a = 0; a < 3; ++a) vb[q].c[a] = vert[q].p[a];
+    vb[q].R = 0.0;
+  }
+  Cells ccl, vcl;
+  if (nc > 0) cells_build(&ccl, cb, nc, 2.0 * Rmax);
+  if (nv > 0) cells_build(&vcl, vb, nv, 2.0 * Rmax);
+
+  /* 4. distances: pass 0 keeps every exposed candidate, pass 1 drops the
+   * candidates of enclosed solvent bubbles found after pass 0 */
+  const double reach_d = probe + band; /* candidates farther than this do not matter */
+  uint8_t* bubble = NULL;
+  for (int pass = 0; pass < 2; ++pass) {
+  GridInfo gi = {bubble, origin, nx, ny, nz, h};
+#pragma omp parallel for schedule(dynamic, 2)
+  for (int i = 0; i < nx; ++i) {
+    int* nb = (int*)malloc(sizeof(int) * 8192);
+    int* nb2 = (int*)malloc(sizeof(int) * 8192);
+    for (int j = 0; j < ny; ++j)
+      for (int k = 0; k < nz; ++k) {
+        int64_t q = ((int64_t)i * ny + j) * nz + k;
+        double x[3] = {origin[0] + i * h, origin[1] + j * h, origin[2] + k * h};
+        if (s[q] >= 0.0 && !(bubble && bubble[q])) {
+          /* probe centre: at least r_p from the molecule */
+          out[q] = -(probe + (s[q] < 1e3 ? s[q] : 1e3));
+          continue;
+        }
+        if (inner[q] - probe > band) {
+          out[q] = inner[q] - probe; /* deep inside: a lower bound is enough */
+          continue;
+        }
+        double best = 1e300;
+        /* sphere patches */
+        int m = cells_query(&cl, b, x, Rmax + reach_d, nb, 8192);
+        for (int t = 0; t < m; ++t) {
+          const Ball* B = &b[nb[t]];
+          double dxc = dist3(x, B->c);
+          if (dxc == 0.0) continue;
+          double dd = fabs(B->R - dxc);
+          if (dd >= best) continue;
+          double dir[3], p[3];
+          for (int a = 0; a < 3; ++a) {
+            dir[a] = (x[a] - B->c[a]) / dxc;
+            p[a] = B->c[a] + B->R * dir[a];
+          }
+          int m2 = cells_query(&cl, b, p, Rmax, nb2, 8192);
+          if (buried(b, nb2, m2, p, nb[t], -1, -1)) continue;
+          if (in_bubble(&gi, p)) continue;
+          best = dd;
+        }
+        /* circle arcs */
+        if (nc > 0) {
+          int mc = cells_query(&ccl, cb, x, Rmax + reach_d, nb, 8192);
+          for (int t = 0; t < mc; ++t) {
+            const Circle* C = &circ[nb[t]];
+            double w[3] = {x[0] - C->C[0], x[1] - C->C[1], x[2] - C->C[2]};
+            double wu = w[0] * C->u[0] + w[1] * C->u[1] + w[2] * C->u[2];
+            double wp[3] = {w[0] - wu * C->u[0], w[1] - wu * C->u[1], w[2] - wu * C->u[2]};
+            double L = sqrt(wp[0] * wp[0] + wp[1] * wp[1] + wp[2] * wp[2]);
+            if (L == 0.0) continue;
+            double p[3];
+            for (int a = 0; a < 3; ++a) p[a] = C->C[a] + C->rho * wp[a] / L;
+            double dd = dist3(x, p);
+            if (dd >= best) continue;
+            int m2 = cells_query(&cl, b, p, Rmax, nb2, 8192);
+            if (buried(b, nb2, m2, p, C->i, C->j, -1)) continue;
+            if (in_bubble(&gi, p)) continue;
+            best = dd;
+          }
+        }
+        /* vertices */
+        if (nv > 0) {
+          int mv = cells_query(&vcl, vb, x, reach_d, nb, 8192);
+          for (int t = 0; t < mv; ++t) {
+            const Vertex* V = &vert[nb[t]];
+            double dd = dist3(x, V->p);
+            if (dd >= best) continue;
+            if (in_bubble(&gi, V->p)) continue;
+            best = dd;
+          }
+        }
+        /* no exposed boundary point within reach_d: the distance is at least
+         * reach_d (and at least the ball depth) */
+        if (best > 1e299) best = inner[q] > reach_d ? inner[q] : reach_d;
+        out[q] = best - probe;
+      }
+    free(nb);
+    free(nb2);
+  }
+  if (pass == 0) {
+    /* flood fill the solvent (d < 0) from the grid boundary */
+    uint8_t* reach = (uint8_t*)calloc(ng, 1);
+    int64_t* stack = (int64_t*)malloc(sizeof(int64_t) * ng);
+    int64_t top = 0;
+    for (int i = 0; i < nx; ++i)
+      for (int j = 0; j < ny; ++j)
+        for (int k = 0; k < nz; ++k) {
+          if (i == 0 || j == 0 || k == 0 || i == nx - 1 || j == ny - 1 || k == nz - 1) {
+            int64_t q = ((int64_t)i * ny + j) * nz + k;
+            if (out[q] < 0.0 && !reach[q]) {
+              reach[q] = 1;
+              stack[top++] = q;
+            }
+          }
+        }
+    while (top > 0) {
+      int64_t q = stack[--top];
+      int i = (int)(q / ((int64_t)ny * nz)), j = (int)((q / nz) % ny), k = (int)(q % nz);
+      int nbr[6][3] = {{i - 1, j, k}, {i + 1, j, k}, {i, j - 1, k},
+                       {i, j + 1, k}, {i, j, k - 1}, {i, j, k + 1}};
+      for (int t = 0; t < 6; ++t) {
+        int a = nbr[t][0], c = nbr[t][1], e = nbr[t][2];
+        if (a < 0 || c < 0 || e < 0 || a >= nx || c >= ny || e >= nz) continue;
+        int64_t r = ((int64_t)a * ny + c) * nz + e;
+        if (out[r] < 0.0 && !reach[r]) {
+          reach[r] = 1;
+          stack[top++] = r;
+        }
+      }
+    }
+    free(stack);
+    bubble = (uint8_t*)calloc(ng, 1);
+    int64_t nb_bubble = 0;
+    for (int64_t q = 0; q < ng; ++q) {
+      bubble[q] = (out[q] < 0.0 && !reach[q]) ? 1 : 0;
+      nb_bubble += bubble[q];
+    }
+    free(reach);
+    if (nb_bubble == 0) break; /* no enclosed cavity: pass 0 is final */
+  }
+  }
+  free(bubble);
+  free(b);
+  free(s);
+  free(inner);
+  free(circ);
+  free(vert);
+  free(cb);
+  free(vb);
+  free(cl.start);
+  free(cl.idx);
+  if (nc > 0) {
+    free(ccl.start);
+    free(ccl.idx);
+  }
+  if (nv > 0) {
+    free(vcl.start);
+    free(vcl.idx);
+  }
+  return 0;
+}
