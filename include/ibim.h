@@ -187,6 +187,77 @@ int ibim_energy(ibim_ctx* ctx, const double* x, double* g_pol, void* stream);
 int ibim_pair_timing(ibim_ctx* ctx, int enable);
 int ibim_pair_timing_read(ibim_ctx* ctx, int64_t* launches, double* total_ms);
 
+/* ------------------------------------------------------------------------ */
+/*
+ * Solve server: continuous batching of many independent problems on one GPU.
+ *
+ * Requests (a signed-distance grid and charges, as for ibim_setup, plus a
+ * GMRES tolerance) are queued by ibim_server_submit, which copies the inputs
+ * and starts the host part of their setup on a background thread.  Each
+ * ibim_server_step is one round:
+ *   1. admission: prepared requests are set up on the device, in submission
+ *      order, while a solve slot is free and the estimated device footprint
+ *      (geometry, corrections, split partial sums, Krylov basis) fits in the
+ *      HBM budget (a request that does not fit lets later smaller ones pass);
+ *   2. ONE persistent batched pair-kernel launch covers a work list of
+ *      (request, target tile, source chunk) items of every active solve; each
+ *      item is computed exactly as in the single-problem kernel;
+ *   3. per request: sparse correction, one GMRES (Arnoldi + Givens) step or a
+ *      residual step, all on the device, then a single status read-back;
+ *   4. finished solves compute G_pol (eq. pol-energy), keep their solution on
+ *      the host and release their device memory.
+ * Every request runs the same arithmetic as ibim_solve followed by ibim_energy
+ * with the server's options, so its results do not depend on which other
+ * requests share the rounds.  All server calls must come from one host thread.
+ */
+typedef struct ibim_server ibim_server;
+
+typedef struct {
+  int64_t submitted, admitted, finished, failed;
+  int64_t rounds;           /* ibim_server_step calls that did device work */
+  int64_t batched_items;    /* pair-kernel work items over all rounds */
+  size_t bytes_in_use;      /* device bytes held by active solves */
+  size_t bytes_peak;
+  size_t budget_bytes;
+  int active, waiting, max_active_seen;
+} ibim_server_stats;
+
+#define IBIM_REQ_WAITING 0 /* preparing on the host or queued for admission */
+#define IBIM_REQ_ACTIVE 1
+#define IBIM_REQ_DONE 2
+#define IBIM_REQ_FAILED (-1)
+
+/* opt: solver options of every request (precision, restart, max_iter,
+ * check_residual, device, r_near); hbm_budget_bytes > 0; max_slots >= 1
+ * concurrent solves; host_threads >= 1 background setup threads; stream:
+ * the hipStream_t every round runs on (NULL: the null stream). */
+int ibim_server_create(const ibim_options* opt, size_t hbm_budget_bytes, int max_slots,
+                       int host_threads, void* stream, ibim_server** out);
+/* Inputs as in ibim_setup (host, copied); tol > 0.  *ticket identifies the
+ * request.  Never blocks on the device. */
+int ibim_server_submit(ibim_server* srv, const double* sdf, int nx, int ny, int nz,
+                       const double origin[3], double h, double eps_tube, double eps_in,
+                       double eps_out, double kappa, const double* charge_xyz,
+                       const double* charge_q, int n_charges, double tol, int64_t* ticket);
+/* One round (see above); *active, *waiting may be NULL.  With no solve
+ * active it first waits for a background setup to finish.  A request that
+ * fails (setup error, footprint above the whole budget, NaN) is marked
+ * IBIM_REQ_FAILED and the others go on.  A nonzero return is a device error
+ * (launch or copy failure); the server should then be destroyed. */
+int ibim_server_step(ibim_server* srv, int* active, int* waiting);
+/* State of a request (IBIM_REQ_*); for a finished request also G_pol and the
+ * solve information; for a failed one the error code is returned. */
+int ibim_server_poll(ibim_server* srv, int64_t ticket, int* state, double* g_pol,
+                     ibim_solve_info* info);
+/* Solution of a finished request: *M nodes; x (host, 2M) may be NULL to query M. */
+int ibim_server_solution(ibim_server* srv, int64_t ticket, double* x, int64_t* M);
+/* Forget a finished or failed request (frees its stored solution). */
+int ibim_server_release(ibim_server* srv, int64_t ticket);
+/* Counters of the server (host values, no device synchronisation). */
+int ibim_server_get_stats(ibim_server* srv, ibim_server_stats* st);
+/* Waits for background setup threads, frees everything (safe on NULL). */
+void ibim_server_destroy(ibim_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -12,6 +13,7 @@
 #include <vector>
 
 #include "../../include/ibim.h"
+#include "context.h"
 #include "ibim_internal.h"
 #include "krylov.h"
 #include "operator.h"
@@ -19,7 +21,7 @@
 
 using namespace ibim;
 
-namespace {
+namespace ibim {
 
 thread_local std::string g_last_error = "no error";
 
@@ -33,90 +35,7 @@ int hip_fail(hipError_t e, const char* where) {
               std::string(where) + ": " + hipGetErrorString(e));
 }
 
-#define HIP_TRY(expr, where)                    \
-  do {                                          \
-    hipError_t _e = (expr);                     \
-    if (_e != hipSuccess) return hip_fail(_e, where); \
-  } while (0)
-
-template <class T>
-hipError_t dalloc(T** p, size_t n) {
-  *p = nullptr;
-  if (n == 0) n = 1;
-  return hipMalloc((void**)p, n * sizeof(T));
-}
-
-template <class T>
-hipError_t upload(T** p, const T* src, size_t n, hipStream_t s) {
-  hipError_t e = dalloc(p, n);
-  if (e != hipSuccess) return e;
-  if (n == 0) return hipSuccess;
-  return hipMemcpyAsync(*p, src, n * sizeof(T), hipMemcpyHostToDevice, s);
-}
-
-template <class T>
-void dfree(T*& p) {
-  if (p) (void)hipFree((void*)p);
-  p = nullptr;
-}
-
-// Restores the caller's current device on scope exit.
-struct DeviceScope {
-  int prev = -1;
-  bool ok = true;
-  explicit DeviceScope(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (dev >= 0 && dev != prev) ok = hipSetDevice(dev) == hipSuccess;
-  }
-  ~DeviceScope() {
-    int cur = -1;
-    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-  }
-};
-
-}  // namespace
-
-struct ibim_ctx {
-  HostPlan plan;
-  ibim_options opt{};
-  double eps_in = 1, eps_out = 1, kappa = 0;
-  std::vector<double> zq, q;  // charges (host)
-  // device state
-  DeviceProblem P;
-  PairPlan pair;
-  double* partial = nullptr;  // nsplit * 2M
-  double* om11 = nullptr;
-  double* om21 = nullptr;
-  double* d_zq = nullptr;
-  double* d_q = nullptr;
-  double* d_psi = nullptr;
-  Krylov kr;
-  bool kr_ready = false;
-  // pair-kernel timing (events bracket every pair launch while enabled)
-  bool timing = false;
-  std::vector<hipEvent_t> tev;  // 2 per launch
-  size_t tcount = 0;            // launches recorded
-  int applies = 0;              // operator applications of the current solve
-
-  bool on_device() const { return opt.device >= 0; }
-
-  void release() {
-    if (!on_device()) return;
-    DeviceScope ds(opt.device);
-    dfree(P.px); dfree(P.py); dfree(P.pz); dfree(P.nx); dfree(P.ny); dfree(P.nz); dfree(P.w);
-    dfree(P.px32); dfree(P.py32); dfree(P.pz32); dfree(P.nx32); dfree(P.ny32); dfree(P.nz32);
-    dfree(P.crow); dfree(P.ccol); dfree(P.blocks); dfree(P.nrow); dfree(P.ncol);
-    dfree(P.xrow); dfree(P.xtile);
-    dfree(partial); dfree(om11); dfree(om21); dfree(d_zq); dfree(d_q); dfree(d_psi);
-    dfree(kr.V); dfree(kr.H); dfree(kr.cs); dfree(kr.sn); dfree(kr.g); dfree(kr.y);
-    dfree(kr.hcol); dfree(kr.hcol2); dfree(kr.scal); dfree(kr.status); dfree(kr.partial);
-    dfree(kr.tmp); dfree(kr.tmp2);
-    if (kr.host_status) (void)hipHostFree(kr.host_status);
-    kr.host_status = nullptr;
-    for (hipEvent_t e : tev) (void)hipEventDestroy(e);
-    tev.clear();
-  }
-};
+}  // namespace ibim
 
 namespace {
 
@@ -198,6 +117,18 @@ int check_dev(const ibim_ctx* c) {
   return IBIM_OK;
 }
 
+int fetch(ibim_ctx* c, const double* d, int n, hipStream_t s, double* out) {
+  HIP_TRY(hipMemcpyAsync(c->kr.host_status, d, n * sizeof(double), hipMemcpyDeviceToHost, s),
+          "hipMemcpyAsync");
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  for (int i = 0; i < n; ++i) out[i] = c->kr.host_status[i];
+  return IBIM_OK;
+}
+
+}  // namespace
+
+namespace ibim {
+
 int apply_impl(ibim_ctx* c, const double* u, double* out, hipStream_t s) {
   const int prec = c->opt.precision;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -250,48 +181,21 @@ int ensure_krylov(ibim_ctx* c) {
   HIP_TRY(dalloc(&k.tmp2, (size_t)k.n), "alloc");
   HIP_TRY(hipHostMalloc((void**)&k.host_status, 4 * sizeof(double), hipHostMallocDefault),
           "pinned allocation");
+  c->device_bytes += ((m + 3) * (size_t)k.n + (m + 1) * (m + 1030) + 8 * m) * sizeof(double);
   c->kr_ready = true;
   return IBIM_OK;
 }
 
 // Copies n device doubles to the pinned mirror and waits for them.
-int fetch(ibim_ctx* c, const double* d, int n, hipStream_t s, double* out) {
-  HIP_TRY(hipMemcpyAsync(c->kr.host_status, d, n * sizeof(double), hipMemcpyDeviceToHost, s),
-          "hipMemcpyAsync");
-  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
-  for (int i = 0; i < n; ++i) out[i] = c->kr.host_status[i];
-  return IBIM_OK;
-}
-
-}  // namespace
-
-extern "C" {
-
-void ibim_default_options(ibim_options* opt) {
-  if (!opt) return;
-  opt->precision = IBIM_FP64;
-  opt->restart = 60;
-  opt->max_iter = 300;
-  opt->check_residual = 1;
-  opt->device = 0;
-  opt->r_near = 0.0;
-}
-
-const char* ibim_last_error(void) { return g_last_error.c_str(); }
-
-int ibim_setup(const double* sdf, int nx, int ny, int nz, const double origin[3], double h,
-               double eps_tube, double eps_in, double eps_out, double kappa,
-               const double* charge_xyz, const double* charge_q, int n_charges,
-               const ibim_options* opt, void* stream, ibim_ctx** out) {
-  if (!out) return fail(IBIM_EINVAL, "out is NULL");
+int ctx_create_host(const double* sdf, int nx, int ny, int nz, const double origin[3], double h,
+                    double eps_tube, double eps_in, double eps_out, double kappa,
+                    const double* charge_xyz, const double* charge_q, int n_charges,
+                    const ibim_options& o, ibim_ctx** out) {
   *out = nullptr;
   if (!(eps_in > 0) || !(eps_out > 0) || !(kappa >= 0) || !std::isfinite(kappa))
     return fail(IBIM_EINVAL, "eps_in, eps_out must be > 0 and kappa >= 0");
   if (n_charges < 0 || (n_charges > 0 && (!charge_xyz || !charge_q)))
     return fail(IBIM_EINVAL, "bad charge arrays");
-  ibim_options o;
-  ibim_default_options(&o);
-  if (opt) o = *opt;
   if (o.precision != IBIM_FP64 && o.precision != IBIM_MIXED)
     return fail(IBIM_EINVAL, "unknown precision mode");
   if (!(o.r_near >= 0.0) || !std::isfinite(o.r_near))
@@ -304,50 +208,79 @@ int ibim_setup(const double* sdf, int nx, int ny, int nz, const double origin[3]
   c->eps_in = eps_in;
   c->eps_out = eps_out;
   c->kappa = kappa;
-  c->zq.assign(charge_xyz, charge_xyz + 3 * (size_t)n_charges);
-  c->q.assign(charge_q, charge_q + (size_t)n_charges);
+  c->nx = nx;
+  c->ny = ny;
+  c->nz = nz;
+  if (n_charges > 0) {
+    c->zq.assign(charge_xyz, charge_xyz + 3 * (size_t)n_charges);
+    c->q.assign(charge_q, charge_q + (size_t)n_charges);
+  }
   std::string err;
   int r = build_host_plan(sdf, nx, ny, nz, origin, h, eps_tube, &c->plan, &err);
   if (r) {
     delete c;
     return fail(r, err);
   }
-  if (!c->on_device()) {
-    *out = c;
-    return IBIM_OK;
+  *out = c;
+  return IBIM_OK;
+}
+
+size_t ctx_footprint_estimate(const ibim_ctx* c) {
+  const HostPlan& pl = c->plan;
+  const size_t M = (size_t)pl.M, nnz = (size_t)pl.crow[pl.M];
+  const PairPlan pp = make_pair_plan((int32_t)M, c->opt.precision);
+  const size_t ntile = (size_t)pp.ntile;
+  const size_t m = (size_t)c->opt.restart, n = 2 * M, nc = c->q.size();
+  // geometry and weights, corrections (ccol, om11, om21, 2x2 blocks), exclusion
+  // tiles (at most one entry per corrected pair), split partial sums
+  size_t b = 7 * M * 8 + (M + 1) * 4 + nnz * (4 + 6 * 8);
+  b += (ntile + 1) * 4 + std::min(nnz, ntile * ntile) * 4;
+  b += (size_t)pp.nsplit * n * 8 + (4 * nc + (nc > 0 ? nc : 1)) * 8;
+  // Krylov basis and GMRES scratch (as allocated by ensure_krylov)
+  b += ((m + 3) * n + (m + 1) * (m + 1030) + 8 * m) * 8;
+  if (c->opt.precision == IBIM_MIXED) {
+    const double h = pl.h, eps = pl.eps;
+    const double rn = c->opt.r_near > 0.0 ? c->opt.r_near : 4.0 * h;
+    // near pairs per row: a disc of radius r_near in a slab of thickness 2 eps
+    const double per_row = 3.14159265358979 * rn * rn * 2.0 * eps / (h * h * h) * 1.3 + 16.0;
+    b += 6 * M * 4 + (M + 1) * 8 + (size_t)(per_row * (double)M) * 4;
   }
+  return b;
+}
+
+int ctx_setup_device(ibim_ctx* c, hipStream_t s) {
+  const ibim_options& o = c->opt;
   DeviceScope ds(o.device);
-  if (!ds.ok) {
-    delete c;
-    return fail(IBIM_EHIP, "hipSetDevice failed");
-  }
-  hipStream_t s = as_stream(stream);
+  if (!ds.ok) return fail(IBIM_EHIP, "hipSetDevice failed");
   const HostPlan& pl = c->plan;
   const int32_t M = (int32_t)pl.M;
   const int64_t nnz = pl.crow[M];
+  const int nx = c->nx, ny = c->ny, nz = c->nz;
+  const double h = pl.h, eps_tube = pl.eps;
+  const int n_charges = (int)c->q.size();
   DeviceProblem& P = c->P;
   P.M = M;
   P.nnz = nnz;
-  P.eps_in = eps_in;
-  P.eps_out = eps_out;
-  P.kappa = kappa;
+  P.eps_in = c->eps_in;
+  P.eps_out = c->eps_out;
+  P.kappa = c->kappa;
   P.h = h;
-  P.lam1 = 0.5 * (1.0 + eps_out / eps_in);
-  P.lam2 = 0.5 * (1.0 + eps_in / eps_out);
+  P.lam1 = 0.5 * (1.0 + c->eps_out / c->eps_in);
+  P.lam2 = 0.5 * (1.0 + c->eps_in / c->eps_out);
+  c->device_ready = true;  // release() frees whatever is allocated below
+  size_t bytes = 0;
   std::vector<int32_t> crow32(M + 1);
   for (int32_t k = 0; k <= M; ++k) crow32[k] = (int32_t)pl.crow[k];
 
-  auto cleanup = [&](int code, const std::string& msg) {
-    c->release();
-    delete c;
-    return fail(code, msg);
+  auto bad = [&](hipError_t e, const char* what) {
+    return fail(e == hipErrorOutOfMemory ? IBIM_ENOMEM : IBIM_EHIP,
+                std::string(what) + ": " + hipGetErrorString(e));
   };
-#define UP(dst, vec)                                                             \
-  do {                                                                           \
-    hipError_t _e = upload(&(dst), (vec).data(), (vec).size(), s);               \
-    if (_e != hipSuccess)                                                        \
-      return cleanup(_e == hipErrorOutOfMemory ? IBIM_ENOMEM : IBIM_EHIP,        \
-                     std::string("upload: ") + hipGetErrorString(_e));           \
+#define UP(dst, vec)                                                   \
+  do {                                                                 \
+    hipError_t _e = upload(&(dst), (vec).data(), (vec).size(), s);     \
+    if (_e != hipSuccess) return bad(_e, "upload");                    \
+    bytes += (vec).size() * sizeof((vec)[0]);                          \
   } while (0)
   UP(P.px, pl.px); UP(P.py, pl.py); UP(P.pz, pl.pz);
   UP(P.nx, pl.nx); UP(P.ny, pl.ny); UP(P.nz, pl.nz);
@@ -367,12 +300,18 @@ int ibim_setup(const double* sdf, int nx, int ny, int nz, const double origin[3]
   int8_t* d_axis = nullptr;
   double *d_alpha = nullptr, *d_beta = nullptr, *d_eta = nullptr, *d_tau = nullptr;
   double *d_k1 = nullptr, *d_k2 = nullptr;
-  UP(d_rowid, pl.crowid); UP(d_axis, pl.caxis); UP(d_alpha, pl.calpha); UP(d_beta, pl.cbeta);
-  UP(d_eta, pl.ceta); UP(d_tau, pl.tau); UP(d_k1, pl.kap1); UP(d_k2, pl.kap2);
-#undef UP
-  hipError_t e = dalloc(&c->om11, (size_t)nnz);
+  hipError_t e = upload(&d_rowid, pl.crowid.data(), pl.crowid.size(), s);
+  if (e == hipSuccess) e = upload(&d_axis, pl.caxis.data(), pl.caxis.size(), s);
+  if (e == hipSuccess) e = upload(&d_alpha, pl.calpha.data(), pl.calpha.size(), s);
+  if (e == hipSuccess) e = upload(&d_beta, pl.cbeta.data(), pl.cbeta.size(), s);
+  if (e == hipSuccess) e = upload(&d_eta, pl.ceta.data(), pl.ceta.size(), s);
+  if (e == hipSuccess) e = upload(&d_tau, pl.tau.data(), pl.tau.size(), s);
+  if (e == hipSuccess) e = upload(&d_k1, pl.kap1.data(), pl.kap1.size(), s);
+  if (e == hipSuccess) e = upload(&d_k2, pl.kap2.data(), pl.kap2.size(), s);
+  if (e == hipSuccess) e = dalloc(&c->om11, (size_t)nnz);
   if (e == hipSuccess) e = dalloc(&c->om21, (size_t)nnz);
   if (e == hipSuccess) e = dalloc(&P.blocks, 4 * (size_t)nnz);
+  bytes += 6 * (size_t)nnz * 8;
   if (e == hipSuccess) {
     WeightArgs wa;
     wa.nnz = nnz;
@@ -386,9 +325,9 @@ int ibim_setup(const double* sdf, int nx, int ny, int nz, const double origin[3]
     wa.kap1 = d_k1;
     wa.kap2 = d_k2;
     wa.w = P.w;
-    wa.eps_in = eps_in;
-    wa.eps_out = eps_out;
-    wa.kappa = kappa;
+    wa.eps_in = c->eps_in;
+    wa.eps_out = c->eps_out;
+    wa.kappa = c->kappa;
     wa.h = h;
     wa.om11 = c->om11;
     wa.om21 = c->om21;
@@ -398,9 +337,7 @@ int ibim_setup(const double* sdf, int nx, int ny, int nz, const double origin[3]
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   dfree(d_rowid); dfree(d_axis); dfree(d_alpha); dfree(d_beta); dfree(d_eta); dfree(d_tau);
   dfree(d_k1); dfree(d_k2);
-  if (e != hipSuccess)
-    return cleanup(e == hipErrorOutOfMemory ? IBIM_ENOMEM : IBIM_EHIP,
-                   std::string("correction weights: ") + hipGetErrorString(e));
+  if (e != hipSuccess) return bad(e, "correction weights");
   if (o.precision == IBIM_MIXED) {
     // float32 geometry relative to the centroid, and the near list
     double cen[3] = {0, 0, 0};
@@ -423,6 +360,7 @@ int ibim_setup(const double* sdf, int nx, int ny, int nz, const double origin[3]
     if (e == hipSuccess) e = up32(&P.nx32, pl.nx, 0.0);
     if (e == hipSuccess) e = up32(&P.ny32, pl.ny, 0.0);
     if (e == hipSuccess) e = up32(&P.nz32, pl.nz, 0.0);
+    bytes += 6 * (size_t)M * 4;
     int32_t* d_node_of = nullptr;
     int64_t* d_gidx = nullptr;
     if (e == hipSuccess) {
@@ -437,16 +375,92 @@ int ibim_setup(const double* sdf, int nx, int ny, int nz, const double origin[3]
       e = build_near_list(P, d_node_of, d_gidx, nx, ny, nz, r_near, eps_tube, s);
     dfree(d_node_of);
     dfree(d_gidx);
-    if (e != hipSuccess)
-      return cleanup(e == hipErrorOutOfMemory ? IBIM_ENOMEM : IBIM_EHIP,
-                     std::string("mixed-precision setup: ") + hipGetErrorString(e));
+    if (e != hipSuccess) return bad(e, "mixed-precision setup");
+    bytes += ((size_t)M + 1) * 8 + (size_t)P.nnear * 4;
   }
   c->pair = make_pair_plan(M, o.precision);
   e = dalloc(&c->partial, (size_t)c->pair.nsplit * 2 * (size_t)M);
   if (e == hipSuccess) e = dalloc(&c->d_psi, (size_t)(n_charges > 0 ? n_charges : 1));
-  if (e != hipSuccess)
-    return cleanup(e == hipErrorOutOfMemory ? IBIM_ENOMEM : IBIM_EHIP,
-                   std::string("setup: ") + hipGetErrorString(e));
+  if (e != hipSuccess) return bad(e, "setup");
+  bytes += (size_t)c->pair.nsplit * 2 * (size_t)M * 8;
+  c->device_bytes = bytes;
+  return IBIM_OK;
+}
+
+int rhs_impl(ibim_ctx* c, double* g, hipStream_t s) {
+  const DeviceProblem& P = c->P;
+  const int nc = (int)c->q.size();
+  hipLaunchKernelGGL(rhs_kernel, dim3((P.M + 255) / 256), dim3(256), 0, s, P.px, P.py, P.pz, P.nx,
+                     P.ny, P.nz, P.M, c->d_zq, c->d_q, nc, 1.0 / c->eps_in, g);
+  HIP_TRY(hipGetLastError(), "rhs kernel launch");
+  return IBIM_OK;
+}
+
+int energy_launch(ibim_ctx* c, const double* x, hipStream_t s) {
+  const int nc = (int)c->q.size();
+  if (nc == 0) return IBIM_OK;
+  const DeviceProblem& P = c->P;
+  hipLaunchKernelGGL(psi_rxn_kernel, dim3(nc), dim3(256), 0, s, P.px, P.py, P.pz, P.nx, P.ny,
+                     P.nz, P.w, P.M, x, c->d_zq, c->eps_out / c->eps_in, c->kappa,
+                     P.h * P.h * P.h, c->d_psi);
+  HIP_TRY(hipGetLastError(), "energy kernel launch");
+  return IBIM_OK;
+}
+
+double energy_sum(const ibim_ctx* c, const double* psi) {
+  double G = 0.0;
+  for (size_t j = 0; j < c->q.size(); ++j) G += 0.5 * c->q[j] * psi[j];
+  return G;
+}
+
+hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t s) {
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const double* a, double* b, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(copy_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, b, n);
+  return hipGetLastError();
+}
+
+}  // namespace ibim
+
+extern "C" {
+
+void ibim_default_options(ibim_options* opt) {
+  if (!opt) return;
+  opt->precision = IBIM_FP64;
+  opt->restart = 60;
+  opt->max_iter = 300;
+  opt->check_residual = 1;
+  opt->device = 0;
+  opt->r_near = 0.0;
+}
+
+const char* ibim_last_error(void) { return g_last_error.c_str(); }
+
+int ibim_setup(const double* sdf, int nx, int ny, int nz, const double origin[3], double h,
+               double eps_tube, double eps_in, double eps_out, double kappa,
+               const double* charge_xyz, const double* charge_q, int n_charges,
+               const ibim_options* opt, void* stream, ibim_ctx** out) {
+  if (!out) return fail(IBIM_EINVAL, "out is NULL");
+  *out = nullptr;
+  ibim_options o;
+  ibim_default_options(&o);
+  if (opt) o = *opt;
+  ibim_ctx* c = nullptr;
+  if (int r = ctx_create_host(sdf, nx, ny, nz, origin, h, eps_tube, eps_in, eps_out, kappa,
+                              charge_xyz, charge_q, n_charges, o, &c))
+    return r;
+  if (o.device < 0) {
+    *out = c;
+    return IBIM_OK;
+  }
+  if (int r = ctx_setup_device(c, as_stream(stream))) {
+    std::string msg = ibim_last_error();
+    ibim_destroy(c);
+    return fail(r, msg);
+  }
   *out = c;
   return IBIM_OK;
 }
@@ -650,17 +664,12 @@ int ibim_energy(ibim_ctx* ctx, const double* x, double* g_pol, void* stream) {
     *g_pol = 0.0;
     return IBIM_OK;
   }
-  const DeviceProblem& P = ctx->P;
-  hipLaunchKernelGGL(psi_rxn_kernel, dim3(nc), dim3(256), 0, s, P.px, P.py, P.pz, P.nx, P.ny,
-                     P.nz, P.w, P.M, x, ctx->d_zq, ctx->eps_out / ctx->eps_in, ctx->kappa,
-                     P.h * P.h * P.h, ctx->d_psi);
-  HIP_TRY(hipGetLastError(), "energy kernel launch");
+  if (int r = energy_launch(ctx, x, s)) return r;
   std::vector<double> psi(nc);
   HIP_TRY(hipMemcpyAsync(psi.data(), ctx->d_psi, nc * sizeof(double), hipMemcpyDeviceToHost, s),
           "copy");
   HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
-  double G = 0.0;
-  for (int j = 0; j < nc; ++j) G += 0.5 * ctx->q[j] * psi[j];
+  const double G = energy_sum(ctx, psi.data());
   if (!std::isfinite(G)) return fail(IBIM_ENAN, "energy is not finite");
   *g_pol = G;
   return IBIM_OK;

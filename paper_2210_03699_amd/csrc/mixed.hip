@@ -29,38 +29,15 @@ namespace {
 constexpr int kThreads = kPairThreads;
 constexpr int kTile = kPairTile;
 
-struct MixedArgs {
-  const float* px;
-  const float* py;
-  const float* pz;
-  const float* nx;
-  const float* ny;
-  const float* nz;
-  const double* w;
-  const double* u;
-  const int32_t* crow;
-  const int32_t* ccol;
-  const int32_t* xrow;
-  const int32_t* xtile;
-  int32_t M;
-  int nsplit;
-  int chunk_tiles;
-  PairConstsF c;
-  double scale;
-  double* partial;
-};
-
-__global__ __launch_bounds__(kThreads) void pair_mixed_kernel(MixedArgs a) {
-  __shared__ float4 src[kTile * 2];  // per source: (px,py,pz,nx) (ny,nz,a1,a2)
-
+// One work item of the mixed form; src: LDS tile, per source
+// (px,py,pz,nx) (ny,nz,a1,a2) in float32.
+__device__ inline void pair_chunk_mixed(const PairArgs& a, int split, int tile, float4* src) {
   const int tid = threadIdx.x;
-  int split, tile;
-  pair_block_to_work(blockIdx.x, a.nsplit, &split, &tile);
   const int32_t M = a.M;
   const int32_t k = tile * kThreads + tid;
   const int32_t kc = k < M ? k : M - 1;
-  const float tx = a.px[kc], ty = a.py[kc], tz = a.pz[kc];
-  const float tnx = a.nx[kc], tny = a.ny[kc], tnz = a.nz[kc];
+  const float tx = a.fx[kc], ty = a.fy[kc], tz = a.fz[kc];
+  const float tnx = a.fnx[kc], tny = a.fny[kc], tnz = a.fnz[kc];
   const int32_t s_begin = split * a.chunk_tiles * kTile;
   const int32_t s_end = min(M, s_begin + a.chunk_tiles * kTile);
 
@@ -72,14 +49,14 @@ __global__ __launch_bounds__(kThreads) void pair_mixed_kernel(MixedArgs a) {
   const int32_t xe = a.xrow[tile + 1];
   while (xp < xe && a.xtile[xp] * kTile < s_begin) ++xp;
 
-  const PairConstsF c = a.c;
+  const PairConstsF c{(float)a.c1, (float)a.c2, (float)a.kappa, (float)(a.kappa * a.kappa)};
   double S1 = 0.0, S2 = 0.0;
   for (int32_t s0 = s_begin; s0 < s_end; s0 += kTile) {
     const int32_t m = s0 + tid;
     if (m < s_end) {
       const double wm = a.w[m];
-      src[2 * tid + 0] = make_float4(a.px[m], a.py[m], a.pz[m], a.nx[m]);
-      src[2 * tid + 1] = make_float4(a.ny[m], a.nz[m], (float)(wm * a.u[m]),
+      src[2 * tid + 0] = make_float4(a.fx[m], a.fy[m], a.fz[m], a.fnx[m]);
+      src[2 * tid + 1] = make_float4(a.fny[m], a.fnz[m], (float)(wm * a.u[m]),
                                      (float)(wm * a.u[M + m]));
     }
     __syncthreads();
@@ -117,6 +94,29 @@ __global__ __launch_bounds__(kThreads) void pair_mixed_kernel(MixedArgs a) {
     double* out = a.partial + (size_t)split * 2 * (size_t)M;
     out[k] = a.scale * S1;
     out[M + k] = a.scale * S2;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void pair_mixed_kernel(PairArgs a) {
+  __shared__ float4 src[kTile * 2];
+  int split, tile;
+  pair_block_to_work(blockIdx.x, a.nsplit, &split, &tile);
+  pair_chunk_mixed(a, split, tile, src);
+}
+
+__global__ __launch_bounds__(kThreads) void pair_batched_mixed_kernel(const PairArgs* reqs,
+                                                                      const int32_t* items,
+                                                                      int n_items, int* counter) {
+  __shared__ float4 src[kTile * 2];
+  __shared__ int next;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = next;
+    __syncthreads();  // everyone has read `next` before it is overwritten
+    if (it >= n_items) break;
+    const PairArgs a = reqs[items[3 * it]];
+    pair_chunk_mixed(a, items[3 * it + 2], items[3 * it + 1], src);
   }
 }
 
@@ -241,25 +241,28 @@ __global__ __launch_bounds__(256) void near_kernel(NearArgs a) {
 
 hipError_t launch_pair_mixed(const DeviceProblem& P, const PairPlan& plan, const double* u,
                              double* partial, hipStream_t stream) {
-  MixedArgs a;
-  a.px = P.px32; a.py = P.py32; a.pz = P.pz32;
-  a.nx = P.nx32; a.ny = P.ny32; a.nz = P.nz32;
-  a.w = P.w;
-  a.u = u;
-  a.crow = P.crow;
-  a.ccol = P.ccol;
-  a.xrow = P.xrow;
-  a.xtile = P.xtile;
-  a.M = P.M;
-  a.nsplit = plan.nsplit;
-  a.chunk_tiles = plan.chunk_tiles;
-  a.c = PairConstsF{(float)(P.eps_out / P.eps_in), (float)(P.eps_in / P.eps_out), (float)P.kappa,
-                    (float)(P.kappa * P.kappa)};
-  a.scale = P.h * P.h * P.h / (4.0 * kPiD);
-  a.partial = partial;
+  const PairArgs a = make_pair_args(P, plan, u, partial);
   const unsigned blocks = (unsigned)plan.ntile * (unsigned)plan.nsplit;
   hipLaunchKernelGGL(pair_mixed_kernel, dim3(blocks), dim3(kThreads), 0, stream, a);
   return hipGetLastError();
+}
+
+hipError_t launch_pair_batched_mixed(const PairArgs* reqs, const int32_t* items, int n_items,
+                                     int* counter, int grid, hipStream_t stream) {
+  hipLaunchKernelGGL(pair_batched_mixed_kernel, dim3((unsigned)grid), dim3(kThreads), 0, stream,
+                     reqs, items, n_items, counter);
+  return hipGetLastError();
+}
+
+int pair_batched_grid_mixed() {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1024;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 1024;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pair_batched_mixed_kernel, kThreads, 0) !=
+          hipSuccess || per < 1)
+    per = 1;
+  return cus * per;
 }
 
 hipError_t launch_finish_mixed(const DeviceProblem& P, const PairPlan& plan, const double* u,

@@ -73,6 +73,39 @@ struct PairPlan {
 
 PairPlan make_pair_plan(int32_t M, int precision);
 
+// Arguments of one problem's pair sum: workgroup (split, tile) sums the
+// sources of chunk `split` for the targets of tile `tile`.
+struct PairArgs {
+  const double *px, *py, *pz, *nx, *ny, *nz, *w;  // float64 geometry
+  const float *fx, *fy, *fz, *fnx, *fny, *fnz;     // float32 geometry (mixed form)
+  const double* u;
+  const int32_t* crow;
+  const int32_t* ccol;
+  const int32_t* xrow;   // per target tile: range in xtile
+  const int32_t* xtile;  // sorted source tiles holding a corrected pair of the tile
+  int32_t M;
+  int nsplit;
+  int chunk_tiles;
+  double c1;     // eps_out / eps_in
+  double c2;     // eps_in / eps_out
+  double kappa;
+  double scale;  // h^3 / (4 pi)
+  double* partial;
+};
+
+PairArgs make_pair_args(const DeviceProblem& P, const PairPlan& plan, const double* u,
+                        double* partial);
+
+// One persistent launch over a work list of several problems: item i is
+// (problem items[3i], target tile items[3i+1], source chunk items[3i+2]);
+// workgroups take items from *counter (which must be 0) until the list is
+// exhausted.  Each item is computed exactly as in the single-problem kernel.
+hipError_t launch_pair_batched(int precision, const PairArgs* reqs, const int32_t* items,
+                               int n_items, int* counter, int grid, hipStream_t stream);
+
+// Workgroups of the persistent launch that fit on the device at once.
+int pair_batched_grid(int precision);
+
 // Host: per target tile, the sorted list of source tiles containing one of
 // its corrected pairs (CSR: xrow has one entry per tile plus one).
 void exclusion_tiles(int32_t M, const int64_t* crow, const int32_t* ccol,

@@ -35,35 +35,10 @@ constexpr int kThreads = kPairThreads;
 constexpr int kTile = kPairTile;
 constexpr int kXcd = kXcdCount;
 
-struct PairArgs {
-  const double* px;
-  const double* py;
-  const double* pz;
-  const double* nx;
-  const double* ny;
-  const double* nz;
-  const double* w;
-  const double* u;
-  const int32_t* crow;
-  const int32_t* ccol;
-  const int32_t* xrow;   // per target tile: range in xtile
-  const int32_t* xtile;  // sorted source tiles holding a corrected pair of the tile
-  int32_t M;
-  int nsplit;
-  int chunk_tiles;
-  double c1;     // eps_out / eps_in
-  double c2;     // eps_in / eps_out
-  double kappa;
-  double scale;  // h^3 / (4 pi)
-  double* partial;
-};
-
-__global__ __launch_bounds__(kThreads) void pair_fp64_kernel(PairArgs a) {
-  __shared__ double2 src[kTile * 4];  // per source: (px,py) (pz,nx) (ny,nz) (a1,a2)
-
+// One work item: target tile `tile`, source chunk `split`.  src: LDS tile,
+// per source (px,py) (pz,nx) (ny,nz) (a1,a2).
+__device__ inline void pair_chunk_fp64(const PairArgs& a, int split, int tile, double2* src) {
   const int tid = threadIdx.x;
-  int split, tile;
-  pair_block_to_work(blockIdx.x, a.nsplit, &split, &tile);
   const int32_t M = a.M;
   const int32_t k = tile * kThreads + tid;
   const int32_t kc = k < M ? k : M - 1;
@@ -126,6 +101,29 @@ __global__ __launch_bounds__(kThreads) void pair_fp64_kernel(PairArgs a) {
     double* out = a.partial + (size_t)split * 2 * (size_t)M;
     out[k] = a.scale * S1;
     out[M + k] = a.scale * S2;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void pair_fp64_kernel(PairArgs a) {
+  __shared__ double2 src[kTile * 4];
+  int split, tile;
+  pair_block_to_work(blockIdx.x, a.nsplit, &split, &tile);
+  pair_chunk_fp64(a, split, tile, src);
+}
+
+__global__ __launch_bounds__(kThreads) void pair_batched_fp64_kernel(const PairArgs* reqs,
+                                                                     const int32_t* items,
+                                                                     int n_items, int* counter) {
+  __shared__ double2 src[kTile * 4];
+  __shared__ int next;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = next;
+    __syncthreads();  // everyone has read `next` before it is overwritten
+    if (it >= n_items) break;
+    const PairArgs a = reqs[items[3 * it]];
+    pair_chunk_fp64(a, items[3 * it + 2], items[3 * it + 1], src);
   }
 }
 
@@ -198,13 +196,14 @@ PairPlan make_pair_plan(int32_t M, int precision) {
   return pl;
 }
 
-hipError_t launch_pair(const DeviceProblem& P, const PairPlan& plan, int precision,
-                       const double* u, double* partial, hipStream_t stream) {
-  (void)precision;
-  PairArgs a;
+PairArgs make_pair_args(const DeviceProblem& P, const PairPlan& plan, const double* u,
+                        double* partial) {
+  PairArgs a{};
   a.px = P.px; a.py = P.py; a.pz = P.pz;
   a.nx = P.nx; a.ny = P.ny; a.nz = P.nz;
   a.w = P.w;
+  a.fx = P.px32; a.fy = P.py32; a.fz = P.pz32;
+  a.fnx = P.nx32; a.fny = P.ny32; a.fnz = P.nz32;
   a.u = u;
   a.crow = P.crow;
   a.ccol = P.ccol;
@@ -218,9 +217,49 @@ hipError_t launch_pair(const DeviceProblem& P, const PairPlan& plan, int precisi
   a.kappa = P.kappa;
   a.scale = P.h * P.h * P.h / (4.0 * kPiD);
   a.partial = partial;
+  return a;
+}
+
+hipError_t launch_pair(const DeviceProblem& P, const PairPlan& plan, int precision,
+                       const double* u, double* partial, hipStream_t stream) {
+  (void)precision;
+  const PairArgs a = make_pair_args(P, plan, u, partial);
   const unsigned blocks = (unsigned)plan.ntile * (unsigned)plan.nsplit;
   hipLaunchKernelGGL(pair_fp64_kernel, dim3(blocks), dim3(kThreads), 0, stream, a);
   return hipGetLastError();
+}
+
+hipError_t launch_pair_batched_fp64(const PairArgs* reqs, const int32_t* items, int n_items,
+                                    int* counter, int grid, hipStream_t stream) {
+  hipLaunchKernelGGL(pair_batched_fp64_kernel, dim3((unsigned)grid), dim3(kThreads), 0, stream,
+                     reqs, items, n_items, counter);
+  return hipGetLastError();
+}
+
+int pair_batched_grid_fp64() {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1024;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 1024;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pair_batched_fp64_kernel, kThreads, 0) !=
+          hipSuccess || per < 1)
+    per = 1;
+  return cus * per;
+}
+
+hipError_t launch_pair_batched_mixed(const PairArgs* reqs, const int32_t* items, int n_items,
+                                     int* counter, int grid, hipStream_t stream);
+int pair_batched_grid_mixed();
+
+hipError_t launch_pair_batched(int precision, const PairArgs* reqs, const int32_t* items,
+                               int n_items, int* counter, int grid, hipStream_t stream) {
+  if (precision == 1)
+    return launch_pair_batched_mixed(reqs, items, n_items, counter, grid, stream);
+  return launch_pair_batched_fp64(reqs, items, n_items, counter, grid, stream);
+}
+
+int pair_batched_grid(int precision) {
+  return precision == 1 ? pair_batched_grid_mixed() : pair_batched_grid_fp64();
 }
 
 hipError_t launch_finish(const DeviceProblem& P, const PairPlan& plan, int precision,

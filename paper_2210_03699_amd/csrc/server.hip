@@ -1,0 +1,607 @@
+// Solve server: continuous batching of independent CTR-IBIM solves on one GPU.
+//
+// A request moves through: submitted -> host setup on a background thread
+// (geometry and correction sets) -> waiting for admission -> active (device
+// data, Krylov basis) -> done (G_pol and the solution kept on the host) or
+// failed.  Each round does one persistent batched pair-kernel launch over the
+// work items of every active solve, then the per-request GMRES step.  The
+// per-request sequence of kernels and their inputs are those of ibim_solve
+// and ibim_energy, so results do not depend on the mix of requests.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/ibim.h"
+#include "context.h"
+#include "krylov.h"
+#include "operator.h"
+
+using namespace ibim;
+
+namespace {
+
+enum class Phase { kIter, kResid };
+
+struct Request {
+  int64_t ticket = 0;
+  // inputs (released after the host setup)
+  std::vector<double> sdf;
+  int dims[3] = {0, 0, 0};
+  double origin[3] = {0, 0, 0};
+  double h = 0, eps = 0, eps_in = 0, eps_out = 0, kappa = 0, tol = 0;
+  std::vector<double> zq, q;
+  // lifecycle
+  int state = IBIM_REQ_WAITING;
+  bool prepared = false;  // host setup finished (guarded by the server mutex)
+  int error = 0;
+  std::string error_msg;
+  ibim_ctx* ctx = nullptr;
+  size_t estimate = 0;
+  size_t held = 0;  // device bytes charged to the budget
+  int slot = -1;
+  double* d_b = nullptr;  // right-hand side
+  double* d_x = nullptr;  // iterate
+  // GMRES state (the driver of ibim_solve, one step per round)
+  Phase phase = Phase::kIter;
+  bool final_check = false;
+  int j = 0, total = 0;
+  double bnorm = -1.0, resid = 0.0, explicit_rel = -1.0;
+  bool converged = false;
+  // results
+  double g_pol = 0.0;
+  std::vector<double> x_host;
+  int64_t M = 0;
+  std::chrono::steady_clock::time_point t_submit, t_admit;
+  double seconds = 0.0;
+  int applies = 0;
+};
+
+}  // namespace
+
+struct ibim_server {
+  ibim_options opt{};
+  size_t budget = 0, used = 0, peak = 0;
+  int max_slots = 1;
+  hipStream_t stream = nullptr;
+  int grid = 0;
+  int64_t next_ticket = 1;
+  std::map<int64_t, std::unique_ptr<Request>> reqs;
+  std::vector<Request*> waiting;  // submission order
+  std::vector<Request*> active;
+  std::vector<int> free_slots;
+  ibim_server_stats st{};
+  // device buffers of the batched launch and of the per-round status
+  PairArgs* d_args = nullptr;
+  PairArgs* h_args = nullptr;
+  size_t args_cap = 0;
+  int32_t* d_items = nullptr;
+  int32_t* h_items = nullptr;
+  size_t items_cap = 0;
+  int* d_counter = nullptr;
+  double* d_status = nullptr;  // 8 doubles per slot
+  double* h_status = nullptr;  // pinned
+  // background host setup
+  std::mutex mu;
+  std::condition_variable cv;        // work for the setup threads
+  std::condition_variable ready_cv;  // a host setup finished
+  std::deque<Request*> prep_queue;
+  std::vector<std::thread> workers;
+  bool stopping = false;
+};
+
+namespace {
+
+constexpr int kStatusStride = 8;  // per slot: |g_{j+1}|, H(j+1,j), ||b||^2, ||r||^2
+
+__global__ void zero_int_kernel(int* p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+}
+
+void worker_main(ibim_server* srv) {
+  for (;;) {
+    Request* r = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(srv->mu);
+      srv->cv.wait(lk, [&] { return srv->stopping || !srv->prep_queue.empty(); });
+      if (srv->stopping && srv->prep_queue.empty()) return;
+      r = srv->prep_queue.front();
+      srv->prep_queue.pop_front();
+    }
+    ibim_options o = srv->opt;
+    ibim_ctx* c = nullptr;
+    const int code = ctx_create_host(r->sdf.data(), r->dims[0], r->dims[1], r->dims[2],
+                                     r->origin, r->h, r->eps, r->eps_in, r->eps_out, r->kappa,
+                                     r->zq.data(), r->q.data(), (int)r->q.size(), o, &c);
+    std::string msg = code ? std::string(ibim_last_error()) : std::string();
+    size_t est = c ? ctx_footprint_estimate(c) + 4 * 2 * (size_t)c->plan.M * 8 : 0;
+    {
+      std::lock_guard<std::mutex> lk(srv->mu);
+      r->ctx = c;
+      r->error = code;
+      r->error_msg = msg;
+      r->estimate = est;
+      std::vector<double>().swap(r->sdf);
+      r->prepared = true;
+    }
+    srv->ready_cv.notify_all();
+  }
+}
+
+void release_device(ibim_server* srv, Request* r) {
+  if (r->ctx) {
+    ibim_destroy(r->ctx);
+    r->ctx = nullptr;
+  }
+  dfree(r->d_b);
+  dfree(r->d_x);
+  srv->used -= r->held;
+  r->held = 0;
+  if (r->slot >= 0) srv->free_slots.push_back(r->slot);
+  r->slot = -1;
+}
+
+void mark_failed(ibim_server* srv, Request* r, int code, const std::string& msg) {
+  release_device(srv, r);
+  r->state = IBIM_REQ_FAILED;
+  r->error = code;
+  r->error_msg = msg;
+  srv->st.failed++;
+}
+
+// Device setup and the first GMRES cycle's start (r = b, V0 = b/||b||).
+int admit(ibim_server* srv, Request* r) {
+  hipStream_t s = srv->stream;
+  ibim_ctx* c = r->ctx;
+  c->opt.device = srv->opt.device;
+  if (int e = ctx_setup_device(c, s)) return e;
+  if (int e = ensure_krylov(c)) return e;
+  const int64_t N = c->kr.n;
+  HIP_TRY(dalloc(&r->d_b, (size_t)N), "right-hand side allocation");
+  HIP_TRY(dalloc(&r->d_x, (size_t)N), "iterate allocation");
+  r->held = c->device_bytes + 2 * (size_t)N * 8;
+  srv->used += r->held;
+  if (srv->used > srv->peak) srv->peak = srv->used;
+  r->slot = srv->free_slots.back();
+  srv->free_slots.pop_back();
+  r->M = c->P.M;
+  double* st = srv->d_status + (size_t)r->slot * kStatusStride;
+  if (int e = rhs_impl(c, r->d_b, s)) return e;
+  Krylov& K = c->kr;
+  HIP_TRY(K.dots(r->d_b, N, 1, r->d_b, N, st + 2, 0, s), "dots");
+  HIP_TRY(launch_fill(r->d_x, N, 0.0, s), "fill");
+  HIP_TRY(launch_copy(r->d_b, K.tmp, N, s), "copy");
+  HIP_TRY(K.normalize(K.tmp, st + 2, K.V, N, s), "normalize");
+  HIP_TRY(K.init_g(st + 2, s), "init_g");
+  r->phase = Phase::kIter;
+  r->j = 0;
+  r->total = 0;
+  r->applies = 0;
+  r->bnorm = -1.0;
+  r->t_admit = std::chrono::steady_clock::now();
+  r->state = IBIM_REQ_ACTIVE;
+  srv->st.admitted++;
+  return IBIM_OK;
+}
+
+// Finishing a request: G_pol from psi at the charges, solution to the host.
+int finish_request(ibim_server* srv, Request* r) {
+  hipStream_t s = srv->stream;
+  ibim_ctx* c = r->ctx;
+  const int nc = (int)c->q.size();
+  std::vector<double> psi(nc > 0 ? nc : 1);
+  if (int e = energy_launch(c, r->d_x, s)) return e;
+  r->x_host.resize((size_t)c->kr.n);
+  if (nc > 0)
+    HIP_TRY(hipMemcpyAsync(psi.data(), c->d_psi, nc * sizeof(double), hipMemcpyDeviceToHost, s),
+            "copy");
+  HIP_TRY(hipMemcpyAsync(r->x_host.data(), r->d_x, (size_t)c->kr.n * sizeof(double),
+                         hipMemcpyDeviceToHost, s),
+          "copy");
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  r->g_pol = nc > 0 ? energy_sum(c, psi.data()) : 0.0;
+  if (!std::isfinite(r->g_pol)) return fail(IBIM_ENAN, "energy is not finite");
+  r->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - r->t_admit).count();
+  release_device(srv, r);
+  r->state = IBIM_REQ_DONE;
+  srv->st.finished++;
+  return IBIM_OK;
+}
+
+int ensure_capacity(ibim_server* srv, size_t nargs, size_t nitems) {
+  if (nargs > srv->args_cap) {
+    dfree(srv->d_args);
+    if (srv->h_args) (void)hipHostFree(srv->h_args);
+    srv->h_args = nullptr;
+    size_t cap = nargs * 2;
+    HIP_TRY(dalloc(&srv->d_args, cap), "alloc");
+    HIP_TRY(hipHostMalloc((void**)&srv->h_args, cap * sizeof(PairArgs), hipHostMallocDefault),
+            "pinned allocation");
+    srv->args_cap = cap;
+  }
+  if (3 * nitems > srv->items_cap) {
+    dfree(srv->d_items);
+    if (srv->h_items) (void)hipHostFree(srv->h_items);
+    srv->h_items = nullptr;
+    size_t cap = 6 * nitems;
+    HIP_TRY(dalloc(&srv->d_items, cap), "alloc");
+    HIP_TRY(hipHostMalloc((void**)&srv->h_items, cap * sizeof(int32_t), hipHostMallocDefault),
+            "pinned allocation");
+    srv->items_cap = cap;
+  }
+  return IBIM_OK;
+}
+
+int step_impl(ibim_server* srv) {
+  hipStream_t s = srv->stream;
+  // with no solve running, wait for a host setup rather than return idle
+  if (srv->active.empty() && !srv->waiting.empty()) {
+    std::unique_lock<std::mutex> lk(srv->mu);
+    srv->ready_cv.wait(lk, [&] {
+      for (Request* r : srv->waiting)
+        if (r->prepared) return true;
+      return false;
+    });
+  }
+  // 1. admission (first fit in submission order)
+  {
+    std::vector<Request*> still;
+    for (Request* r : srv->waiting) {
+      bool prepared;
+      {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        prepared = r->prepared;
+      }
+      if (!prepared) {
+        still.push_back(r);
+        continue;
+      }
+      if (r->error) {
+        mark_failed(srv, r, r->error, r->error_msg);
+        continue;
+      }
+      const bool slot = !srv->free_slots.empty();
+      if (slot && srv->used + r->estimate <= srv->budget) {
+        const int e = admit(srv, r);
+        if (e) {
+          mark_failed(srv, r, e, ibim_last_error());
+          continue;
+        }
+        srv->active.push_back(r);
+        if ((int)srv->active.size() > srv->st.max_active_seen)
+          srv->st.max_active_seen = (int)srv->active.size();
+      } else {
+        if (srv->active.empty() && slot && r->estimate > srv->budget) {
+          mark_failed(srv, r, IBIM_ENOMEM, "request footprint exceeds the server's HBM budget");
+          continue;
+        }
+        still.push_back(r);
+      }
+    }
+    srv->waiting.swap(still);
+  }
+  if (srv->active.empty()) return IBIM_OK;
+
+  // 2. one batched pair launch over every active request
+  size_t nitems = 0;
+  for (Request* r : srv->active)
+    nitems += (size_t)r->ctx->pair.ntile * (size_t)r->ctx->pair.nsplit;
+  if (int e = ensure_capacity(srv, srv->active.size(), nitems)) return e;
+  size_t it = 0;
+  for (size_t i = 0; i < srv->active.size(); ++i) {
+    Request* r = srv->active[i];
+    ibim_ctx* c = r->ctx;
+    const int64_t N = c->kr.n;
+    const double* u = r->phase == Phase::kIter ? c->kr.V + (int64_t)r->j * N : r->d_x;
+    srv->h_args[i] = make_pair_args(c->P, c->pair, u, c->partial);
+    for (int t = 0; t < c->pair.ntile; ++t)
+      for (int sp = 0; sp < c->pair.nsplit; ++sp) {
+        srv->h_items[3 * it] = (int32_t)i;
+        srv->h_items[3 * it + 1] = t;
+        srv->h_items[3 * it + 2] = sp;
+        ++it;
+      }
+  }
+  HIP_TRY(hipMemcpyAsync(srv->d_args, srv->h_args, srv->active.size() * sizeof(PairArgs),
+                         hipMemcpyHostToDevice, s),
+          "copy");
+  HIP_TRY(hipMemcpyAsync(srv->d_items, srv->h_items, 3 * nitems * sizeof(int32_t),
+                         hipMemcpyHostToDevice, s),
+          "copy");
+  hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, s, srv->d_counter);
+  HIP_TRY(hipGetLastError(), "zero");
+  HIP_TRY(launch_pair_batched(srv->opt.precision, srv->d_args, srv->d_items, (int)nitems,
+                              srv->d_counter, srv->grid, s),
+          "batched pair launch");
+  srv->st.rounds++;
+  srv->st.batched_items += (int64_t)nitems;
+
+  // 3. per request: correction, then one GMRES or residual step
+  for (Request* r : srv->active) {
+    ibim_ctx* c = r->ctx;
+    Krylov& K = c->kr;
+    const int64_t N = K.n;
+    double* st = srv->d_status + (size_t)r->slot * kStatusStride;
+    const double* u = r->phase == Phase::kIter ? K.V + (int64_t)r->j * N : r->d_x;
+    double* out = r->phase == Phase::kIter ? K.V + (int64_t)(r->j + 1) * N : K.tmp2;
+    if (c->opt.precision == IBIM_MIXED)
+      HIP_TRY(launch_finish_mixed(c->P, c->pair, u, c->partial, out, s), "finish");
+    else
+      HIP_TRY(launch_finish(c->P, c->pair, c->opt.precision, u, c->partial, out, s), "finish");
+    r->applies++;
+    if (r->phase == Phase::kIter) {
+      const int j = r->j;
+      HIP_TRY(K.dots(K.V, N, j + 1, out, N, K.hcol, 0, s), "dots");
+      HIP_TRY(K.sub(K.V, N, j + 1, K.hcol, out, N, s), "sub");
+      HIP_TRY(K.dots(K.V, N, j + 1, out, N, K.hcol2, 0, s), "dots");
+      HIP_TRY(K.sub(K.V, N, j + 1, K.hcol2, out, N, s), "sub");
+      HIP_TRY(K.dots(out, N, 1, out, N, K.scal, 0, s), "dots");
+      HIP_TRY(K.normalize(out, K.scal, out, N, s), "normalize");
+      HIP_TRY(K.givens(j, s), "givens");
+      HIP_TRY(hipMemcpyAsync(st, K.status, 2 * sizeof(double), hipMemcpyDeviceToDevice, s),
+              "copy");
+    } else {
+      HIP_TRY(K.residual(r->d_b, K.tmp2, K.tmp, N, s), "residual");
+      HIP_TRY(K.dots(K.tmp, N, 1, K.tmp, N, st + 3, 0, s), "dots");
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(srv->h_status, srv->d_status,
+                         (size_t)srv->max_slots * kStatusStride * sizeof(double),
+                         hipMemcpyDeviceToHost, s),
+          "copy");
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+
+  // 4. decisions
+  std::vector<Request*> keep;
+  for (Request* r : srv->active) {
+    ibim_ctx* c = r->ctx;
+    Krylov& K = c->kr;
+    const int64_t N = K.n;
+    const double* hs = srv->h_status + (size_t)r->slot * kStatusStride;
+    double* st = srv->d_status + (size_t)r->slot * kStatusStride;
+    if (r->bnorm < 0.0) r->bnorm = std::sqrt(hs[2]);
+    bool done = false;
+    int err = 0;
+    if (!std::isfinite(r->bnorm)) {
+      err = fail(IBIM_ENAN, "right-hand side is not finite");
+    } else if (r->bnorm == 0.0) {
+      r->converged = true;
+      r->explicit_rel = 0.0;
+      r->resid = 0.0;
+      done = true;
+    } else if (r->phase == Phase::kIter) {
+      r->total++;
+      r->resid = hs[0];
+      const int jend = r->j + 1;
+      if (!std::isfinite(r->resid)) {
+        err = fail(IBIM_ENAN, "NaN in the GMRES recurrence");
+      } else {
+        const bool conv = r->resid <= r->tol * r->bnorm || hs[1] == 0.0;
+        if (conv || jend == K.m || r->total >= c->opt.max_iter) {
+          HIP_TRY(K.backsolve(jend, s), "backsolve");
+          HIP_TRY(K.add(K.V, N, jend, K.y, r->d_x, N, s), "update");
+          r->converged = conv;
+          r->final_check = conv || r->total >= c->opt.max_iter;
+          if (r->final_check && !c->opt.check_residual) {
+            done = true;
+          } else {
+            r->phase = Phase::kResid;
+          }
+        } else {
+          r->j++;
+        }
+      }
+    } else {
+      const double beta = std::sqrt(hs[3]);
+      if (!std::isfinite(beta)) {
+        err = fail(IBIM_ENAN, "NaN in the residual");
+      } else if (r->final_check) {
+        r->explicit_rel = beta / r->bnorm;
+        done = true;
+      } else if (beta <= r->tol * r->bnorm) {
+        // converged at a restart: the residual just formed is the explicit one
+        r->converged = true;
+        r->resid = beta;
+        r->explicit_rel = c->opt.check_residual ? beta / r->bnorm : -1.0;
+        done = true;
+      } else {
+        HIP_TRY(K.normalize(K.tmp, st + 3, K.V, N, s), "normalize");
+        HIP_TRY(K.init_g(st + 3, s), "init_g");
+        r->phase = Phase::kIter;
+        r->j = 0;
+      }
+    }
+    if (err) {
+      mark_failed(srv, r, err, ibim_last_error());
+      continue;
+    }
+    if (done) {
+      if (int e = finish_request(srv, r)) mark_failed(srv, r, e, ibim_last_error());
+      continue;
+    }
+    keep.push_back(r);
+  }
+  srv->active.swap(keep);
+  return IBIM_OK;
+}
+
+Request* find(ibim_server* srv, int64_t ticket) {
+  auto it = srv->reqs.find(ticket);
+  return it == srv->reqs.end() ? nullptr : it->second.get();
+}
+
+}  // namespace
+
+extern "C" {
+
+int ibim_server_create(const ibim_options* opt, size_t hbm_budget_bytes, int max_slots,
+                       int host_threads, void* stream, ibim_server** out) {
+  if (!out) return fail(IBIM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (hbm_budget_bytes == 0 || max_slots < 1 || max_slots > 4096 || host_threads < 1 ||
+      host_threads > 64)
+    return fail(IBIM_EINVAL, "need hbm_budget_bytes > 0, 1 <= max_slots <= 4096, "
+                             "1 <= host_threads <= 64");
+  ibim_options o;
+  ibim_default_options(&o);
+  if (opt) o = *opt;
+  if (o.device < 0) return fail(IBIM_EINVAL, "the server needs a device (options.device >= 0)");
+  if (o.precision != IBIM_FP64 && o.precision != IBIM_MIXED)
+    return fail(IBIM_EINVAL, "unknown precision mode");
+  if (o.restart < 1 || o.restart > 1000 || o.max_iter < 1)
+    return fail(IBIM_EINVAL, "restart must be in [1, 1000] and max_iter >= 1");
+  ibim_server* srv = new (std::nothrow) ibim_server();
+  if (!srv) return fail(IBIM_ENOMEM, "host allocation failed");
+  srv->opt = o;
+  srv->budget = hbm_budget_bytes;
+  srv->max_slots = max_slots;
+  srv->stream = reinterpret_cast<hipStream_t>(stream);
+  for (int sl = max_slots - 1; sl >= 0; --sl) srv->free_slots.push_back(sl);
+  {
+    DeviceScope ds(o.device);
+    srv->grid = pair_batched_grid(o.precision);
+    hipError_t e = dalloc(&srv->d_counter, 1);
+    if (e == hipSuccess) e = dalloc(&srv->d_status, (size_t)max_slots * kStatusStride);
+    if (e == hipSuccess)
+      e = hipHostMalloc((void**)&srv->h_status, (size_t)max_slots * kStatusStride * sizeof(double),
+                        hipHostMallocDefault);
+    if (e != hipSuccess) {
+      ibim_server_destroy(srv);
+      return hip_fail(e, "server allocation");
+    }
+  }
+  srv->st.budget_bytes = hbm_budget_bytes;
+  for (int t = 0; t < host_threads; ++t) srv->workers.emplace_back(worker_main, srv);
+  *out = srv;
+  return IBIM_OK;
+}
+
+int ibim_server_submit(ibim_server* srv, const double* sdf, int nx, int ny, int nz,
+                       const double origin[3], double h, double eps_tube, double eps_in,
+                       double eps_out, double kappa, const double* charge_xyz,
+                       const double* charge_q, int n_charges, double tol, int64_t* ticket) {
+  if (!srv || !sdf || !origin || !ticket) return fail(IBIM_EINVAL, "NULL argument");
+  if (nx < 1 || ny < 1 || nz < 1 || n_charges < 0 || !(tol > 0) ||
+      (n_charges > 0 && (!charge_xyz || !charge_q)))
+    return fail(IBIM_EINVAL, "bad request arguments");
+  auto r = std::make_unique<Request>();
+  r->ticket = srv->next_ticket++;
+  r->sdf.assign(sdf, sdf + (size_t)nx * ny * nz);
+  r->dims[0] = nx;
+  r->dims[1] = ny;
+  r->dims[2] = nz;
+  for (int a = 0; a < 3; ++a) r->origin[a] = origin[a];
+  r->h = h;
+  r->eps = eps_tube;
+  r->eps_in = eps_in;
+  r->eps_out = eps_out;
+  r->kappa = kappa;
+  r->tol = tol;
+  r->zq.assign(charge_xyz, charge_xyz + 3 * (size_t)n_charges);
+  r->q.assign(charge_q, charge_q + (size_t)n_charges);
+  r->t_submit = std::chrono::steady_clock::now();
+  Request* raw = r.get();
+  *ticket = raw->ticket;
+  srv->reqs.emplace(raw->ticket, std::move(r));
+  srv->waiting.push_back(raw);
+  srv->st.submitted++;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->prep_queue.push_back(raw);
+  }
+  srv->cv.notify_one();
+  return IBIM_OK;
+}
+
+int ibim_server_step(ibim_server* srv, int* active, int* waiting) {
+  if (!srv) return fail(IBIM_EINVAL, "NULL server");
+  DeviceScope ds(srv->opt.device);
+  const int e = step_impl(srv);
+  if (active) *active = (int)srv->active.size();
+  if (waiting) *waiting = (int)srv->waiting.size();
+  return e;
+}
+
+int ibim_server_poll(ibim_server* srv, int64_t ticket, int* state, double* g_pol,
+                     ibim_solve_info* info) {
+  if (!srv || !state) return fail(IBIM_EINVAL, "NULL argument");
+  Request* r = find(srv, ticket);
+  if (!r) return fail(IBIM_EINVAL, "unknown ticket");
+  *state = r->state;
+  if (r->state == IBIM_REQ_FAILED) return fail(r->error, r->error_msg);
+  if (r->state == IBIM_REQ_DONE) {
+    if (g_pol) *g_pol = r->g_pol;
+    if (info)
+      *info = ibim_solve_info{r->total, r->applies, r->converged ? 1 : 0, r->resid / r->bnorm,
+                              r->explicit_rel, r->seconds};
+  }
+  return IBIM_OK;
+}
+
+int ibim_server_solution(ibim_server* srv, int64_t ticket, double* x, int64_t* M) {
+  if (!srv || !M) return fail(IBIM_EINVAL, "NULL argument");
+  Request* r = find(srv, ticket);
+  if (!r) return fail(IBIM_EINVAL, "unknown ticket");
+  if (r->state != IBIM_REQ_DONE) return fail(IBIM_EINVAL, "request is not finished");
+  *M = r->M;
+  if (x) std::memcpy(x, r->x_host.data(), r->x_host.size() * sizeof(double));
+  return IBIM_OK;
+}
+
+int ibim_server_release(ibim_server* srv, int64_t ticket) {
+  if (!srv) return fail(IBIM_EINVAL, "NULL server");
+  Request* r = find(srv, ticket);
+  if (!r) return fail(IBIM_EINVAL, "unknown ticket");
+  if (r->state != IBIM_REQ_DONE && r->state != IBIM_REQ_FAILED)
+    return fail(IBIM_EINVAL, "request is still in progress");
+  srv->reqs.erase(ticket);
+  return IBIM_OK;
+}
+
+int ibim_server_get_stats(ibim_server* srv, ibim_server_stats* st) {
+  if (!srv || !st) return fail(IBIM_EINVAL, "NULL argument");
+  srv->st.bytes_in_use = srv->used;
+  srv->st.bytes_peak = srv->peak;
+  srv->st.active = (int)srv->active.size();
+  srv->st.waiting = (int)srv->waiting.size();
+  *st = srv->st;
+  return IBIM_OK;
+}
+
+void ibim_server_destroy(ibim_server* srv) {
+  if (!srv) return;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->stopping = true;
+  }
+  srv->cv.notify_all();
+  for (auto& t : srv->workers) t.join();
+  DeviceScope ds(srv->opt.device);
+  for (auto& kv : srv->reqs) {
+    Request* r = kv.second.get();
+    if (r->ctx) ibim_destroy(r->ctx);
+    r->ctx = nullptr;
+    dfree(r->d_b);
+    dfree(r->d_x);
+  }
+  dfree(srv->d_args);
+  dfree(srv->d_items);
+  dfree(srv->d_counter);
+  dfree(srv->d_status);
+  if (srv->h_args) (void)hipHostFree(srv->h_args);
+  if (srv->h_items) (void)hipHostFree(srv->h_items);
+  if (srv->h_status) (void)hipHostFree(srv->h_status);
+  delete srv;
+}
+
+}  // extern "C"

@@ -46,6 +46,17 @@ class _SolveInfo(ctypes.Structure):
                 ("seconds", ctypes.c_double)]
 
 
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64),
+                ("finished", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("rounds", ctypes.c_int64), ("batched_items", ctypes.c_int64),
+                ("bytes_in_use", ctypes.c_size_t), ("bytes_peak", ctypes.c_size_t),
+                ("budget_bytes", ctypes.c_size_t), ("active", ctypes.c_int),
+                ("waiting", ctypes.c_int), ("max_active_seen", ctypes.c_int)]
+
+
+REQ_WAITING, REQ_ACTIVE, REQ_DONE, REQ_FAILED = 0, 1, 2, -1
+
 _lib = None
 _D = ctypes.POINTER(ctypes.c_double)
 _I64 = ctypes.POINTER(ctypes.c_int64)
@@ -95,6 +106,21 @@ def load():
     lib.ibim_energy.argtypes = [_VP, _VP, _D, _VP]
     lib.ibim_pair_timing.argtypes = [_VP, ctypes.c_int]
     lib.ibim_pair_timing_read.argtypes = [_VP, _I64, _D]
+    lib.ibim_server_create.argtypes = [ctypes.POINTER(_Options), ctypes.c_size_t, ctypes.c_int,
+                                       ctypes.c_int, _VP, ctypes.POINTER(_VP)]
+    lib.ibim_server_submit.argtypes = [_VP, _D, ctypes.c_int, ctypes.c_int, ctypes.c_int, _D,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, _D, _D, ctypes.c_int,
+                                       ctypes.c_double, _I64]
+    lib.ibim_server_step.argtypes = [_VP, ctypes.POINTER(ctypes.c_int),
+                                     ctypes.POINTER(ctypes.c_int)]
+    lib.ibim_server_poll.argtypes = [_VP, ctypes.c_int64, ctypes.POINTER(ctypes.c_int), _D,
+                                     ctypes.POINTER(_SolveInfo)]
+    lib.ibim_server_solution.argtypes = [_VP, ctypes.c_int64, _D, _I64]
+    lib.ibim_server_release.argtypes = [_VP, ctypes.c_int64]
+    lib.ibim_server_get_stats.argtypes = [_VP, ctypes.POINTER(_ServerStats)]
+    lib.ibim_server_destroy.argtypes = [_VP]
+    lib.ibim_server_destroy.restype = None
     _lib = lib
     return lib
 
@@ -262,3 +288,113 @@ class Problem:
         x, info = self.solve(g, tol, stream=stream)
         info["g_pol"] = self.energy(x, stream=stream)
         return x, info
+
+
+def _info_dict(info):
+    return {"iters": info.iters, "applies": info.applies, "converged": bool(info.converged),
+            "rel_resid": info.rel_resid, "explicit_rel_resid": info.explicit_rel_resid,
+            "seconds": info.seconds}
+
+
+class Server:
+    """Continuous-batching solve server (``ibim_server_*``): many independent
+    problems share one persistent batched pair-kernel launch per round."""
+
+    def __init__(self, hbm_budget_bytes, max_slots=16, host_threads=4, precision=FP64,
+                 restart=60, max_iter=300, check_residual=True, device=0, r_near=0.0,
+                 stream=None):
+        lib = load()
+        self._lib = lib
+        opt = _Options()
+        lib.ibim_default_options(ctypes.byref(opt))
+        opt.precision = int(precision)
+        opt.restart = int(restart)
+        opt.max_iter = int(max_iter)
+        opt.check_residual = int(bool(check_residual))
+        opt.device = int(device)
+        opt.r_near = float(r_near)
+        srv = ctypes.c_void_p()
+        _check(lib.ibim_server_create(ctypes.byref(opt), int(hbm_budget_bytes), int(max_slots),
+                                      int(host_threads), _stream_ptr(stream), ctypes.byref(srv)))
+        self._srv = srv
+
+    def submit(self, sdf, origin, h, eps_tube, eps_in, eps_out, kappa, charge_xyz=None,
+               charge_q=None, tol=1e-8) -> int:
+        sdf = np.ascontiguousarray(sdf, dtype=np.float64)
+        if sdf.ndim != 3:
+            raise ValueError("sdf must be a 3-D array")
+        origin = np.ascontiguousarray(origin, dtype=np.float64).reshape(3)
+        zq = np.ascontiguousarray(np.zeros((0, 3)) if charge_xyz is None else charge_xyz,
+                                  dtype=np.float64).reshape(-1, 3)
+        q = np.ascontiguousarray(np.zeros(0) if charge_q is None else charge_q, dtype=np.float64)
+        if q.shape[0] != zq.shape[0]:
+            raise ValueError("charge_xyz and charge_q disagree")
+        t = ctypes.c_int64()
+        _check(self._lib.ibim_server_submit(self._srv, _dp(sdf), sdf.shape[0], sdf.shape[1],
+                                            sdf.shape[2], _dp(origin), float(h), float(eps_tube),
+                                            float(eps_in), float(eps_out), float(kappa), _dp(zq),
+                                            _dp(q), int(q.shape[0]), float(tol), ctypes.byref(t)))
+        return int(t.value)
+
+    def submit_workload(self, wl, tol=None) -> int:
+        return self.submit(wl.sdf, wl.origin, wl.h, wl.eps_tube, wl.eps_in, wl.eps_out, wl.kappa,
+                           wl.charge_xyz, wl.charge_q, tol=wl.tol if tol is None else tol)
+
+    def step(self):
+        """One round; returns (active, waiting)."""
+        a = ctypes.c_int()
+        w = ctypes.c_int()
+        _check(self._lib.ibim_server_step(self._srv, ctypes.byref(a), ctypes.byref(w)))
+        return int(a.value), int(w.value)
+
+    def poll(self, ticket):
+        """(state, g_pol or None, info dict or None); raises IbimError for a failed request."""
+        st = ctypes.c_int()
+        g = ctypes.c_double()
+        info = _SolveInfo()
+        _check(self._lib.ibim_server_poll(self._srv, int(ticket), ctypes.byref(st),
+                                          ctypes.byref(g), ctypes.byref(info)))
+        if st.value == REQ_DONE:
+            return REQ_DONE, float(g.value), _info_dict(info)
+        return int(st.value), None, None
+
+    def state(self, ticket) -> int:
+        st = ctypes.c_int()
+        code = self._lib.ibim_server_poll(self._srv, int(ticket), ctypes.byref(st), None, None)
+        if code < 0 and st.value != REQ_FAILED:
+            _check(code)
+        return int(st.value)
+
+    def solution(self, ticket) -> np.ndarray:
+        M = ctypes.c_int64()
+        _check(self._lib.ibim_server_solution(self._srv, int(ticket), None, ctypes.byref(M)))
+        x = np.empty(2 * M.value)
+        _check(self._lib.ibim_server_solution(self._srv, int(ticket), _dp(x), ctypes.byref(M)))
+        return x
+
+    def release(self, ticket):
+        _check(self._lib.ibim_server_release(self._srv, int(ticket)))
+
+    def stats(self) -> dict:
+        st = _ServerStats()
+        _check(self._lib.ibim_server_get_stats(self._srv, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in _ServerStats._fields_}
+
+    def run_until_idle(self, max_rounds=1_000_000):
+        for _ in range(max_rounds):
+            a, w = self.step()
+            if a == 0 and w == 0:
+                return
+        raise RuntimeError("server did not drain")
+
+    def close(self):
+        srv = getattr(self, "_srv", None)
+        if srv is not None and srv.value:
+            self._lib.ibim_server_destroy(srv)
+        self._srv = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

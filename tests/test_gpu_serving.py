@@ -1,0 +1,170 @@
+"""GPU tests of the continuous-batching solve server (``ibim_server_*``).
+
+Every request must give bit-identical results whether it runs alone or in a
+mix with other problems (the batched pair launch computes each work item as
+the single-problem kernel does, and the per-request GMRES sequence is the
+one of ``ibim_solve``), and the same bits as ``ibim_solve`` + ``ibim_energy``
+through the single-problem entry points.  Admission must respect the HBM
+budget, and a bad request must fail alone.  One energy is checked against
+the FP64 oracle.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2210_03699_amd import ibim  # noqa: E402
+
+GiB = 1 << 30
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+# different sizes, so the batched work list mixes tile counts and ragged tails
+MIX = {
+    "born_h0.4": lambda: workloads.born_sphere(h=0.4),
+    "offset_sphere": lambda: workloads.born_sphere(h=0.25, radius=1.7,
+                                                   offset=(0.37, 0.11, -0.23)),
+    "tiny_sphere": lambda: workloads.born_sphere(h=0.3, radius=0.6, eps_factor=1.5),
+    "kirkwood_small": lambda: workloads.kirkwood_sphere(h=0.3, radius=3.0, r_charges=2.0,
+                                                        n_charges=5, seed=7, tol=1e-10),
+    "torus": lambda: workloads.torus_case(h=0.1),
+    "ses_molecule": lambda: workloads.ses_molecule(20, 9.0, 0.35, 2.0, seed=11, tol=1e-10),
+}
+
+
+@pytest.fixture(scope="module")
+def wls():
+    return {k: f() for k, f in MIX.items()}
+
+
+def _serve(wls, names, budget=8 * GiB, slots=8, **opt):
+    srv = ibim.Server(budget, max_slots=slots, host_threads=4, **opt)
+    try:
+        tickets = {n: srv.submit_workload(wls[n]) for n in names}
+        srv.run_until_idle()
+        out = {}
+        for n, t in tickets.items():
+            st, g, info = srv.poll(t)
+            assert st == ibim.REQ_DONE, n
+            out[n] = (g, srv.solution(t), info)
+        return out, srv.stats()
+    finally:
+        srv.close()
+
+
+def _direct(wl, **opt):
+    prob = ibim.Problem.from_workload(wl, device=0, **opt)
+    x, info = prob.solve_energy(wl.tol)
+    torch.cuda.synchronize()
+    out = (info["g_pol"], x.cpu().numpy(), info)
+    prob.close()
+    return out
+
+
+def _same(a, b, name):
+    ga, xa, ia = a
+    gb, xb, ib = b
+    assert ga == gb, f"{name}: G_pol {ga!r} != {gb!r}"
+    assert np.array_equal(xa, xb), f"{name}: solutions differ (max {np.max(np.abs(xa - xb))})"
+    assert ia["iters"] == ib["iters"], name
+    assert ia["converged"] == ib["converged"], name
+
+
+@pytest.mark.parametrize("precision,restart", [(ibim.FP64, 60), (ibim.FP64, 4),
+                                               (ibim.MIXED, 60)])
+def test_alone_equals_mixed_equals_direct(wls, precision, restart):
+    names = list(MIX)
+    _say(f"[serving] precision={precision} restart={restart}: mix of {len(names)}")
+    mixed, stats = _serve(wls, names, precision=precision, restart=restart)
+    _say(f"[serving] rounds={stats['rounds']} max_active={stats['max_active_seen']} "
+         f"items={stats['batched_items']}")
+    assert stats["finished"] == len(names) and stats["failed"] == 0
+    assert stats["max_active_seen"] == len(names)
+    assert stats["bytes_in_use"] == 0
+    for n in names:
+        alone, _ = _serve(wls, [n], slots=1, precision=precision, restart=restart)
+        _same(alone[n], mixed[n], f"{n} alone vs mix")
+        direct = _direct(wls[n], precision=precision, restart=restart)
+        _same(direct, mixed[n], f"{n} ibim_solve vs server")
+        if restart >= 60:
+            assert mixed[n][2]["converged"]
+        _say(f"[serving] {n}: iters={mixed[n][2]['iters']} G={mixed[n][0]:.12e}")
+
+
+def test_energy_matches_oracle(wls):
+    wl = wls["kirkwood_small"]
+    out, _ = _serve(wls, ["kirkwood_small", "born_h0.4"])
+    orc = oracle.Oracle.from_workload(wl)
+    _, info_o = orc.solve_energy(wl.charge_xyz, wl.charge_q, wl.tol)
+    g = out["kirkwood_small"][0]
+    assert abs(g - info_o["g_pol"]) <= 1e-10 * abs(info_o["g_pol"])
+
+
+def test_budget_admission(wls):
+    names = list(MIX)
+    free, _ = _serve(wls, names)
+    # the budget of the two largest footprints measured alone
+    held = {}
+    for n in names:
+        _, st = _serve(wls, [n], slots=1)
+        held[n] = st["bytes_peak"]
+    budget = int(sum(sorted(held.values())[-2:]) * 1.05)
+    out, st = _serve(wls, names, budget=budget)
+    _say(f"[serving] budget={budget} peak={st['bytes_peak']} "
+         f"max_active={st['max_active_seen']}")
+    assert st["bytes_peak"] <= budget
+    assert 1 <= st["max_active_seen"] < len(names)
+    assert st["finished"] == len(names)
+    for n in names:
+        _same(out[n], free[n], f"{n} budgeted vs free")
+
+
+def test_bad_requests_fail_alone(wls):
+    srv = ibim.Server(8 * GiB, max_slots=4, host_threads=2)
+    try:
+        good = srv.submit_workload(wls["born_h0.4"])
+        # no tube: the distance function never changes sign near zero
+        far = wls["born_h0.4"]
+        flat = np.full_like(far.sdf, 5.0)
+        bad_geom = srv.submit(flat, far.origin, far.h, far.eps_tube, far.eps_in, far.eps_out,
+                              far.kappa, far.charge_xyz, far.charge_q, tol=1e-8)
+        bad_eps = srv.submit(far.sdf, far.origin, far.h, far.eps_tube, -1.0, far.eps_out,
+                             far.kappa, far.charge_xyz, far.charge_q, tol=1e-8)
+        good2 = srv.submit_workload(wls["tiny_sphere"])
+        srv.run_until_idle()
+        assert srv.state(bad_geom) == ibim.REQ_FAILED
+        assert srv.state(bad_eps) == ibim.REQ_FAILED
+        with pytest.raises(ibim.IbimError):
+            srv.poll(bad_eps)
+        for t, n in ((good, "born_h0.4"), (good2, "tiny_sphere")):
+            st, g, info = srv.poll(t)
+            assert st == ibim.REQ_DONE
+            _same((g, srv.solution(t), info), _direct(wls[n]), n)
+        s = srv.stats()
+        assert s["failed"] == 2 and s["finished"] == 2
+        srv.release(bad_geom)
+        with pytest.raises(ibim.IbimError):
+            srv.poll(bad_geom)
+    finally:
+        srv.close()
+    # a request larger than the whole budget is refused, not left waiting
+    srv = ibim.Server(1 << 20, max_slots=2, host_threads=1)
+    try:
+        t = srv.submit_workload(wls["offset_sphere"])
+        srv.run_until_idle()
+        assert srv.state(t) == ibim.REQ_FAILED
+        with pytest.raises(ibim.IbimError) as ei:
+            srv.poll(t)
+        assert ei.value.code == -3
+    finally:
+        srv.close()
