@@ -226,6 +226,33 @@ def by_name(name: str) -> Workload:
     raise KeyError(name)
 
 
+def serving_stream(n_requests=32, seed=4, sphere_radius=(2.0, 10.0), max_charges=30,
+                   ses_atoms=(50, 200), hs=(0.3, 0.5), tol=1e-6) -> list:
+    """Seeded mix of solve requests for the serving benchmark.
+
+    Half spheres (radius uniform in ``sphere_radius``, 1..``max_charges``
+    charges in r <= 0.8 R), half random-walk SES molecules (atom count uniform
+    in ``ses_atoms``, box scaled as 25 A * (n/500)^(1/3)); grid spacing drawn
+    from ``hs``, tube half-width 2h, GMRES tolerance ``tol``.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(n_requests):
+        h = float(rng.choice(np.asarray(hs, dtype=np.float64)))
+        sub_seed = int(rng.integers(1, 2**31 - 1))
+        if rng.random() < 0.5:
+            R = float(rng.uniform(*sphere_radius))
+            nq = int(rng.integers(1, max_charges + 1))
+            wl = kirkwood_sphere(h=h, radius=R, eps_factor=2.0, n_charges=nq, r_charges=0.8 * R,
+                                 seed=sub_seed, tol=tol)
+        else:
+            n = int(rng.integers(ses_atoms[0], ses_atoms[1] + 1))
+            box = 25.0 * (n / 500.0) ** (1.0 / 3.0)
+            wl = ses_molecule(n, box, h, 2.0, seed=sub_seed, tol=tol)
+        out.append(wl)
+    return out
+
+
 def random_vector(n: int, seed: int) -> np.ndarray:
     """Seeded standard-normal test vector (float64)."""
     rng = np.random.Generator(np.random.PCG64(seed))

@@ -16,7 +16,8 @@
  * candidate whose nearest grid node lies in a bubble (a probe centre's own
  * ball lies in its bubble) and treats bubble nodes as interior.  Points
  * farther than `band` from the surface get a cheap bound with the right sign
- * instead.
+ * instead: only candidates within probe + band are examined, nearest first,
+ * and a point with none exposed gets a lower bound of at least band.
  */
 #include <math.h>
 #include <stdint.h>
@@ -116,6 +117,19 @@ typedef struct {
   double h;
 } GridInfo;
 
+/* a boundary candidate of A: point p at distance dd from the grid node;
+ * e1, e2: balls it lies on (excluded from its burial test); vertices were
+ * tested at construction */
+typedef struct {
+  double dd, p[3];
+  int e1, e2, vertex;
+} Cand;
+
+static int cand_cmp(const void* a, const void* b) {
+  double x = ((const Cand*)a)->dd, y = ((const Cand*)b)->dd;
+  return (x > y) - (x < y);
+}
+
 static int buried(const Ball* b, const int* nb, int nn, const double* p, int e1, int e2, int e3) {
   for (int t = 0; t < nn; ++t) {
     int k = nb[t];
@@ -149,8 +163,30 @@ int ses_sdf(const double* xyz, const double* radii, int n, double probe, const d
     b[i].R = radii[i] + probe;
     if (b[i].R > Rmax) Rmax = b[i].R;
   }
-  Cells cl;
+  Cells cl, fcl; /* coarse cells for the wide query of step 1, fine ones elsewhere */
   cells_build(&cl, b, n, 2.0 * Rmax);
+  cells_build(&fcl, b, n, 0.5 * Rmax);
+  /* overlapping balls of every ball: a point on sphere i can only lie inside
+   * ball k if the two balls overlap */
+  int* ov_start = (int*)calloc((size_t)n + 1, sizeof(int));
+  int ov_cap = 32 * n + 32;
+  int* ov = (int*)malloc(sizeof(int) * ov_cap);
+  {
+    int nb[4096];
+    for (int i = 0; i < n; ++i) {
+      int m = cells_query(&cl, b, b[i].c, 2.0 * Rmax, nb, 4096);
+      for (int t = 0; t < m; ++t) {
+        int k = nb[t];
+        if (k == i || dist3(b[i].c, b[k].c) >= b[i].R + b[k].R) continue;
+        if (ov_start[i + 1] + 1 > ov_cap) {
+          ov_cap *= 2;
+          ov = (int*)realloc(ov, sizeof(int) * ov_cap);
+        }
+        ov[ov_start[i + 1]++] = k;
+      }
+      if (i + 1 < n) ov_start[i + 2] = ov_start[i + 1];
+    }
+  }
   const int64_t ng = (int64_t)nx * ny * nz;
 
   /* 1. s(x) = min_i |x - c_i| - R_i (>= 0 in A), inner(x) = max_i R_i - |x - c_i| */
@@ -235,7 +271,7 @@ int ses_sdf(const double* xyz, const double* radii, int n, double probe, const d
           double p[3];
           for (int q = 0; q < 3; ++q) p[q] = C->C[q] + C->rho * (cph * e1[q] + sg * sph * e2[q]);
           int nb2[4096];
-          int m2 = cells_query(&cl, b, p, Rmax, nb2, 4096);
+          int m2 = cells_query(&fcl, b, p, Rmax, nb2, 4096);
           if (buried(b, nb2, m2, p, C->i, C->j, k)) continue;
           if (nv >= vcap) {
             vcap *= 2;
@@ -262,8 +298,8 @@ int ses_sdf(const double* xyz, const double* radii, int n, double probe, const d
     vb[q].R = 0.0;
   }
   Cells ccl, vcl;
-  if (nc > 0) cells_build(&ccl, cb, nc, 2.0 * Rmax);
-  if (nv > 0) cells_build(&vcl, vb, nv, 2.0 * Rmax);
+  if (nc > 0) cells_build(&ccl, cb, nc, 0.5 * Rmax);
+  if (nv > 0) cells_build(&vcl, vb, nv, 0.5 * Rmax);
 
   /* 4. distances: pass 0 keeps every exposed candidate, pass 1 drops the
    * candidates of enclosed solvent bubbles found after pass 0 */
@@ -274,7 +310,7 @@ int ses_sdf(const double* xyz, const double* radii, int n, double probe, const d
 #pragma omp parallel for schedule(dynamic, 2)
   for (int i = 0; i < nx; ++i) {
     int* nb = (int*)malloc(sizeof(int) * 8192);
-    int* nb2 = (int*)malloc(sizeof(int) * 8192);
+    Cand* cand = (Cand*)malloc(sizeof(Cand) * 3 * 8192);
     for (int j = 0; j < ny; ++j)
       for (int k = 0; k < nz; ++k) {
         int64_t q = ((int64_t)i * ny + j) * nz + k;
@@ -288,55 +324,64 @@ int ses_sdf(const double* xyz, const double* radii, int n, double probe, const d
           out[q] = inner[q] - probe; /* deep inside: a lower bound is enough */
           continue;
         }
-        double best = 1e300;
-        /* sphere patches */
-        int m = cells_query(&cl, b, x, Rmax + reach_d, nb, 8192);
+        /* every candidate (sphere patch, circle arc, vertex) within reach_d,
+         * with its distance; the nearest exposed one gives the distance */
+        int nk = 0;
+        int m = cells_query(&fcl, b, x, Rmax + reach_d, nb, 8192);
         for (int t = 0; t < m; ++t) {
           const Ball* B = &b[nb[t]];
           double dxc = dist3(x, B->c);
-          if (dxc == 0.0) continue;
-          double dd = fabs(B->R - dxc);
-          if (dd >= best) continue;
-          double dir[3], p[3];
-          for (int a = 0; a < 3; ++a) {
-            dir[a] = (x[a] - B->c[a]) / dxc;
-            p[a] = B->c[a] + B->R * dir[a];
-          }
-          int m2 = cells_query(&cl, b, p, Rmax, nb2, 8192);
-          if (buried(b, nb2, m2, p, nb[t], -1, -1)) continue;
-          if (in_bubble(&gi, p)) continue;
-          best = dd;
+          if (dxc == 0.0 || fabs(B->R - dxc) > reach_d) continue;
+          Cand* K = &cand[nk++];
+          K->dd = fabs(B->R - dxc);
+          for (int a = 0; a < 3; ++a) K->p[a] = B->c[a] + B->R * ((x[a] - B->c[a]) / dxc);
+          K->e1 = nb[t];
+          K->e2 = -1;
+          K->vertex = 0;
         }
-        /* circle arcs */
         if (nc > 0) {
           int mc = cells_query(&ccl, cb, x, Rmax + reach_d, nb, 8192);
           for (int t = 0; t < mc; ++t) {
             const Circle* C = &circ[nb[t]];
             double w[3] = {x[0] - C->C[0], x[1] - C->C[1], x[2] - C->C[2]};
+            /* every point of the circle is at least |x - C| - rho away */
+            if (sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]) - C->rho > reach_d) continue;
             double wu = w[0] * C->u[0] + w[1] * C->u[1] + w[2] * C->u[2];
             double wp[3] = {w[0] - wu * C->u[0], w[1] - wu * C->u[1], w[2] - wu * C->u[2]};
             double L = sqrt(wp[0] * wp[0] + wp[1] * wp[1] + wp[2] * wp[2]);
             if (L == 0.0) continue;
-            double p[3];
-            for (int a = 0; a < 3; ++a) p[a] = C->C[a] + C->rho * wp[a] / L;
-            double dd = dist3(x, p);
-            if (dd >= best) continue;
-            int m2 = cells_query(&cl, b, p, Rmax, nb2, 8192);
-            if (buried(b, nb2, m2, p, C->i, C->j, -1)) continue;
-            if (in_bubble(&gi, p)) continue;
-            best = dd;
+            Cand* K = &cand[nk];
+            for (int a = 0; a < 3; ++a) K->p[a] = C->C[a] + C->rho * wp[a] / L;
+            K->dd = dist3(x, K->p);
+            if (K->dd > reach_d) continue;
+            ++nk;
+            K->e1 = C->i;
+            K->e2 = C->j;
+            K->vertex = 0;
           }
         }
-        /* vertices */
         if (nv > 0) {
           int mv = cells_query(&vcl, vb, x, reach_d, nb, 8192);
           for (int t = 0; t < mv; ++t) {
             const Vertex* V = &vert[nb[t]];
-            double dd = dist3(x, V->p);
-            if (dd >= best) continue;
-            if (in_bubble(&gi, V->p)) continue;
-            best = dd;
+            Cand* K = &cand[nk++];
+            for (int a = 0; a < 3; ++a) K->p[a] = V->p[a];
+            K->dd = dist3(x, V->p);
+            K->e1 = K->e2 = -1;
+            K->vertex = 1;
           }
+        }
+        qsort(cand, (size_t)nk, sizeof(Cand), cand_cmp);
+        double best = 1e300;
+        for (int t = 0; t < nk; ++t) {
+          const Cand* K = &cand[t];
+          if (!K->vertex) {
+            const int o0 = ov_start[K->e1], o1 = ov_start[K->e1 + 1];
+            if (buried(b, ov + o0, o1 - o0, K->p, K->e1, K->e2, -1)) continue;
+          }
+          if (in_bubble(&gi, K->p)) continue;
+          best = K->dd;
+          break;
         }
         /* no exposed boundary point within reach_d: the distance is at least
          * reach_d (and at least the ball depth) */
@@ -344,7 +389,7 @@ int ses_sdf(const double* xyz, const double* radii, int n, double probe, const d
         out[q] = best - probe;
       }
     free(nb);
-    free(nb2);
+    free(cand);
   }
   if (pass == 0) {
     /* flood fill the solvent (d < 0) from the grid boundary */
@@ -398,6 +443,10 @@ int ses_sdf(const double* xyz, const double* radii, int n, double probe, const d
   free(vb);
   free(cl.start);
   free(cl.idx);
+  free(fcl.start);
+  free(fcl.idx);
+  free(ov_start);
+  free(ov);
   if (nc > 0) {
     free(ccl.start);
     free(ccl.idx);
