@@ -33,6 +33,29 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6  # MI355X vector FP64
 PEAK_FP32_VECTOR_TFLOPS = 157.3  # MI355X vector FP32 (counts packed float32 issue)
 
 
+# HBM bytes per pair-kernel launch on the Kirkwood workload, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch, scaled by 2.0 and 1.0: what the
+# counters read for a plain 256 MiB copy).  Valid only while the kernel sources
+# hash to the recorded digest; otherwise the traffic is reported as null.
+MEASURED_TRAFFIC = {
+    "fp64": ("482f75c3", 149.8e6),
+    "mixed": ("b66acdbf", 126.6e6),
+}
+KERNEL_SOURCES = {
+    "fp64": ["operator.hip", "operator.h", "pair_math.h", "fastmath.h"],
+    "mixed": ["operator.hip", "operator.h", "pair_math.h", "fastmath.h", "mixed.hip"],
+}
+
+
+def kernel_digest(precision):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[precision]:
+        with open(os.path.join(ROOT, "paper_2210_03699_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:8]
+
+
 def percentile(xs, p):
     xs = sorted(xs)
     if not xs:
@@ -73,6 +96,105 @@ def cpu_baseline(wl, M, seconds):
     }
 
 
+def serve_bench(args):
+    """Serving benchmark: a seeded stream of independent solve requests
+    (spheres and random-walk molecules at several grid spacings) through the
+    continuous-batching server.  First a closed batch measures the capacity
+    (solves/s); then the same requests arrive as a Poisson stream at 0.9x
+    that rate and the latency arrival -> G_pol available is recorded."""
+    import numpy as np
+
+    import workloads
+    from paper_2210_03699_amd import FP64, MIXED, REQ_DONE, REQ_FAILED, Server
+
+    mode = FP64 if args.precision == "fp64" else MIXED
+    t = time.perf_counter()
+    reqs = workloads.serving_stream(args.requests, seed=4)
+    print(f"[serve] generated {len(reqs)} requests in {time.perf_counter() - t:.1f}s",
+          file=sys.stderr, flush=True)
+    budget = int(args.hbm_budget_gib * (1 << 30))
+
+    def run(arrivals):
+        srv = Server(budget, max_slots=args.slots, host_threads=args.host_threads,
+                     precision=mode)
+        order = np.argsort(arrivals, kind="stable")
+        tickets, t_arr, t_done = {}, {}, {}
+        nxt = 0
+        t0 = time.perf_counter()
+        while nxt < len(order) or len(t_done) < len(order):
+            now = time.perf_counter() - t0
+            while nxt < len(order) and arrivals[order[nxt]] <= now:
+                i = int(order[nxt])
+                tickets[i] = srv.submit_workload(reqs[i])
+                t_arr[i] = t0 + arrivals[i]
+                nxt += 1
+            active, waiting = srv.step() if tickets else (0, 0)
+            now_abs = time.perf_counter()
+            for i, tk in tickets.items():
+                if i not in t_done and srv.state(tk) in (REQ_DONE, REQ_FAILED):
+                    t_done[i] = now_abs
+            if active == 0 and waiting == 0 and nxt < len(order):
+                time.sleep(max(0.0, arrivals[order[nxt]] - (time.perf_counter() - t0)))
+        makespan = max(t_done.values()) - t0
+        res = []
+        for i, tk in tickets.items():
+            st, g, info = srv.poll(tk)
+            assert st == REQ_DONE, f"request {i} did not finish"
+            M = len(srv.solution(tk)) // 2
+            res.append({"i": i, "M": M, "applies": info["applies"], "iters": info["iters"],
+                        "latency": t_done[i] - t_arr[i], "g_pol": g})
+        stats = srv.stats()
+        srv.close()
+        return makespan, res, stats
+
+    # closed batch: capacity
+    mk, res, st = run(np.zeros(len(reqs)))
+    capacity = len(reqs) / mk
+    print(f"[serve] closed batch: {len(reqs)} solves in {mk:.2f}s -> {capacity:.2f} solves/s, "
+          f"max active {st['max_active_seen']}", file=sys.stderr, flush=True)
+    # open loop at 0.9x capacity
+    rate = 0.9 * capacity
+    rng = np.random.Generator(np.random.PCG64(4))
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(reqs)))
+    arrivals -= arrivals[0]
+    mk2, res2, st2 = run(arrivals)
+    lat = [r["latency"] for r in res2]
+    pairs = sum(float(r["applies"]) * r["M"] * r["M"] for r in res2)
+    Ms = sorted(r["M"] for r in res2)
+    out = {
+        "metric": METRIC,
+        "value": pairs / mk2,
+        "unit": "pair-interactions/s",
+        "n_gpus": 1,
+        "steps": len(reqs),
+        "warmup": 0,
+        "ms_per_step": mk2 / len(reqs) * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"serving_stream_{len(reqs)}", "seed": 4, "tol": 1e-6,
+            "spheres": "R~U[2,10], 1..30 charges", "ses": "50..200 atoms",
+            "h": [0.3, 0.5], "eps_tube": "2h", "slots": args.slots,
+            "hbm_budget_gib": args.hbm_budget_gib, "pair_kernel": args.precision,
+            "M_min": Ms[0], "M_median": Ms[len(Ms) // 2], "M_max": Ms[-1],
+        },
+        "solves_per_s": len(reqs) / mk2,
+        "capacity_solves_per_s": capacity,
+        "arrival_rate_per_s": rate,
+        "latency_ms": {"p50": percentile(lat, 50) * 1e3, "p99": percentile(lat, 99) * 1e3},
+        "closed_batch_latency_ms": {
+            "p50": percentile([r["latency"] for r in res], 50) * 1e3,
+            "p99": percentile([r["latency"] for r in res], 99) * 1e3},
+        "rounds": st2["rounds"],
+        "max_active": st2["max_active_seen"],
+        "bytes_peak": st2["bytes_peak"],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,10 +209,20 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: 3 operator applications and one plain "
                          "256 MiB device copy (the reference for the HBM byte counters)")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving benchmark: a seeded stream of independent requests through "
+                         "the continuous-batching server (p50/p99 latency, solves/s)")
+    ap.add_argument("--requests", type=int, default=32)
+    ap.add_argument("--slots", type=int, default=16)
+    ap.add_argument("--host-threads", type=int, default=8)
+    ap.add_argument("--hbm-budget-gib", type=float, default=64.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
+    if args.serve:
+        serve_bench(args)
+        return
 
     import numpy as np
     import torch
@@ -150,6 +282,9 @@ def main():
     pairs = float(applies) * M * M
     avg_pair_ms = pair_ms / max(n_launch, 1)
     achieved_tflops = FLOPS_PER_PAIR * float(M) * M / (avg_pair_ms * 1e-3) / 1e12
+    digest, measured = MEASURED_TRAFFIC[args.precision]
+    traffic = measured if (args.workload == "kirkwood"
+                           and kernel_digest(args.precision) == digest) else None
     out = {
         "metric": METRIC,
         "value": pairs / elapsed,
@@ -182,7 +317,7 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": achieved_tflops / peak,
-            "traffic": None,
+            "traffic": traffic,
         },
     }
     golden = os.path.join(ROOT, "tests", "golden", "kirkwood_R10_h0.25.json")
