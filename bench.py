@@ -28,7 +28,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "pair-interactions/s in IBIM matvec; solves/s + p50/p99 latency at fixed error"
-FLOPS_PER_PAIR = 60            # algorithmic flops of one pair (FMA = 2), see the design doc
 PEAK_FP64_VECTOR_TFLOPS = 78.6  # MI355X vector FP64
 PEAK_FP32_VECTOR_TFLOPS = 157.3  # MI355X vector FP32 (counts packed float32 issue)
 
@@ -42,7 +41,8 @@ MEASURED_TRAFFIC = {
     "mixed": ("b66acdbf", 126.6e6),
 }
 KERNEL_SOURCES = {
-    "fp64": ["operator.hip", "operator.h", "pair_math.h", "fastmath.h"],
+    "fp64": ["operator.hip", "operator.h", "symmetric.hip", "symmetric.h", "pair_math.h",
+             "fastmath.h"],
     "mixed": ["operator.hip", "operator.h", "pair_math.h", "fastmath.h", "mixed.hip"],
 }
 
@@ -281,7 +281,8 @@ def main():
     peak = PEAK_FP64_VECTOR_TFLOPS if args.precision == "fp64" else PEAK_FP32_VECTOR_TFLOPS
     pairs = float(applies) * M * M
     avg_pair_ms = pair_ms / max(n_launch, 1)
-    achieved_tflops = FLOPS_PER_PAIR * float(M) * M / (avg_pair_ms * 1e-3) / 1e12
+    _, pair_flops = prob.pair_work()
+    achieved_tflops = pair_flops / (avg_pair_ms * 1e-3) / 1e12
     digest, measured = MEASURED_TRAFFIC[args.precision]
     traffic = measured if (args.workload == "kirkwood"
                            and kernel_digest(args.precision) == digest) else None
@@ -309,6 +310,7 @@ def main():
         "applies_per_solve": applies / args.steps,
         "pair_kernel_ms": avg_pair_ms,
         "pair_kernel_pairs_per_s": float(M) * M / (avg_pair_ms * 1e-3),
+        "pair_kernel_flops_per_launch": pair_flops,
         "setup_s": setup_s,
         "g_pol": G,
         "roofline": {

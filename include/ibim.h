@@ -187,6 +187,17 @@ int ibim_energy(ibim_ctx* ctx, const double* x, double* g_pol, void* stream);
 int ibim_pair_timing(ibim_ctx* ctx, int enable);
 int ibim_pair_timing_read(ibim_ctx* ctx, int64_t* launches, double* total_ms);
 
+/*
+ * Work of one dense pair-sum launch as this context performs it (device
+ * contexts only): *pairs = M^2 ordered (target, source) pairs; *flops = the
+ * floating-point operations of the pair formulas (FMA counted as 2, exp and
+ * rsqrt not counted): 60 per ordered pair when each pair is evaluated on its
+ * own, 68 per unordered pair when both directions share one evaluation (the
+ * symmetric float64 kernel; tile pairs holding corrected pairs and the
+ * diagonal tiles are still evaluated one direction at a time).
+ */
+int ibim_pair_work(const ibim_ctx* ctx, double* pairs, double* flops);
+
 /* ------------------------------------------------------------------------ */
 /*
  * Solve server: continuous batching of many independent problems on one GPU.

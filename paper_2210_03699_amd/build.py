@@ -16,7 +16,8 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libibim.so")
 
-HIP_SOURCES = ["weights.hip", "operator.hip", "mixed.hip", "krylov.hip", "capi.hip", "server.hip"]
+HIP_SOURCES = ["weights.hip", "operator.hip", "symmetric.hip", "mixed.hip", "krylov.hip", "capi.hip",
+               "server.hip"]
 # The mixed-precision file needs bit-reproducible float32 evaluations in two
 # kernels: no automatic contraction there (its fused multiply-adds are explicit).
 PER_FILE_FLAGS = {"mixed.hip": ["-ffp-contract=off"]}

@@ -146,6 +146,11 @@ int apply_impl(ibim_ctx* c, const double* u, double* out, hipStream_t s) {
   }
   if (prec == IBIM_MIXED)
     HIP_TRY(launch_pair_mixed(c->P, c->pair, u, c->partial, s), "pair kernel launch");
+  else if (c->sym.enabled)
+    HIP_TRY(launch_pair_sym(make_sym_args(c->P, c->sym, c->d_sym_items, c->d_careful, u,
+                                          c->sym_scratch),
+                            c->n_sym_items, s),
+            "pair kernel launch");
   else
     HIP_TRY(launch_pair(c->P, c->pair, prec, u, c->partial, s), "pair kernel launch");
   if (c->timing) {
@@ -154,6 +159,8 @@ int apply_impl(ibim_ctx* c, const double* u, double* out, hipStream_t s) {
   }
   if (prec == IBIM_MIXED)
     HIP_TRY(launch_finish_mixed(c->P, c->pair, u, c->partial, out, s), "finish kernel launch");
+  else if (c->sym.enabled)
+    HIP_TRY(launch_finish_sym(c->P, c->sym, u, c->sym_scratch, out, s), "finish kernel launch");
   else
     HIP_TRY(launch_finish(c->P, c->pair, prec, u, c->partial, out, s), "finish kernel launch");
   ++c->applies;
@@ -235,7 +242,14 @@ size_t ctx_footprint_estimate(const ibim_ctx* c) {
   // tiles (at most one entry per corrected pair), split partial sums
   size_t b = 7 * M * 8 + (M + 1) * 4 + nnz * (4 + 6 * 8);
   b += (ntile + 1) * 4 + std::min(nnz, ntile * ntile) * 4;
-  b += (size_t)pp.nsplit * n * 8 + (4 * nc + (nc > 0 ? nc : 1)) * 8;
+  b += (4 * nc + (nc > 0 ? nc : 1)) * 8;
+  const SymPlan sp = c->opt.precision == IBIM_FP64 ? make_sym_plan((int32_t)M, kSymScratchMax)
+                                                   : SymPlan{};
+  if (sp.enabled)
+    b += sp.scratch_doubles * 8 + ((size_t)sp.nRB * sp.nCB * 2 + 2) * 4 +
+         (((size_t)sp.T * sp.T + 31) / 32) * 4;
+  else
+    b += (size_t)pp.nsplit * n * 8;
   // Krylov basis and GMRES scratch (as allocated by ensure_krylov)
   b += ((m + 3) * n + (m + 1) * (m + 1030) + 8 * m) * 8;
   if (c->opt.precision == IBIM_MIXED) {
@@ -379,10 +393,38 @@ int ctx_setup_device(ibim_ctx* c, hipStream_t s) {
     bytes += ((size_t)M + 1) * 8 + (size_t)P.nnear * 4;
   }
   c->pair = make_pair_plan(M, o.precision);
-  e = dalloc(&c->partial, (size_t)c->pair.nsplit * 2 * (size_t)M);
+  c->sym = o.precision == IBIM_FP64 ? make_sym_plan(M, kSymScratchMax) : SymPlan{};
+  if (c->sym.enabled) {
+    std::vector<int32_t> items;
+    sym_items(c->sym, &items);
+    std::vector<uint32_t> bits;
+    sym_careful_bits(c->sym.T, xrow, xtile, &bits);
+    c->n_sym_items = (int)(items.size() / 2);
+    // flops: 68 per shared evaluation, 60 per one-way pair (diagonal, careful, ragged)
+    const int T = c->sym.T;
+    auto nodes = [&](int X) { return (double)std::min(kPairTile, M - X * kPairTile); };
+    double fl = 0.0;
+    for (int I = 0; I < T; ++I) {
+      fl += 60.0 * nodes(I) * nodes(I);
+      for (int J = I + 1; J < T; ++J) {
+        const size_t bI = (size_t)I * T + J;
+        const bool slow = ((bits[bI >> 5] >> (bI & 31)) & 1u) || (J == T - 1 && M % kPairTile);
+        fl += slow ? 120.0 * nodes(I) * nodes(J) : 68.0 * nodes(I) * nodes(J);
+      }
+    }
+    c->pair_flops = fl;
+    UP(c->d_sym_items, items);
+    UP(c->d_careful, bits);
+    e = dalloc(&c->sym_scratch, c->sym.scratch_doubles);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // items, bits are host temporaries
+    bytes += c->sym.scratch_doubles * 8;
+  } else {
+    c->pair_flops = 60.0 * (double)M * (double)M;
+    e = dalloc(&c->partial, (size_t)c->pair.nsplit * 2 * (size_t)M);
+    bytes += (size_t)c->pair.nsplit * 2 * (size_t)M * 8;
+  }
   if (e == hipSuccess) e = dalloc(&c->d_psi, (size_t)(n_charges > 0 ? n_charges : 1));
   if (e != hipSuccess) return bad(e, "setup");
-  bytes += (size_t)c->pair.nsplit * 2 * (size_t)M * 8;
   c->device_bytes = bytes;
   return IBIM_OK;
 }
@@ -679,6 +721,14 @@ int ibim_pair_timing(ibim_ctx* ctx, int enable) {
   if (int r = check_dev(ctx)) return r;
   ctx->timing = enable != 0;
   if (enable) ctx->tcount = 0;
+  return IBIM_OK;
+}
+
+int ibim_pair_work(const ibim_ctx* ctx, double* pairs, double* flops) {
+  if (int r = check_dev(ctx)) return r;
+  if (!pairs || !flops) return fail(IBIM_EINVAL, "NULL output");
+  *pairs = (double)ctx->P.M * (double)ctx->P.M;
+  *flops = ctx->pair_flops;
   return IBIM_OK;
 }
 

@@ -11,6 +11,7 @@
 #include "ibim_internal.h"
 #include "krylov.h"
 #include "operator.h"
+#include "symmetric.h"
 
 namespace ibim {
 
@@ -66,6 +67,7 @@ using ibim::DeviceScope;
 using ibim::HostPlan;
 using ibim::Krylov;
 using ibim::PairPlan;
+using ibim::SymPlan;
 using ibim::dfree;
 
 struct ibim_ctx {
@@ -76,7 +78,14 @@ struct ibim_ctx {
   // device state
   DeviceProblem P;
   PairPlan pair;
-  double* partial = nullptr;  // nsplit * 2M
+  double* partial = nullptr;  // nsplit * 2M (one-directional kernels)
+  // symmetric float64 pair sum (used when sym.enabled)
+  SymPlan sym;
+  int32_t* d_sym_items = nullptr;  // (rb, cb) pairs
+  int n_sym_items = 0;
+  uint32_t* d_careful = nullptr;   // T x T bits
+  double* sym_scratch = nullptr;   // sym.scratch_doubles
+  double pair_flops = 0.0;         // flops of one pair-sum launch (see ibim_pair_work)
   double* om11 = nullptr;
   double* om21 = nullptr;
   double* d_zq = nullptr;
@@ -102,6 +111,7 @@ struct ibim_ctx {
     dfree(P.px32); dfree(P.py32); dfree(P.pz32); dfree(P.nx32); dfree(P.ny32); dfree(P.nz32);
     dfree(P.crow); dfree(P.ccol); dfree(P.blocks); dfree(P.nrow); dfree(P.ncol);
     dfree(P.xrow); dfree(P.xtile);
+    dfree(d_sym_items); dfree(d_careful); dfree(sym_scratch);
     dfree(partial); dfree(om11); dfree(om21); dfree(d_zq); dfree(d_q); dfree(d_psi);
     dfree(kr.V); dfree(kr.H); dfree(kr.cs); dfree(kr.sn); dfree(kr.g); dfree(kr.y);
     dfree(kr.hcol); dfree(kr.hcol2); dfree(kr.scal); dfree(kr.status); dfree(kr.partial);

@@ -88,7 +88,15 @@ struct ibim_server {
   int32_t* d_items = nullptr;
   int32_t* h_items = nullptr;
   size_t items_cap = 0;
-  int* d_counter = nullptr;
+  // problems on the symmetric float64 kernel and their (problem, item) list
+  SymArgs* d_sargs = nullptr;
+  SymArgs* h_sargs = nullptr;
+  size_t sargs_cap = 0;
+  int32_t* d_swork = nullptr;
+  int32_t* h_swork = nullptr;
+  size_t swork_cap = 0;
+  int sym_grid = 0;
+  int* d_counter = nullptr;  // two counters: one-directional and symmetric launches
   double* d_status = nullptr;  // 8 doubles per slot
   double* h_status = nullptr;  // pinned
   // background host setup
@@ -104,8 +112,8 @@ namespace {
 
 constexpr int kStatusStride = 8;  // per slot: |g_{j+1}|, H(j+1,j), ||b||^2, ||r||^2
 
-__global__ void zero_int_kernel(int* p) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+__global__ void zero_ints_kernel(int* p, int n) {
+  if (blockIdx.x == 0 && (int)threadIdx.x < n) p[threadIdx.x] = 0;
 }
 
 void worker_main(ibim_server* srv) {
@@ -218,27 +226,18 @@ int finish_request(ibim_server* srv, Request* r) {
   return IBIM_OK;
 }
 
-int ensure_capacity(ibim_server* srv, size_t nargs, size_t nitems) {
-  if (nargs > srv->args_cap) {
-    dfree(srv->d_args);
-    if (srv->h_args) (void)hipHostFree(srv->h_args);
-    srv->h_args = nullptr;
-    size_t cap = nargs * 2;
-    HIP_TRY(dalloc(&srv->d_args, cap), "alloc");
-    HIP_TRY(hipHostMalloc((void**)&srv->h_args, cap * sizeof(PairArgs), hipHostMallocDefault),
-            "pinned allocation");
-    srv->args_cap = cap;
-  }
-  if (3 * nitems > srv->items_cap) {
-    dfree(srv->d_items);
-    if (srv->h_items) (void)hipHostFree(srv->h_items);
-    srv->h_items = nullptr;
-    size_t cap = 6 * nitems;
-    HIP_TRY(dalloc(&srv->d_items, cap), "alloc");
-    HIP_TRY(hipHostMalloc((void**)&srv->h_items, cap * sizeof(int32_t), hipHostMallocDefault),
-            "pinned allocation");
-    srv->items_cap = cap;
-  }
+// Grows a device array and its pinned host staging copy to hold n elements.
+template <class T>
+int ensure_staging(T** d, T** h, size_t* cap, size_t n) {
+  if (n <= *cap) return IBIM_OK;
+  dfree(*d);
+  if (*h) (void)hipHostFree(*h);
+  *h = nullptr;
+  *cap = 0;
+  const size_t c = 2 * n;
+  HIP_TRY(dalloc(d, c), "alloc");
+  HIP_TRY(hipHostMalloc((void**)h, c * sizeof(T), hipHostMallocDefault), "pinned allocation");
+  *cap = c;
   return IBIM_OK;
 }
 
@@ -292,39 +291,75 @@ int step_impl(ibim_server* srv) {
   }
   if (srv->active.empty()) return IBIM_OK;
 
-  // 2. one batched pair launch over every active request
-  size_t nitems = 0;
-  for (Request* r : srv->active)
-    nitems += (size_t)r->ctx->pair.ntile * (size_t)r->ctx->pair.nsplit;
-  if (int e = ensure_capacity(srv, srv->active.size(), nitems)) return e;
-  size_t it = 0;
-  for (size_t i = 0; i < srv->active.size(); ++i) {
-    Request* r = srv->active[i];
+  // 2. batched pair launches over every active request: one for the problems
+  // on the one-directional kernels, one for those on the symmetric kernel
+  size_t nargs = 0, nitems = 0, nsargs = 0, nswork = 0;
+  for (Request* r : srv->active) {
+    const ibim_ctx* c = r->ctx;
+    if (c->sym.enabled) {
+      ++nsargs;
+      nswork += (size_t)c->n_sym_items;
+    } else {
+      ++nargs;
+      nitems += (size_t)c->pair.ntile * (size_t)c->pair.nsplit;
+    }
+  }
+  if (int e = ensure_staging(&srv->d_args, &srv->h_args, &srv->args_cap, nargs)) return e;
+  if (int e = ensure_staging(&srv->d_items, &srv->h_items, &srv->items_cap, 3 * nitems)) return e;
+  if (int e = ensure_staging(&srv->d_sargs, &srv->h_sargs, &srv->sargs_cap, nsargs)) return e;
+  if (int e = ensure_staging(&srv->d_swork, &srv->h_swork, &srv->swork_cap, 2 * nswork)) return e;
+  size_t ia = 0, it = 0, isa = 0, isw = 0;
+  for (Request* r : srv->active) {
     ibim_ctx* c = r->ctx;
     const int64_t N = c->kr.n;
     const double* u = r->phase == Phase::kIter ? c->kr.V + (int64_t)r->j * N : r->d_x;
-    srv->h_args[i] = make_pair_args(c->P, c->pair, u, c->partial);
-    for (int t = 0; t < c->pair.ntile; ++t)
-      for (int sp = 0; sp < c->pair.nsplit; ++sp) {
-        srv->h_items[3 * it] = (int32_t)i;
-        srv->h_items[3 * it + 1] = t;
-        srv->h_items[3 * it + 2] = sp;
-        ++it;
+    if (c->sym.enabled) {
+      srv->h_sargs[isa] =
+          make_sym_args(c->P, c->sym, c->d_sym_items, c->d_careful, u, c->sym_scratch);
+      for (int q = 0; q < c->n_sym_items; ++q) {
+        srv->h_swork[2 * isw] = (int32_t)isa;
+        srv->h_swork[2 * isw + 1] = q;
+        ++isw;
       }
+      ++isa;
+    } else {
+      srv->h_args[ia] = make_pair_args(c->P, c->pair, u, c->partial);
+      for (int t = 0; t < c->pair.ntile; ++t)
+        for (int sp = 0; sp < c->pair.nsplit; ++sp) {
+          srv->h_items[3 * it] = (int32_t)ia;
+          srv->h_items[3 * it + 1] = t;
+          srv->h_items[3 * it + 2] = sp;
+          ++it;
+        }
+      ++ia;
+    }
   }
-  HIP_TRY(hipMemcpyAsync(srv->d_args, srv->h_args, srv->active.size() * sizeof(PairArgs),
-                         hipMemcpyHostToDevice, s),
-          "copy");
-  HIP_TRY(hipMemcpyAsync(srv->d_items, srv->h_items, 3 * nitems * sizeof(int32_t),
-                         hipMemcpyHostToDevice, s),
-          "copy");
-  hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, s, srv->d_counter);
+  hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, s, srv->d_counter, 2);
   HIP_TRY(hipGetLastError(), "zero");
-  HIP_TRY(launch_pair_batched(srv->opt.precision, srv->d_args, srv->d_items, (int)nitems,
-                              srv->d_counter, srv->grid, s),
-          "batched pair launch");
+  if (nitems > 0) {
+    HIP_TRY(hipMemcpyAsync(srv->d_args, srv->h_args, nargs * sizeof(PairArgs),
+                           hipMemcpyHostToDevice, s),
+            "copy");
+    HIP_TRY(hipMemcpyAsync(srv->d_items, srv->h_items, 3 * nitems * sizeof(int32_t),
+                           hipMemcpyHostToDevice, s),
+            "copy");
+    HIP_TRY(launch_pair_batched(srv->opt.precision, srv->d_args, srv->d_items, (int)nitems,
+                                srv->d_counter, srv->grid, s),
+            "batched pair launch");
+  }
+  if (nswork > 0) {
+    HIP_TRY(hipMemcpyAsync(srv->d_sargs, srv->h_sargs, nsargs * sizeof(SymArgs),
+                           hipMemcpyHostToDevice, s),
+            "copy");
+    HIP_TRY(hipMemcpyAsync(srv->d_swork, srv->h_swork, 2 * nswork * sizeof(int32_t),
+                           hipMemcpyHostToDevice, s),
+            "copy");
+    HIP_TRY(launch_pair_sym_batched(srv->d_sargs, srv->d_swork, (int)nswork, srv->d_counter + 1,
+                                    srv->sym_grid, s),
+            "batched symmetric pair launch");
+  }
   srv->st.rounds++;
-  srv->st.batched_items += (int64_t)nitems;
+  srv->st.batched_items += (int64_t)(nitems + nswork);
 
   // 3. per request: correction, then one GMRES or residual step
   for (Request* r : srv->active) {
@@ -336,6 +371,8 @@ int step_impl(ibim_server* srv) {
     double* out = r->phase == Phase::kIter ? K.V + (int64_t)(r->j + 1) * N : K.tmp2;
     if (c->opt.precision == IBIM_MIXED)
       HIP_TRY(launch_finish_mixed(c->P, c->pair, u, c->partial, out, s), "finish");
+    else if (c->sym.enabled)
+      HIP_TRY(launch_finish_sym(c->P, c->sym, u, c->sym_scratch, out, s), "finish");
     else
       HIP_TRY(launch_finish(c->P, c->pair, c->opt.precision, u, c->partial, out, s), "finish");
     r->applies++;
@@ -470,7 +507,8 @@ int ibim_server_create(const ibim_options* opt, size_t hbm_budget_bytes, int max
   {
     DeviceScope ds(o.device);
     srv->grid = pair_batched_grid(o.precision);
-    hipError_t e = dalloc(&srv->d_counter, 1);
+    srv->sym_grid = pair_sym_batched_grid();
+    hipError_t e = dalloc(&srv->d_counter, 2);
     if (e == hipSuccess) e = dalloc(&srv->d_status, (size_t)max_slots * kStatusStride);
     if (e == hipSuccess)
       e = hipHostMalloc((void**)&srv->h_status, (size_t)max_slots * kStatusStride * sizeof(double),
@@ -596,6 +634,10 @@ void ibim_server_destroy(ibim_server* srv) {
   }
   dfree(srv->d_args);
   dfree(srv->d_items);
+  dfree(srv->d_sargs);
+  dfree(srv->d_swork);
+  if (srv->h_sargs) (void)hipHostFree(srv->h_sargs);
+  if (srv->h_swork) (void)hipHostFree(srv->h_swork);
   dfree(srv->d_counter);
   dfree(srv->d_status);
   if (srv->h_args) (void)hipHostFree(srv->h_args);

@@ -1,0 +1,64 @@
+// Symmetric (both directions per evaluation) float64 pair sum.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "operator.h"
+
+namespace ibim {
+
+constexpr int kSymRows = 4;  // row tiles per work item
+// Largest row-and-column scratch of the symmetric kernel; larger problems use
+// the one-directional kernel, whose scratch grows only linearly.
+constexpr size_t kSymScratchMax = size_t(4) << 30;
+
+// Decomposition of the upper triangle of tile pairs into work items.
+struct SymPlan {
+  bool enabled = false;
+  int T = 0;    // tiles of 256 nodes
+  int b = 0;    // column tiles per item
+  int nRB = 0;  // row blocks (kSymRows tiles each)
+  int nCB = 0;  // column blocks
+  size_t scratch_doubles = 0;  // row sums (nCB x T) + column sums (nRB x T), 512 doubles each
+};
+
+struct SymArgs {
+  const double *px, *py, *pz, *nx, *ny, *nz, *w;
+  const double* u;
+  const int32_t* crow;
+  const int32_t* ccol;
+  const uint32_t* careful;  // bit I*T + J: tile pair (I, J) holds a pair of N_k (either way)
+  const int2* items;        // (row block, column block), larger items first
+  int32_t M;
+  int T;
+  int b;
+  double c1, c2, kappa;
+  double scale;       // h^3 / (4 pi)
+  double* rowpart;    // [nCB][T][2][256]
+  double* colpart;    // [nRB][T][2][256]
+};
+
+// Plan for M nodes; disabled when the scratch would exceed max_scratch_bytes
+// (the one-directional kernel is used then).
+SymPlan make_sym_plan(int32_t M, size_t max_scratch_bytes);
+// Work items as (rb, cb) pairs, larger first.
+void sym_items(const SymPlan& pl, std::vector<int32_t>* items);
+// Bit matrix of tile pairs that need the exclusion-aware evaluation.
+void sym_careful_bits(int T, const std::vector<int32_t>& xrow, const std::vector<int32_t>& xtile,
+                      std::vector<uint32_t>* bits);
+
+// Arguments for problem P with input u; scratch holds plan.scratch_doubles.
+SymArgs make_sym_args(const DeviceProblem& P, const SymPlan& pl, const int32_t* items,
+                      const uint32_t* careful, const double* u, double* scratch);
+hipError_t launch_pair_sym(const SymArgs& a, int n_items, hipStream_t stream);
+// One persistent launch over several problems: work holds (problem, item) int32 pairs.
+hipError_t launch_pair_sym_batched(const SymArgs* probs, const int32_t* work, int n_work,
+                                   int* counter, int grid, hipStream_t stream);
+int pair_sym_batched_grid();
+hipError_t launch_finish_sym(const DeviceProblem& P, const SymPlan& pl, const double* u,
+                             const double* scratch, double* out, hipStream_t stream);
+
+}  // namespace ibim

@@ -106,6 +106,7 @@ def load():
     lib.ibim_energy.argtypes = [_VP, _VP, _D, _VP]
     lib.ibim_pair_timing.argtypes = [_VP, ctypes.c_int]
     lib.ibim_pair_timing_read.argtypes = [_VP, _I64, _D]
+    lib.ibim_pair_work.argtypes = [_VP, _D, _D]
     lib.ibim_server_create.argtypes = [ctypes.POINTER(_Options), ctypes.c_size_t, ctypes.c_int,
                                        ctypes.c_int, _VP, ctypes.POINTER(_VP)]
     lib.ibim_server_submit.argtypes = [_VP, _D, ctypes.c_int, ctypes.c_int, ctypes.c_int, _D,
@@ -282,6 +283,13 @@ class Problem:
         ms = ctypes.c_double()
         _check(self._lib.ibim_pair_timing_read(self._ctx, ctypes.byref(n), ctypes.byref(ms)))
         return int(n.value), float(ms.value)
+
+    def pair_work(self):
+        """(ordered pairs, flops) of one dense pair-sum launch (``ibim_pair_work``)."""
+        p = ctypes.c_double()
+        f = ctypes.c_double()
+        _check(self._lib.ibim_pair_work(self._ctx, ctypes.byref(p), ctypes.byref(f)))
+        return float(p.value), float(f.value)
 
     def solve_energy(self, tol, stream=None):
         g = self.rhs(stream=stream)
