@@ -111,19 +111,20 @@ __global__ __launch_bounds__(kThreads) void pair_fp64_kernel(PairArgs a) {
   pair_chunk_fp64(a, split, tile, src);
 }
 
-__global__ __launch_bounds__(kThreads) void pair_batched_fp64_kernel(const PairArgs* reqs,
-                                                                     const int32_t* items,
-                                                                     int n_items, int* counter) {
+__global__ __launch_bounds__(kThreads) void pair_batched_fp64_kernel(
+    const PairArgs* __restrict__ reqs, const int32_t* __restrict__ items, int n_items,
+    int* counter) {
   __shared__ double2 src[kTile * 4];
   __shared__ int next;
   for (;;) {
     if (threadIdx.x == 0) next = atomicAdd(counter, 1);
     __syncthreads();
-    const int it = next;
+    const int it = __builtin_amdgcn_readfirstlane(next);
     __syncthreads();  // everyone has read `next` before it is overwritten
     if (it >= n_items) break;
-    const PairArgs a = reqs[items[3 * it]];
-    pair_chunk_fp64(a, items[3 * it + 2], items[3 * it + 1], src);
+    const PairArgs a = reqs[__builtin_amdgcn_readfirstlane(items[3 * it])];
+    pair_chunk_fp64(a, __builtin_amdgcn_readfirstlane(items[3 * it + 2]),
+                    __builtin_amdgcn_readfirstlane(items[3 * it + 1]), src);
   }
 }
 

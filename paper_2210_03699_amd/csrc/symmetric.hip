@@ -80,6 +80,11 @@ __device__ __forceinline__ void one_way(const SymArgs& a, int X, int Y, const Sr
   }
 }
 
+// Element of a shared double2 array at a byte offset.
+__device__ __forceinline__ double2* lds_at(double2* base, unsigned byte_off) {
+  return reinterpret_cast<double2*>(reinterpret_cast<char*>(base) + byte_off);
+}
+
 __device__ __forceinline__ bool careful_pair(const SymArgs& a, int I, int J) {
   const int64_t bit = (int64_t)I * a.T + J;
   return (a.careful[bit >> 5] >> (bit & 31)) & 1u;
@@ -87,7 +92,7 @@ __device__ __forceinline__ bool careful_pair(const SymArgs& a, int I, int J) {
 
 struct SymShared {
   double2 sA[kT], sB[kT], sC[kT], sD[kT];  // records of J: (px,py) (pz,nx) (ny,nz) (a1,a2)
-  double cacc1[kT], cacc2[kT];             // column sums of J
+  double2 cacc[kT];                        // column sums of J (row 1, row 2)
   double racc1[kRows][kT], racc2[kRows][kT];  // row sums, lane-private slots
 };
 
@@ -97,8 +102,7 @@ __device__ void sym_item(const SymArgs& a, int rb, int cb, SymShared& sh) {
   double2* const sB = sh.sB;
   double2* const sC = sh.sC;
   double2* const sD = sh.sD;
-  double* const cacc1 = sh.cacc1;
-  double* const cacc2 = sh.cacc2;
+  double2* const cacc = sh.cacc;
   auto& racc1 = sh.racc1;
   auto& racc2 = sh.racc2;
   const int tid = threadIdx.x;
@@ -121,8 +125,7 @@ __device__ void sym_item(const SymArgs& a, int rb, int cb, SymShared& sh) {
         sC[tid] = make_double2(r.ny, r.nz);
         sD[tid] = make_double2(r.a1, r.a2);
       }
-      cacc1[tid] = 0.0;
-      cacc2[tid] = 0.0;
+      cacc[tid] = make_double2(0.0, 0.0);
     }
     __syncthreads();
     for (int i = 0; i < kRows; ++i) {
@@ -142,8 +145,8 @@ __device__ void sym_item(const SymArgs& a, int rb, int cb, SymShared& sh) {
           // row J from the sources of I (uniform global loads)
           double c1 = 0.0, c2 = 0.0;
           one_way(a, J, I, [&](int j) { return load_rec(a, I * kT + j); }, c1, c2);
-          cacc1[tid] += c1;
-          cacc2[tid] += c2;
+          cacc[tid].x += c1;
+          cacc[tid].y += c2;
         }
         __syncthreads();
         continue;
@@ -151,11 +154,15 @@ __device__ void sym_item(const SymArgs& a, int rb, int cb, SymShared& sh) {
       const int32_t k = I * kT + tid;
       const Rec f = load_rec(a, k);
       for (int ph = 0; ph < 4; ++ph) {
-        const int sb = ((wv + ph) & 3) * 64;
+        // byte offsets into the double2 arrays: sub-block base | ((l + s) mod 64) * 16
+        const unsigned sb16 = (unsigned)(((wv + ph) & 3) * 64) << 4;
+        unsigned x16 = (unsigned)l << 4;
 #pragma unroll 2
         for (int s = 0; s < 64; ++s) {
-          const int slot = sb + ((l + s) & 63);
-          const double2 q0 = sA[slot], q1 = sB[slot], q2 = sC[slot], q3 = sD[slot];
+          const unsigned off = (x16 & 1008u) | sb16;
+          x16 += 16u;
+          const double2 q0 = *lds_at(sA, off), q1 = *lds_at(sB, off);
+          const double2 q2 = *lds_at(sC, off), q3 = *lds_at(sD, off);
           // r = x_k - P_m
           const double rx = f.px - q0.x, ry = f.py - q0.y, rz = f.pz - q1.x;
           const double R2s = fma(rz, rz, fma(ry, ry, rx * rx));
@@ -169,24 +176,24 @@ __device__ void sym_item(const SymArgs& a, int rb, int cb, SymShared& sh) {
           const double rny = fma(rz, q2.y, fma(ry, q2.x, rx * q1.y));  // r . n_m
           const double rnx = fma(rz, f.nz, fma(ry, f.ny, rx * f.nx));  // r . n_k
           const double nn = fma(f.nz, q2.y, fma(f.ny, q2.x, f.nx * q1.y));
-          const double f1 = fma(-pc.c1, te, 1.0);
-          const double f2 = fma(-pc.c2, te, 1.0);
-          const double g12 = (1.0 - e) * R2s;
+          // kernel factors with 1/R^3 folded in
+          const double f1 = fma(-pc.c1, te, 1.0) * iR3;
+          const double f2 = fma(-pc.c2, te, 1.0) * iR3;
+          const double g12 = (1.0 - e) * iR;
           const double phi2 = 1.0 - te;
           const double q = rnx * rny;
-          const double g21 = fma(phi2, fma(q * iR2, -3.0, nn), pc.kappa2 * e * q);
+          const double g21 = fma(phi2, fma(q * iR2, -3.0, nn), pc.kappa2 * e * q) * iR3;
           // k <- m
-          const double A1 = q3.x * iR3, A2 = q3.y * iR3;
           const double g11 = rny * f1, g22 = rnx * f2;
-          S1 = fma(g11, A1, fma(-g12, A2, S1));
-          S2 = fma(g21, A1, fma(g22, A2, S2));
+          S1 = fma(g11, q3.x, fma(-g12, q3.y, S1));
+          S2 = fma(g21, q3.x, fma(g22, q3.y, S2));
           // m <- k: r.n_k and r.n_m swap roles with a sign change
-          const double B1 = f.a1 * iR3, B2 = f.a2 * iR3;
           const double h11 = -rnx * f1, h22 = -rny * f2;
-          const double C1 = fma(h11, B1, -g12 * B2);
-          const double C2 = fma(g21, B1, h22 * B2);
-          atomicAdd(&cacc1[slot], C1);
-          atomicAdd(&cacc2[slot], C2);
+          const double C1 = fma(h11, f.a1, -g12 * f.a2);
+          const double C2 = fma(g21, f.a1, h22 * f.a2);
+          double2* c = lds_at(cacc, off);
+          atomicAdd(&c->x, C1);
+          atomicAdd(&c->y, C2);
         }
         __syncthreads();
       }
@@ -195,8 +202,8 @@ __device__ void sym_item(const SymArgs& a, int rb, int cb, SymShared& sh) {
     }
     // column sums of J
     double* cp = a.colpart + ((size_t)rb * T + J) * (2 * kT);
-    cp[tid] = a.scale * cacc1[tid];
-    cp[kT + tid] = a.scale * cacc2[tid];
+    cp[tid] = a.scale * cacc[tid].x;
+    cp[kT + tid] = a.scale * cacc[tid].y;
     __syncthreads();  // LDS is refilled for the next column tile
   }
   // row sums of this item's row tiles that met at least one J >= I
@@ -217,20 +224,23 @@ __global__ __launch_bounds__(256) void pair_sym_fp64_kernel(SymArgs a) {
 
 // Persistent form over the items of several problems: entry i of `work` is
 // (problem, item index); workgroups take entries from *counter (initially 0).
-__global__ __launch_bounds__(256) void pair_sym_batched_kernel(const SymArgs* probs,
-                                                               const int32_t* work, int n_work,
-                                                               int* counter) {
+__global__ __launch_bounds__(256, 4) void pair_sym_batched_kernel(
+    const SymArgs* __restrict__ probs, const int32_t* __restrict__ work, int n_work,
+    int* counter) {
   __shared__ SymShared sh;
   __shared__ int next;
   for (;;) {
     if (threadIdx.x == 0) next = atomicAdd(counter, 1);
     __syncthreads();
-    const int it = next;
+    // the item index is uniform: keep it (and so the argument record) scalar
+    const int it = __builtin_amdgcn_readfirstlane(next);
     __syncthreads();  // every thread has read `next` before it is overwritten
     if (it >= n_work) break;
-    const SymArgs& a = probs[work[2 * it]];
-    const int2 item = a.items[work[2 * it + 1]];
-    sym_item(a, item.x, item.y, sh);
+    const int pi = __builtin_amdgcn_readfirstlane(work[2 * it]);
+    const int ii = __builtin_amdgcn_readfirstlane(work[2 * it + 1]);
+    const SymArgs a = probs[pi];
+    const int2 item = a.items[ii];
+    sym_item(a, __builtin_amdgcn_readfirstlane(item.x), __builtin_amdgcn_readfirstlane(item.y), sh);
     __syncthreads();  // LDS is reused by the next item
   }
 }
