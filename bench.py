@@ -41,9 +41,10 @@ MEASURED_TRAFFIC = {
     "mixed": ("b66acdbf", 126.6e6),
 }
 KERNEL_SOURCES = {
-    "fp64": ["operator.hip", "operator.h", "symmetric.hip", "symmetric.h", "pair_math.h",
+    "fp64": ["operator.h", "symmetric.hip", "symmetric.h", "sym_core.h", "pair_math.h",
              "fastmath.h"],
-    "mixed": ["operator.hip", "operator.h", "pair_math.h", "fastmath.h", "mixed.hip"],
+    "mixed": ["operator.h", "symmetric_mixed.hip", "symmetric.h", "sym_core.h", "pair_math.h",
+              "fastmath.h"],
 }
 
 

@@ -193,8 +193,9 @@ int ibim_pair_timing_read(ibim_ctx* ctx, int64_t* launches, double* total_ms);
  * floating-point operations of the pair formulas (FMA counted as 2, exp and
  * rsqrt not counted): 60 per ordered pair when each pair is evaluated on its
  * own, 68 per unordered pair when both directions share one evaluation (the
- * symmetric float64 kernel; tile pairs holding corrected pairs and the
- * diagonal tiles are still evaluated one direction at a time).
+ * symmetric kernels; tile pairs holding corrected pairs and the diagonal
+ * tiles are still evaluated one direction at a time).  In the mixed form
+ * these are float32 operations.
  */
 int ibim_pair_work(const ibim_ctx* ctx, double* pairs, double* flops);
 

@@ -16,11 +16,12 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libibim.so")
 
-HIP_SOURCES = ["weights.hip", "operator.hip", "symmetric.hip", "mixed.hip", "krylov.hip", "capi.hip",
-               "server.hip"]
-# The mixed-precision file needs bit-reproducible float32 evaluations in two
-# kernels: no automatic contraction there (its fused multiply-adds are explicit).
-PER_FILE_FLAGS = {"mixed.hip": ["-ffp-contract=off"]}
+HIP_SOURCES = ["weights.hip", "operator.hip", "symmetric.hip", "symmetric_mixed.hip", "mixed.hip",
+               "krylov.hip", "capi.hip", "server.hip"]
+# The mixed-precision files need bit-reproducible float32 evaluations in the
+# pair and finishing kernels: no automatic contraction there (their fused
+# multiply-adds are explicit).
+PER_FILE_FLAGS = {"mixed.hip": ["-ffp-contract=off"], "symmetric_mixed.hip": ["-ffp-contract=off"]}
 HOST_SOURCES = ["setup_host.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -144,23 +144,28 @@ int apply_impl(ibim_ctx* c, const double* u, double* out, hipStream_t s) {
     e1 = c->tev[2 * c->tcount + 1];
     HIP_TRY(hipEventRecord(e0, s), "hipEventRecord");
   }
-  if (prec == IBIM_MIXED)
+  if (c->sym.enabled) {
+    const SymArgs sa =
+        make_sym_args(c->P, c->sym, c->d_sym_items, c->d_careful, u, c->sym_scratch);
+    if (prec == IBIM_MIXED)
+      HIP_TRY(launch_pair_sym_mixed(sa, c->n_sym_items, s), "pair kernel launch");
+    else
+      HIP_TRY(launch_pair_sym(sa, c->n_sym_items, s), "pair kernel launch");
+  } else if (prec == IBIM_MIXED)
     HIP_TRY(launch_pair_mixed(c->P, c->pair, u, c->partial, s), "pair kernel launch");
-  else if (c->sym.enabled)
-    HIP_TRY(launch_pair_sym(make_sym_args(c->P, c->sym, c->d_sym_items, c->d_careful, u,
-                                          c->sym_scratch),
-                            c->n_sym_items, s),
-            "pair kernel launch");
   else
     HIP_TRY(launch_pair(c->P, c->pair, prec, u, c->partial, s), "pair kernel launch");
   if (c->timing) {
     HIP_TRY(hipEventRecord(e1, s), "hipEventRecord");
     ++c->tcount;
   }
-  if (prec == IBIM_MIXED)
-    HIP_TRY(launch_finish_mixed(c->P, c->pair, u, c->partial, out, s), "finish kernel launch");
+  if (c->sym.enabled && prec == IBIM_MIXED)
+    HIP_TRY(launch_finish_sym_mixed(c->P, c->sym, c->d_careful, u, c->sym_scratch, out, s),
+            "finish kernel launch");
   else if (c->sym.enabled)
     HIP_TRY(launch_finish_sym(c->P, c->sym, u, c->sym_scratch, out, s), "finish kernel launch");
+  else if (prec == IBIM_MIXED)
+    HIP_TRY(launch_finish_mixed(c->P, c->pair, u, c->partial, out, s), "finish kernel launch");
   else
     HIP_TRY(launch_finish(c->P, c->pair, prec, u, c->partial, out, s), "finish kernel launch");
   ++c->applies;
@@ -243,8 +248,7 @@ size_t ctx_footprint_estimate(const ibim_ctx* c) {
   size_t b = 7 * M * 8 + (M + 1) * 4 + nnz * (4 + 6 * 8);
   b += (ntile + 1) * 4 + std::min(nnz, ntile * ntile) * 4;
   b += (4 * nc + (nc > 0 ? nc : 1)) * 8;
-  const SymPlan sp = c->opt.precision == IBIM_FP64 ? make_sym_plan((int32_t)M, kSymScratchMax)
-                                                   : SymPlan{};
+  const SymPlan sp = make_sym_plan((int32_t)M, kSymScratchMax);
   if (sp.enabled)
     b += sp.scratch_doubles * 8 + ((size_t)sp.nRB * sp.nCB * 2 + 2) * 4 +
          (((size_t)sp.T * sp.T + 31) / 32) * 4;
@@ -393,7 +397,7 @@ int ctx_setup_device(ibim_ctx* c, hipStream_t s) {
     bytes += ((size_t)M + 1) * 8 + (size_t)P.nnear * 4;
   }
   c->pair = make_pair_plan(M, o.precision);
-  c->sym = o.precision == IBIM_FP64 ? make_sym_plan(M, kSymScratchMax) : SymPlan{};
+  c->sym = make_sym_plan(M, kSymScratchMax);
   if (c->sym.enabled) {
     std::vector<int32_t> items;
     sym_items(c->sym, &items);

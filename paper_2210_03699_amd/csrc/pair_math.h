@@ -93,4 +93,40 @@ __device__ __forceinline__ void pair_f32(float x, float y, float z, float nxk, f
   d2 = __fmaf_rn(g21, A1, g22 * A2);
 }
 
+// float32, both directions of one pair for the symmetric kernel: fixed node f
+// (target k) and rotating node m.  (d1, d2): contribution to k from m with
+// m's amplitudes (am1, am2); (c1, c2): contribution to m from k with k's
+// amplitudes (ak1, ak2).  With r' = -r the reverse pair has r'.n_k = -r.n_m
+// and r'.n_m = -r.n_k.  Every operation explicit, as in pair_f32.
+__device__ __forceinline__ void pair_f32_sym(float xk, float yk, float zk, float nxk, float nyk,
+                                             float nzk, float ak1, float ak2, float xm, float ym,
+                                             float zm, float nxm, float nym, float nzm, float am1,
+                                             float am2, const PairConstsF& c, float& d1,
+                                             float& d2, float& c1, float& c2) {
+  const float rx = xk - xm, ry = yk - ym, rz = zk - zm;
+  const float R2 = __fmaf_rn(rz, rz, __fmaf_rn(ry, ry, rx * rx));
+  const float iR = __builtin_amdgcn_rsqf(R2);
+  const float R = R2 * iR;
+  const float iR2 = iR * iR;
+  const float iR3 = iR2 * iR;
+  const float kr = c.kappa * R;
+  const float e = exp_neg_f32(kr);
+  const float te = __fmaf_rn(e, kr, e);
+  const float rny = __fmaf_rn(rz, nzm, __fmaf_rn(ry, nym, rx * nxm));
+  const float rnx = __fmaf_rn(rz, nzk, __fmaf_rn(ry, nyk, rx * nxk));
+  const float nn = __fmaf_rn(nzk, nzm, __fmaf_rn(nyk, nym, nxk * nxm));
+  const float f1 = __fmaf_rn(-c.c1, te, 1.0f) * iR3;
+  const float f2 = __fmaf_rn(-c.c2, te, 1.0f) * iR3;
+  const float g12 = (1.0f - e) * iR;
+  const float phi2 = 1.0f - te;
+  const float q = rnx * rny;
+  const float g21 = __fmaf_rn(phi2, __fmaf_rn(q * iR2, -3.0f, nn), (c.kappa2 * e) * q) * iR3;
+  const float g11 = rny * f1, g22 = rnx * f2;
+  d1 = __fmaf_rn(g11, am1, -(g12 * am2));
+  d2 = __fmaf_rn(g21, am1, g22 * am2);
+  const float h11 = -rnx * f1, h22 = -rny * f2;
+  c1 = __fmaf_rn(h11, ak1, -(g12 * ak2));
+  c2 = __fmaf_rn(g21, ak1, h22 * ak2);
+}
+
 }  // namespace ibim

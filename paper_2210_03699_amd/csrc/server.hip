@@ -354,9 +354,14 @@ int step_impl(ibim_server* srv) {
     HIP_TRY(hipMemcpyAsync(srv->d_swork, srv->h_swork, 2 * nswork * sizeof(int32_t),
                            hipMemcpyHostToDevice, s),
             "copy");
-    HIP_TRY(launch_pair_sym_batched(srv->d_sargs, srv->d_swork, (int)nswork, srv->d_counter + 1,
-                                    srv->sym_grid, s),
-            "batched symmetric pair launch");
+    if (srv->opt.precision == IBIM_MIXED)
+      HIP_TRY(launch_pair_sym_mixed_batched(srv->d_sargs, srv->d_swork, (int)nswork,
+                                            srv->d_counter + 1, srv->sym_grid, s),
+              "batched symmetric pair launch");
+    else
+      HIP_TRY(launch_pair_sym_batched(srv->d_sargs, srv->d_swork, (int)nswork,
+                                      srv->d_counter + 1, srv->sym_grid, s),
+              "batched symmetric pair launch");
   }
   srv->st.rounds++;
   srv->st.batched_items += (int64_t)(nitems + nswork);
@@ -369,10 +374,13 @@ int step_impl(ibim_server* srv) {
     double* st = srv->d_status + (size_t)r->slot * kStatusStride;
     const double* u = r->phase == Phase::kIter ? K.V + (int64_t)r->j * N : r->d_x;
     double* out = r->phase == Phase::kIter ? K.V + (int64_t)(r->j + 1) * N : K.tmp2;
-    if (c->opt.precision == IBIM_MIXED)
-      HIP_TRY(launch_finish_mixed(c->P, c->pair, u, c->partial, out, s), "finish");
+    if (c->sym.enabled && c->opt.precision == IBIM_MIXED)
+      HIP_TRY(launch_finish_sym_mixed(c->P, c->sym, c->d_careful, u, c->sym_scratch, out, s),
+              "finish");
     else if (c->sym.enabled)
       HIP_TRY(launch_finish_sym(c->P, c->sym, u, c->sym_scratch, out, s), "finish");
+    else if (c->opt.precision == IBIM_MIXED)
+      HIP_TRY(launch_finish_mixed(c->P, c->pair, u, c->partial, out, s), "finish");
     else
       HIP_TRY(launch_finish(c->P, c->pair, c->opt.precision, u, c->partial, out, s), "finish");
     r->applies++;
@@ -507,7 +515,8 @@ int ibim_server_create(const ibim_options* opt, size_t hbm_budget_bytes, int max
   {
     DeviceScope ds(o.device);
     srv->grid = pair_batched_grid(o.precision);
-    srv->sym_grid = pair_sym_batched_grid();
+    srv->sym_grid =
+        o.precision == IBIM_MIXED ? pair_sym_mixed_batched_grid() : pair_sym_batched_grid();
     hipError_t e = dalloc(&srv->d_counter, 2);
     if (e == hipSuccess) e = dalloc(&srv->d_status, (size_t)max_slots * kStatusStride);
     if (e == hipSuccess)

@@ -1,0 +1,167 @@
+// Work-item body of the symmetric pair sum, shared by the float64 and the
+// mixed-precision kernels (each translation unit instantiates it with its
+// own arithmetic policy).  The schedule is described in symmetric.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+
+#include "operator.h"
+#include "symmetric.h"
+
+namespace ibim {
+namespace sym {
+
+constexpr int kT = kPairTile;
+constexpr int kRows = kSymRows;
+
+__device__ __forceinline__ bool careful_pair(const SymArgs& a, int I, int J) {
+  const int64_t bit = (int64_t)I * a.T + J;
+  return (a.careful[bit >> 5] >> (bit & 31)) & 1u;
+}
+
+template <class T>
+__device__ __forceinline__ T* lds_at(T* base, unsigned byte_off) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off);
+}
+
+template <class P>
+struct Shared {
+  typename P::Lds rec;                     // records of the column tile J
+  double2 cacc[kT];                        // column sums of J (row 1, row 2)
+  double racc1[kRows][kT], racc2[kRows][kT];  // row sums, lane-private slots
+};
+
+// Sums over the sources of tile Y for the target of this lane in tile X
+// (k = X*256 + tid), pairs of N_k skipped.  src(j) returns source j of Y.
+template <class P, class Src>
+__device__ __forceinline__ void one_way(const SymArgs& a, const typename P::Consts& pc, int X,
+                                        int Y, const Src& src, double& S1, double& S2) {
+  const int tid = threadIdx.x;
+  const int32_t M = a.M;
+  const int32_t k = X * kT + tid;
+  const int32_t kc = k < M ? k : M - 1;
+  const typename P::Rec t = P::load(a, kc);
+  const int32_t s0 = Y * kT;
+  const int n = min(kT, M - s0);
+  int32_t p = a.crow[kc];
+  const int32_t pe = a.crow[kc + 1];
+  while (p < pe && a.ccol[p] < s0) ++p;
+  int32_t nxt = p < pe ? a.ccol[p] : INT_MAX;
+  for (int j = 0; j < n; ++j) {
+    double d1, d2;
+    P::one(t, src(j), pc, d1, d2);
+    const bool ex = (s0 + j == nxt);
+    if (ex) {
+      ++p;
+      nxt = p < pe ? a.ccol[p] : INT_MAX;
+    }
+    S1 += ex ? 0.0 : d1;
+    S2 += ex ? 0.0 : d2;
+  }
+}
+
+// One work item (rb, cb).  Called by all 256 threads of the workgroup.
+template <class P>
+__device__ void item(const SymArgs& a, int rb, int cb, Shared<P>& sh) {
+  double2* const cacc = sh.cacc;
+  auto& racc1 = sh.racc1;
+  auto& racc2 = sh.racc2;
+  const int tid = threadIdx.x;
+  const int wv = tid >> 6, l = tid & 63;
+  const int T = a.T;
+  const int32_t M = a.M;
+  const int I0 = rb * kRows;
+  const int J0 = cb * a.b, J1 = min(J0 + a.b, T);
+  const typename P::Consts pc = P::consts(a);
+
+  for (int i = 0; i < kRows; ++i) racc1[i][tid] = racc2[i][tid] = 0.0;
+
+  for (int J = max(J0, I0); J < J1; ++J) {
+    {
+      const int32_t m = J * kT + tid;
+      if (m < M) P::store(sh.rec, tid, P::load(a, m));
+      cacc[tid] = make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int i = 0; i < kRows; ++i) {
+      const int I = I0 + i;
+      if (I >= T || I > J) continue;  // uniform
+      double S1 = racc1[i][tid], S2 = racc2[i][tid];
+      const bool slow = I == J || careful_pair(a, I, J) || (J == T - 1 && M % kT != 0);
+      if (slow) {
+        // row I from the sources of J (LDS broadcasts)
+        one_way<P>(a, pc, I, J, [&](int j) { return P::at(sh.rec, (unsigned)j << 4); }, S1, S2);
+        racc1[i][tid] = S1;
+        racc2[i][tid] = S2;
+        if (I != J) {
+          // row J from the sources of I (uniform global loads)
+          double c1 = 0.0, c2 = 0.0;
+          one_way<P>(a, pc, J, I, [&](int j) { return P::load(a, I * kT + j); }, c1, c2);
+          cacc[tid].x += c1;
+          cacc[tid].y += c2;
+        }
+        __syncthreads();
+        continue;
+      }
+      const typename P::Rec f = P::load(a, I * kT + tid);
+      for (int ph = 0; ph < 4; ++ph) {
+        // byte offsets into the 16-byte-record arrays: sub-block | ((l + s) mod 64) * 16
+        const unsigned sb16 = (unsigned)(((wv + ph) & 3) * 64) << 4;
+        unsigned x16 = (unsigned)l << 4;
+#pragma unroll 2
+        for (int s = 0; s < 64; ++s) {
+          const unsigned off = (x16 & 1008u) | sb16;
+          x16 += 16u;
+          double C1, C2;
+          P::both(f, P::at(sh.rec, off), pc, S1, S2, C1, C2);
+          double2* c = lds_at(cacc, off);
+          atomicAdd(&c->x, C1);
+          atomicAdd(&c->y, C2);
+        }
+        __syncthreads();
+      }
+      racc1[i][tid] = S1;
+      racc2[i][tid] = S2;
+    }
+    // column sums of J
+    double* cp = a.colpart + ((size_t)rb * T + J) * (2 * kT);
+    cp[tid] = a.scale * cacc[tid].x;
+    cp[kT + tid] = a.scale * cacc[tid].y;
+    __syncthreads();  // LDS is refilled for the next column tile
+  }
+  // row sums of this item's row tiles that met at least one J >= I
+  for (int i = 0; i < kRows; ++i) {
+    const int I = I0 + i;
+    if (I >= T || I > J1 - 1) continue;
+    double* rp = a.rowpart + ((size_t)cb * T + I) * (2 * kT);
+    rp[tid] = a.scale * racc1[i][tid];
+    rp[kT + tid] = a.scale * racc2[i][tid];
+  }
+}
+
+// Persistent loop over (problem, item) entries taken from *counter.
+template <class P>
+__device__ void batched(const SymArgs* __restrict__ probs, const int32_t* __restrict__ work,
+                        int n_work, int* counter, Shared<P>& sh) {
+  __shared__ int next;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+    __syncthreads();
+    // the entry index is uniform: keep it (and so the argument record) scalar
+    const int it = __builtin_amdgcn_readfirstlane(next);
+    __syncthreads();  // every thread has read `next` before it is overwritten
+    if (it >= n_work) break;
+    const int pi = __builtin_amdgcn_readfirstlane(work[2 * it]);
+    const int ii = __builtin_amdgcn_readfirstlane(work[2 * it + 1]);
+    const SymArgs a = probs[pi];
+    const int2 it2 = a.items[ii];
+    item<P>(a, __builtin_amdgcn_readfirstlane(it2.x), __builtin_amdgcn_readfirstlane(it2.y), sh);
+    __syncthreads();  // LDS is reused by the next entry
+  }
+}
+
+}  // namespace sym
+}  // namespace ibim

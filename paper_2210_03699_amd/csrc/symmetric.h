@@ -27,6 +27,7 @@ struct SymPlan {
 
 struct SymArgs {
   const double *px, *py, *pz, *nx, *ny, *nz, *w;
+  const float *fx, *fy, *fz, *fnx, *fny, *fnz;  // float32 geometry (mixed form)
   const double* u;
   const int32_t* crow;
   const int32_t* ccol;
@@ -60,5 +61,17 @@ hipError_t launch_pair_sym_batched(const SymArgs* probs, const int32_t* work, in
 int pair_sym_batched_grid();
 hipError_t launch_finish_sym(const DeviceProblem& P, const SymPlan& pl, const double* u,
                              const double* scratch, double* out, hipStream_t stream);
+
+// Mixed form (float32 pairs, float64 sums) on the same schedule, and its
+// finishing kernel, which also replaces the float32 value of every near pair
+// by its float64 value (recomputing the float32 value exactly as the pair
+// kernel produced it: forward, reverse or one-directional evaluation).
+hipError_t launch_pair_sym_mixed(const SymArgs& a, int n_items, hipStream_t stream);
+hipError_t launch_pair_sym_mixed_batched(const SymArgs* probs, const int32_t* work, int n_work,
+                                         int* counter, int grid, hipStream_t stream);
+int pair_sym_mixed_batched_grid();
+hipError_t launch_finish_sym_mixed(const DeviceProblem& P, const SymPlan& pl,
+                                   const uint32_t* careful, const double* u,
+                                   const double* scratch, double* out, hipStream_t stream);
 
 }  // namespace ibim

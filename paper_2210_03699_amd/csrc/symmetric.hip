@@ -28,6 +28,7 @@
 
 #include "operator.h"
 #include "pair_math.h"
+#include "sym_core.h"
 #include "symmetric.h"
 #include "weights.h"
 
@@ -37,212 +38,84 @@ namespace {
 constexpr int kT = kPairTile;
 constexpr int kRows = kSymRows;
 
-struct Rec {
-  double px, py, pz, nx, ny, nz, a1, a2;
+// float64 arithmetic: records of 8 doubles, LDS as four double2 arrays.
+struct Fp64 {
+  struct Rec {
+    double px, py, pz, nx, ny, nz, a1, a2;
+  };
+  struct Lds {
+    double2 A[kT], B[kT], C[kT], D[kT];  // (px,py) (pz,nx) (ny,nz) (a1,a2)
+  };
+  using Consts = PairConsts;
+  static __device__ __forceinline__ Consts consts(const SymArgs& a) {
+    return PairConsts{a.c1, a.c2, a.kappa, a.kappa * a.kappa};
+  }
+  static __device__ __forceinline__ Rec load(const SymArgs& a, int32_t m) {
+    const double wm = a.w[m];
+    return Rec{a.px[m], a.py[m], a.pz[m], a.nx[m], a.ny[m], a.nz[m], wm * a.u[m],
+               wm * a.u[a.M + m]};
+  }
+  static __device__ __forceinline__ void store(Lds& s, int i, const Rec& r) {
+    s.A[i] = make_double2(r.px, r.py);
+    s.B[i] = make_double2(r.pz, r.nx);
+    s.C[i] = make_double2(r.ny, r.nz);
+    s.D[i] = make_double2(r.a1, r.a2);
+  }
+  static __device__ __forceinline__ Rec at(Lds& s, unsigned off) {
+    const double2 q0 = *sym::lds_at(s.A, off), q1 = *sym::lds_at(s.B, off);
+    const double2 q2 = *sym::lds_at(s.C, off), q3 = *sym::lds_at(s.D, off);
+    return Rec{q0.x, q0.y, q1.x, q1.y, q2.x, q2.y, q3.x, q3.y};
+  }
+  static __device__ __forceinline__ void one(const Rec& t, const Rec& r, const Consts& pc,
+                                             double& d1, double& d2) {
+    pair_f64<false>(t.px, t.py, t.pz, t.nx, t.ny, t.nz, r.px, r.py, r.pz, r.nx, r.ny, r.nz, r.a1,
+                    r.a2, pc, d1, d2);
+  }
+  // Both directions of the pair (fixed f, rotating m): k <- m added to
+  // (S1, S2), m <- k returned in (C1, C2).
+  static __device__ __forceinline__ void both(const Rec& f, const Rec& m, const Consts& pc,
+                                              double& S1, double& S2, double& C1, double& C2) {
+    const double rx = f.px - m.px, ry = f.py - m.py, rz = f.pz - m.pz;  // r = x_k - P_m
+    const double R2s = fma(rz, rz, fma(ry, ry, rx * rx));
+    const double iR = rsqrt_pos(R2s);
+    const double R = R2s * iR;
+    const double iR2 = iR * iR;
+    const double iR3 = iR2 * iR;
+    const double kr = pc.kappa * R;
+    const double e = exp_neg(kr);
+    const double te = fma(e, kr, e);
+    const double rny = fma(rz, m.nz, fma(ry, m.ny, rx * m.nx));  // r . n_m
+    const double rnx = fma(rz, f.nz, fma(ry, f.ny, rx * f.nx));  // r . n_k
+    const double nn = fma(f.nz, m.nz, fma(f.ny, m.ny, f.nx * m.nx));
+    // kernel factors with 1/R^3 folded in
+    const double f1 = fma(-pc.c1, te, 1.0) * iR3;
+    const double f2 = fma(-pc.c2, te, 1.0) * iR3;
+    const double g12 = (1.0 - e) * iR;
+    const double phi2 = 1.0 - te;
+    const double q = rnx * rny;
+    const double g21 = fma(phi2, fma(q * iR2, -3.0, nn), pc.kappa2 * e * q) * iR3;
+    // k <- m
+    const double g11 = rny * f1, g22 = rnx * f2;
+    S1 = fma(g11, m.a1, fma(-g12, m.a2, S1));
+    S2 = fma(g21, m.a1, fma(g22, m.a2, S2));
+    // m <- k: r.n_k and r.n_m swap roles with a sign change
+    const double h11 = -rnx * f1, h22 = -rny * f2;
+    C1 = fma(h11, f.a1, -g12 * f.a2);
+    C2 = fma(g21, f.a1, h22 * f.a2);
+  }
 };
-
-__device__ __forceinline__ Rec load_rec(const SymArgs& a, int32_t m) {
-  const double wm = a.w[m];
-  return Rec{a.px[m], a.py[m], a.pz[m], a.nx[m], a.ny[m], a.nz[m], wm * a.u[m],
-             wm * a.u[a.M + m]};
-}
-
-// Sums over the sources of tile Y for the target of this lane in tile X
-// (k = X*256 + tid), pairs of N_k skipped.  src(j) returns source j of Y.
-template <class Src>
-__device__ __forceinline__ void one_way(const SymArgs& a, int X, int Y, const Src& src,
-                                        double& S1, double& S2) {
-  const int tid = threadIdx.x;
-  const int32_t M = a.M;
-  const int32_t k = X * kT + tid;
-  const int32_t kc = k < M ? k : M - 1;
-  const double tx = a.px[kc], ty = a.py[kc], tz = a.pz[kc];
-  const double tnx = a.nx[kc], tny = a.ny[kc], tnz = a.nz[kc];
-  const int32_t s0 = Y * kT;
-  const int n = min(kT, M - s0);
-  int32_t p = a.crow[kc];
-  const int32_t pe = a.crow[kc + 1];
-  while (p < pe && a.ccol[p] < s0) ++p;
-  int32_t nxt = p < pe ? a.ccol[p] : INT_MAX;
-  const PairConsts pc{a.c1, a.c2, a.kappa, a.kappa * a.kappa};
-  for (int j = 0; j < n; ++j) {
-    const Rec r = src(j);
-    double d1, d2;
-    pair_f64<false>(tx, ty, tz, tnx, tny, tnz, r.px, r.py, r.pz, r.nx, r.ny, r.nz, r.a1, r.a2,
-                    pc, d1, d2);
-    const bool ex = (s0 + j == nxt);
-    if (ex) {
-      ++p;
-      nxt = p < pe ? a.ccol[p] : INT_MAX;
-    }
-    S1 += ex ? 0.0 : d1;
-    S2 += ex ? 0.0 : d2;
-  }
-}
-
-// Element of a shared double2 array at a byte offset.
-__device__ __forceinline__ double2* lds_at(double2* base, unsigned byte_off) {
-  return reinterpret_cast<double2*>(reinterpret_cast<char*>(base) + byte_off);
-}
-
-__device__ __forceinline__ bool careful_pair(const SymArgs& a, int I, int J) {
-  const int64_t bit = (int64_t)I * a.T + J;
-  return (a.careful[bit >> 5] >> (bit & 31)) & 1u;
-}
-
-struct SymShared {
-  double2 sA[kT], sB[kT], sC[kT], sD[kT];  // records of J: (px,py) (pz,nx) (ny,nz) (a1,a2)
-  double2 cacc[kT];                        // column sums of J (row 1, row 2)
-  double racc1[kRows][kT], racc2[kRows][kT];  // row sums, lane-private slots
-};
-
-// One work item (rb, cb).  Called by all 256 threads of the workgroup.
-__device__ void sym_item(const SymArgs& a, int rb, int cb, SymShared& sh) {
-  double2* const sA = sh.sA;
-  double2* const sB = sh.sB;
-  double2* const sC = sh.sC;
-  double2* const sD = sh.sD;
-  double2* const cacc = sh.cacc;
-  auto& racc1 = sh.racc1;
-  auto& racc2 = sh.racc2;
-  const int tid = threadIdx.x;
-  const int wv = tid >> 6, l = tid & 63;
-  const int T = a.T;
-  const int32_t M = a.M;
-  const int I0 = rb * kRows;
-  const int J0 = cb * a.b, J1 = min(J0 + a.b, T);
-  const PairConsts pc{a.c1, a.c2, a.kappa, a.kappa * a.kappa};
-
-  for (int i = 0; i < kRows; ++i) racc1[i][tid] = racc2[i][tid] = 0.0;
-
-  for (int J = max(J0, I0); J < J1; ++J) {
-    {
-      const int32_t m = J * kT + tid;
-      if (m < M) {
-        const Rec r = load_rec(a, m);
-        sA[tid] = make_double2(r.px, r.py);
-        sB[tid] = make_double2(r.pz, r.nx);
-        sC[tid] = make_double2(r.ny, r.nz);
-        sD[tid] = make_double2(r.a1, r.a2);
-      }
-      cacc[tid] = make_double2(0.0, 0.0);
-    }
-    __syncthreads();
-    for (int i = 0; i < kRows; ++i) {
-      const int I = I0 + i;
-      if (I >= T || I > J) continue;  // uniform
-      double S1 = racc1[i][tid], S2 = racc2[i][tid];
-      const bool slow = I == J || careful_pair(a, I, J) || (J == T - 1 && M % kT != 0);
-      if (slow) {
-        // row I from the sources of J (LDS broadcasts)
-        one_way(a, I, J, [&](int j) {
-          const double2 q0 = sA[j], q1 = sB[j], q2 = sC[j], q3 = sD[j];
-          return Rec{q0.x, q0.y, q1.x, q1.y, q2.x, q2.y, q3.x, q3.y};
-        }, S1, S2);
-        racc1[i][tid] = S1;
-        racc2[i][tid] = S2;
-        if (I != J) {
-          // row J from the sources of I (uniform global loads)
-          double c1 = 0.0, c2 = 0.0;
-          one_way(a, J, I, [&](int j) { return load_rec(a, I * kT + j); }, c1, c2);
-          cacc[tid].x += c1;
-          cacc[tid].y += c2;
-        }
-        __syncthreads();
-        continue;
-      }
-      const int32_t k = I * kT + tid;
-      const Rec f = load_rec(a, k);
-      for (int ph = 0; ph < 4; ++ph) {
-        // byte offsets into the double2 arrays: sub-block base | ((l + s) mod 64) * 16
-        const unsigned sb16 = (unsigned)(((wv + ph) & 3) * 64) << 4;
-        unsigned x16 = (unsigned)l << 4;
-#pragma unroll 2
-        for (int s = 0; s < 64; ++s) {
-          const unsigned off = (x16 & 1008u) | sb16;
-          x16 += 16u;
-          const double2 q0 = *lds_at(sA, off), q1 = *lds_at(sB, off);
-          const double2 q2 = *lds_at(sC, off), q3 = *lds_at(sD, off);
-          // r = x_k - P_m
-          const double rx = f.px - q0.x, ry = f.py - q0.y, rz = f.pz - q1.x;
-          const double R2s = fma(rz, rz, fma(ry, ry, rx * rx));
-          const double iR = rsqrt_pos(R2s);
-          const double R = R2s * iR;
-          const double iR2 = iR * iR;
-          const double iR3 = iR2 * iR;
-          const double kr = pc.kappa * R;
-          const double e = exp_neg(kr);
-          const double te = fma(e, kr, e);
-          const double rny = fma(rz, q2.y, fma(ry, q2.x, rx * q1.y));  // r . n_m
-          const double rnx = fma(rz, f.nz, fma(ry, f.ny, rx * f.nx));  // r . n_k
-          const double nn = fma(f.nz, q2.y, fma(f.ny, q2.x, f.nx * q1.y));
-          // kernel factors with 1/R^3 folded in
-          const double f1 = fma(-pc.c1, te, 1.0) * iR3;
-          const double f2 = fma(-pc.c2, te, 1.0) * iR3;
-          const double g12 = (1.0 - e) * iR;
-          const double phi2 = 1.0 - te;
-          const double q = rnx * rny;
-          const double g21 = fma(phi2, fma(q * iR2, -3.0, nn), pc.kappa2 * e * q) * iR3;
-          // k <- m
-          const double g11 = rny * f1, g22 = rnx * f2;
-          S1 = fma(g11, q3.x, fma(-g12, q3.y, S1));
-          S2 = fma(g21, q3.x, fma(g22, q3.y, S2));
-          // m <- k: r.n_k and r.n_m swap roles with a sign change
-          const double h11 = -rnx * f1, h22 = -rny * f2;
-          const double C1 = fma(h11, f.a1, -g12 * f.a2);
-          const double C2 = fma(g21, f.a1, h22 * f.a2);
-          double2* c = lds_at(cacc, off);
-          atomicAdd(&c->x, C1);
-          atomicAdd(&c->y, C2);
-        }
-        __syncthreads();
-      }
-      racc1[i][tid] = S1;
-      racc2[i][tid] = S2;
-    }
-    // column sums of J
-    double* cp = a.colpart + ((size_t)rb * T + J) * (2 * kT);
-    cp[tid] = a.scale * cacc[tid].x;
-    cp[kT + tid] = a.scale * cacc[tid].y;
-    __syncthreads();  // LDS is refilled for the next column tile
-  }
-  // row sums of this item's row tiles that met at least one J >= I
-  for (int i = 0; i < kRows; ++i) {
-    const int I = I0 + i;
-    if (I >= T || I > J1 - 1) continue;
-    double* rp = a.rowpart + ((size_t)cb * T + I) * (2 * kT);
-    rp[tid] = a.scale * racc1[i][tid];
-    rp[kT + tid] = a.scale * racc2[i][tid];
-  }
-}
 
 __global__ __launch_bounds__(256) void pair_sym_fp64_kernel(SymArgs a) {
-  __shared__ SymShared sh;
-  const int2 item = a.items[blockIdx.x];
-  sym_item(a, item.x, item.y, sh);
+  __shared__ sym::Shared<Fp64> sh;
+  const int2 it = a.items[blockIdx.x];
+  sym::item<Fp64>(a, it.x, it.y, sh);
 }
 
-// Persistent form over the items of several problems: entry i of `work` is
-// (problem, item index); workgroups take entries from *counter (initially 0).
 __global__ __launch_bounds__(256, 4) void pair_sym_batched_kernel(
     const SymArgs* __restrict__ probs, const int32_t* __restrict__ work, int n_work,
     int* counter) {
-  __shared__ SymShared sh;
-  __shared__ int next;
-  for (;;) {
-    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
-    __syncthreads();
-    // the item index is uniform: keep it (and so the argument record) scalar
-    const int it = __builtin_amdgcn_readfirstlane(next);
-    __syncthreads();  // every thread has read `next` before it is overwritten
-    if (it >= n_work) break;
-    const int pi = __builtin_amdgcn_readfirstlane(work[2 * it]);
-    const int ii = __builtin_amdgcn_readfirstlane(work[2 * it + 1]);
-    const SymArgs a = probs[pi];
-    const int2 item = a.items[ii];
-    sym_item(a, __builtin_amdgcn_readfirstlane(item.x), __builtin_amdgcn_readfirstlane(item.y), sh);
-    __syncthreads();  // LDS is reused by the next item
-  }
+  __shared__ sym::Shared<Fp64> sh;
+  sym::batched<Fp64>(probs, work, n_work, counter, sh);
 }
 
 struct SymFinishArgs {
@@ -350,6 +223,8 @@ SymArgs make_sym_args(const DeviceProblem& P, const SymPlan& pl, const int32_t* 
   a.px = P.px; a.py = P.py; a.pz = P.pz;
   a.nx = P.nx; a.ny = P.ny; a.nz = P.nz;
   a.w = P.w;
+  a.fx = P.px32; a.fy = P.py32; a.fz = P.pz32;
+  a.fnx = P.nx32; a.fny = P.ny32; a.fnz = P.nz32;
   a.u = u;
   a.crow = P.crow;
   a.ccol = P.ccol;

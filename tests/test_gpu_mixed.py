@@ -37,15 +37,26 @@ def _rel(a, b, M):
                np.max(np.abs(a[M:] - b[M:])) / np.max(np.abs(b[M:])))
 
 
-def test_near_fixup_replaces_every_pair_exactly():
-    wl = workloads.born_sphere(h=0.4)
+ALL_NEAR = {
+    "born_h0.4": lambda: workloads.born_sphere(h=0.4),
+    "offset_sphere": lambda: workloads.born_sphere(h=0.25, radius=1.7,
+                                                   offset=(0.37, 0.11, -0.23)),
+    "ses_molecule": lambda: workloads.ses_molecule(20, 9.0, 0.35, 2.0, seed=11, tol=1e-10),
+}
+
+
+@pytest.mark.parametrize("name", list(ALL_NEAR))
+def test_near_fixup_replaces_every_pair_exactly(name):
+    """Every pair evaluation path (forward and reverse of the symmetric
+    kernel, one-directional tiles) is reproduced bit for bit by the fix-up."""
+    wl = ALL_NEAR[name]()
     p64 = ibim.Problem.from_workload(wl, device=0)
     pmx = ibim.Problem.from_workload(wl, device=0, precision=ibim.MIXED, r_near=100.0)
     u = torch.from_numpy(workloads.random_vector(2 * p64.M, 3)).to(DEV)
     a = p64.apply(u).cpu().numpy()
     b = pmx.apply(u).cpu().numpy()
     err = _rel(b, a, p64.M)
-    _say(f"[mixed all-near] rel diff vs float64 operator {err:.3e}")
+    _say(f"[mixed all-near {name}] M={p64.M} rel diff vs float64 operator {err:.3e}")
     assert err < 1e-13
 
 
