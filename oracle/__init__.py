@@ -49,6 +49,11 @@ def _load():
                              ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]
     lib.oc_build_rows.restype = ctypes.c_void_p
     lib.oc_build_rows.argtypes = lib.oc_build.argtypes + [_I64, ctypes.c_int64]
+    lib.oc_build_hyb.restype = ctypes.c_void_p
+    lib.oc_build_hyb.argtypes = lib.oc_build.argtypes + [ctypes.c_int, _I64, ctypes.c_int64]
+    lib.oc_get_bad.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint8)]
+    lib.oc_kreg_c12.restype = ctypes.c_double
+    lib.oc_kreg_c12.argtypes = [ctypes.c_double, ctypes.c_double]
     lib.oc_free.argtypes = [ctypes.c_void_p]
     lib.oc_last_error.restype = ctypes.c_char_p
     lib.oc_num_nodes.restype = ctypes.c_int64
@@ -67,8 +72,8 @@ def _load():
     lib.oc_area.restype = ctypes.c_double
     lib.oc_area.argtypes = [ctypes.c_void_p]
     lib.oc_gmres.restype = ctypes.c_int
-    lib.oc_gmres.argtypes = [ctypes.c_void_p, _D, ctypes.c_double, ctypes.c_int, ctypes.c_int, _D,
-                             ctypes.POINTER(ctypes.c_int), _D, _D]
+    lib.oc_gmres.argtypes = [ctypes.c_void_p, _D, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                             ctypes.c_int, _D, ctypes.POINTER(ctypes.c_int), _D, _D]
     lib.oc_lattice_sums.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int, _D, _D]
     lib.oc_ell.argtypes = [_D, _D, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                            ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -98,9 +103,12 @@ def num_threads() -> int:
 class Oracle:
     """One discretised problem: tube nodes, geometry, correction sets, weights."""
 
-    def __init__(self, sdf, origin, h, eps_tube, eps_in, eps_out, kappa, weight_rows=None):
+    def __init__(self, sdf, origin, h, eps_tube, eps_in, eps_out, kappa, weight_rows=None,
+                 hybrid=0):
         """``weight_rows``: build correction weights only for these rows (the
-        others hold NaN, so only ``apply_rows`` on listed rows is meaningful)."""
+        others hold NaN, so only ``apply_rows`` on listed rows is meaningful).
+        ``hybrid``: 0 CTR2 rows everywhere, 1 HYB-IBIM (K-reg rows and J = 1
+        at bad nodes), 2 every node bad (K-reg everywhere, J = 1)."""
         lib = _load()
         self._lib = lib
         sdf = _f64(sdf)
@@ -109,14 +117,16 @@ class Oracle:
         self.h, self.eps, self.eps_in, self.eps_out, self.kappa = (
             float(h), float(eps_tube), float(eps_in), float(eps_out), float(kappa))
         self._sdf = sdf
+        self.hybrid = int(hybrid)
         if weight_rows is None:
-            ptr = lib.oc_build(_dp(sdf), sdf.shape[0], sdf.shape[1], sdf.shape[2], _dp(origin),
-                               self.h, self.eps, self.eps_in, self.eps_out, self.kappa)
+            ptr = lib.oc_build_hyb(_dp(sdf), sdf.shape[0], sdf.shape[1], sdf.shape[2],
+                                   _dp(origin), self.h, self.eps, self.eps_in, self.eps_out,
+                                   self.kappa, self.hybrid, None, 0)
         else:
             wr = np.ascontiguousarray(weight_rows, dtype=np.int64)
-            ptr = lib.oc_build_rows(_dp(sdf), sdf.shape[0], sdf.shape[1], sdf.shape[2],
-                                    _dp(origin), self.h, self.eps, self.eps_in, self.eps_out,
-                                    self.kappa, wr.ctypes.data_as(_I64), wr.shape[0])
+            ptr = lib.oc_build_hyb(_dp(sdf), sdf.shape[0], sdf.shape[1], sdf.shape[2],
+                                   _dp(origin), self.h, self.eps, self.eps_in, self.eps_out,
+                                   self.kappa, self.hybrid, wr.ctypes.data_as(_I64), wr.shape[0])
         if not ptr:
             raise ValueError("oracle setup failed: " + lib.oc_last_error().decode())
         self._c = ctypes.c_void_p(ptr)
@@ -124,9 +134,15 @@ class Oracle:
         self.nnz = int(lib.oc_num_corrections(self._c))
 
     @classmethod
-    def from_workload(cls, wl, weight_rows=None):
+    def from_workload(cls, wl, weight_rows=None, hybrid=0):
         return cls(wl.sdf, wl.origin, wl.h, wl.eps_tube, wl.eps_in, wl.eps_out, wl.kappa,
-                   weight_rows=weight_rows)
+                   weight_rows=weight_rows, hybrid=hybrid)
+
+    def bad_nodes(self) -> np.ndarray:
+        """Boolean per node: in M_B (K-reg row, J = 1)."""
+        out = np.empty(self.M, np.uint8)
+        self._lib.oc_get_bad(self._c, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+        return out.astype(bool)
 
     def __del__(self):
         c = getattr(self, "_c", None)
@@ -197,25 +213,31 @@ class Oracle:
     def psi_rxn(self, x, z) -> float:
         return float(self._lib.oc_psi_rxn(self._c, _dp(_f64(x)), _dp(_f64(z))))
 
-    def gmres(self, b, tol, restart=60, maxit=300):
+    def gmres(self, b, tol, restart=60, maxit=300, precond=1):
+        """GMRES(restart) from x0 = 0; precond 1: on D^-1 A x = D^-1 b (D = Lambda)."""
         b = _f64(b)
         x = np.empty(2 * self.M)
         it = ctypes.c_int(0)
         est = np.zeros(1)
         true = np.zeros(1)
         status = self._lib.oc_gmres(self._c, _dp(b), float(tol), int(restart), int(maxit),
-                                    _dp(x), ctypes.byref(it), _dp(est), _dp(true))
+                                    int(precond), _dp(x), ctypes.byref(it), _dp(est), _dp(true))
         return x, {"status": int(status), "iters": int(it.value), "est_relres": float(est[0]),
                    "true_relres": float(true[0])}
 
-    def solve_energy(self, charge_xyz, charge_q, tol, restart=60, maxit=300):
+    def solve_energy(self, charge_xyz, charge_q, tol, restart=60, maxit=300, precond=1):
         g = self.rhs(charge_xyz, charge_q)
-        x, info = self.gmres(g, tol, restart, maxit)
+        x, info = self.gmres(g, tol, restart, maxit, precond)
         info["g_pol"] = self.energy(x, charge_xyz, charge_q)
         return x, info
 
 
 # -- free functions used by the weight and expansion pins -------------------
+def kreg_c12(kappa: float, tau: float) -> float:
+    """K-reg constant of K12 for radius tau (Section 2.3)."""
+    return float(_load().oc_kreg_c12(float(kappa), float(tau)))
+
+
 def lattice_sums(alpha: float, beta: float, nmode: int = 41):
     """Z_{2j}(alpha, beta), j < nmode (complex), the regularised lattice sums."""
     lib = _load()

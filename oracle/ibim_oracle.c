@@ -28,8 +28,20 @@
  *  - Weights are evaluated exactly (Ewald form of the lattice sum that the
  *    limit definition eq. single_correction_weight reduces to), not from a
  *    table.
- *  - GMRES: x0 = 0, no preconditioner, modified Gram-Schmidt, Givens
- *    rotations, stop when |g_{j+1}| <= tol ||b||_2.
+ *  - GMRES: x0 = 0, modified Gram-Schmidt, Givens rotations, stop when
+ *    |g_{j+1}| <= tol ||b||_2; by default on the system with each block row
+ *    divided by its free-term coefficient (D^-1 A x = D^-1 b, D = Lambda), the
+ *    form whose iteration counts match the paper's; precond = 0 keeps A x = b.
+ *  - HYB-IBIM (Section 3.2): the paper calls a node bad when its curvatures
+ *    are away from the true ones, which needs the true surface.  From the
+ *    signed distance alone a node is taken as bad when its finite-difference
+ *    geometry is unreliable: | |grad_h d| - 1 | > 0.05, or the Hessian's
+ *    normal component |g.H g| > 0.1/h, or a corrected plane has
+ *    1 - |eta| max|kappa| < 0.2 (D0 near singular).  Bad rows use K-reg
+ *    (eq. regularized-kernel) with tau = 2h; its regularised set is the tube
+ *    nodes y with tangential distance |(I - n n^T)(y - P(y_k))| < tau and
+ *    normal distance |n.(y - P(y_k))| <= eps + h (the same reach as the CTR2
+ *    planes); bad nodes carry J = 1 (eq. Jacobian-hybrid).
  */
 #include <math.h>
 #include <stdint.h>
@@ -76,6 +88,11 @@ typedef struct {
   double* om11;
   double* om21;
   int64_t nnz;
+  /* HYB-IBIM (Section 3.2): node classification and K-reg parameter */
+  int hybrid;         /* 0: CTR2 rows everywhere; 1: HYB; 2: every node bad (K-reg) */
+  double ktau;        /* K-reg radius */
+  double c12;         /* K-reg constant of K12 */
+  unsigned char* bad; /* M: node in M_B */
 } oc_ctx;
 
 static char oc_err[512];
@@ -95,8 +112,22 @@ void oc_free(oc_ctx* c) {
   free(c->grid_node); free(c->ijk); free(c->y); free(c->d); free(c->g);
   free(c->nrm); free(c->P); free(c->J); free(c->w); free(c->kap); free(c->tau);
   free(c->crow); free(c->ccol); free(c->cplane); free(c->calpha); free(c->cbeta);
-  free(c->ceta); free(c->om11); free(c->om21);
+  free(c->ceta); free(c->om11); free(c->om21); free(c->bad);
   free(c);
+}
+
+/* ------------------------------------------------------------------------ */
+/* K-reg constant of K12 (Section 2.3): the mean of K12 over the tangent disc
+ * of radius tau, (e^{-k tau} - 1 + k tau) / (2 pi k tau^2); the constants of
+ * K11, K21 and K22 are zero.  Small k tau by the series of the numerator. */
+double oc_kreg_c12(double kappa, double tau) {
+  if (kappa == 0.0) return 0.0;
+  double x = kappa * tau, num;
+  if (x < 1e-2)
+    num = x * x * (0.5 - x * (1.0 / 6.0 - x * (1.0 / 24.0 - x / 120.0)));
+  else
+    num = expm1(-x) + x;
+  return num / (2.0 * OC_PI * kappa * tau * tau);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -301,15 +332,19 @@ static void eig2(double p, double q, double r, double* mu, double* v /* 2x2 cols
 /* Returns NULL on error (message in oc_last_error()).                       */
 /* Weights are computed for every row, or only for the rows listed in
  * weight_rows (other rows get NaN weights, so using them fails loudly). */
-oc_ctx* oc_build_rows(const double* sdf, int nx, int ny, int nz, const double* origin, double h,
-                      double eps, double eps_in, double eps_out, double kappa,
-                      const int64_t* weight_rows, int64_t n_weight_rows) {
+oc_ctx* oc_build_hyb(const double* sdf, int nx, int ny, int nz, const double* origin, double h,
+                     double eps, double eps_in, double eps_out, double kappa, int hybrid,
+                     const int64_t* weight_rows, int64_t n_weight_rows) {
   oc_err[0] = 0;
-  if (!(h > 0) || !(eps > 0) || !(eps_in > 0) || !(eps_out > 0) || !(kappa >= 0)) {
+  if (!(h > 0) || !(eps > 0) || !(eps_in > 0) || !(eps_out > 0) || !(kappa >= 0) ||
+      hybrid < 0 || hybrid > 2) {
     snprintf(oc_err, sizeof oc_err, "bad scalar parameter");
     return NULL;
   }
   oc_ctx* c = (oc_ctx*)calloc(1, sizeof(oc_ctx));
+  c->hybrid = hybrid;
+  c->ktau = 2.0 * h;
+  c->c12 = oc_kreg_c12(kappa, c->ktau);
   c->dims[0] = nx; c->dims[1] = ny; c->dims[2] = nz;
   for (int a = 0; a < 3; ++a) c->origin[a] = origin[a];
   c->h = h; c->eps = eps; c->eps_in = eps_in; c->eps_out = eps_out; c->kappa = kappa;
@@ -340,6 +375,7 @@ oc_ctx* oc_build_rows(const double* sdf, int nx, int ny, int nz, const double* o
   c->w = (double*)xmalloc(sizeof(double) * M);
   c->kap = (double*)xmalloc(sizeof(double) * 2 * M);
   c->tau = (double*)xmalloc(sizeof(double) * 6 * M);
+  c->bad = (unsigned char*)calloc((size_t)M, 1);
 
 #define SDF(i, j, k) sdf[((int64_t)(i) * ny + (j)) * nz + (k)]
   int bad = 0;
@@ -379,6 +415,16 @@ oc_ctx* oc_build_rows(const double* sdf, int nx, int ny, int nz, const double* o
                          SDF(i, j - 1, k - 1)) / (4.0 * h * h);
     double gn = sqrt(gx * gx + gy * gy + gz * gz);
     double g[3] = {gx / gn, gy / gn, gz / gn};
+    if (hybrid == 1) {
+      /* unreliable finite-difference geometry: |grad| away from 1 or a large
+       * Hessian component along the normal (a distance function has none) */
+      double gHg = 0.0;
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) gHg += g[a] * H[a][b] * g[b];
+      if (fabs(gn - 1.0) > 0.05 || fabs(gHg) > 0.1 / h) c->bad[m] = 1;
+    } else if (hybrid == 2) {
+      c->bad[m] = 1;
+    }
     for (int a = 0; a < 3; ++a) {
       c->y[3 * m + a] = y[a];
       c->g[3 * m + a] = g[a];
@@ -487,6 +533,86 @@ oc_ctx* oc_build_rows(const double* sdf, int nx, int ny, int nz, const double* o
   }
   c->crow[M] = nnz;
   c->nnz = nnz;
+  if (hybrid) {
+    /* a corrected plane where 1 - |eta| max|kappa| < 0.2 makes D0 near singular */
+    for (int64_t k = 0; k < M; ++k) {
+      double kmax = fmax(fabs(c->kap[2 * k]), fabs(c->kap[2 * k + 1]));
+      for (int64_t e = c->crow[k]; e < c->crow[k + 1]; ++e)
+        if (1.0 - fabs(c->ceta[e]) * kmax < 0.2) c->bad[k] = 1;
+    }
+    /* eq. Jacobian-hybrid: J = 1 at bad nodes */
+    for (int64_t m = 0; m < M; ++m)
+      if (c->bad[m]) {
+        c->J[m] = 1.0;
+        c->w[m] = phi_cos(c->d[m] / eps) / eps;
+      }
+    /* bad rows: the regularised set of eq. (regularized-kernel) replaces N_k */
+    const double tau = c->ktau, reach = eps + h;
+    const double rb = sqrt(tau * tau + reach * reach) + eps;
+    const int W = (int)ceil(rb / h);
+    int64_t cap2 = nnz + 16;
+    for (int64_t k = 0; k < M; ++k)
+      if (c->bad[k]) cap2 += (int64_t)(2 * W + 1) * (2 * W + 1) * (2 * W + 1);
+    int64_t* nrow = (int64_t*)xmalloc(sizeof(int64_t) * (M + 1));
+    int64_t* ncol = (int64_t*)xmalloc(sizeof(int64_t) * cap2);
+    int32_t* npl = (int32_t*)xmalloc(sizeof(int32_t) * cap2);
+    double* nal = (double*)xmalloc(sizeof(double) * cap2);
+    double* nbe = (double*)xmalloc(sizeof(double) * cap2);
+    double* net = (double*)xmalloc(sizeof(double) * cap2);
+    int64_t n2 = 0;
+    for (int64_t k = 0; k < M; ++k) {
+      nrow[k] = n2;
+      if (!c->bad[k]) {
+        for (int64_t e = c->crow[k]; e < c->crow[k + 1]; ++e) {
+          ncol[n2] = c->ccol[e];
+          npl[n2] = c->cplane[e];
+          nal[n2] = c->calpha[e];
+          nbe[n2] = c->cbeta[e];
+          net[n2] = c->ceta[e];
+          ++n2;
+        }
+        continue;
+      }
+      const double* xk = &c->P[3 * k];
+      const double* nk = &c->nrm[3 * k];
+      const int i0 = c->ijk[3 * k], j0 = c->ijk[3 * k + 1], l0 = c->ijk[3 * k + 2];
+      int64_t start = n2;
+      for (int di = -W; di <= W; ++di)
+        for (int dj = -W; dj <= W; ++dj)
+          for (int dl = -W; dl <= W; ++dl) {
+            int i = i0 + di, j = j0 + dj, l = l0 + dl;
+            if (i < 0 || j < 0 || l < 0 || i >= nx || j >= ny || l >= nz) continue;
+            int64_t mm = c->grid_node[((int64_t)i * ny + j) * nz + l];
+            if (mm < 0) continue;
+            const double v0 = (origin[0] + (double)i * h) - xk[0];
+            const double v1 = (origin[1] + (double)j * h) - xk[1];
+            const double v2 = (origin[2] + (double)l * h) - xk[2];
+            const double vn = v0 * nk[0] + v1 * nk[1] + v2 * nk[2];
+            const double t0 = v0 - vn * nk[0], t1 = v1 - vn * nk[1], t2 = v2 - vn * nk[2];
+            const double tt = t0 * t0 + t1 * t1 + t2 * t2;
+            if (!(tt < tau * tau) || !(fabs(vn) <= reach)) continue;
+            ncol[n2] = mm;
+            npl[n2] = -1; /* K-reg entry */
+            nal[n2] = 0.0;
+            nbe[n2] = 0.0;
+            net[n2] = vn;
+            ++n2;
+          }
+      /* column order (insertion sort: short rows) */
+      for (int64_t a = start + 1; a < n2; ++a)
+        for (int64_t b = a; b > start && ncol[b - 1] > ncol[b]; --b) {
+          int64_t tc = ncol[b]; ncol[b] = ncol[b - 1]; ncol[b - 1] = tc;
+          double te = net[b]; net[b] = net[b - 1]; net[b - 1] = te;
+        }
+    }
+    nrow[M] = n2;
+    free(c->crow); free(c->ccol); free(c->cplane); free(c->calpha); free(c->cbeta);
+    free(c->ceta);
+    c->crow = nrow; c->ccol = ncol; c->cplane = npl; c->calpha = nal; c->cbeta = nbe;
+    c->ceta = net;
+    nnz = n2;
+    c->nnz = nnz;
+  }
   c->om11 = (double*)xmalloc(sizeof(double) * (nnz ? nnz : 1));
   c->om21 = (double*)xmalloc(sizeof(double) * (nnz ? nnz : 1));
   for (int64_t e = 0; e < nnz; ++e) c->om11[e] = c->om21[e] = NAN;
@@ -497,6 +623,10 @@ oc_ctx* oc_build_rows(const double* sdf, int nx, int ny, int nz, const double* o
     if (k < 0 || k >= M) continue;
     for (int64_t e = c->crow[k]; e < c->crow[k + 1]; ++e) {
       int ia = c->cplane[e];
+      if (ia < 0) { /* K-reg entry: its constants enter the apply directly */
+        c->om11[e] = c->om21[e] = 0.0;
+        continue;
+      }
       plane_weights(&c->tau[6 * k], &c->tau[6 * k + 3], c->kap[2 * k], c->kap[2 * k + 1],
                     c->ceta[e], (ia + 1) % 3, (ia + 2) % 3, c->calpha[e], c->cbeta[e],
                     eps_in, eps_out, kappa, &c->om11[e], &c->om21[e]);
@@ -506,10 +636,19 @@ oc_ctx* oc_build_rows(const double* sdf, int nx, int ny, int nz, const double* o
   return c;
 }
 
+oc_ctx* oc_build_rows(const double* sdf, int nx, int ny, int nz, const double* origin, double h,
+                      double eps, double eps_in, double eps_out, double kappa,
+                      const int64_t* weight_rows, int64_t n_weight_rows) {
+  return oc_build_hyb(sdf, nx, ny, nz, origin, h, eps, eps_in, eps_out, kappa, 0, weight_rows,
+                      n_weight_rows);
+}
+
 oc_ctx* oc_build(const double* sdf, int nx, int ny, int nz, const double* origin, double h,
                  double eps, double eps_in, double eps_out, double kappa) {
   return oc_build_rows(sdf, nx, ny, nz, origin, h, eps, eps_in, eps_out, kappa, NULL, 0);
 }
+
+void oc_get_bad(const oc_ctx* c, unsigned char* bad) { memcpy(bad, c->bad, (size_t)c->M); }
 
 /* ------------------------------------------------------------------------ */
 /* Kernels K11, K12, K21, K22 of eq. (Kij-kernels) at target x (normal nx)   */
@@ -580,8 +719,13 @@ static void apply_row(const oc_ctx* c, const double* u, int64_t k, char* excl, d
   for (int64_t e = c->crow[k]; e < c->crow[k + 1]; ++e) {
     int64_t m = c->ccol[e];
     double a1 = u[m] * c->w[m], a2 = u[M + m] * c->w[m];
-    c1 += h2 * c->om11[e] * a1 - h3 * w12 * a2;
-    c2 += h2 * c->om21[e] * a1 - h2 * (-r22 * c->om11[e]) * a2;
+    if (c->cplane[e] < 0) {
+      /* K-reg: the regularised kernels are the constants 0, C12, 0, 0 */
+      c1 += -h3 * c->c12 * a2;
+    } else {
+      c1 += h2 * c->om11[e] * a1 - h3 * w12 * a2;
+      c2 += h2 * c->om21[e] * a1 - h2 * (-r22 * c->om11[e]) * a2;
+    }
     excl[m] = 0;
   }
   *o1 = lam1 * u[k] + h3 * s1 + c1;
@@ -671,17 +815,42 @@ double oc_area(const oc_ctx* c) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* Restarted GMRES(m): x0 = 0, modified Gram-Schmidt, Givens rotations.      */
+/* Restarted GMRES(m): x0 = 0, modified Gram-Schmidt, Givens rotations.
+ * precond = 1 solves D^-1 A x = D^-1 b with D = Lambda (lambda1 on the psi
+ * rows, lambda2 on the psi_n rows): each block row divided by its free-term
+ * coefficient; residuals and the stopping test are those of that system.    */
+static void apply_op(const oc_ctx* c, int precond, const double* u, double* out) {
+  oc_apply(c, u, out);
+  if (!precond) return;
+  const int64_t M = c->M;
+  const double lam1 = 0.5 * (1.0 + c->eps_out / c->eps_in);
+  const double lam2 = 0.5 * (1.0 + c->eps_in / c->eps_out);
+  for (int64_t k = 0; k < M; ++k) {
+    out[k] /= lam1;
+    out[M + k] /= lam2;
+  }
+}
+
 static double dot(const double* a, const double* b, int64_t n) {
   double s = 0.0;
   for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
   return s;
 }
 
-int oc_gmres(const oc_ctx* c, const double* b, double tol, int restart, int maxit, double* x,
-             int* iters, double* est_relres, double* true_relres) {
+int oc_gmres(const oc_ctx* c, const double* b_in, double tol, int restart, int maxit,
+             int precond, double* x, int* iters, double* est_relres, double* true_relres) {
   const int64_t N = 2 * c->M;
   const int m = restart;
+  double* b = (double*)xmalloc(sizeof(double) * N);
+  memcpy(b, b_in, sizeof(double) * N);
+  if (precond) {
+    const double lam1 = 0.5 * (1.0 + c->eps_out / c->eps_in);
+    const double lam2 = 0.5 * (1.0 + c->eps_in / c->eps_out);
+    for (int64_t k = 0; k < c->M; ++k) {
+      b[k] /= lam1;
+      b[c->M + k] /= lam2;
+    }
+  }
   double* V = (double*)xmalloc(sizeof(double) * (size_t)N * (m + 1));
   double* H = (double*)calloc((size_t)(m + 1) * m, sizeof(double)); /* H[i*m + j] */
   double* cs = (double*)xmalloc(sizeof(double) * m);
@@ -697,12 +866,12 @@ int oc_gmres(const oc_ctx* c, const double* b, double tol, int restart, int maxi
     *iters = 0;
     *est_relres = 0.0;
     *true_relres = 0.0;
-    free(V); free(H); free(cs); free(sn); free(gv); free(yv); free(r);
+    free(V); free(H); free(cs); free(sn); free(gv); free(yv); free(r); free(b);
     return 0;
   }
   while (total < maxit && !converged) {
     /* r = b - A x */
-    oc_apply(c, x, r);
+    apply_op(c, precond, x, r);
     for (int64_t i = 0; i < N; ++i) r[i] = b[i] - r[i];
     double beta = sqrt(dot(r, r, N));
     if (beta <= tol * bnorm) {
@@ -717,7 +886,7 @@ int oc_gmres(const oc_ctx* c, const double* b, double tol, int restart, int maxi
     int jend = 0;
     for (int j = 0; j < m; ++j) {
       double* w = &V[(size_t)(j + 1) * N];
-      oc_apply(c, &V[(size_t)j * N], w);
+      apply_op(c, precond, &V[(size_t)j * N], w);
       ++total;
       for (int i = 0; i <= j; ++i) {
         double hij = dot(&V[(size_t)i * N], w, N);
@@ -758,12 +927,12 @@ int oc_gmres(const oc_ctx* c, const double* b, double tol, int restart, int maxi
     for (int i = 0; i < jend; ++i)
       for (int64_t t = 0; t < N; ++t) x[t] += yv[i] * V[(size_t)i * N + t];
   }
-  oc_apply(c, x, r);
+  apply_op(c, precond, x, r);
   for (int64_t i = 0; i < N; ++i) r[i] = b[i] - r[i];
   *true_relres = sqrt(dot(r, r, N)) / bnorm;
   *est_relres = resid / bnorm;
   *iters = total;
-  free(V); free(H); free(cs); free(sn); free(gv); free(yv); free(r);
+  free(V); free(H); free(cs); free(sn); free(gv); free(yv); free(r); free(b);
   return converged ? 0 : 1;
 }
 

@@ -1,11 +1,13 @@
-"""Write the stored oracle values for the full-size Kirkwood workload.
+"""Write the stored oracle values for the full-size workloads.
 
-Calls only ``oracle`` and ``workloads``.  Output: ``kirkwood_R10_h0.25.json``
-beside this script.  The full oracle solve at this size (~1.2e5 tube nodes,
-1.45e10 pair evaluations per operator application) takes about an hour on
-eight cores, so its results are stored instead of recomputed in every test.
+Calls only ``oracle`` and ``workloads``.  Outputs beside this script:
+``kirkwood_R10_h0.25.json`` (Kirkwood sphere), ``ses500_h0.3.json``
+(500-atom molecule) and, with --no-solve, ``ses2000_h0.35.json`` (sampled
+rows only).  A full oracle solve at these sizes (1.2e5-1.3e5 tube nodes,
+~1.5e10 pair evaluations per operator application) takes 30-60 minutes on
+eight cores, so the results are stored instead of recomputed in every test.
 
-Usage: python tests/golden/make_golden.py
+Usage: python tests/golden/make_golden.py [kirkwood|ses500|ses2000] [--no-solve]
 """
 import json
 import os
@@ -25,10 +27,24 @@ SEED_ROWS = 77
 SEED_U = 78
 
 
+OUTPUT = {"kirkwood": "kirkwood_R10_h0.25.json", "ses500": "ses500_h0.3.json",
+          "ses2000": "ses2000_h0.35.json"}
+
+
 def main():
-    wl = workloads.by_name("kirkwood")
+    name = sys.argv[1] if len(sys.argv) > 1 and not sys.argv[1].startswith("-") else "kirkwood"
+    solve = "--no-solve" not in sys.argv
+    wl = workloads.by_name(name)
     t0 = time.time()
-    o = oracle.Oracle.from_workload(wl)
+    rng = np.random.Generator(np.random.PCG64(SEED_ROWS))
+    if solve:
+        o = oracle.Oracle.from_workload(wl)
+    else:
+        # weights only at the sampled rows (the other rows are never applied)
+        o0 = oracle.Oracle.from_workload(wl, weight_rows=np.zeros(1, dtype=np.int64))
+        rows0 = np.sort(rng.choice(o0.M, size=N_SAMPLE, replace=False))
+        rng = np.random.Generator(np.random.PCG64(SEED_ROWS))
+        o = oracle.Oracle.from_workload(wl, weight_rows=rows0)
     t_setup = time.time() - t0
     M = o.M
     print(f"M={M} nnz={o.nnz} setup {t_setup:.1f}s threads={oracle.num_threads()}", flush=True)
@@ -46,11 +62,6 @@ def main():
         for e in range(corr["row"][r], corr["row"][r + 1]):
             sel.append(e)
     sel = np.array(sel, dtype=np.int64)
-    t0 = time.time()
-    x, info = o.gmres(g, wl.tol, restart=60, maxit=300)
-    t_solve = time.time() - t0
-    gpol = o.energy(x, wl.charge_xyz, wl.charge_q)
-    print(f"solve {t_solve:.1f}s info={info} gpol={gpol!r}", flush=True)
     out = {
         "workload": wl.describe(),
         "M": M,
@@ -66,14 +77,21 @@ def main():
         "corr_col": corr["col"][sel].tolist(),
         "corr_om11": corr["om11"][sel].tolist(),
         "corr_om21": corr["om21"][sel].tolist(),
-        "gmres": {"tol": wl.tol, "restart": 60, **info},
-        "g_pol": gpol,
-        "x_rows_1": x[rows].tolist(),
-        "x_rows_2": x[M + rows].tolist(),
-        "oracle_seconds": {"setup": t_setup, "sampled_apply": t_rows, "solve": t_solve,
+        "oracle_seconds": {"setup": t_setup, "sampled_apply": t_rows,
                            "threads": oracle.num_threads()},
     }
-    path = os.path.join(HERE, "kirkwood_R10_h0.25.json")
+    if solve:
+        t0 = time.time()
+        x, info = o.gmres(g, wl.tol, restart=60, maxit=300, precond=1)
+        t_solve = time.time() - t0
+        gpol = o.energy(x, wl.charge_xyz, wl.charge_q)
+        print(f"solve {t_solve:.1f}s info={info} gpol={gpol!r}", flush=True)
+        out["gmres"] = {"tol": wl.tol, "restart": 60, "precond": 1, **info}
+        out["g_pol"] = gpol
+        out["x_rows_1"] = x[rows].tolist()
+        out["x_rows_2"] = x[M + rows].tolist()
+        out["oracle_seconds"]["solve"] = t_solve
+    path = os.path.join(HERE, OUTPUT[name])
     with open(path + ".tmp", "w") as f:
         json.dump(out, f, indent=1)
     os.replace(path + ".tmp", path)
