@@ -66,7 +66,39 @@ typedef struct {
                           and inspection only, no device memory) */
   double r_near;       /* IBIM_MIXED: pairs closer than r_near (Angstrom) are
                           re-evaluated in float64 (default 0 = 4 h) */
+  int hybrid;          /* IBIM_CTR2 (default), IBIM_HYB or IBIM_KREG, below */
+  int precond;         /* IBIM_PRECOND_DIAG (default) or IBIM_PRECOND_NONE, below */
 } ibim_options;
+
+/*
+ * System handed to GMRES (Section 2.5):
+ *  IBIM_PRECOND_DIAG  Lambda^-1 A p = Lambda^-1 g: each block row divided by its
+ *                     free-term coefficient (lambda1 = (1 + eps_E/eps_I)/2 on the
+ *                     psi rows, lambda2 = (1 + eps_I/eps_E)/2 on the psi_n rows).
+ *                     Same solution; the stopping test and the reported residuals
+ *                     refer to the scaled system.
+ *  IBIM_PRECOND_NONE  A p = g as written in eq. (linear-system).
+ */
+#define IBIM_PRECOND_NONE 0
+#define IBIM_PRECOND_DIAG 1
+
+/*
+ * Quadrature of the rows (Section 3.2, eq. linear-system-hyb):
+ *  IBIM_CTR2  corrected trapezoidal rule CTR2 in every row.
+ *  IBIM_HYB   HYB-IBIM: rows of "bad" nodes, whose finite-difference geometry
+ *             is unreliable (| |grad_h d| - 1 | > 0.05, or |g.H g| > 0.1/h for
+ *             the normalised gradient g and Hessian H, or a corrected plane with
+ *             1 - |eta| max|kappa| < 0.2), use the kernel regularisation K-reg
+ *             of eq. (regularized-kernel) with tau = 2h, and bad nodes carry
+ *             J = 1 (eq. Jacobian-hybrid); other rows use CTR2.
+ *  IBIM_KREG  every node bad (K-reg rows and J = 1 everywhere).
+ * K-reg replaces the kernels by their tangent-disc means for the tube nodes y
+ * with |(I - n n^T)(y - P(y_k))| < tau and |n.(y - P(y_k))| <= eps + h: 0 for
+ * K11, K21, K22 and (e^{-k tau} - 1 + k tau) / (2 pi k tau^2) for K12.
+ */
+#define IBIM_CTR2 0
+#define IBIM_HYB 1
+#define IBIM_KREG 2
 
 typedef struct {
   int iters;                 /* GMRES iterations */
@@ -126,6 +158,10 @@ int ibim_node_grid_index(const ibim_ctx* ctx, int64_t* idx);
  */
 int ibim_node_geometry(const ibim_ctx* ctx, double* P, double* n, double* w);
 
+/* bad (host, M): 1 for the nodes of M_B (K-reg row, J = 1), else 0.  All zero
+ * with IBIM_CTR2.  *n_bad (may be NULL) receives their number. */
+int ibim_node_flags(const ibim_ctx* ctx, uint8_t* bad, int64_t* n_bad);
+
 /* Number of correction entries (sum over rows of |N_h(y_k)|). */
 int ibim_num_corrections(const ibim_ctx* ctx, int64_t* nnz);
 
@@ -133,8 +169,9 @@ int ibim_num_corrections(const ibim_ctx* ctx, int64_t* nnz);
  * Host copies of the correction sets N_h(y_k) (Section 2.4): rowptr (M+1),
  * col (nnz, sorted ascending in each row), axis (nnz, dominant axis 0..2),
  * alpha, beta (nnz, shifts of the nearest node in [-1/2, 1/2)), eta (nnz,
- * signed distance of the normal-line point in that plane).  Any pointer may
- * be NULL.
+ * signed distance of the normal-line point in that plane).  In K-reg rows
+ * the entries are the regularised nodes: axis -1, alpha = beta = 0, eta the
+ * normal offset n.(y - P(y_k)).  Any pointer may be NULL.
  */
 int ibim_corrections(const ibim_ctx* ctx, int64_t* rowptr, int64_t* col, int32_t* axis,
                      double* alpha, double* beta, double* eta);

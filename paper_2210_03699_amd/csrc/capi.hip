@@ -100,6 +100,13 @@ __global__ void fill_kernel(double* x, int64_t n, double v) {
   if (r < n) x[r] = v;
 }
 
+// y = D^-1 x with D = Lambda: the psi rows divided by lambda1, the psi_n rows by lambda2.
+__global__ void unscale_kernel(const double* x, double* y, int64_t M, double lam1, double lam2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < M) y[i] = x[i] / lam1;
+  else if (i < 2 * M) y[i] = x[i] / lam2;
+}
+
 __global__ void copy_kernel(const double* a, double* b, int64_t n) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r < n) b[r] = a[r];
@@ -191,9 +198,10 @@ int ensure_krylov(ibim_ctx* c) {
   HIP_TRY(dalloc(&k.partial, (m + 1) * 1024), "alloc");
   HIP_TRY(dalloc(&k.tmp, (size_t)k.n), "alloc");
   HIP_TRY(dalloc(&k.tmp2, (size_t)k.n), "alloc");
+  HIP_TRY(dalloc(&k.bsc, (size_t)k.n), "alloc");
   HIP_TRY(hipHostMalloc((void**)&k.host_status, 4 * sizeof(double), hipHostMallocDefault),
           "pinned allocation");
-  c->device_bytes += ((m + 3) * (size_t)k.n + (m + 1) * (m + 1030) + 8 * m) * sizeof(double);
+  c->device_bytes += ((m + 4) * (size_t)k.n + (m + 1) * (m + 1030) + 8 * m) * sizeof(double);
   c->kr_ready = true;
   return IBIM_OK;
 }
@@ -214,6 +222,10 @@ int ctx_create_host(const double* sdf, int nx, int ny, int nz, const double orig
     return fail(IBIM_EINVAL, "r_near must be >= 0");
   if (o.restart < 1 || o.restart > 1000 || o.max_iter < 1)
     return fail(IBIM_EINVAL, "restart must be in [1, 1000] and max_iter >= 1");
+  if (o.hybrid != IBIM_CTR2 && o.hybrid != IBIM_HYB && o.hybrid != IBIM_KREG)
+    return fail(IBIM_EINVAL, "unknown hybrid mode");
+  if (o.precond != IBIM_PRECOND_NONE && o.precond != IBIM_PRECOND_DIAG)
+    return fail(IBIM_EINVAL, "unknown preconditioning mode");
   ibim_ctx* c = new (std::nothrow) ibim_ctx();
   if (!c) return fail(IBIM_ENOMEM, "host allocation failed");
   c->opt = o;
@@ -228,7 +240,7 @@ int ctx_create_host(const double* sdf, int nx, int ny, int nz, const double orig
     c->q.assign(charge_q, charge_q + (size_t)n_charges);
   }
   std::string err;
-  int r = build_host_plan(sdf, nx, ny, nz, origin, h, eps_tube, &c->plan, &err);
+  int r = build_host_plan(sdf, nx, ny, nz, origin, h, eps_tube, o.hybrid, &c->plan, &err);
   if (r) {
     delete c;
     return fail(r, err);
@@ -255,7 +267,7 @@ size_t ctx_footprint_estimate(const ibim_ctx* c) {
   else
     b += (size_t)pp.nsplit * n * 8;
   // Krylov basis and GMRES scratch (as allocated by ensure_krylov)
-  b += ((m + 3) * n + (m + 1) * (m + 1030) + 8 * m) * 8;
+  b += ((m + 4) * n + (m + 1) * (m + 1030) + 8 * m) * 8;
   if (c->opt.precision == IBIM_MIXED) {
     const double h = pl.h, eps = pl.eps;
     const double rn = c->opt.r_near > 0.0 ? c->opt.r_near : 4.0 * h;
@@ -347,6 +359,7 @@ int ctx_setup_device(ibim_ctx* c, hipStream_t s) {
     wa.eps_out = c->eps_out;
     wa.kappa = c->kappa;
     wa.h = h;
+    wa.c12 = kreg_constant(c->kappa, pl.ktau);
     wa.om11 = c->om11;
     wa.om21 = c->om21;
     wa.blocks = P.blocks;
@@ -464,6 +477,13 @@ hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_row_scaling(const ibim_ctx* c, const double* x, double* y, hipStream_t s) {
+  const int64_t M = c->P.M;
+  hipLaunchKernelGGL(unscale_kernel, dim3((unsigned)((2 * M + 255) / 256)), dim3(256), 0, s, x, y,
+                     M, c->P.lam1, c->P.lam2);
+  return hipGetLastError();
+}
+
 hipError_t launch_copy(const double* a, double* b, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(copy_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, b, n);
   return hipGetLastError();
@@ -481,6 +501,8 @@ void ibim_default_options(ibim_options* opt) {
   opt->check_residual = 1;
   opt->device = 0;
   opt->r_near = 0.0;
+  opt->hybrid = IBIM_CTR2;
+  opt->precond = IBIM_PRECOND_DIAG;
 }
 
 const char* ibim_last_error(void) { return g_last_error.c_str(); }
@@ -557,6 +579,14 @@ int ibim_num_corrections(const ibim_ctx* ctx, int64_t* nnz) {
   return IBIM_OK;
 }
 
+int ibim_node_flags(const ibim_ctx* ctx, uint8_t* bad, int64_t* n_bad) {
+  if (int r = check_ctx(ctx)) return r;
+  const HostPlan& pl = ctx->plan;
+  if (bad) std::memcpy(bad, pl.bad.data(), (size_t)pl.M);
+  if (n_bad) *n_bad = pl.n_bad;
+  return IBIM_OK;
+}
+
 int ibim_corrections(const ibim_ctx* ctx, int64_t* rowptr, int64_t* col, int32_t* axis,
                      double* alpha, double* beta, double* eta) {
   if (int r = check_ctx(ctx)) return r;
@@ -619,8 +649,20 @@ int ibim_solve(ibim_ctx* ctx, const double* rhs, double tol, double* x, ibim_sol
   const int m = K.m;
   const unsigned nblk = (unsigned)((N + 255) / 256);
   double hv[2];
+  // the system handed to GMRES: A x = b, or Lambda^-1 A x = Lambda^-1 b
+  const bool diag = ctx->opt.precond == IBIM_PRECOND_DIAG;
+  const double* b = rhs;
+  if (diag) {
+    HIP_TRY(launch_row_scaling(ctx, rhs, K.bsc, s), "row scaling");
+    b = K.bsc;
+  }
+  auto op = [&](const double* u, double* out) -> int {
+    if (int r = apply_impl(ctx, u, out, s)) return r;
+    if (diag) HIP_TRY(launch_row_scaling(ctx, out, out, s), "row scaling");
+    return IBIM_OK;
+  };
 
-  HIP_TRY(K.dots(rhs, N, 1, rhs, N, K.scal + 1, 0, s), "dots");
+  HIP_TRY(K.dots(b, N, 1, b, N, K.scal + 1, 0, s), "dots");
   if (int r = fetch(ctx, K.scal + 1, 1, s, hv)) return r;
   const double bnorm = std::sqrt(hv[0]);
   hipLaunchKernelGGL(fill_kernel, dim3(nblk), dim3(256), 0, s, x, N, 0.0);
@@ -637,11 +679,11 @@ int ibim_solve(ibim_ctx* ctx, const double* rhs, double tol, double* x, ibim_sol
   while (total < ctx->opt.max_iter && !converged) {
     // r = b - A x (x = 0 on the first cycle, where A x = 0 exactly)
     if (first) {
-      hipLaunchKernelGGL(copy_kernel, dim3(nblk), dim3(256), 0, s, rhs, K.tmp, N);
+      hipLaunchKernelGGL(copy_kernel, dim3(nblk), dim3(256), 0, s, b, K.tmp, N);
       HIP_TRY(hipGetLastError(), "copy");
     } else {
-      if (int r = apply_impl(ctx, x, K.tmp2, s)) return r;
-      HIP_TRY(K.residual(rhs, K.tmp2, K.tmp, N, s), "residual");
+      if (int r = op(x, K.tmp2)) return r;
+      HIP_TRY(K.residual(b, K.tmp2, K.tmp, N, s), "residual");
     }
     first = false;
     HIP_TRY(K.dots(K.tmp, N, 1, K.tmp, N, K.scal + 1, 0, s), "dots");
@@ -659,7 +701,7 @@ int ibim_solve(ibim_ctx* ctx, const double* rhs, double tol, double* x, ibim_sol
     for (int j = 0; j < m; ++j) {
       double* vj = K.V + (int64_t)j * N;
       double* w = K.V + (int64_t)(j + 1) * N;
-      if (int r = apply_impl(ctx, vj, w, s)) return r;
+      if (int r = op(vj, w)) return r;
       ++total;
       // classical Gram-Schmidt, twice
       HIP_TRY(K.dots(K.V, N, j + 1, w, N, K.hcol, 0, s), "dots");
@@ -684,8 +726,8 @@ int ibim_solve(ibim_ctx* ctx, const double* rhs, double tol, double* x, ibim_sol
   }
   double explicit_rel = -1.0;
   if (ctx->opt.check_residual) {
-    if (int r = apply_impl(ctx, x, K.tmp2, s)) return r;
-    HIP_TRY(K.residual(rhs, K.tmp2, K.tmp, N, s), "residual");
+    if (int r = op(x, K.tmp2)) return r;
+    HIP_TRY(K.residual(b, K.tmp2, K.tmp, N, s), "residual");
     HIP_TRY(K.dots(K.tmp, N, 1, K.tmp, N, K.scal + 2, 0, s), "dots");
     if (int r = fetch(ctx, K.scal + 2, 1, s, hv)) return r;
     explicit_rel = std::sqrt(hv[0]) / bnorm;

@@ -115,7 +115,7 @@ struct ibim_ctx {
     dfree(partial); dfree(om11); dfree(om21); dfree(d_zq); dfree(d_q); dfree(d_psi);
     dfree(kr.V); dfree(kr.H); dfree(kr.cs); dfree(kr.sn); dfree(kr.g); dfree(kr.y);
     dfree(kr.hcol); dfree(kr.hcol2); dfree(kr.scal); dfree(kr.status); dfree(kr.partial);
-    dfree(kr.tmp); dfree(kr.tmp2);
+    dfree(kr.tmp); dfree(kr.tmp2); dfree(kr.bsc);
     if (kr.host_status) (void)hipHostFree(kr.host_status);
     kr.host_status = nullptr;
     for (hipEvent_t e : tev) (void)hipEventDestroy(e);
@@ -145,5 +145,7 @@ int energy_launch(ibim_ctx* c, const double* x, hipStream_t s);
 double energy_sum(const ibim_ctx* c, const double* psi_host);
 hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t s);
 hipError_t launch_copy(const double* a, double* b, int64_t n, hipStream_t s);
+// y = Lambda^-1 x (x == y allowed): the row scaling of IBIM_PRECOND_DIAG.
+hipError_t launch_row_scaling(const ibim_ctx* c, const double* x, double* y, hipStream_t s);
 
 }  // namespace ibim

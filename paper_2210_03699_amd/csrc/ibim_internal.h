@@ -26,12 +26,17 @@ struct HostPlan {
   std::vector<int64_t> crow;        // M+1
   std::vector<int32_t> ccol;        // nnz
   std::vector<int32_t> crowid;      // nnz: owning row
-  std::vector<int8_t> caxis;        // nnz: dominant axis of the row
+  std::vector<int8_t> caxis;        // nnz: dominant axis of the row; -1: K-reg entry
   std::vector<double> calpha, cbeta, ceta;
+  // HYB-IBIM: nodes in M_B (K-reg rows, J = 1) and the K-reg constant of K12
+  std::vector<uint8_t> bad;         // M
+  double ktau = 0.0;                // K-reg radius (2h)
+  int64_t n_bad = 0;
 };
 
 // Builds the plan; returns 0 or a negative IBIM_E* code with *err set.
+// hybrid: 0 CTR2 rows everywhere, 1 HYB-IBIM, 2 every node bad (K-reg).
 int build_host_plan(const double* sdf, int nx, int ny, int nz, const double origin[3], double h,
-                    double eps, HostPlan* plan, std::string* err);
+                    double eps, int hybrid, HostPlan* plan, std::string* err);
 
 }  // namespace ibim

@@ -23,6 +23,7 @@ struct Krylov {
   double* partial = nullptr;  // (m+1) * 1024 reduction scratch
   double* tmp = nullptr;   // n: residual / scratch vector
   double* tmp2 = nullptr;  // n: scratch vector
+  double* bsc = nullptr;   // n: right-hand side of the row-scaled system
   double* host_status = nullptr;  // pinned host mirror of status
 
   static int dot_blocks(int64_t n);

@@ -185,6 +185,8 @@ int admit(ibim_server* srv, Request* r) {
   r->M = c->P.M;
   double* st = srv->d_status + (size_t)r->slot * kStatusStride;
   if (int e = rhs_impl(c, r->d_b, s)) return e;
+  if (c->opt.precond == IBIM_PRECOND_DIAG)
+    HIP_TRY(launch_row_scaling(c, r->d_b, r->d_b, s), "row scaling");  // as ibim_solve
   Krylov& K = c->kr;
   HIP_TRY(K.dots(r->d_b, N, 1, r->d_b, N, st + 2, 0, s), "dots");
   HIP_TRY(launch_fill(r->d_x, N, 0.0, s), "fill");
@@ -383,6 +385,8 @@ int step_impl(ibim_server* srv) {
       HIP_TRY(launch_finish_mixed(c->P, c->pair, u, c->partial, out, s), "finish");
     else
       HIP_TRY(launch_finish(c->P, c->pair, c->opt.precision, u, c->partial, out, s), "finish");
+    if (c->opt.precond == IBIM_PRECOND_DIAG)
+      HIP_TRY(launch_row_scaling(c, out, out, s), "row scaling");
     r->applies++;
     if (r->phase == Phase::kIter) {
       const int j = r->j;

@@ -14,10 +14,18 @@
 // nearest grid node (shift (alpha, beta) in [-1/2, 1/2)) is corrected when it
 // lies in the tube.  eta = -s is the signed distance of L.
 //
-// The quantities that decide which node is corrected (gradient, P, n, the
-// dominant axis, L and the nearest node) are evaluated with plain IEEE
-// operations in a fixed order and without contraction (this file is
-// compiled with -ffp-contract=off), so the sets are reproducible exactly.
+// HYB-IBIM (Section 3.2): a node is bad when its finite-difference geometry
+// is unreliable (| |grad d| - 1 | > 0.05, |g.H g| > 0.1/h, or a corrected
+// plane with 1 - |eta| max|kappa| < 0.2).  Bad rows take the K-reg rule of
+// eq. (regularized-kernel) with tau = 2h over the tube nodes y with
+// tangential distance |(I - n n^T)(y - x*)| < tau and normal distance
+// |n.(y - x*)| <= eps + h; bad nodes carry J = 1 (eq. Jacobian-hybrid).
+//
+// The quantities that decide which node is corrected, regularised or bad
+// (gradient, Hessian, P, n, the dominant axis, L, the nearest node, the
+// tangential distance) are evaluated with plain IEEE operations in a fixed
+// order and without contraction (this file is compiled with
+// -ffp-contract=off), so the sets are reproducible exactly.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -82,13 +90,17 @@ struct Candidate {
 }  // namespace
 
 int build_host_plan(const double* sdf, int nx, int ny, int nz, const double origin[3], double h,
-                    double eps, HostPlan* plan, std::string* err) {
+                    double eps, int hybrid, HostPlan* plan, std::string* err) {
   if (!sdf || !origin || !plan || nx < 5 || ny < 5 || nz < 5) {
     *err = "null pointer or grid smaller than 5 nodes per axis";
     return IBIM_EINVAL;
   }
   if (!(h > 0.0) || !(eps > 0.0) || !std::isfinite(h) || !std::isfinite(eps)) {
     *err = "h and eps_tube must be positive and finite";
+    return IBIM_EINVAL;
+  }
+  if (hybrid < 0 || hybrid > 2) {
+    *err = "hybrid must be 0, 1 or 2";
     return IBIM_EINVAL;
   }
   const int64_t ngrid = (int64_t)nx * ny * nz;
@@ -130,6 +142,9 @@ int build_host_plan(const double* sdf, int nx, int ny, int nz, const double orig
   G.px.resize(M); G.py.resize(M); G.pz.resize(M);
   G.nx.resize(M); G.ny.resize(M); G.nz.resize(M);
   G.w.resize(M); G.kap1.resize(M); G.kap2.resize(M); G.tau.resize(6 * M);
+  G.bad.assign(M, hybrid == 2 ? 1 : 0);
+  G.ktau = 2.0 * h;
+  std::vector<double> dval(M);
   std::vector<int32_t> ijk(3 * M);
   int edge = 0;
   for (int64_t m = 0; m < M; ++m) {
@@ -145,7 +160,6 @@ int build_host_plan(const double* sdf, int nx, int ny, int nz, const double orig
     return IBIM_EGEOM;
   }
 
-  const double inv4h2 = 1.0 / (4.0 * h * h);
   int bad_grad = 0;
 #pragma omp parallel for schedule(static) reduction(| : bad_grad)
   for (int64_t m = 0; m < M; ++m) {
@@ -171,17 +185,26 @@ int build_host_plan(const double* sdf, int nx, int ny, int nz, const double orig
     G.ny[m] = -g[1];
     G.nz[m] = -g[2];
 
-    // Hessian, central difference of the central gradient
+    // Hessian, central difference of the central gradient (each entry as
+    // (sum of the stencil values in a fixed order) / (4 h^2))
+    const double fh2 = 4.0 * h * h;
     double H[3][3];
-    H[0][0] = (D(i + 2, j, k) + D(i - 2, j, k) - 2.0 * d0) * inv4h2;
-    H[1][1] = (D(i, j + 2, k) + D(i, j - 2, k) - 2.0 * d0) * inv4h2;
-    H[2][2] = (D(i, j, k + 2) + D(i, j, k - 2) - 2.0 * d0) * inv4h2;
-    H[0][1] = H[1][0] = ((D(i + 1, j + 1, k) + D(i - 1, j - 1, k)) -
-                         (D(i + 1, j - 1, k) + D(i - 1, j + 1, k))) * inv4h2;
-    H[0][2] = H[2][0] = ((D(i + 1, j, k + 1) + D(i - 1, j, k - 1)) -
-                         (D(i + 1, j, k - 1) + D(i - 1, j, k + 1))) * inv4h2;
-    H[1][2] = H[2][1] = ((D(i, j + 1, k + 1) + D(i, j - 1, k - 1)) -
-                         (D(i, j + 1, k - 1) + D(i, j - 1, k + 1))) * inv4h2;
+    H[0][0] = (D(i + 2, j, k) - 2.0 * d0 + D(i - 2, j, k)) / fh2;
+    H[1][1] = (D(i, j + 2, k) - 2.0 * d0 + D(i, j - 2, k)) / fh2;
+    H[2][2] = (D(i, j, k + 2) - 2.0 * d0 + D(i, j, k - 2)) / fh2;
+    H[0][1] = H[1][0] = (D(i + 1, j + 1, k) - D(i + 1, j - 1, k) - D(i - 1, j + 1, k) +
+                         D(i - 1, j - 1, k)) / fh2;
+    H[0][2] = H[2][0] = (D(i + 1, j, k + 1) - D(i + 1, j, k - 1) - D(i - 1, j, k + 1) +
+                         D(i - 1, j, k - 1)) / fh2;
+    H[1][2] = H[2][1] = (D(i, j + 1, k + 1) - D(i, j + 1, k - 1) - D(i, j - 1, k + 1) +
+                         D(i, j - 1, k - 1)) / fh2;
+    if (hybrid == 1) {
+      double gHg = 0.0;
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) gHg += g[a] * H[a][b] * g[b];
+      if (std::fabs(gn - 1.0) > 0.05 || std::fabs(gHg) > 0.1 / h) G.bad[m] = 1;
+    }
+    dval[m] = d0;
     // Shape operator of the level set: tangential part of H.  Adding a large
     // multiple of g g^T isolates the normal direction as the top eigenvector,
     // so the other two eigenvectors span the tangent plane exactly even when
@@ -287,6 +310,58 @@ int build_host_plan(const double* sdf, int nx, int ny, int nz, const double orig
            " is not the nearest node of its own normal line (reach violated or degenerate normal)";
     return IBIM_EGEOM;
   }
+  if (hybrid) {
+    // bad rows by the plane margin, then J = 1 and the K-reg sets at bad nodes
+    for (int64_t k = 0; k < M; ++k) {
+      const double kmax = std::fmax(std::fabs(G.kap1[k]), std::fabs(G.kap2[k]));
+      const Candidate* in = &cand[(size_t)k * cap];
+      for (int c = 0; c < count[k]; ++c)
+        if (1.0 - std::fabs(in[c].eta) * kmax < 0.2) G.bad[k] = 1;
+    }
+    for (int64_t m = 0; m < M; ++m)
+      if (G.bad[m]) {
+        const double xi = dval[m] / eps;
+        const double phi = (std::fabs(xi) <= 1.0) ? 0.5 * (1.0 + std::cos(kPi * xi)) : 0.0;
+        G.w[m] = phi / eps;
+      }
+  }
+  std::vector<std::vector<Candidate>> kreg(M);
+  if (hybrid) {
+    const double tau = G.ktau, reach = eps + h;
+    const double rb = std::sqrt(tau * tau + reach * reach) + eps;
+    const int W = (int)std::ceil(rb / h);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t k = 0; k < M; ++k) {
+      if (!G.bad[k]) continue;
+      const double xk[3] = {G.px[k], G.py[k], G.pz[k]};
+      const double nk[3] = {G.nx[k], G.ny[k], G.nz[k]};
+      const int i0 = ijk[3 * k], j0 = ijk[3 * k + 1], l0 = ijk[3 * k + 2];
+      std::vector<Candidate>& out = kreg[k];
+      for (int di = -W; di <= W; ++di)
+        for (int dj = -W; dj <= W; ++dj)
+          for (int dl = -W; dl <= W; ++dl) {
+            const int i = i0 + di, j = j0 + dj, l = l0 + dl;
+            if (i < 0 || j < 0 || l < 0 || i >= nx || j >= ny || l >= nz) continue;
+            const int32_t mm = node_of[((int64_t)i * ny + j) * nz + l];
+            if (mm < 0) continue;
+            const double v0 = (origin[0] + (double)i * h) - xk[0];
+            const double v1 = (origin[1] + (double)j * h) - xk[1];
+            const double v2 = (origin[2] + (double)l * h) - xk[2];
+            const double vn = v0 * nk[0] + v1 * nk[1] + v2 * nk[2];
+            const double t0 = v0 - vn * nk[0], t1 = v1 - vn * nk[1], t2 = v2 - vn * nk[2];
+            const double tt = t0 * t0 + t1 * t1 + t2 * t2;
+            if (!(tt < tau * tau) || !(std::fabs(vn) <= reach)) continue;
+            out.push_back(Candidate{mm, (int8_t)-1, 0.0, 0.0, vn});
+          }
+      std::sort(out.begin(), out.end(),
+                [](const Candidate& a, const Candidate& b) { return a.col < b.col; });
+    }
+    for (int64_t k = 0; k < M; ++k) {
+      if (!G.bad[k]) continue;
+      count[k] = (int32_t)kreg[k].size();
+      ++G.n_bad;
+    }
+  }
   G.crow.resize(M + 1);
   G.crow[0] = 0;
   for (int64_t k = 0; k < M; ++k) G.crow[k + 1] = G.crow[k] + count[k];
@@ -299,7 +374,7 @@ int build_host_plan(const double* sdf, int nx, int ny, int nz, const double orig
   G.calpha.resize(nnz); G.cbeta.resize(nnz); G.ceta.resize(nnz);
 #pragma omp parallel for schedule(static)
   for (int64_t k = 0; k < M; ++k) {
-    const Candidate* in = &cand[(size_t)k * cap];
+    const Candidate* in = G.bad[k] ? kreg[k].data() : &cand[(size_t)k * cap];
     for (int c = 0; c < count[k]; ++c) {
       const int64_t e = G.crow[k] + c;
       G.ccol[e] = in[c].col;

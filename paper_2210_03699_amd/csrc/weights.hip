@@ -18,6 +18,8 @@
 // samples, the Fourier modes and the lattice points.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include <cstdint>
 
 #include "weights.h"
@@ -61,9 +63,12 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock) void weights_kernel(WeightAr
   const int64_t e = valid ? e_raw : a.nnz - 1;
 
   const int32_t k = a.rowid[e];
-  const int ax = a.axis[e];
+  // K-reg entries (axis -1) run the same steps on harmless values and are
+  // written as the regularised constants at the end
+  const bool kreg = a.axis[e] < 0;
+  const int ax = kreg ? 0 : a.axis[e];
   const int ia = (ax + 1) % 3, ib = (ax + 2) % 3;
-  const double al = a.alpha[e], be = a.beta[e], eta = a.eta[e];
+  const double al = a.alpha[e], be = a.beta[e], eta = kreg ? 0.0 : a.eta[e];
   const double* tau = a.tau + 6 * (int64_t)k;
   const double t1a = tau[ia], t1b = tau[ib], t2a = tau[3 + ia], t2b = tau[3 + ib];
   const double d1 = 1.0 / (1.0 - eta * a.kap1[k]);
@@ -216,20 +221,38 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock) void weights_kernel(WeightAr
   const double z11 = wave_sum(acc11);
   const double z21 = wave_sum(acc21);
   if (lane == 0 && valid) {
-    const double om11 = -z11, om21 = -z21;
-    a.om11[e] = om11;
-    a.om21[e] = om21;
     const double wm = a.w[a.col[e]];
     const double h2 = a.h * a.h, h3 = h2 * a.h;
     double* B = a.blocks + 4 * e;
-    B[0] = h2 * om11 * wm;
-    B[1] = -h3 * (a.kappa / (4.0 * kPiD)) * wm;
-    B[2] = h2 * om21 * wm;
-    B[3] = h2 * (a.eps_in / a.eps_out) * om11 * wm;
+    if (kreg) {
+      a.om11[e] = 0.0;
+      a.om21[e] = 0.0;
+      B[0] = 0.0;
+      B[1] = -h3 * a.c12 * wm;
+      B[2] = 0.0;
+      B[3] = 0.0;
+    } else {
+      const double om11 = -z11, om21 = -z21;
+      a.om11[e] = om11;
+      a.om21[e] = om21;
+      B[0] = h2 * om11 * wm;
+      B[1] = -h3 * (a.kappa / (4.0 * kPiD)) * wm;
+      B[2] = h2 * om21 * wm;
+      B[3] = h2 * (a.eps_in / a.eps_out) * om11 * wm;
+    }
   }
 }
 
 }  // namespace
+
+double kreg_constant(double kappa, double tau) {
+  if (kappa == 0.0) return 0.0;
+  const double x = kappa * tau;
+  // numerator e^{-x} - 1 + x, by its series where it would cancel
+  const double num =
+      x < 1e-2 ? x * x * (0.5 - x * (1.0 / 6.0 - x * (1.0 / 24.0 - x / 120.0))) : std::expm1(-x) + x;
+  return num / (2.0 * kPiD * kappa * tau * tau);
+}
 
 hipError_t launch_weights(const WeightArgs& a, hipStream_t stream) {
   if (a.nnz == 0) return hipSuccess;

@@ -21,6 +21,8 @@ HEADER = os.path.join(ROOT, "include", "ibim.h")
 
 FP64 = 0
 MIXED = 1
+CTR2, HYB, KREG = 0, 1, 2  # quadrature of the rows (ibim_options.hybrid)
+PRECOND_NONE, PRECOND_DIAG = 0, 1  # system handed to GMRES (ibim_options.precond)
 
 _ERRORS = {
     -1: "IBIM_EINVAL", -2: "IBIM_EGEOM", -3: "IBIM_ENOMEM", -4: "IBIM_EHIP", -5: "IBIM_ENAN",
@@ -37,7 +39,8 @@ class IbimError(RuntimeError):
 class _Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("restart", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("check_residual", ctypes.c_int), ("device", ctypes.c_int),
-                ("r_near", ctypes.c_double)]
+                ("r_near", ctypes.c_double), ("hybrid", ctypes.c_int),
+                ("precond", ctypes.c_int)]
 
 
 class _SolveInfo(ctypes.Structure):
@@ -98,6 +101,7 @@ def load():
     lib.ibim_node_grid_index.argtypes = [_VP, _I64]
     lib.ibim_node_geometry.argtypes = [_VP, _D, _D, _D]
     lib.ibim_num_corrections.argtypes = [_VP, _I64]
+    lib.ibim_node_flags.argtypes = [_VP, ctypes.POINTER(ctypes.c_uint8), _I64]
     lib.ibim_corrections.argtypes = [_VP, _I64, _I64, _I32, _D, _D, _D]
     lib.ibim_correction_weights.argtypes = [_VP, _D, _D, _VP]
     lib.ibim_rhs.argtypes = [_VP, _VP, _VP]
@@ -158,7 +162,7 @@ class Problem:
 
     def __init__(self, sdf, origin, h, eps_tube, eps_in, eps_out, kappa, charge_xyz=None,
                  charge_q=None, precision=FP64, restart=60, max_iter=300, check_residual=True,
-                 device=0, r_near=0.0, stream=None):
+                 device=0, r_near=0.0, hybrid=CTR2, precond=PRECOND_DIAG, stream=None):
         lib = load()
         self._lib = lib
         sdf = np.ascontiguousarray(sdf, dtype=np.float64)
@@ -178,6 +182,8 @@ class Problem:
         opt.check_residual = int(bool(check_residual))
         opt.device = int(device)
         opt.r_near = float(r_near)
+        opt.hybrid = int(hybrid)
+        opt.precond = int(precond)
         self.device = int(device)
         self.h = float(h)
         ctx = ctypes.c_void_p()
@@ -223,6 +229,13 @@ class Problem:
         w = np.empty(self.M)
         _check(self._lib.ibim_node_geometry(self._ctx, _dp(P), _dp(n), _dp(w)))
         return P, n, w
+
+    def node_flags(self) -> np.ndarray:
+        """Boolean per node: in M_B (K-reg row, J = 1)."""
+        out = np.empty(self.M, np.uint8)
+        _check(self._lib.ibim_node_flags(self._ctx, out.ctypes.data_as(
+            ctypes.POINTER(ctypes.c_uint8)), None))
+        return out.astype(bool)
 
     def corrections(self) -> dict:
         out = {"row": np.empty(self.M + 1, np.int64), "col": np.empty(self.nnz, np.int64),
@@ -310,7 +323,7 @@ class Server:
 
     def __init__(self, hbm_budget_bytes, max_slots=16, host_threads=4, precision=FP64,
                  restart=60, max_iter=300, check_residual=True, device=0, r_near=0.0,
-                 stream=None):
+                 hybrid=CTR2, precond=PRECOND_DIAG, stream=None):
         lib = load()
         self._lib = lib
         opt = _Options()
@@ -321,6 +334,8 @@ class Server:
         opt.check_residual = int(bool(check_residual))
         opt.device = int(device)
         opt.r_near = float(r_near)
+        opt.hybrid = int(hybrid)
+        opt.precond = int(precond)
         srv = ctypes.c_void_p()
         _check(lib.ibim_server_create(ctypes.byref(opt), int(hbm_budget_bytes), int(max_slots),
                                       int(host_threads), _stream_ptr(stream), ctypes.byref(srv)))

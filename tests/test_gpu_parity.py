@@ -140,6 +140,52 @@ def test_restarted_solve_matches_oracle():
     assert abs(info["g_pol"] - info_o["g_pol"]) <= 1e-9 * abs(info_o["g_pol"])
 
 
+def test_unscaled_gmres_matches_oracle():
+    """IBIM_PRECOND_NONE: GMRES on A x = b as written, against the oracle's."""
+    wl = workloads.kirkwood_sphere(h=0.3, radius=3.0, r_charges=2.0, n_charges=5, seed=7,
+                                   tol=1e-10)
+    prob = ibim.Problem.from_workload(wl, device=0, precond=ibim.PRECOND_NONE)
+    orc = oracle.Oracle.from_workload(wl)
+    x, info = prob.solve_energy(1e-10)
+    xo, info_o = orc.solve_energy(wl.charge_xyz, wl.charge_q, 1e-10, precond=0)
+    _say(f"[unscaled] iters {info['iters']} oracle {info_o['iters']}")
+    assert abs(info["iters"] - info_o["iters"]) <= 1
+    assert abs(info["g_pol"] - info_o["g_pol"]) <= 1e-10 * abs(info_o["g_pol"])
+
+
+HYBRID_CASES = {
+    "hyb_ses": (lambda: workloads.ses_molecule(20, 9.0, 0.35, 2.0, seed=11, tol=1e-10),
+                ibim.HYB),
+    "kreg_sphere": (lambda: workloads.born_sphere(h=0.4, offset=(0.13, -0.07, 0.21)),
+                    ibim.KREG),
+}
+
+
+@pytest.mark.parametrize("name", list(HYBRID_CASES))
+def test_hybrid_rows_match_oracle(name):
+    """HYB-IBIM / K-reg rows: flags, weights (K-reg entries zero), apply and solve."""
+    make, hybrid = HYBRID_CASES[name]
+    wl = make()
+    prob = ibim.Problem.from_workload(wl, device=0, hybrid=hybrid)
+    orc = oracle.Oracle.from_workload(wl, hybrid=hybrid)
+    bad = orc.bad_nodes()
+    assert np.array_equal(prob.node_flags(), bad) and bad.any()
+    om11, om21 = prob.correction_weights()
+    cl = prob.corrections()
+    assert np.all(om11[cl["axis"] < 0] == 0.0) and np.all(om21[cl["axis"] < 0] == 0.0)
+    u = workloads.random_vector(2 * prob.M, 11)
+    out = prob.apply(torch.from_numpy(u).to(DEV)).cpu().numpy()
+    err = _blockwise_rel(out, orc.apply(u), prob.M)
+    x, info = prob.solve_energy(1e-10)
+    xo, info_o = orc.solve_energy(wl.charge_xyz, wl.charge_q, 1e-10)
+    eg = abs(info["g_pol"] - info_o["g_pol"]) / abs(info_o["g_pol"])
+    _say(f"[{name}] M={prob.M} bad={int(bad.sum())} apply {err:.2e} G {eg:.2e} "
+         f"iters {info['iters']}/{info_o['iters']}")
+    assert err < 1e-12
+    assert abs(info["iters"] - info_o["iters"]) <= 1
+    assert eg <= 1e-10
+
+
 def test_not_converged_is_reported():
     wl = workloads.born_sphere(h=0.4)
     prob = ibim.Problem.from_workload(wl, device=0, max_iter=3)

@@ -25,10 +25,11 @@ def test_library_exports_every_header_function():
         assert hasattr(lib, n), n
 
 
-def _compare(wl):
-    lib = ibim.Problem.from_workload(wl, device=-1)
-    orc = oracle.Oracle.from_workload(wl)
+def _compare(wl, hybrid=ibim.CTR2):
+    lib = ibim.Problem.from_workload(wl, device=-1, hybrid=hybrid)
+    orc = oracle.Oracle.from_workload(wl, hybrid=hybrid)
     assert lib.M == orc.M and lib.nnz == orc.nnz
+    assert np.array_equal(lib.node_flags(), orc.bad_nodes())
     nd = orc.nodes()
     gi = lib.node_grid_index()
     ny, nz = wl.sdf.shape[1], wl.sdf.shape[2]
@@ -67,6 +68,29 @@ def test_host_setup_matches_oracle_wide_tube():
 
 def test_host_setup_matches_oracle_ses_molecule():
     _compare(workloads.ses_molecule(20, 9.0, 0.35, 2.0, seed=11))
+
+
+def test_hybrid_sets_match_oracle_ses_molecule():
+    """HYB-IBIM: bad-node flags, K-reg sets (axis -1) and J = 1 weights agree."""
+    lib, orc = _compare(workloads.ses_molecule(20, 9.0, 0.35, 2.0, seed=11), hybrid=ibim.HYB)
+    bad = orc.bad_nodes()
+    assert 0 < bad.sum() < 0.2 * lib.M
+    cl = lib.corrections()
+    rows = np.repeat(np.arange(lib.M), np.diff(cl["row"]))
+    assert np.all((cl["axis"] < 0) == bad[rows])
+
+
+def test_kreg_everywhere_matches_oracle_sphere():
+    lib, orc = _compare(workloads.born_sphere(h=0.4), hybrid=ibim.KREG)
+    assert lib.node_flags().all()
+    assert np.all(lib.corrections()["axis"] == -1)
+
+
+def test_hybrid_flags_no_node_on_smooth_surfaces():
+    for wl in (workloads.born_sphere(h=0.2), workloads.torus_case(h=0.1),
+               workloads.kirkwood_sphere(h=0.3, radius=3.0, r_charges=2.0, n_charges=5, seed=7)):
+        p = ibim.Problem.from_workload(wl, device=-1, hybrid=ibim.HYB)
+        assert not p.node_flags().any(), wl.name
 
 
 def test_every_row_corrects_its_own_node():
