@@ -205,6 +205,11 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="kirkwood")
+    ap.add_argument("--rows", default="ctr2", choices=["ctr2", "hyb", "kreg"],
+                    help="quadrature of the rows: CTR2 everywhere, HYB-IBIM (K-reg rows at "
+                         "bad nodes), or K-reg everywhere")
+    ap.add_argument("--unscaled", action="store_true",
+                    help="GMRES on A x = b as written instead of the row-scaled system")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
                     help="fp64: float64 pairs; mixed: float32 pairs with float64 sums, "
                          "float64 near pairs, weights and Krylov")
@@ -232,14 +237,17 @@ def main():
     import torch
 
     import workloads
-    from paper_2210_03699_amd import FP64, MIXED, Problem
+    from paper_2210_03699_amd import (CTR2, FP64, HYB, KREG, MIXED, PRECOND_DIAG, PRECOND_NONE,
+                                      Problem)
 
     wl = workloads.by_name(args.workload)
     dev = "cuda:0"
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     mode = FP64 if args.precision == "fp64" else MIXED
-    prob = Problem.from_workload(wl, device=0, precision=mode)
+    rows = {"ctr2": CTR2, "hyb": HYB, "kreg": KREG}[args.rows]
+    precond = PRECOND_NONE if args.unscaled else PRECOND_DIAG
+    prob = Problem.from_workload(wl, device=0, precision=mode, hybrid=rows, precond=precond)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     M = prob.M
@@ -306,6 +314,8 @@ def main():
         "config": {
             "workload": wl.name, "M": M, "unknowns": 2 * M, "h": wl.h, "eps_tube": wl.eps_tube,
             "tol": wl.tol, "n_charges": int(wl.charge_q.shape[0]), "gmres_restart": 60,
+            "gmres_system": "A x = b" if args.unscaled else "Lambda^-1 A x = Lambda^-1 b",
+            "rows": args.rows,
             "pair_kernel": args.precision,
         },
         "solves_per_s": args.steps / elapsed,

@@ -16,7 +16,7 @@
  *  - d > 0 inside, outward normal n = -grad d / |grad d| (Section 2.1).
  *  - psi_n is the interior normal derivative (Juffer BIE, eq. PB-BIE-1/2).
  *  - P(y) = y - d(y) g(y) with the *normalised* finite-difference gradient g.
- *  - "5 grid nodes per direction" (Section 3.3): gradient = central
+ *  - Five-node stencils per direction (Section 3.3): gradient = central
  *    difference, Hessian = central difference of the central gradient.
  *  - Theorem 2.1 leading terms with the sign of s0^(11), s0^(22) flipped and
  *    the factor kappa^2 added to s0^(21) (derived from the kernels; pinned by
