@@ -34,6 +34,10 @@ struct HostPlan {
   int64_t n_bad = 0;
 };
 
+// OpenMP threads used by build_host_plan when called from the current host
+// thread (setup threads of the solve server share the cores).
+void set_host_setup_threads(int n);
+
 // Builds the plan; returns 0 or a negative IBIM_E* code with *err set.
 // hybrid: 0 CTR2 rows everywhere, 1 HYB-IBIM, 2 every node bad (K-reg).
 int build_host_plan(const double* sdf, int nx, int ny, int nz, const double origin[3], double h,

@@ -9,9 +9,11 @@
 // and ibim_energy, so results do not depend on the mix of requests.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -116,7 +118,9 @@ __global__ void zero_ints_kernel(int* p, int n) {
   if (blockIdx.x == 0 && (int)threadIdx.x < n) p[threadIdx.x] = 0;
 }
 
-void worker_main(ibim_server* srv) {
+void worker_main(ibim_server* srv, int omp_threads) {
+  // the setup threads share the host cores instead of each starting a full team
+  set_host_setup_threads(omp_threads);
   for (;;) {
     Request* r = nullptr;
     {
@@ -532,7 +536,13 @@ int ibim_server_create(const ibim_options* opt, size_t hbm_budget_bytes, int max
     }
   }
   srv->st.budget_bytes = hbm_budget_bytes;
-  for (int t = 0; t < host_threads; ++t) srv->workers.emplace_back(worker_main, srv);
+  int cores = (int)std::thread::hardware_concurrency();
+  if (const char* env = std::getenv("OMP_NUM_THREADS")) {
+    const int v = std::atoi(env);
+    if (v > 0) cores = v;
+  }
+  const int per = std::max(1, cores / host_threads);
+  for (int t = 0; t < host_threads; ++t) srv->workers.emplace_back(worker_main, srv, per);
   *out = srv;
   return IBIM_OK;
 }

@@ -26,6 +26,8 @@
 // tangential distance) are evaluated with plain IEEE operations in a fixed
 // order and without contraction (this file is compiled with
 // -ffp-contract=off), so the sets are reproducible exactly.
+#include <omp.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -88,6 +90,8 @@ struct Candidate {
 };
 
 }  // namespace
+
+void set_host_setup_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 
 int build_host_plan(const double* sdf, int nx, int ny, int nz, const double origin[3], double h,
                     double eps, int hybrid, HostPlan* plan, std::string* err) {

@@ -12,9 +12,10 @@
 // in LDS and, for each row tile I, evaluates all 256 x 256 pairs: wave w holds
 // targets I[64w + l] (one per lane) and, in phase p, visits the 64 sources of
 // sub-block (w + p) mod 4 in the rotated order l, l+1, ... (mod 64).  The
-// row sums stay in registers across the item; the column sums of J go to an
-// LDS accumulator, which in any phase each wave updates in its own sub-block
-// and each lane at its own slot, so every slot is summed in a fixed order.
+// row sums of a tile pair stay in registers and are kept across the item in
+// lane-private LDS slots; the column sums of J go to an LDS accumulator,
+// which in any phase each wave updates in its own sub-block and each lane at
+// its own slot, so every slot is summed in a fixed order.
 // Diagonal tile pairs, pairs holding a corrected pair (either direction) and
 // pairs with the ragged last tile are evaluated one direction at a time with
 // the pairs of N_k skipped.  Row sums are written per (cb, I), column sums

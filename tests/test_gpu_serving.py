@@ -80,21 +80,23 @@ def _same(a, b, name):
     assert ia["converged"] == ib["converged"], name
 
 
-@pytest.mark.parametrize("precision,restart", [(ibim.FP64, 60), (ibim.FP64, 4),
-                                               (ibim.MIXED, 60)])
-def test_alone_equals_mixed_equals_direct(wls, precision, restart):
+@pytest.mark.parametrize("precision,restart,hybrid", [(ibim.FP64, 60, ibim.CTR2),
+                                                      (ibim.FP64, 4, ibim.CTR2),
+                                                      (ibim.MIXED, 60, ibim.CTR2),
+                                                      (ibim.FP64, 60, ibim.HYB)])
+def test_alone_equals_mixed_equals_direct(wls, precision, restart, hybrid):
     names = list(MIX)
-    _say(f"[serving] precision={precision} restart={restart}: mix of {len(names)}")
-    mixed, stats = _serve(wls, names, precision=precision, restart=restart)
+    _say(f"[serving] precision={precision} restart={restart} hybrid={hybrid}: mix of {len(names)}")
+    mixed, stats = _serve(wls, names, precision=precision, restart=restart, hybrid=hybrid)
     _say(f"[serving] rounds={stats['rounds']} max_active={stats['max_active_seen']} "
          f"items={stats['batched_items']}")
     assert stats["finished"] == len(names) and stats["failed"] == 0
     assert stats["max_active_seen"] == len(names)
     assert stats["bytes_in_use"] == 0
     for n in names:
-        alone, _ = _serve(wls, [n], slots=1, precision=precision, restart=restart)
+        alone, _ = _serve(wls, [n], slots=1, precision=precision, restart=restart, hybrid=hybrid)
         _same(alone[n], mixed[n], f"{n} alone vs mix")
-        direct = _direct(wls[n], precision=precision, restart=restart)
+        direct = _direct(wls[n], precision=precision, restart=restart, hybrid=hybrid)
         _same(direct, mixed[n], f"{n} ibim_solve vs server")
         if restart >= 60:
             assert mixed[n][2]["converged"]
