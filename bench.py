@@ -37,7 +37,7 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3  # MI355X vector FP32 (counts packed float32 iss
 # counters read for a plain 256 MiB copy).  Valid only while the kernel sources
 # hash to the recorded digest; otherwise the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "fp64": ("c2f16689", 679.1e6),
+    "fp64": ("ea4cd468", 679.1e6),
     "mixed": ("e35557be", 498.6e6),
 }
 # stored oracle results (tests/golden/make_golden.py) per workload
