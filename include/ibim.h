@@ -197,14 +197,22 @@ int ibim_rhs(ibim_ctx* ctx, double* g, void* stream);
 int ibim_apply(ibim_ctx* ctx, const double* u, double* out, void* stream);
 
 /*
- * Solve A x = rhs by GMRES(restart) from x0 = 0 until |g_{j+1}| <= tol ||rhs||
- * (Section 2.5).  rhs, x: device, 2M float64.  info may be NULL.  Returns 0
- * when converged, 1 when max_iter was reached (x holds the last iterate).
- * Workspace ((restart+1) vectors of 2M float64) is allocated on first use and
- * kept with the context.
+ * Solve A x = rhs by GMRES(restart) from x0 = 0 until |g_{j+1}| <= tol ||b||
+ * (Section 2.5), where b = rhs, or Lambda^-1 rhs for the row-scaled system of
+ * IBIM_PRECOND_DIAG (the residuals in info refer to that system).  rhs, x:
+ * device, 2M float64, distinct.  info may be NULL.  Returns 0 when converged,
+ * 1 when max_iter was reached (x holds the last iterate).  Workspace
+ * ((restart+4) vectors of 2M float64) is allocated on first use and kept with
+ * the context.
  */
 int ibim_solve(ibim_ctx* ctx, const double* rhs, double tol, double* x, ibim_solve_info* info,
                void* stream);
+
+/* As ibim_solve, but GMRES starts from the x given on entry (a warm start,
+ * for example the solution of a nearby geometry mapped onto this one's nodes
+ * through ibim_node_grid_index). */
+int ibim_solve_guess(ibim_ctx* ctx, const double* rhs, double tol, double* x,
+                     ibim_solve_info* info, void* stream);
 
 /*
  * Polarisation energy G_pol = 1/2 sum_k q_k psi_rxn(z_k) (eq. pol-energy,

@@ -634,8 +634,11 @@ int ibim_apply(ibim_ctx* ctx, const double* u, double* out, void* stream) {
   return apply_impl(ctx, u, out, as_stream(stream));
 }
 
-int ibim_solve(ibim_ctx* ctx, const double* rhs, double tol, double* x, ibim_solve_info* info,
-               void* stream) {
+namespace {
+
+// GMRES driver of ibim_solve (x0 = 0) and ibim_solve_guess (x0 = x on entry).
+int solve_impl(ibim_ctx* ctx, const double* rhs, double tol, double* x, ibim_solve_info* info,
+               void* stream, bool warm) {
   if (int r = check_dev(ctx)) return r;
   if (!rhs || !x || rhs == x) return fail(IBIM_EINVAL, "rhs and x must be distinct device vectors");
   if (!(tol > 0)) return fail(IBIM_EINVAL, "tol must be > 0");
@@ -665,8 +668,10 @@ int ibim_solve(ibim_ctx* ctx, const double* rhs, double tol, double* x, ibim_sol
   HIP_TRY(K.dots(b, N, 1, b, N, K.scal + 1, 0, s), "dots");
   if (int r = fetch(ctx, K.scal + 1, 1, s, hv)) return r;
   const double bnorm = std::sqrt(hv[0]);
-  hipLaunchKernelGGL(fill_kernel, dim3(nblk), dim3(256), 0, s, x, N, 0.0);
-  HIP_TRY(hipGetLastError(), "fill");
+  if (!warm || bnorm == 0.0) {
+    hipLaunchKernelGGL(fill_kernel, dim3(nblk), dim3(256), 0, s, x, N, 0.0);
+    HIP_TRY(hipGetLastError(), "fill");
+  }
   int total = 0;
   bool converged = false;
   double resid = bnorm;
@@ -675,9 +680,9 @@ int ibim_solve(ibim_ctx* ctx, const double* rhs, double tol, double* x, ibim_sol
     if (info) *info = ibim_solve_info{0, 0, 1, 0.0, 0.0, 0.0};
     return IBIM_OK;
   }
-  bool first = true;
+  bool first = !warm;
   while (total < ctx->opt.max_iter && !converged) {
-    // r = b - A x (x = 0 on the first cycle, where A x = 0 exactly)
+    // r = b - A x (x = 0 on a cold first cycle, where A x = 0 exactly)
     if (first) {
       hipLaunchKernelGGL(copy_kernel, dim3(nblk), dim3(256), 0, s, b, K.tmp, N);
       HIP_TRY(hipGetLastError(), "copy");
@@ -740,6 +745,18 @@ int ibim_solve(ibim_ctx* ctx, const double* rhs, double tol, double* x, ibim_sol
   if (info)
     *info = ibim_solve_info{total, ctx->applies, converged ? 1 : 0, resid / bnorm, explicit_rel, secs};
   return converged ? IBIM_OK : IBIM_NOT_CONVERGED;
+}
+
+}  // namespace
+
+int ibim_solve(ibim_ctx* ctx, const double* rhs, double tol, double* x, ibim_solve_info* info,
+               void* stream) {
+  return solve_impl(ctx, rhs, tol, x, info, stream, false);
+}
+
+int ibim_solve_guess(ibim_ctx* ctx, const double* rhs, double tol, double* x,
+                     ibim_solve_info* info, void* stream) {
+  return solve_impl(ctx, rhs, tol, x, info, stream, true);
 }
 
 int ibim_energy(ibim_ctx* ctx, const double* x, double* g_pol, void* stream) {

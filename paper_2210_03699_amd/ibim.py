@@ -107,6 +107,7 @@ def load():
     lib.ibim_rhs.argtypes = [_VP, _VP, _VP]
     lib.ibim_apply.argtypes = [_VP, _VP, _VP, _VP]
     lib.ibim_solve.argtypes = [_VP, _VP, ctypes.c_double, _VP, ctypes.POINTER(_SolveInfo), _VP]
+    lib.ibim_solve_guess.argtypes = lib.ibim_solve.argtypes
     lib.ibim_energy.argtypes = [_VP, _VP, _D, _VP]
     lib.ibim_pair_timing.argtypes = [_VP, ctypes.c_int]
     lib.ibim_pair_timing_read.argtypes = [_VP, _I64, _D]
@@ -270,12 +271,15 @@ class Problem:
                                     _dev_ptr(out, 2 * self.M), _stream_ptr(stream)))
         return out
 
-    def solve(self, rhs, tol, x=None, stream=None):
+    def solve(self, rhs, tol, x=None, stream=None, warm=False):
+        """GMRES from x0 = 0, or (warm=True) from the given x, which is updated in place."""
+        if warm and x is None:
+            raise ValueError("a warm start needs x")
         x = self.new_vector() if x is None else x
         info = _SolveInfo()
-        code = _check(self._lib.ibim_solve(self._ctx, _dev_ptr(rhs, 2 * self.M), float(tol),
-                                           _dev_ptr(x, 2 * self.M), ctypes.byref(info),
-                                           _stream_ptr(stream)))
+        fn = self._lib.ibim_solve_guess if warm else self._lib.ibim_solve
+        code = _check(fn(self._ctx, _dev_ptr(rhs, 2 * self.M), float(tol),
+                         _dev_ptr(x, 2 * self.M), ctypes.byref(info), _stream_ptr(stream)))
         return x, {"status": int(code), "iters": info.iters, "applies": info.applies,
                    "converged": bool(info.converged),
                    "rel_resid": info.rel_resid, "explicit_rel_resid": info.explicit_rel_resid,

@@ -185,6 +185,24 @@ def test_hybrid_rows_match_oracle(name):
     assert eg <= 1e-10
 
 
+def test_warm_start():
+    """ibim_solve_guess: from the solution it stops at once; from a nearby
+    guess it needs fewer iterations than from zero and reaches the same G_pol."""
+    wl = workloads.kirkwood_sphere(h=0.3, radius=3.0, r_charges=2.0, n_charges=5, seed=7,
+                                   tol=1e-10)
+    prob = ibim.Problem.from_workload(wl, device=0)
+    g = prob.rhs()
+    x, info = prob.solve(g, 1e-10)
+    G = prob.energy(x)
+    x1, info1 = prob.solve(g, 1e-10, x=x.clone(), warm=True)
+    assert info1["converged"] and info1["iters"] <= 1
+    x2, info2 = prob.solve(g, 1e-10, x=0.9 * x, warm=True)
+    G2 = prob.energy(x2)
+    _say(f"[warm] cold {info['iters']} from solution {info1['iters']} from 0.9x {info2['iters']}")
+    assert info2["converged"] and info2["iters"] < info["iters"]
+    assert abs(G2 - G) <= 1e-9 * abs(G)
+
+
 def test_zero_charges_give_the_zero_solution():
     """Degenerate input: no charges, so g = 0 and the solve returns at once."""
     wl = workloads.born_sphere(h=0.4)
