@@ -213,6 +213,11 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
                     help="fp64: float64 pairs; mixed: float32 pairs with float64 sums, "
                          "float64 near pairs, weights and Krylov")
+    ap.add_argument("--summation", default="direct", choices=["direct", "tree"],
+                    help="dense pair sum: every pair (default) or the treecode (float64 only; "
+                         "value then counts the M^2 pairs each application stands for)")
+    ap.add_argument("--tree-order", type=int, default=8)
+    ap.add_argument("--tree-theta", type=float, default=0.7)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile", action="store_true",
@@ -238,7 +243,7 @@ def main():
 
     import workloads
     from paper_2210_03699_amd import (CTR2, FP64, HYB, KREG, MIXED, PRECOND_DIAG, PRECOND_NONE,
-                                      Problem)
+                                      SUM_DIRECT, SUM_TREE, Problem)
 
     wl = workloads.by_name(args.workload)
     dev = "cuda:0"
@@ -247,7 +252,13 @@ def main():
     mode = FP64 if args.precision == "fp64" else MIXED
     rows = {"ctr2": CTR2, "hyb": HYB, "kreg": KREG}[args.rows]
     precond = PRECOND_NONE if args.unscaled else PRECOND_DIAG
-    prob = Problem.from_workload(wl, device=0, precision=mode, hybrid=rows, precond=precond)
+    tree = args.summation == "tree"
+    if tree and mode != FP64:
+        print("bench.py: the treecode runs in float64 only", file=sys.stderr)
+        sys.exit(2)
+    prob = Problem.from_workload(wl, device=0, precision=mode, hybrid=rows, precond=precond,
+                                 summation=SUM_TREE if tree else SUM_DIRECT,
+                                 tree_order=args.tree_order, tree_theta=args.tree_theta)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     M = prob.M
@@ -296,7 +307,7 @@ def main():
     _, pair_flops = prob.pair_work()
     achieved_tflops = pair_flops / (avg_pair_ms * 1e-3) / 1e12
     digest, measured = MEASURED_TRAFFIC[args.precision]
-    traffic = measured if (args.workload == "kirkwood"
+    traffic = measured if (args.workload == "kirkwood" and not tree
                            and kernel_digest(args.precision) == digest) else None
     out = {
         "metric": METRIC,
@@ -317,6 +328,7 @@ def main():
             "gmres_system": "A x = b" if args.unscaled else "Lambda^-1 A x = Lambda^-1 b",
             "rows": args.rows,
             "pair_kernel": args.precision,
+            "summation": args.summation,
         },
         "solves_per_s": args.steps / elapsed,
         "latency_ms": {"p50": percentile(lat, 50) * 1e3, "p99": percentile(lat, 99) * 1e3},
@@ -336,6 +348,14 @@ def main():
             "traffic": traffic,
         },
     }
+    if tree:
+        tc = prob.tree_counts()
+        out["config"]["tree"] = {"order": args.tree_order, "theta": args.tree_theta,
+                                 "batches": tc["batches"], "proxy_clusters": tc["proxy_clusters"]}
+        ev = tc["far_evals"] + tc["near_evals"]
+        out["tree_evaluations_per_apply"] = {k: tc[k] for k in ("far_evals", "near_evals",
+                                                                "proxy_terms")}
+        out["tree_evaluations_per_s"] = ev / (avg_pair_ms * 1e-3)
     golden = os.path.join(ROOT, "tests", "golden", GOLDEN.get(args.workload, "-"))
     if os.path.exists(golden):
         gold = json.load(open(golden))

@@ -68,7 +68,34 @@ typedef struct {
                           re-evaluated in float64 (default 0 = 4 h) */
   int hybrid;          /* IBIM_CTR2 (default), IBIM_HYB or IBIM_KREG, below */
   int precond;         /* IBIM_PRECOND_DIAG (default) or IBIM_PRECOND_NONE, below */
+  int summation;       /* IBIM_SUM_DIRECT (default) or IBIM_SUM_TREE, below */
+  int tree_order;      /* IBIM_SUM_TREE: Chebyshev points per dimension, 2..16 (default 8) */
+  double tree_theta;   /* IBIM_SUM_TREE: separation parameter, (0, 1] (default 0.7) */
 } ibim_options;
+
+/*
+ * Evaluation of the dense pair sum h^3 K W p (Section 2.5):
+ *  IBIM_SUM_DIRECT  every (target, source) pair, exactly as written (the path
+ *                   the parity bars of this header refer to).
+ *  IBIM_SUM_TREE    a treecode, the far-field acceleration that the paper
+ *                   obtains with a black-box fast multipole method: sources of
+ *                   a cluster far from a batch of 256 targets are replaced by
+ *                   charges at tree_order^3 tensor Chebyshev points of the
+ *                   cluster's box (Lagrange interpolation of the kernels in the
+ *                   source variable, normal derivatives through the derivative
+ *                   of the interpolant); nearer clusters are summed directly,
+ *                   with the pairs of N_k skipped by index as in the direct
+ *                   path.  A cluster is far when (r_batch + r_cluster) <
+ *                   tree_theta * distance of the box centres, it holds more
+ *                   than tree_order^3 nodes and the box gap exceeds the largest
+ *                   corrected-pair distance.  An approximation: its error falls
+ *                   geometrically with tree_order and with smaller tree_theta.
+ *                   Float64 only (IBIM_MIXED is rejected); not accepted by the
+ *                   solve server.  The corrections, GMRES and energy are those
+ *                   of the direct path.
+ */
+#define IBIM_SUM_DIRECT 0
+#define IBIM_SUM_TREE 1
 
 /*
  * System handed to GMRES (Section 2.5):
@@ -240,9 +267,19 @@ int ibim_pair_timing_read(ibim_ctx* ctx, int64_t* launches, double* total_ms);
  * own, 68 per unordered pair when both directions share one evaluation (the
  * symmetric kernels; tile pairs holding corrected pairs and the diagonal
  * tiles are still evaluated one direction at a time).  In the mixed form
- * these are float32 operations.
+ * these are float32 operations.  For IBIM_SUM_TREE, *pairs is still M^2 (the
+ * pairs the sum stands for) and *flops counts what the treecode performs: 60
+ * per direct pair, 36 per target-proxy evaluation, 15 per source-proxy term.
  */
 int ibim_pair_work(const ibim_ctx* ctx, double* pairs, double* flops);
+
+/*
+ * Work of one treecode pair sum (IBIM_SUM_TREE contexts; IBIM_EINVAL for
+ * others).  out (host, 5 doubles): [0] target-proxy evaluations, [1] direct
+ * pair evaluations, [2] source-proxy terms of the proxy charges, [3] batches
+ * of targets, [4] proxy clusters.  Each application performs exactly these.
+ */
+int ibim_tree_counts(const ibim_ctx* ctx, double* out);
 
 /* ------------------------------------------------------------------------ */
 /*

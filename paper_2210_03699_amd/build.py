@@ -17,12 +17,12 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libibim.so")
 
 HIP_SOURCES = ["weights.hip", "operator.hip", "symmetric.hip", "symmetric_mixed.hip", "mixed.hip",
-               "krylov.hip", "capi.hip", "server.hip"]
+               "krylov.hip", "treecode.hip", "capi.hip", "server.hip"]
 # The mixed-precision files need bit-reproducible float32 evaluations in the
 # pair and finishing kernels: no automatic contraction there (their fused
 # multiply-adds are explicit).
 PER_FILE_FLAGS = {"mixed.hip": ["-ffp-contract=off"], "symmetric_mixed.hip": ["-ffp-contract=off"]}
-HOST_SOURCES = ["setup_host.cpp"]
+HOST_SOURCES = ["setup_host.cpp", "tree_host.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

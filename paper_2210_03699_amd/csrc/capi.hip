@@ -151,7 +151,10 @@ int apply_impl(ibim_ctx* c, const double* u, double* out, hipStream_t s) {
     e1 = c->tev[2 * c->tcount + 1];
     HIP_TRY(hipEventRecord(e0, s), "hipEventRecord");
   }
-  if (c->sym.enabled) {
+  const bool tree = c->opt.summation == IBIM_SUM_TREE;
+  if (tree) {
+    HIP_TRY(launch_tree_sum(c->tree, c->P, u, s), "treecode launch");
+  } else if (c->sym.enabled) {
     const SymArgs sa =
         make_sym_args(c->P, c->sym, c->d_sym_items, c->d_careful, u, c->sym_scratch);
     if (prec == IBIM_MIXED)
@@ -166,7 +169,9 @@ int apply_impl(ibim_ctx* c, const double* u, double* out, hipStream_t s) {
     HIP_TRY(hipEventRecord(e1, s), "hipEventRecord");
     ++c->tcount;
   }
-  if (c->sym.enabled && prec == IBIM_MIXED)
+  if (tree)
+    HIP_TRY(launch_tree_finish(c->tree, c->P, u, out, s), "finish kernel launch");
+  else if (c->sym.enabled && prec == IBIM_MIXED)
     HIP_TRY(launch_finish_sym_mixed(c->P, c->sym, c->d_careful, u, c->sym_scratch, out, s),
             "finish kernel launch");
   else if (c->sym.enabled)
@@ -226,6 +231,15 @@ int ctx_create_host(const double* sdf, int nx, int ny, int nz, const double orig
     return fail(IBIM_EINVAL, "unknown hybrid mode");
   if (o.precond != IBIM_PRECOND_NONE && o.precond != IBIM_PRECOND_DIAG)
     return fail(IBIM_EINVAL, "unknown preconditioning mode");
+  if (o.summation != IBIM_SUM_DIRECT && o.summation != IBIM_SUM_TREE)
+    return fail(IBIM_EINVAL, "unknown summation mode");
+  if (o.summation == IBIM_SUM_TREE) {
+    if (o.precision != IBIM_FP64) return fail(IBIM_EINVAL, "the treecode runs in float64 only");
+    if (o.tree_order < 2 || o.tree_order > ibim::kTreeMaxOrder)
+      return fail(IBIM_EINVAL, "tree_order must be in [2, 16]");
+    if (!(o.tree_theta > 0.0 && o.tree_theta <= 1.0))
+      return fail(IBIM_EINVAL, "tree_theta must be in (0, 1]");
+  }
   ibim_ctx* c = new (std::nothrow) ibim_ctx();
   if (!c) return fail(IBIM_ENOMEM, "host allocation failed");
   c->opt = o;
@@ -410,7 +424,30 @@ int ctx_setup_device(ibim_ctx* c, hipStream_t s) {
     bytes += ((size_t)M + 1) * 8 + (size_t)P.nnear * 4;
   }
   c->pair = make_pair_plan(M, o.precision);
-  c->sym = make_sym_plan(M, kSymScratchMax);
+  c->sym = make_sym_plan(M, o.summation == IBIM_SUM_TREE ? 0 : kSymScratchMax);
+  if (o.summation == IBIM_SUM_TREE) {
+    TreeParams prm;
+    prm.order = o.tree_order;
+    prm.theta = o.tree_theta;
+    std::string terr;
+    if (int r = build_tree_plan(prm, M, pl.px.data(), pl.py.data(), pl.pz.data(), pl.crow.data(),
+                                pl.ccol.data(), h, &c->tplan, &terr))
+      return fail(r, terr);
+    e = tree_upload(c->tplan, P, pl.px.data(), pl.py.data(), pl.pz.data(), pl.nx.data(),
+                    pl.ny.data(), pl.nz.data(), pl.w.data(), &c->tree, s);
+    if (e != hipSuccess) return bad(e, "treecode setup");
+    bytes += c->tree.bytes;
+    c->pair_flops = 60.0 * c->tplan.near_evals + 36.0 * c->tplan.far_evals +
+                    15.0 * c->tplan.proxy_evals;
+  }
+  if (c->sym.enabled) {
+    // the quadratic scratch comes first: if the device cannot hold it, the
+    // one-directional kernel (linear scratch) takes over
+    if (dalloc(&c->sym_scratch, c->sym.scratch_doubles) != hipSuccess) {
+      (void)hipGetLastError();
+      c->sym.enabled = false;
+    }
+  }
   if (c->sym.enabled) {
     std::vector<int32_t> items;
     sym_items(c->sym, &items);
@@ -432,10 +469,9 @@ int ctx_setup_device(ibim_ctx* c, hipStream_t s) {
     c->pair_flops = fl;
     UP(c->d_sym_items, items);
     UP(c->d_careful, bits);
-    e = dalloc(&c->sym_scratch, c->sym.scratch_doubles);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);  // items, bits are host temporaries
+    e = hipStreamSynchronize(s);  // items, bits are host temporaries
     bytes += c->sym.scratch_doubles * 8;
-  } else {
+  } else if (o.summation != IBIM_SUM_TREE) {
     c->pair_flops = 60.0 * (double)M * (double)M;
     e = dalloc(&c->partial, (size_t)c->pair.nsplit * 2 * (size_t)M);
     bytes += (size_t)c->pair.nsplit * 2 * (size_t)M * 8;
@@ -503,6 +539,9 @@ void ibim_default_options(ibim_options* opt) {
   opt->r_near = 0.0;
   opt->hybrid = IBIM_CTR2;
   opt->precond = IBIM_PRECOND_DIAG;
+  opt->summation = IBIM_SUM_DIRECT;
+  opt->tree_order = 8;
+  opt->tree_theta = 0.7;
 }
 
 const char* ibim_last_error(void) { return g_last_error.c_str(); }
@@ -792,6 +831,19 @@ int ibim_pair_work(const ibim_ctx* ctx, double* pairs, double* flops) {
   if (!pairs || !flops) return fail(IBIM_EINVAL, "NULL output");
   *pairs = (double)ctx->P.M * (double)ctx->P.M;
   *flops = ctx->pair_flops;
+  return IBIM_OK;
+}
+
+int ibim_tree_counts(const ibim_ctx* ctx, double* out) {
+  if (int r = check_dev(ctx)) return r;
+  if (!out) return fail(IBIM_EINVAL, "NULL output");
+  if (ctx->opt.summation != IBIM_SUM_TREE) return fail(IBIM_EINVAL, "not a treecode context");
+  const ibim::TreePlan& t = ctx->tplan;
+  out[0] = t.far_evals;
+  out[1] = t.near_evals;
+  out[2] = t.proxy_evals;
+  out[3] = (double)(t.bstart.size() - 1);
+  out[4] = (double)t.pstart.size();
   return IBIM_OK;
 }
 

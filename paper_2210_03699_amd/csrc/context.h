@@ -12,6 +12,7 @@
 #include "krylov.h"
 #include "operator.h"
 #include "symmetric.h"
+#include "treecode.h"
 
 namespace ibim {
 
@@ -86,6 +87,9 @@ struct ibim_ctx {
   uint32_t* d_careful = nullptr;   // T x T bits
   double* sym_scratch = nullptr;   // sym.scratch_doubles
   double pair_flops = 0.0;         // flops of one pair-sum launch (see ibim_pair_work)
+  // treecode summation (used when opt.summation == IBIM_SUM_TREE)
+  ibim::TreePlan tplan;
+  ibim::TreeDevice tree;
   double* om11 = nullptr;
   double* om21 = nullptr;
   double* d_zq = nullptr;
@@ -112,6 +116,7 @@ struct ibim_ctx {
     dfree(P.crow); dfree(P.ccol); dfree(P.blocks); dfree(P.nrow); dfree(P.ncol);
     dfree(P.xrow); dfree(P.xtile);
     dfree(d_sym_items); dfree(d_careful); dfree(sym_scratch);
+    tree.release();
     dfree(partial); dfree(om11); dfree(om21); dfree(d_zq); dfree(d_q); dfree(d_psi);
     dfree(kr.V); dfree(kr.H); dfree(kr.cs); dfree(kr.sn); dfree(kr.g); dfree(kr.y);
     dfree(kr.hcol); dfree(kr.hcol2); dfree(kr.scal); dfree(kr.status); dfree(kr.partial);

@@ -511,6 +511,8 @@ int ibim_server_create(const ibim_options* opt, size_t hbm_budget_bytes, int max
   if (o.device < 0) return fail(IBIM_EINVAL, "the server needs a device (options.device >= 0)");
   if (o.precision != IBIM_FP64 && o.precision != IBIM_MIXED)
     return fail(IBIM_EINVAL, "unknown precision mode");
+  if (o.summation != IBIM_SUM_DIRECT)
+    return fail(IBIM_EINVAL, "the server batches direct pair sums only (summation must be IBIM_SUM_DIRECT)");
   if (o.restart < 1 || o.restart > 1000 || o.max_iter < 1)
     return fail(IBIM_EINVAL, "restart must be in [1, 1000] and max_iter >= 1");
   ibim_server* srv = new (std::nothrow) ibim_server();

@@ -127,7 +127,7 @@ __device__ void item(const SymArgs& a, int rb, int cb, Shared<P>& sh) {
       racc2[i][tid] = S2;
     }
     // column sums of J
-    double* cp = a.colpart + ((size_t)rb * T + J) * (2 * kT);
+    double* cp = a.colpart + sym_col_slot(rb, J) * (2 * kT);
     cp[tid] = a.scale * cacc[tid].x;
     cp[kT + tid] = a.scale * cacc[tid].y;
     __syncthreads();  // LDS is refilled for the next column tile

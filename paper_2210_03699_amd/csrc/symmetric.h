@@ -11,9 +11,18 @@
 namespace ibim {
 
 constexpr int kSymRows = 4;  // row tiles per work item
-// Largest row-and-column scratch of the symmetric kernel; larger problems use
-// the one-directional kernel, whose scratch grows only linearly.
-constexpr size_t kSymScratchMax = size_t(4) << 30;
+// Largest row-and-column scratch of the symmetric kernel (an eighth of the
+// 288 GB of HBM; it grows as M^2 / 2^19 doubles, so this covers M ~ 2e6).
+// Larger problems, and setups where the allocation fails, use the
+// one-directional kernel, whose scratch grows only linearly.
+constexpr size_t kSymScratchMax = size_t(32) << 30;
+
+// Column-sum slot of (row block rb, column tile J), rb <= J / kSymRows: the
+// slots of tile J follow those of tiles 0 .. J-1 (a packed lower triangle).
+__host__ __device__ inline size_t sym_col_slot(int rb, int J) {
+  const size_t q = (size_t)(J / kSymRows), r = (size_t)(J % kSymRows);
+  return kSymRows * q * (q + 1) / 2 + r * (q + 1) + (size_t)rb;
+}
 
 // Decomposition of the upper triangle of tile pairs into work items.
 struct SymPlan {
@@ -22,7 +31,7 @@ struct SymPlan {
   int b = 0;    // column tiles per item
   int nRB = 0;  // row blocks (kSymRows tiles each)
   int nCB = 0;  // column blocks
-  size_t scratch_doubles = 0;  // row sums (nCB x T) + column sums (nRB x T), 512 doubles each
+  size_t scratch_doubles = 0;  // row sums (nCB x T) + column sums (sym_col_slot(0, T)), 512 doubles each
 };
 
 struct SymArgs {
@@ -39,7 +48,7 @@ struct SymArgs {
   double c1, c2, kappa;
   double scale;       // h^3 / (4 pi)
   double* rowpart;    // [nCB][T][2][256]
-  double* colpart;    // [nRB][T][2][256]
+  double* colpart;    // [sym_col_slot(rb, J)][2][256]
 };
 
 // Plan for M nodes; disabled when the scratch would exceed max_scratch_bytes

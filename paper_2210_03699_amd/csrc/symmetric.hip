@@ -19,7 +19,8 @@
 // Diagonal tile pairs, pairs holding a corrected pair (either direction) and
 // pairs with the ragged last tile are evaluated one direction at a time with
 // the pairs of N_k skipped.  Row sums are written per (cb, I), column sums
-// per (rb, J); the finishing kernel adds them in a fixed order.
+// per (rb, J) (only rb <= J / kRows occur, so those slots are packed); the
+// finishing kernel adds them in a fixed order.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -143,8 +144,9 @@ __global__ __launch_bounds__(256) void finish_sym_kernel(SymFinishArgs a) {
     s1 += rp[t];
     s2 += rp[kT + t];
   }
+  const size_t c0 = sym_col_slot(0, X);
   for (int rb = 0; rb <= X / kRows; ++rb) {
-    const double* cp = a.colpart + ((size_t)rb * a.T + X) * (2 * kT);
+    const double* cp = a.colpart + (c0 + rb) * (2 * kT);
     s1 += cp[t];
     s2 += cp[kT + t];
   }
@@ -177,7 +179,7 @@ SymPlan make_sym_plan(int32_t M, size_t max_scratch_bytes) {
   }
   pl.b = b;
   pl.nCB = (pl.T + b - 1) / b;
-  pl.scratch_doubles = ((size_t)pl.nRB + pl.nCB) * pl.T * 2 * kT;
+  pl.scratch_doubles = ((size_t)pl.nCB * pl.T + sym_col_slot(0, pl.T)) * 2 * kT;
   pl.enabled = pl.T >= 2 && pl.scratch_doubles * 8 <= max_scratch_bytes;
   return pl;
 }

@@ -120,7 +120,7 @@ __global__ __launch_bounds__(256) void finish_sym_mixed_kernel(FinishArgs a) {
   const int cb0 = X / a.b, nr = a.nCB - cb0, nc = X / kRows + 1;
   for (int j = lane; j < nr + nc; j += 64) {
     const double* sp = j < nr ? a.rowpart + ((size_t)(cb0 + j) * T + X) * (2 * kT)
-                              : a.colpart + ((size_t)(j - nr) * T + X) * (2 * kT);
+                              : a.colpart + sym_col_slot(j - nr, X) * (2 * kT);
     p1 += sp[t];
     p2 += sp[kT + t];
   }

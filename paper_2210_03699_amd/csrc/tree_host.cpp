@@ -1,0 +1,244 @@
+// Host planning of the treecode: cluster tree, batches, interaction lists.
+//
+// The tree is a binary space partition of the projected points P(y_m): a
+// cluster with more than one batch of points is split across its longest
+// bounding-box side, the left part taking the nearest multiple of the batch
+// size to half the points, so every leaf (a batch of targets) holds exactly
+// kTreeBatch points except the last one.  A cluster C is approximated for a
+// batch B by its proxies when it has more points than proxies and
+//   r_B + r_C < theta * d   and   d - r_B - r_C > gap,
+// d the distance of the box centres, r the half diagonals; the second
+// condition keeps every pair (k, m) with m in N_k in the direct part, where it
+// is skipped by index.  Clusters that are neither far nor splittable into
+// far parts are summed directly.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/ibim.h"
+#include "tree.h"
+
+namespace ibim {
+namespace {
+
+struct Node {
+  int32_t s = 0, e = 0;
+  int32_t kid[2] = {-1, -1};
+  double lo[3], hi[3];
+  double c[3], r = 0.0;
+};
+
+struct Builder {
+  const double* p[3];
+  std::vector<int32_t>* perm;
+  std::vector<Node> nodes;
+
+  void box(Node& nd) const {
+    for (int d = 0; d < 3; ++d) {
+      nd.lo[d] = INFINITY;
+      nd.hi[d] = -INFINITY;
+    }
+    for (int32_t i = nd.s; i < nd.e; ++i) {
+      const int32_t m = (*perm)[i];
+      for (int d = 0; d < 3; ++d) {
+        nd.lo[d] = std::min(nd.lo[d], p[d][m]);
+        nd.hi[d] = std::max(nd.hi[d], p[d][m]);
+      }
+    }
+    double r2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      nd.c[d] = 0.5 * (nd.lo[d] + nd.hi[d]);
+      r2 += 0.25 * (nd.hi[d] - nd.lo[d]) * (nd.hi[d] - nd.lo[d]);
+    }
+    nd.r = std::sqrt(r2);
+  }
+
+  int build(int32_t s, int32_t e) {
+    Node nd;
+    nd.s = s;
+    nd.e = e;
+    box(nd);
+    const int id = (int)nodes.size();
+    nodes.push_back(nd);
+    if (e - s > kTreeBatch) {
+      int d = 0;
+      for (int q = 1; q < 3; ++q)
+        if (nd.hi[q] - nd.lo[q] > nd.hi[d] - nd.lo[d]) d = q;
+      const int32_t nb = (e - s + kTreeBatch - 1) / kTreeBatch;
+      const int32_t mid = s + ((nb + 1) / 2) * kTreeBatch;
+      const double* pd = p[d];
+      std::nth_element(perm->begin() + s, perm->begin() + mid, perm->begin() + e,
+                       [pd](int32_t a, int32_t b) { return pd[a] < pd[b] || (pd[a] == pd[b] && a < b); });
+      const int l = build(s, mid);
+      const int r = build(mid, e);
+      nodes[id].kid[0] = l;
+      nodes[id].kid[1] = r;
+    }
+    return id;
+  }
+};
+
+}  // namespace
+
+int build_tree_plan(const TreeParams& prm, int64_t M64, const double* px, const double* py,
+                    const double* pz, const int64_t* crow, const int32_t* ccol, double h,
+                    TreePlan* plan, std::string* err) {
+  if (prm.order < 2 || prm.order > kTreeMaxOrder) {
+    *err = "tree order must be in [2, " + std::to_string(kTreeMaxOrder) + "]";
+    return IBIM_EINVAL;
+  }
+  if (!(prm.theta > 0.0 && prm.theta <= 1.0)) {
+    *err = "tree theta must be in (0, 1]";
+    return IBIM_EINVAL;
+  }
+  if (M64 < 1 || M64 > INT32_MAX / 2) {
+    *err = "node count out of range for the treecode";
+    return IBIM_EINVAL;
+  }
+  TreePlan& pl = *plan;
+  pl = TreePlan();
+  const int32_t M = (int32_t)M64;
+  const int n3 = prm.order * prm.order * prm.order;
+  pl.M = M;
+  pl.order = prm.order;
+
+  // gap: the largest distance of a corrected pair
+  double gap = 0.0;
+  for (int32_t k = 0; k < M; ++k)
+    for (int64_t e = crow[k]; e < crow[k + 1]; ++e) {
+      const int32_t m = ccol[e];
+      const double dx = px[k] - px[m], dy = py[k] - py[m], dz = pz[k] - pz[m];
+      gap = std::max(gap, std::sqrt(dx * dx + dy * dy + dz * dz));
+    }
+  pl.gap = gap * (1.0 + 1e-9) + 1e-9 * h;
+
+  pl.perm.resize(M);
+  std::iota(pl.perm.begin(), pl.perm.end(), 0);
+  Builder B;
+  B.p[0] = px;
+  B.p[1] = py;
+  B.p[2] = pz;
+  B.perm = &pl.perm;
+  B.build(0, M);
+  const std::vector<Node>& nd = B.nodes;
+  pl.pos.resize(M);
+  for (int32_t t = 0; t < M; ++t) pl.pos[pl.perm[t]] = t;
+
+  // batches: the leaves, in tree order
+  std::vector<int> leaves;
+  for (int i = 0; i < (int)nd.size(); ++i)
+    if (nd[i].kid[0] < 0) leaves.push_back(i);
+  std::sort(leaves.begin(), leaves.end(), [&](int a, int b) { return nd[a].s < nd[b].s; });
+  const int nb = (int)leaves.size();
+  pl.bstart.resize(nb + 1);
+  for (int b = 0; b < nb; ++b) pl.bstart[b] = nd[leaves[b]].s;
+  pl.bstart[nb] = M;
+
+  // interaction lists
+  std::vector<std::vector<int>> far(nb);
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> near(nb);
+  const double theta = prm.theta;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int b = 0; b < nb; ++b) {
+    const Node& L = nd[leaves[b]];
+    std::vector<int> stack{0};
+    while (!stack.empty()) {
+      const int ci = stack.back();
+      stack.pop_back();
+      const Node& C = nd[ci];
+      const double dx = L.c[0] - C.c[0], dy = L.c[1] - C.c[1], dz = L.c[2] - C.c[2];
+      const double d = std::sqrt(dx * dx + dy * dy + dz * dz);
+      const bool sep = L.r + C.r < theta * d && d - L.r - C.r > pl.gap;
+      if (sep && C.e - C.s > n3) {
+        far[b].push_back(ci);
+      } else if (C.kid[0] < 0 || C.e - C.s <= n3) {
+        near[b].push_back({C.s, C.e});
+      } else {
+        stack.push_back(C.kid[1]);
+        stack.push_back(C.kid[0]);
+      }
+    }
+    std::sort(far[b].begin(), far[b].end());
+    auto& nr = near[b];
+    std::sort(nr.begin(), nr.end());
+    std::vector<std::pair<int32_t, int32_t>> merged;
+    for (const auto& r : nr) {
+      if (!merged.empty() && merged.back().second == r.first)
+        merged.back().second = r.second;
+      else
+        merged.push_back(r);
+    }
+    nr.swap(merged);
+  }
+
+  // proxy slots: the clusters used as far clusters, in node order
+  std::vector<int32_t> slot(nd.size(), -1);
+  for (int b = 0; b < nb; ++b)
+    for (int ci : far[b]) slot[ci] = 0;
+  int ns = 0;
+  for (size_t ci = 0; ci < nd.size(); ++ci)
+    if (slot[ci] == 0) {
+      slot[ci] = ns++;
+      pl.pstart.push_back(nd[ci].s);
+      pl.pend.push_back(nd[ci].e);
+      // boxes padded to a width of at least h in every direction (flat clusters)
+      double lo[3], hi[3];
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = nd[ci].lo[d];
+        hi[d] = nd[ci].hi[d];
+        if (hi[d] - lo[d] < h) {
+          const double c = 0.5 * (lo[d] + hi[d]);
+          lo[d] = c - 0.5 * h;
+          hi[d] = c + 0.5 * h;
+        }
+      }
+      pl.pbox.insert(pl.pbox.end(), lo, lo + 3);
+      pl.pbox.insert(pl.pbox.end(), hi, hi + 3);
+      pl.proxy_evals += (double)(nd[ci].e - nd[ci].s) * n3;
+    }
+
+  pl.frow.assign(1, 0);
+  pl.nrow.assign(1, 0);
+  std::vector<double> work(nb);
+  for (int b = 0; b < nb; ++b) {
+    const double nt = pl.bstart[b + 1] - pl.bstart[b];
+    for (int ci : far[b]) pl.fcol.push_back(slot[ci]);
+    pl.frow.push_back((int32_t)pl.fcol.size());
+    double ns_near = 0.0;
+    for (const auto& r : near[b]) {
+      pl.nlo.push_back(r.first);
+      pl.nhi.push_back(r.second);
+      ns_near += r.second - r.first;
+    }
+    pl.nrow.push_back((int32_t)pl.nlo.size());
+    pl.far_evals += nt * n3 * (double)far[b].size();
+    pl.near_evals += nt * ns_near;
+    work[b] = (double)far[b].size() * n3 * 0.8 + ns_near;
+  }
+  pl.border.resize(nb);
+  std::iota(pl.border.begin(), pl.border.end(), 0);
+  std::stable_sort(pl.border.begin(), pl.border.end(),
+                   [&](int a, int b) { return work[a] > work[b]; });
+
+  // N_k in tree positions
+  pl.xrow.resize(M + 1);
+  pl.xrow[0] = 0;
+  for (int32_t t = 0; t < M; ++t) {
+    const int32_t k = pl.perm[t];
+    pl.xrow[t + 1] = pl.xrow[t] + (int32_t)(crow[k + 1] - crow[k]);
+  }
+  pl.xcol.resize(pl.xrow[M]);
+  for (int32_t t = 0; t < M; ++t) {
+    const int32_t k = pl.perm[t];
+    int32_t* o = pl.xcol.data() + pl.xrow[t];
+    for (int64_t e = crow[k]; e < crow[k + 1]; ++e) *o++ = pl.pos[ccol[e]];
+    std::sort(pl.xcol.data() + pl.xrow[t], o);
+  }
+  pl.enabled = true;
+  return IBIM_OK;
+}
+
+}  // namespace ibim

@@ -1,0 +1,50 @@
+// Device side of the treecode summation (plan in tree.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "operator.h"
+#include "tree.h"
+
+namespace ibim {
+
+// Device copy of a TreePlan plus the per-application buffers.
+struct TreeDevice {
+  int32_t M = 0;
+  int n_batches = 0, n_slots = 0, order = 0;
+  int32_t *perm = nullptr, *pos = nullptr;
+  int32_t *bstart = nullptr, *border = nullptr;
+  int32_t *pstart = nullptr, *pend = nullptr;
+  int32_t *frow = nullptr, *fcol = nullptr;
+  int32_t *nrow = nullptr, *nlo = nullptr, *nhi = nullptr;
+  int32_t *xrow = nullptr, *xcol = nullptr;
+  double* pbox = nullptr;  // 6 per proxy cluster: lo x, y, z, hi x, y, z
+  double* pxyz = nullptr;  // proxy points, 3 per point, order^3 points per cluster
+  double* cheb = nullptr;  // Chebyshev points on [-1, 1], barycentric weights, D (order^2)
+  // geometry in tree order
+  double *tx = nullptr, *ty = nullptr, *tz = nullptr;
+  double *tnx = nullptr, *tny = nullptr, *tnz = nullptr, *tw = nullptr;
+  // per application
+  double *ta1 = nullptr, *ta2 = nullptr;  // w u1, w u2 in tree order
+  double* pq = nullptr;                   // proxy charges (Q1, Q2) per point
+  double* S = nullptr;                    // 2M sums in tree order
+  size_t bytes = 0;
+
+  void release();
+};
+
+// Uploads the plan (and the tree-order geometry of P) to the device.
+hipError_t tree_upload(const TreePlan& pl, const DeviceProblem& P, const double* host_px,
+                       const double* host_py, const double* host_pz, const double* host_nx,
+                       const double* host_ny, const double* host_nz, const double* host_w,
+                       TreeDevice* T, hipStream_t s);
+// Pair sum (gather, proxy charges, batches) into T.S.
+hipError_t launch_tree_sum(const TreeDevice& T, const DeviceProblem& P, const double* u,
+                           hipStream_t s);
+// out = Lambda u + h^3/(4 pi) S (back in node order) + corrections.
+hipError_t launch_tree_finish(const TreeDevice& T, const DeviceProblem& P, const double* u,
+                              double* out, hipStream_t s);
+
+}  // namespace ibim

@@ -1,0 +1,419 @@
+// Treecode summation of the dense pair sum on the device.
+//
+// Interpolation in the source variable.  On the bounding box of a cluster C
+// take the tensor Chebyshev points s_p (second kind, `order` per dimension)
+// and the Lagrange basis L_p(y) = l_i(y_x) l_j(y_y) l_k(y_z).  Every kernel of
+// the pair sum is a derivative of
+//   FA = (1 - c1 e^{-kR})/R,  FB = (1 - e^{-kR})/R,  FC = (1 - c2 e^{-kR})/R
+// (times 1/(4 pi)): K11 = d/dn_y FA, K12 = FB, K21 = d/dn_x d/dn_y FB,
+// K22 = -d/dn_x FC.  Replacing F(x, y) by sum_p F(x, s_p) L_p(y) gives, for
+// the sources of C,
+//   sum_m K11 a1_m - K12 a2_m  ~  sum_p FA(x, s_p) Q1_p - FB(x, s_p) Q2_p,
+//   sum_m K21 a1_m - K22 a2_m  ~  sum_p d/dn_x FB(x, s_p) Q1_p - d/dn_x FC(x, s_p) Q2_p,
+// with the proxy charges Q1_p = sum_m a1_m n_m . grad L_p(y_m) and
+// Q2_p = sum_m a2_m L_p(y_m).  The basis is evaluated in barycentric form and
+// its derivative through the differentiation matrix of the Chebyshev points
+// (l_i' = sum_q l_q D_qi, exact for polynomials of this degree).
+//
+// One workgroup per batch of 256 targets (one per lane) runs through the
+// batch's proxy clusters and then its direct source ranges, staging both in
+// LDS; each target's sum is formed in a fixed order, so results are
+// reproducible.  All arithmetic is float64.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <vector>
+
+#include "context.h"
+#include "pair_math.h"
+#include "treecode.h"
+
+namespace ibim {
+namespace {
+
+constexpr int kUpSrc = 64;  // sources per round of the proxy-charge kernel
+constexpr int kMaxPer = (kTreeMaxOrder * kTreeMaxOrder * kTreeMaxOrder + 255) / 256;
+
+struct TreeArgs {
+  const int32_t *perm, *pos, *bstart, *border, *pstart, *pend, *frow, *fcol, *nrow, *nlo, *nhi,
+      *xrow, *xcol;
+  const double *pbox, *pxyz, *cheb;
+  const double *tx, *ty, *tz, *tnx, *tny, *tnz, *tw;
+  double *ta1, *ta2, *pq, *S;
+  const double* u;
+  PairConsts pc;
+  int32_t M;
+  int order;
+};
+
+TreeArgs make_args(const TreeDevice& T, const DeviceProblem& P, const double* u) {
+  TreeArgs a;
+  a.perm = T.perm; a.pos = T.pos; a.bstart = T.bstart; a.border = T.border;
+  a.pstart = T.pstart; a.pend = T.pend; a.frow = T.frow; a.fcol = T.fcol;
+  a.nrow = T.nrow; a.nlo = T.nlo; a.nhi = T.nhi; a.xrow = T.xrow; a.xcol = T.xcol;
+  a.pbox = T.pbox; a.pxyz = T.pxyz; a.cheb = T.cheb;
+  a.tx = T.tx; a.ty = T.ty; a.tz = T.tz; a.tnx = T.tnx; a.tny = T.tny; a.tnz = T.tnz;
+  a.tw = T.tw;
+  a.ta1 = T.ta1; a.ta2 = T.ta2; a.pq = T.pq; a.S = T.S;
+  a.u = u;
+  a.pc = PairConsts{P.eps_out / P.eps_in, P.eps_in / P.eps_out, P.kappa, P.kappa * P.kappa};
+  a.M = T.M;
+  a.order = T.order;
+  return a;
+}
+
+// a1 = w u1, a2 = w u2 in tree order
+__global__ void tree_gather_kernel(TreeArgs a) {
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.M) return;
+  const int32_t k = a.perm[t];
+  const double w = a.tw[t];
+  a.ta1[t] = w * a.u[k];
+  a.ta2[t] = w * a.u[a.M + k];
+}
+
+// Proxy charges of one cluster per workgroup.
+__global__ __launch_bounds__(256) void tree_upward_kernel(TreeArgs a) {
+  __shared__ double tch[kTreeMaxOrder], wch[kTreeMaxOrder], dch[kTreeMaxOrder * kTreeMaxOrder];
+  __shared__ double bl[kUpSrc][3][kTreeMaxOrder];  // l_i(y_d)
+  __shared__ double bd[kUpSrc][3][kTreeMaxOrder];  // d l_i / d y_d
+  __shared__ double sv[kUpSrc][4];                 // a1 n_x, a1 n_y, a1 n_z, a2
+  const int slot = blockIdx.x, tid = threadIdx.x;
+  const int n = a.order, n2 = n * n, n3 = n2 * n;
+  const int32_t s = a.pstart[slot], e = a.pend[slot];
+  const double* box = a.pbox + 6 * (size_t)slot;
+  if (tid < n) {
+    tch[tid] = a.cheb[tid];
+    wch[tid] = a.cheb[n + tid];
+  }
+  if (tid < n2) dch[tid] = a.cheb[2 * n + tid];
+  double Q1[kMaxPer], Q2[kMaxPer];
+#pragma unroll
+  for (int r = 0; r < kMaxPer; ++r) Q1[r] = Q2[r] = 0.0;
+  for (int32_t c0 = s; c0 < e; c0 += kUpSrc) {
+    __syncthreads();
+    if (tid < 3 * kUpSrc) {
+      const int j = tid / 3, d = tid % 3;
+      const int32_t m = c0 + j;
+      if (m < e) {
+        const double y = d == 0 ? a.tx[m] : (d == 1 ? a.ty[m] : a.tz[m]);
+        const double lo = box[d], hi = box[3 + d];
+        const double half = 0.5 * (hi - lo);
+        const double t = (y - 0.5 * (lo + hi)) / half;
+        int hit = -1;
+        for (int i = 0; i < n; ++i)
+          if (t == tch[i]) hit = i;
+        double l[kTreeMaxOrder];
+        if (hit >= 0) {
+          for (int i = 0; i < n; ++i) l[i] = i == hit ? 1.0 : 0.0;
+        } else {
+          double sum = 0.0;
+          for (int i = 0; i < n; ++i) {
+            l[i] = wch[i] / (t - tch[i]);
+            sum += l[i];
+          }
+          const double is = 1.0 / sum;
+          for (int i = 0; i < n; ++i) l[i] *= is;
+        }
+        for (int i = 0; i < n; ++i) {
+          double dl = 0.0;
+          for (int q = 0; q < n; ++q) dl = fma(l[q], dch[q * n + i], dl);
+          bl[j][d][i] = l[i];
+          bd[j][d][i] = dl / half;
+        }
+        if (d == 0) {
+          const double w = a.ta1[m];
+          sv[j][0] = w * a.tnx[m];
+          sv[j][1] = w * a.tny[m];
+          sv[j][2] = w * a.tnz[m];
+          sv[j][3] = a.ta2[m];
+        }
+      }
+    }
+    __syncthreads();
+    const int cnt = min(kUpSrc, (int)(e - c0));
+#pragma unroll
+    for (int r = 0; r < kMaxPer; ++r) {
+      const int p = tid + 256 * r;
+      if (p < n3) {
+        const int i = p / n2, jj = (p / n) % n, k = p % n;
+        double q1 = Q1[r], q2 = Q2[r];
+        for (int j = 0; j < cnt; ++j) {
+          const double lx = bl[j][0][i], ly = bl[j][1][jj], lz = bl[j][2][k];
+          const double dx = bd[j][0][i], dy = bd[j][1][jj], dz = bd[j][2][k];
+          const double lyz = ly * lz;
+          q2 = fma(lx * lyz, sv[j][3], q2);
+          q1 = fma(sv[j][0] * dx, lyz, q1);
+          q1 = fma(sv[j][1] * lx, dy * lz, q1);
+          q1 = fma(sv[j][2] * lx, ly * dz, q1);
+        }
+        Q1[r] = q1;
+        Q2[r] = q2;
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kMaxPer; ++r) {
+    const int p = tid + 256 * r;
+    if (p < n3) {
+      a.pq[2 * ((size_t)slot * n3 + p)] = Q1[r];
+      a.pq[2 * ((size_t)slot * n3 + p) + 1] = Q2[r];
+    }
+  }
+}
+
+// Far field of one proxy point (sx, sy, sz) with charges (q1, q2).
+__device__ __forceinline__ void far_eval(double x, double y, double z, double nxk, double nyk,
+                                         double nzk, double sx, double sy, double sz, double q1,
+                                         double q2, const PairConsts& c, double& S1, double& S2) {
+  const double rx = x - sx, ry = y - sy, rz = z - sz;
+  const double R2 = fma(rz, rz, fma(ry, ry, rx * rx));
+  const double iR = rsqrt_pos(R2);
+  const double R = R2 * iR;
+  const double kr = c.kappa * R;
+  const double e = exp_neg(kr);
+  const double te = fma(e, kr, e);
+  const double rn = fma(rz, nzk, fma(ry, nyk, rx * nxk));
+  const double iR3 = iR * iR * iR;
+  // FA Q1 - FB Q2
+  S1 = fma(iR, fma(fma(-c.c1, e, 1.0), q1, -(1.0 - e) * q2), S1);
+  // d/dn_x FB Q1 - d/dn_x FC Q2, d/dn_x F = -(r.n_k)(1 - c t)/R^3
+  S2 = fma(rn * iR3, fma(fma(-c.c2, te, 1.0), q2, -(1.0 - te) * q1), S2);
+}
+
+__global__ __launch_bounds__(256) void tree_batch_kernel(TreeArgs a) {
+  __shared__ double sh[8][256];
+  const int b = a.border[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int32_t t0 = a.bstart[b], nt = a.bstart[b + 1] - t0;
+  const int32_t t = t0 + min(tid, nt - 1);
+  const double x = a.tx[t], y = a.ty[t], z = a.tz[t];
+  const double nxk = a.tnx[t], nyk = a.tny[t], nzk = a.tnz[t];
+  const int n3 = a.order * a.order * a.order;
+  double S1 = 0.0, S2 = 0.0;
+  // proxy clusters
+  for (int32_t f = a.frow[b]; f < a.frow[b + 1]; ++f) {
+    const size_t base = (size_t)a.fcol[f] * n3;
+    for (int c0 = 0; c0 < n3; c0 += 256) {
+      const int cnt = min(256, n3 - c0);
+      __syncthreads();
+      if (tid < cnt) {
+        const size_t p = base + c0 + tid;
+        sh[0][tid] = a.pxyz[3 * p];
+        sh[1][tid] = a.pxyz[3 * p + 1];
+        sh[2][tid] = a.pxyz[3 * p + 2];
+        sh[3][tid] = a.pq[2 * p];
+        sh[4][tid] = a.pq[2 * p + 1];
+      }
+      __syncthreads();
+      for (int j = 0; j < cnt; ++j)
+        far_eval(x, y, z, nxk, nyk, nzk, sh[0][j], sh[1][j], sh[2][j], sh[3][j], sh[4][j], a.pc,
+                 S1, S2);
+    }
+  }
+  // direct ranges, pairs of N_k skipped
+  int32_t p = a.xrow[t];
+  const int32_t pe = a.xrow[t + 1];
+  for (int32_t r = a.nrow[b]; r < a.nrow[b + 1]; ++r) {
+    const int32_t lo = a.nlo[r], hi = a.nhi[r];
+    while (p < pe && a.xcol[p] < lo) ++p;
+    int32_t nxt = p < pe ? a.xcol[p] : INT32_MAX;
+    for (int32_t c0 = lo; c0 < hi; c0 += 256) {
+      const int cnt = min(256, (int)(hi - c0));
+      __syncthreads();
+      if (tid < cnt) {
+        const int32_t m = c0 + tid;
+        sh[0][tid] = a.tx[m];
+        sh[1][tid] = a.ty[m];
+        sh[2][tid] = a.tz[m];
+        sh[3][tid] = a.tnx[m];
+        sh[4][tid] = a.tny[m];
+        sh[5][tid] = a.tnz[m];
+        sh[6][tid] = a.ta1[m];
+        sh[7][tid] = a.ta2[m];
+      }
+      __syncthreads();
+      for (int j = 0; j < cnt; ++j) {
+        double d1, d2;
+        pair_f64<false>(x, y, z, nxk, nyk, nzk, sh[0][j], sh[1][j], sh[2][j], sh[3][j], sh[4][j],
+                        sh[5][j], sh[6][j], sh[7][j], a.pc, d1, d2);
+        const bool ex = c0 + j == nxt;
+        if (ex) {
+          ++p;
+          nxt = p < pe ? a.xcol[p] : INT32_MAX;
+        }
+        S1 += ex ? 0.0 : d1;
+        S2 += ex ? 0.0 : d2;
+      }
+    }
+  }
+  if (tid < nt) {
+    a.S[t] = S1;
+    a.S[a.M + t] = S2;
+  }
+}
+
+struct TreeFinishArgs {
+  const double* u;
+  const double* S;
+  const int32_t* pos;
+  const int32_t* crow;
+  const int32_t* ccol;
+  const double* blocks;
+  int32_t M;
+  double lam1, lam2, scale;
+  double* out;
+};
+
+__global__ void tree_finish_kernel(TreeFinishArgs a) {
+  const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= a.M) return;
+  const int32_t M = a.M, t = a.pos[k];
+  double o1 = a.lam1 * a.u[k] + a.scale * a.S[t];
+  double o2 = a.lam2 * a.u[M + k] + a.scale * a.S[M + t];
+  for (int32_t e = a.crow[k]; e < a.crow[k + 1]; ++e) {
+    const int32_t m = a.ccol[e];
+    const double* B = a.blocks + 4 * (size_t)e;
+    const double v1 = a.u[m], v2 = a.u[M + m];
+    o1 += B[0] * v1 + B[1] * v2;
+    o2 += B[2] * v1 + B[3] * v2;
+  }
+  a.out[k] = o1;
+  a.out[M + k] = o2;
+}
+
+template <class T>
+hipError_t up(T** dst, const std::vector<T>& v, size_t* bytes, hipStream_t s) {
+  *bytes += v.size() * sizeof(T);
+  return upload(dst, v.data(), v.size(), s);
+}
+
+}  // namespace
+
+void TreeDevice::release() {
+  dfree(perm); dfree(pos); dfree(bstart); dfree(border); dfree(pstart); dfree(pend);
+  dfree(frow); dfree(fcol); dfree(nrow); dfree(nlo); dfree(nhi); dfree(xrow); dfree(xcol);
+  dfree(pbox); dfree(pxyz); dfree(cheb);
+  dfree(tx); dfree(ty); dfree(tz); dfree(tnx); dfree(tny); dfree(tnz); dfree(tw);
+  dfree(ta1); dfree(ta2); dfree(pq); dfree(S);
+}
+
+hipError_t tree_upload(const TreePlan& pl, const DeviceProblem& P, const double* hpx,
+                       const double* hpy, const double* hpz, const double* hnx, const double* hny,
+                       const double* hnz, const double* hw, TreeDevice* T, hipStream_t s) {
+  TreeDevice& d = *T;
+  d.M = pl.M;
+  d.order = pl.order;
+  d.n_batches = (int)pl.bstart.size() - 1;
+  d.n_slots = (int)pl.pstart.size();
+  const int n = pl.order, n3 = n * n * n;
+  // Chebyshev points of the second kind, barycentric weights, differentiation matrix
+  std::vector<double> cheb(2 * n + n * n);
+  for (int i = 0; i < n; ++i) {
+    cheb[i] = std::cos(kPi * i / (n - 1));
+    cheb[n + i] = ((i % 2) ? -1.0 : 1.0) * ((i == 0 || i == n - 1) ? 0.5 : 1.0);
+  }
+  for (int q = 0; q < n; ++q) {
+    double diag = 0.0;
+    for (int i = 0; i < n; ++i) {
+      if (i == q) continue;
+      const double v = (cheb[n + i] / cheb[n + q]) / (cheb[q] - cheb[i]);
+      cheb[2 * n + q * n + i] = v;  // l_i'(t_q)
+      diag -= v;
+    }
+    cheb[2 * n + q * n + q] = diag;
+  }
+  std::vector<double> pxyz((size_t)d.n_slots * n3 * 3);
+  for (int sl = 0; sl < d.n_slots; ++sl) {
+    const double* b = pl.pbox.data() + 6 * (size_t)sl;
+    double mid[3], half[3];
+    for (int k = 0; k < 3; ++k) {
+      mid[k] = 0.5 * (b[k] + b[3 + k]);
+      half[k] = 0.5 * (b[3 + k] - b[k]);
+    }
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j)
+        for (int k = 0; k < n; ++k) {
+          const size_t p = (size_t)sl * n3 + (size_t)(i * n + j) * n + k;
+          pxyz[3 * p] = mid[0] + half[0] * cheb[i];
+          pxyz[3 * p + 1] = mid[1] + half[1] * cheb[j];
+          pxyz[3 * p + 2] = mid[2] + half[2] * cheb[k];
+        }
+  }
+  const int32_t M = pl.M;
+  std::vector<double> g[7];
+  const double* src[7] = {hpx, hpy, hpz, hnx, hny, hnz, hw};
+  for (int c = 0; c < 7; ++c) {
+    g[c].resize(M);
+    for (int32_t t = 0; t < M; ++t) g[c][t] = src[c][pl.perm[t]];
+  }
+  size_t& by = d.bytes;
+  by = 0;
+  hipError_t e = hipSuccess;
+#define TUP(dst, vec) \
+  if (e == hipSuccess) e = up(&d.dst, vec, &by, s)
+  TUP(perm, pl.perm);
+  TUP(pos, pl.pos);
+  TUP(bstart, pl.bstart);
+  TUP(border, pl.border);
+  TUP(pstart, pl.pstart);
+  TUP(pend, pl.pend);
+  TUP(frow, pl.frow);
+  TUP(fcol, pl.fcol);
+  TUP(nrow, pl.nrow);
+  TUP(nlo, pl.nlo);
+  TUP(nhi, pl.nhi);
+  TUP(xrow, pl.xrow);
+  TUP(xcol, pl.xcol);
+  TUP(pbox, pl.pbox);
+  TUP(pxyz, pxyz);
+  TUP(cheb, cheb);
+  TUP(tx, g[0]);
+  TUP(ty, g[1]);
+  TUP(tz, g[2]);
+  TUP(tnx, g[3]);
+  TUP(tny, g[4]);
+  TUP(tnz, g[5]);
+  TUP(tw, g[6]);
+#undef TUP
+  if (e == hipSuccess) e = dalloc(&d.ta1, (size_t)M);
+  if (e == hipSuccess) e = dalloc(&d.ta2, (size_t)M);
+  if (e == hipSuccess) e = dalloc(&d.pq, (size_t)d.n_slots * n3 * 2);
+  if (e == hipSuccess) e = dalloc(&d.S, 2 * (size_t)M);
+  by += (4 * (size_t)M + (size_t)d.n_slots * n3 * 2) * sizeof(double);
+  // the host vectors above are temporaries
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e;
+}
+
+hipError_t launch_tree_sum(const TreeDevice& T, const DeviceProblem& P, const double* u,
+                           hipStream_t s) {
+  const TreeArgs a = make_args(T, P, u);
+  hipLaunchKernelGGL(tree_gather_kernel, dim3((unsigned)((T.M + 255) / 256)), dim3(256), 0, s, a);
+  if (T.n_slots > 0)
+    hipLaunchKernelGGL(tree_upward_kernel, dim3((unsigned)T.n_slots), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(tree_batch_kernel, dim3((unsigned)T.n_batches), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_tree_finish(const TreeDevice& T, const DeviceProblem& P, const double* u,
+                              double* out, hipStream_t s) {
+  TreeFinishArgs f;
+  f.u = u;
+  f.S = T.S;
+  f.pos = T.pos;
+  f.crow = P.crow;
+  f.ccol = P.ccol;
+  f.blocks = P.blocks;
+  f.M = P.M;
+  f.lam1 = P.lam1;
+  f.lam2 = P.lam2;
+  f.scale = P.h * P.h * P.h / (4.0 * kPi);
+  f.out = out;
+  hipLaunchKernelGGL(tree_finish_kernel, dim3((unsigned)((P.M + 255) / 256)), dim3(256), 0, s, f);
+  return hipGetLastError();
+}
+
+}  // namespace ibim

@@ -23,6 +23,7 @@ FP64 = 0
 MIXED = 1
 CTR2, HYB, KREG = 0, 1, 2  # quadrature of the rows (ibim_options.hybrid)
 PRECOND_NONE, PRECOND_DIAG = 0, 1  # system handed to GMRES (ibim_options.precond)
+SUM_DIRECT, SUM_TREE = 0, 1  # evaluation of the dense pair sum (ibim_options.summation)
 
 _ERRORS = {
     -1: "IBIM_EINVAL", -2: "IBIM_EGEOM", -3: "IBIM_ENOMEM", -4: "IBIM_EHIP", -5: "IBIM_ENAN",
@@ -40,7 +41,8 @@ class _Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("restart", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("check_residual", ctypes.c_int), ("device", ctypes.c_int),
                 ("r_near", ctypes.c_double), ("hybrid", ctypes.c_int),
-                ("precond", ctypes.c_int)]
+                ("precond", ctypes.c_int), ("summation", ctypes.c_int),
+                ("tree_order", ctypes.c_int), ("tree_theta", ctypes.c_double)]
 
 
 class _SolveInfo(ctypes.Structure):
@@ -112,6 +114,7 @@ def load():
     lib.ibim_pair_timing.argtypes = [_VP, ctypes.c_int]
     lib.ibim_pair_timing_read.argtypes = [_VP, _I64, _D]
     lib.ibim_pair_work.argtypes = [_VP, _D, _D]
+    lib.ibim_tree_counts.argtypes = [_VP, _D]
     lib.ibim_server_create.argtypes = [ctypes.POINTER(_Options), ctypes.c_size_t, ctypes.c_int,
                                        ctypes.c_int, _VP, ctypes.POINTER(_VP)]
     lib.ibim_server_submit.argtypes = [_VP, _D, ctypes.c_int, ctypes.c_int, ctypes.c_int, _D,
@@ -163,7 +166,8 @@ class Problem:
 
     def __init__(self, sdf, origin, h, eps_tube, eps_in, eps_out, kappa, charge_xyz=None,
                  charge_q=None, precision=FP64, restart=60, max_iter=300, check_residual=True,
-                 device=0, r_near=0.0, hybrid=CTR2, precond=PRECOND_DIAG, stream=None):
+                 device=0, r_near=0.0, hybrid=CTR2, precond=PRECOND_DIAG, summation=SUM_DIRECT,
+                 tree_order=8, tree_theta=0.7, stream=None):
         lib = load()
         self._lib = lib
         sdf = np.ascontiguousarray(sdf, dtype=np.float64)
@@ -185,6 +189,9 @@ class Problem:
         opt.r_near = float(r_near)
         opt.hybrid = int(hybrid)
         opt.precond = int(precond)
+        opt.summation = int(summation)
+        opt.tree_order = int(tree_order)
+        opt.tree_theta = float(tree_theta)
         self.device = int(device)
         self.h = float(h)
         ctx = ctypes.c_void_p()
@@ -308,6 +315,13 @@ class Problem:
         _check(self._lib.ibim_pair_work(self._ctx, ctypes.byref(p), ctypes.byref(f)))
         return float(p.value), float(f.value)
 
+    def tree_counts(self):
+        """Work of one treecode pair sum (``ibim_tree_counts``)."""
+        out = np.zeros(5)
+        _check(self._lib.ibim_tree_counts(self._ctx, _dp(out)))
+        return {"far_evals": out[0], "near_evals": out[1], "proxy_terms": out[2],
+                "batches": int(out[3]), "proxy_clusters": int(out[4])}
+
     def solve_energy(self, tol, stream=None):
         g = self.rhs(stream=stream)
         x, info = self.solve(g, tol, stream=stream)
@@ -327,7 +341,7 @@ class Server:
 
     def __init__(self, hbm_budget_bytes, max_slots=16, host_threads=4, precision=FP64,
                  restart=60, max_iter=300, check_residual=True, device=0, r_near=0.0,
-                 hybrid=CTR2, precond=PRECOND_DIAG, stream=None):
+                 hybrid=CTR2, precond=PRECOND_DIAG, summation=SUM_DIRECT, stream=None):
         lib = load()
         self._lib = lib
         opt = _Options()
@@ -340,6 +354,7 @@ class Server:
         opt.r_near = float(r_near)
         opt.hybrid = int(hybrid)
         opt.precond = int(precond)
+        opt.summation = int(summation)
         srv = ctypes.c_void_p()
         _check(lib.ibim_server_create(ctypes.byref(opt), int(hbm_budget_bytes), int(max_slots),
                                       int(host_threads), _stream_ptr(stream), ctypes.byref(srv)))

@@ -1,0 +1,111 @@
+"""Treecode summation (IBIM_SUM_TREE) on the GPU.
+
+The treecode approximates the dense pair sum (the far-field acceleration of
+Section 2.5); its reference is the exact sum:
+* with a separation parameter so small that no cluster is far, it sums every
+  pair directly and must equal the direct path to rounding (1e-13);
+* against the FP64 oracle's operator, the error falls geometrically as the
+  number of Chebyshev points grows and as theta shrinks;
+* solves: G_pol within 1e-6 of the direct FP64 solve (the mixed form's bar).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2210_03699_amd import ibim  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _apply(prob, u):
+    return prob.apply(torch.from_numpy(u).to(DEV)).cpu().numpy()
+
+
+def _rel(a, b, M):
+    return max(np.max(np.abs(a[:M] - b[:M])) / np.max(np.abs(b[:M])),
+               np.max(np.abs(a[M:] - b[M:])) / np.max(np.abs(b[M:])))
+
+
+NEAR_CASES = {
+    "born_h0.2": lambda: workloads.born_sphere(h=0.2),
+    "torus": lambda: workloads.torus_case(h=0.1),
+    "ses_molecule": lambda: workloads.ses_molecule(20, 9.0, 0.35, 2.0, seed=11),
+}
+
+
+@pytest.mark.parametrize("name", list(NEAR_CASES))
+def test_all_near_equals_direct(name):
+    wl = NEAR_CASES[name]()
+    direct = ibim.Problem.from_workload(wl, device=0)
+    tree = ibim.Problem.from_workload(wl, device=0, summation=ibim.SUM_TREE, tree_theta=1e-6)
+    cnt = tree.tree_counts()
+    assert cnt["far_evals"] == 0 and cnt["near_evals"] == tree.M * tree.M
+    u = workloads.random_vector(2 * tree.M, 21)
+    err = _rel(_apply(tree, u), _apply(direct, u), tree.M)
+    _say(f"[tree all-near {name}] M={tree.M} batches={cnt['batches']} rel {err:.3e}")
+    assert err < 1e-13
+
+
+@pytest.fixture(scope="module")
+def kw():
+    wl = workloads.kirkwood_sphere(h=0.2, radius=5.0, r_charges=3.0)
+    orc = oracle.Oracle.from_workload(wl)
+    u = workloads.random_vector(2 * orc.M, 22)
+    return wl, u, orc.apply(u), orc
+
+
+def test_error_falls_geometrically(kw):
+    wl, u, ref, orc = kw
+    errs = {}
+    for order in (4, 6, 8, 10):
+        p = ibim.Problem.from_workload(wl, device=0, summation=ibim.SUM_TREE, tree_order=order,
+                                       tree_theta=0.7)
+        errs[order] = _rel(_apply(p, u), ref, p.M)
+        c = p.tree_counts()
+        _say(f"[tree order={order} theta=0.7] M={p.M} far={c['far_evals']:.3e} "
+             f"near={c['near_evals']:.3e} rel err {errs[order]:.3e}")
+        p.close()
+    assert errs[4] < 1e-3
+    assert errs[6] < errs[4] / 4 and errs[8] < errs[6] / 4 and errs[10] < errs[8] / 2
+    p = ibim.Problem.from_workload(wl, device=0, summation=ibim.SUM_TREE, tree_order=8,
+                                   tree_theta=0.5)
+    e = _rel(_apply(p, u), ref, p.M)
+    _say(f"[tree order=8 theta=0.5] rel err {e:.3e}")
+    assert e < errs[8] / 10 and e < 1e-7
+
+
+def test_tree_solve_matches_direct(kw):
+    wl, u, ref, orc = kw
+    g = {}
+    for name, kwargs in (("direct", {}), ("tree", {"summation": ibim.SUM_TREE})):
+        p = ibim.Problem.from_workload(wl, device=0, **kwargs)
+        _, info = p.solve_energy(wl.tol)
+        assert info["converged"]
+        g[name] = info["g_pol"]
+        _say(f"[tree solve {name}] iters={info['iters']} G={info['g_pol']:.15e}")
+        p.close()
+    g_orc = orc.solve_energy(wl.charge_xyz, wl.charge_q, wl.tol)[1]["g_pol"]
+    assert abs(g["direct"] - g_orc) <= 1e-10 * abs(g_orc)
+    assert abs(g["tree"] - g_orc) <= 1e-6 * abs(g_orc)
+
+
+def test_tree_options_rejected():
+    wl = workloads.born_sphere(h=0.4)
+    with pytest.raises(ibim.IbimError):
+        ibim.Problem.from_workload(wl, device=0, summation=ibim.SUM_TREE, precision=ibim.MIXED)
+    with pytest.raises(ibim.IbimError):
+        ibim.Problem.from_workload(wl, device=0, summation=ibim.SUM_TREE, tree_order=17)
+    with pytest.raises(ibim.IbimError):
+        ibim.Server(1 << 30, summation=ibim.SUM_TREE)

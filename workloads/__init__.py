@@ -212,6 +212,7 @@ def by_name(name: str) -> Workload:
     ``ses2000``   2000 atoms, 40 A box, h = 0.35, eps = 2h, tol 1e-6.
     ``ses2000_twin`` the same molecule at h = 0.7 with eps = 1.5h (within the
                   re-entrant reach of the 1.4 A probe).
+    ``kirkwood_h0.1`` the Kirkwood sphere at h = 0.1 (eps = 3h, M ~ 7.5e5).
     """
     if name == "born":
         return born_sphere()
@@ -223,6 +224,8 @@ def by_name(name: str) -> Workload:
         return ses_molecule(2000, 40.0, 0.35, 2.0, seed=5)
     if name == "ses2000_twin":
         return ses_molecule(2000, 40.0, 0.7, 1.5, seed=5)
+    if name == "kirkwood_h0.1":
+        return kirkwood_sphere(h=0.1)
     raise KeyError(name)
 
 
