@@ -69,7 +69,7 @@ typedef struct {
   int hybrid;          /* IBIM_CTR2 (default), IBIM_HYB or IBIM_KREG, below */
   int precond;         /* IBIM_PRECOND_DIAG (default) or IBIM_PRECOND_NONE, below */
   int summation;       /* IBIM_SUM_DIRECT (default) or IBIM_SUM_TREE, below */
-  int tree_order;      /* IBIM_SUM_TREE: Chebyshev points per dimension, 2..16 (default 8) */
+  int tree_order;      /* IBIM_SUM_TREE: Chebyshev points per dimension, 2..12 (default 8) */
   double tree_theta;   /* IBIM_SUM_TREE: separation parameter, (0, 1] (default 0.7) */
 } ibim_options;
 
@@ -269,15 +269,17 @@ int ibim_pair_timing_read(ibim_ctx* ctx, int64_t* launches, double* total_ms);
  * tiles are still evaluated one direction at a time).  In the mixed form
  * these are float32 operations.  For IBIM_SUM_TREE, *pairs is still M^2 (the
  * pairs the sum stands for) and *flops counts what the treecode performs: 60
- * per direct pair, 36 per target-proxy evaluation, 15 per source-proxy term.
+ * per direct pair, 36 per target-proxy evaluation, 15 per source-proxy term
+ * and 12 tree_order^4 per child-to-parent transfer of proxy charges.
  */
 int ibim_pair_work(const ibim_ctx* ctx, double* pairs, double* flops);
 
 /*
  * Work of one treecode pair sum (IBIM_SUM_TREE contexts; IBIM_EINVAL for
- * others).  out (host, 5 doubles): [0] target-proxy evaluations, [1] direct
+ * others).  out (host, 6 doubles): [0] target-proxy evaluations, [1] direct
  * pair evaluations, [2] source-proxy terms of the proxy charges, [3] batches
- * of targets, [4] proxy clusters.  Each application performs exactly these.
+ * of targets, [4] proxy clusters, [5] child-to-parent charge transfers.  Each
+ * application performs exactly these.
  */
 int ibim_tree_counts(const ibim_ctx* ctx, double* out);
 

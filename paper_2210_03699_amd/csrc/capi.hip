@@ -236,7 +236,7 @@ int ctx_create_host(const double* sdf, int nx, int ny, int nz, const double orig
   if (o.summation == IBIM_SUM_TREE) {
     if (o.precision != IBIM_FP64) return fail(IBIM_EINVAL, "the treecode runs in float64 only");
     if (o.tree_order < 2 || o.tree_order > ibim::kTreeMaxOrder)
-      return fail(IBIM_EINVAL, "tree_order must be in [2, 16]");
+      return fail(IBIM_EINVAL, "tree_order must be in [2, 12]");
     if (!(o.tree_theta > 0.0 && o.tree_theta <= 1.0))
       return fail(IBIM_EINVAL, "tree_theta must be in (0, 1]");
   }
@@ -437,8 +437,9 @@ int ctx_setup_device(ibim_ctx* c, hipStream_t s) {
                     pl.ny.data(), pl.nz.data(), pl.w.data(), &c->tree, s);
     if (e != hipSuccess) return bad(e, "treecode setup");
     bytes += c->tree.bytes;
+    const double n4 = std::pow((double)o.tree_order, 4.0);
     c->pair_flops = 60.0 * c->tplan.near_evals + 36.0 * c->tplan.far_evals +
-                    15.0 * c->tplan.proxy_evals;
+                    15.0 * c->tplan.proxy_evals + 12.0 * n4 * c->tplan.m2m_links;
   }
   if (c->sym.enabled) {
     // the quadratic scratch comes first: if the device cannot hold it, the
@@ -844,6 +845,7 @@ int ibim_tree_counts(const ibim_ctx* ctx, double* out) {
   out[2] = t.proxy_evals;
   out[3] = (double)(t.bstart.size() - 1);
   out[4] = (double)t.pstart.size();
+  out[5] = t.m2m_links;
   return IBIM_OK;
 }
 

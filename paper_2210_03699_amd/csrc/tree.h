@@ -14,7 +14,7 @@
 namespace ibim {
 
 constexpr int kTreeBatch = 256;  // targets per batch (one workgroup)
-constexpr int kTreeMaxOrder = 16;
+constexpr int kTreeMaxOrder = 12;
 
 struct TreeParams {
   int order = 8;        // Chebyshev points per dimension (degree order - 1)
@@ -32,18 +32,33 @@ struct TreePlan {
   // batches: target ranges [bstart[b], bstart[b + 1])
   std::vector<int32_t> bstart;
   std::vector<int32_t> border;  // batch indices, most work first
-  // clusters with proxies: source range, bounding box (lo x, y, z, hi x, y, z)
+  // clusters with proxies (every cluster with more nodes than proxies, in
+  // tree preorder): source range, bounding box (lo x, y, z, hi x, y, z)
   std::vector<int32_t> pstart, pend;
   std::vector<double> pbox;
+  // charges of a proxy cluster: from the sources of [dstart, dend) directly
+  // (its children without proxies, or itself when it is a leaf) plus, by
+  // exact interpolation of their proxies, from its children with proxies
+  // (kid, 2 per cluster, -1 if none); mlist orders the clusters by height
+  // above the leaves, mlevel[h] .. mlevel[h + 1] being height h
+  std::vector<int32_t> dstart, dend, kid;
+  std::vector<int32_t> mlist, mlevel;
   // per batch: proxy clusters (far) and merged source ranges (near), CSR
   std::vector<int32_t> frow, fcol;
   std::vector<int32_t> nrow, nlo, nhi;
+  // work items: a batch's lists cut into parts of similar work, so that the
+  // device has many more workgroups than compute units; item i covers the
+  // far entries [ifar0, ifar1) and near ranges [inear0, inear1) of batch
+  // ibatch[i]; the items of batch b are istart[b] .. istart[b + 1]; iorder
+  // lists them most work first
+  std::vector<int32_t> ibatch, ifar0, ifar1, inear0, inear1, istart, iorder;
   // N_k in tree positions, ascending, per tree position (CSR)
   std::vector<int32_t> xrow, xcol;
   double gap = 0.0;         // largest |x_k - P_m| over m in N_k
   double far_evals = 0.0;   // target-proxy evaluations per application
   double near_evals = 0.0;  // direct pair evaluations per application
-  double proxy_evals = 0.0; // source-proxy terms of the upward pass
+  double proxy_evals = 0.0; // source-proxy terms of the direct proxy charges
+  double m2m_links = 0.0;   // child-to-parent proxy transfers
 };
 
 // Builds the plan from the projected points, the correction sets (CSR with

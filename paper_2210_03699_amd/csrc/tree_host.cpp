@@ -136,6 +136,11 @@ int build_tree_plan(const TreeParams& prm, int64_t M64, const double* px, const 
   pl.bstart.resize(nb + 1);
   for (int b = 0; b < nb; ++b) pl.bstart[b] = nd[leaves[b]].s;
   pl.bstart[nb] = M;
+  for (int b = 0; b < nb; ++b)
+    if (pl.bstart[b] != b * kTreeBatch) {  // every leaf but the last holds kTreeBatch points
+      *err = "internal error: unaligned treecode batch";
+      return IBIM_EINVAL;
+    }
 
   // interaction lists
   std::vector<std::vector<int>> far(nb);
@@ -174,31 +179,68 @@ int build_tree_plan(const TreeParams& prm, int64_t M64, const double* px, const 
     nr.swap(merged);
   }
 
-  // proxy slots: the clusters used as far clusters, in node order
+  // proxy slots: every cluster with more points than proxies, in preorder
+  // (a parent before its children)
   std::vector<int32_t> slot(nd.size(), -1);
-  for (int b = 0; b < nb; ++b)
-    for (int ci : far[b]) slot[ci] = 0;
   int ns = 0;
   for (size_t ci = 0; ci < nd.size(); ++ci)
-    if (slot[ci] == 0) {
-      slot[ci] = ns++;
-      pl.pstart.push_back(nd[ci].s);
-      pl.pend.push_back(nd[ci].e);
-      // boxes padded to a width of at least h in every direction (flat clusters)
-      double lo[3], hi[3];
-      for (int d = 0; d < 3; ++d) {
-        lo[d] = nd[ci].lo[d];
-        hi[d] = nd[ci].hi[d];
-        if (hi[d] - lo[d] < h) {
-          const double c = 0.5 * (lo[d] + hi[d]);
-          lo[d] = c - 0.5 * h;
-          hi[d] = c + 0.5 * h;
+    if (nd[ci].e - nd[ci].s > n3) slot[ci] = ns++;
+  pl.kid.assign(2 * (size_t)ns, -1);
+  pl.dstart.resize(ns);
+  pl.dend.resize(ns);
+  std::vector<int> height(ns, 0);
+  for (size_t ci = 0; ci < nd.size(); ++ci) {
+    const int sl = slot[ci];
+    if (sl < 0) continue;
+    pl.pstart.push_back(nd[ci].s);
+    pl.pend.push_back(nd[ci].e);
+    // boxes padded to a width of at least h in every direction (flat clusters)
+    double lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = nd[ci].lo[d];
+      hi[d] = nd[ci].hi[d];
+      if (hi[d] - lo[d] < h) {
+        const double c = 0.5 * (lo[d] + hi[d]);
+        lo[d] = c - 0.5 * h;
+        hi[d] = c + 0.5 * h;
+      }
+    }
+    pl.pbox.insert(pl.pbox.end(), lo, lo + 3);
+    pl.pbox.insert(pl.pbox.end(), hi, hi + 3);
+    // direct part: the children without proxies (contiguous: the left child
+    // ends where the right one starts), or the cluster itself for a leaf
+    int32_t ds = nd[ci].e, de = nd[ci].s;
+    if (nd[ci].kid[0] < 0) {
+      ds = nd[ci].s;
+      de = nd[ci].e;
+    } else {
+      for (int q = 0; q < 2; ++q) {
+        const Node& K = nd[nd[ci].kid[q]];
+        if (slot[nd[ci].kid[q]] >= 0) {
+          pl.kid[2 * sl + q] = slot[nd[ci].kid[q]];
+          pl.m2m_links += 1.0;
+        } else {
+          ds = std::min(ds, K.s);
+          de = std::max(de, K.e);
         }
       }
-      pl.pbox.insert(pl.pbox.end(), lo, lo + 3);
-      pl.pbox.insert(pl.pbox.end(), hi, hi + 3);
-      pl.proxy_evals += (double)(nd[ci].e - nd[ci].s) * n3;
+      if (ds > de) ds = de = nd[ci].s;
     }
+    pl.dstart[sl] = ds;
+    pl.dend[sl] = de;
+    pl.proxy_evals += (double)(de - ds) * n3;
+  }
+  // heights (children follow their parent in preorder)
+  for (int sl = ns - 1; sl >= 0; --sl)
+    for (int q = 0; q < 2; ++q)
+      if (pl.kid[2 * sl + q] >= 0) height[sl] = std::max(height[sl], height[pl.kid[2 * sl + q]] + 1);
+  const int hmax = ns > 0 ? *std::max_element(height.begin(), height.end()) : -1;
+  pl.mlevel.assign(1, 0);
+  for (int hh = 0; hh <= hmax; ++hh) {
+    for (int sl = 0; sl < ns; ++sl)
+      if (height[sl] == hh) pl.mlist.push_back(sl);
+    pl.mlevel.push_back((int32_t)pl.mlist.size());
+  }
 
   pl.frow.assign(1, 0);
   pl.nrow.assign(1, 0);
@@ -222,6 +264,42 @@ int build_tree_plan(const TreeParams& prm, int64_t M64, const double* px, const 
   std::iota(pl.border.begin(), pl.border.end(), 0);
   std::stable_sort(pl.border.begin(), pl.border.end(),
                    [&](int a, int b) { return work[a] > work[b]; });
+
+  // work items: about kItems in all (at least kMinPart of work per target each)
+  constexpr double kItems = 8192.0, kMinPart = 4096.0;
+  double total = 0.0;
+  for (int b = 0; b < nb; ++b) total += work[b];
+  const double part = std::max(kMinPart, total / kItems);
+  const double wfar = (double)n3 * 0.8;  // a proxy evaluation costs ~0.8 direct pairs
+  std::vector<double> iwork;
+  pl.istart.assign(1, 0);
+  for (int b = 0; b < nb; ++b) {
+    int32_t f = pl.frow[b], r = pl.nrow[b];
+    const int32_t fe = pl.frow[b + 1], re = pl.nrow[b + 1];
+    do {
+      const int32_t f0 = f, r0 = r;
+      double acc = 0.0;
+      while (f < fe && (acc == 0.0 || acc + wfar <= part)) {
+        acc += wfar;
+        ++f;
+      }
+      while (f == fe && r < re && (acc == 0.0 || acc + (pl.nhi[r] - pl.nlo[r]) <= part)) {
+        acc += pl.nhi[r] - pl.nlo[r];
+        ++r;
+      }
+      pl.ibatch.push_back(b);
+      pl.ifar0.push_back(f0);
+      pl.ifar1.push_back(f);
+      pl.inear0.push_back(r0);
+      pl.inear1.push_back(r);
+      iwork.push_back(acc);
+    } while (f < fe || r < re);
+    pl.istart.push_back((int32_t)pl.ibatch.size());
+  }
+  pl.iorder.resize(pl.ibatch.size());
+  std::iota(pl.iorder.begin(), pl.iorder.end(), 0);
+  std::stable_sort(pl.iorder.begin(), pl.iorder.end(),
+                   [&](int a, int b) { return iwork[a] > iwork[b]; });
 
   // N_k in tree positions
   pl.xrow.resize(M + 1);

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "operator.h"
 #include "tree.h"
@@ -17,9 +18,14 @@ struct TreeDevice {
   int32_t *perm = nullptr, *pos = nullptr;
   int32_t *bstart = nullptr, *border = nullptr;
   int32_t *pstart = nullptr, *pend = nullptr;
+  int32_t *dstart = nullptr, *dend = nullptr, *kid = nullptr, *mlist = nullptr;
+  std::vector<int32_t> mlevel;  // host: clusters of height h are mlist[mlevel[h] .. mlevel[h + 1])
   int32_t *frow = nullptr, *fcol = nullptr;
   int32_t *nrow = nullptr, *nlo = nullptr, *nhi = nullptr;
   int32_t *xrow = nullptr, *xcol = nullptr;
+  int32_t *ibatch = nullptr, *ifar0 = nullptr, *ifar1 = nullptr, *inear0 = nullptr,
+          *inear1 = nullptr, *istart = nullptr, *iorder = nullptr;
+  int n_items = 0;
   double* pbox = nullptr;  // 6 per proxy cluster: lo x, y, z, hi x, y, z
   double* pxyz = nullptr;  // proxy points, 3 per point, order^3 points per cluster
   double* cheb = nullptr;  // Chebyshev points on [-1, 1], barycentric weights, D (order^2)
@@ -29,7 +35,7 @@ struct TreeDevice {
   // per application
   double *ta1 = nullptr, *ta2 = nullptr;  // w u1, w u2 in tree order
   double* pq = nullptr;                   // proxy charges (Q1, Q2) per point
-  double* S = nullptr;                    // 2M sums in tree order
+  double* S = nullptr;                    // per work item: 2 x 256 partial sums
   size_t bytes = 0;
 
   void release();

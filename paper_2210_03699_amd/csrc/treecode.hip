@@ -13,12 +13,16 @@
 // with the proxy charges Q1_p = sum_m a1_m n_m . grad L_p(y_m) and
 // Q2_p = sum_m a2_m L_p(y_m).  The basis is evaluated in barycentric form and
 // its derivative through the differentiation matrix of the Chebyshev points
-// (l_i' = sum_q l_q D_qi, exact for polynomials of this degree).
+// (l_i' = sum_q l_q D_qi, exact for polynomials of this degree).  Every
+// cluster with more nodes than proxies carries proxies; its charges come
+// from its children's proxies by the exact transfer of bbFMM's upward pass
+// (below) and directly from the sources of children without proxies.
 //
-// One workgroup per batch of 256 targets (one per lane) runs through the
-// batch's proxy clusters and then its direct source ranges, staging both in
-// LDS; each target's sum is formed in a fixed order, so results are
-// reproducible.  All arithmetic is float64.
+// One workgroup per work item (part of the lists of a batch of 256 targets,
+// one target per lane) runs through its proxy clusters and then its direct
+// source ranges, staging both in LDS; the finishing kernel adds a batch's
+// parts in a fixed order, so results are reproducible.  All arithmetic is
+// float64.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,11 +38,11 @@ namespace ibim {
 namespace {
 
 constexpr int kUpSrc = 64;  // sources per round of the proxy-charge kernel
-constexpr int kMaxPer = (kTreeMaxOrder * kTreeMaxOrder * kTreeMaxOrder + 255) / 256;
 
 struct TreeArgs {
   const int32_t *perm, *pos, *bstart, *border, *pstart, *pend, *frow, *fcol, *nrow, *nlo, *nhi,
-      *xrow, *xcol;
+      *xrow, *xcol, *dstart, *dend, *kid, *mlist, *ibatch, *ifar0, *ifar1, *inear0, *inear1,
+      *iorder;
   const double *pbox, *pxyz, *cheb;
   const double *tx, *ty, *tz, *tnx, *tny, *tnz, *tw;
   double *ta1, *ta2, *pq, *S;
@@ -53,6 +57,9 @@ TreeArgs make_args(const TreeDevice& T, const DeviceProblem& P, const double* u)
   a.perm = T.perm; a.pos = T.pos; a.bstart = T.bstart; a.border = T.border;
   a.pstart = T.pstart; a.pend = T.pend; a.frow = T.frow; a.fcol = T.fcol;
   a.nrow = T.nrow; a.nlo = T.nlo; a.nhi = T.nhi; a.xrow = T.xrow; a.xcol = T.xcol;
+  a.dstart = T.dstart; a.dend = T.dend; a.kid = T.kid; a.mlist = T.mlist;
+  a.ibatch = T.ibatch; a.ifar0 = T.ifar0; a.ifar1 = T.ifar1; a.inear0 = T.inear0;
+  a.inear1 = T.inear1; a.iorder = T.iorder;
   a.pbox = T.pbox; a.pxyz = T.pxyz; a.cheb = T.cheb;
   a.tx = T.tx; a.ty = T.ty; a.tz = T.tz; a.tnx = T.tnx; a.tny = T.tny; a.tnz = T.tnz;
   a.tw = T.tw;
@@ -74,24 +81,52 @@ __global__ void tree_gather_kernel(TreeArgs a) {
   a.ta2[t] = w * a.u[a.M + k];
 }
 
-// Proxy charges of one cluster per workgroup.
-__global__ __launch_bounds__(256) void tree_upward_kernel(TreeArgs a) {
+// Barycentric Lagrange basis of the Chebyshev points at t into l[0..n)
+// (t equal to a point gives the unit vector).
+__device__ inline void cheb_basis(double t, const double* tch, const double* wch, int n,
+                                  double* l) {
+  int hit = -1;
+  for (int i = 0; i < n; ++i)
+    if (t == tch[i]) hit = i;
+  if (hit >= 0) {
+    for (int i = 0; i < n; ++i) l[i] = i == hit ? 1.0 : 0.0;
+    return;
+  }
+  double sum = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double v = wch[i] / (t - tch[i]);
+    l[i] = v;
+    sum += v;
+  }
+  const double is = 1.0 / sum;
+  for (int i = 0; i < n; ++i) l[i] *= is;
+}
+
+__device__ inline void load_cheb(const TreeArgs& a, double* tch, double* wch, double* dch) {
+  const int n = a.order, tid = threadIdx.x;
+  if (tid < n) {
+    tch[tid] = a.cheb[tid];
+    wch[tid] = a.cheb[n + tid];
+  }
+  if (dch && tid < n * n) dch[tid] = a.cheb[2 * n + tid];
+}
+
+// Proxy charges of one cluster per workgroup from the sources of
+// [dstart, dend) (zero when empty).  PER proxies per thread.
+template <int PER>
+__global__ __launch_bounds__(256) void tree_p2m_kernel(TreeArgs a) {
   __shared__ double tch[kTreeMaxOrder], wch[kTreeMaxOrder], dch[kTreeMaxOrder * kTreeMaxOrder];
   __shared__ double bl[kUpSrc][3][kTreeMaxOrder];  // l_i(y_d)
   __shared__ double bd[kUpSrc][3][kTreeMaxOrder];  // d l_i / d y_d
   __shared__ double sv[kUpSrc][4];                 // a1 n_x, a1 n_y, a1 n_z, a2
   const int slot = blockIdx.x, tid = threadIdx.x;
   const int n = a.order, n2 = n * n, n3 = n2 * n;
-  const int32_t s = a.pstart[slot], e = a.pend[slot];
+  const int32_t s = a.dstart[slot], e = a.dend[slot];
   const double* box = a.pbox + 6 * (size_t)slot;
-  if (tid < n) {
-    tch[tid] = a.cheb[tid];
-    wch[tid] = a.cheb[n + tid];
-  }
-  if (tid < n2) dch[tid] = a.cheb[2 * n + tid];
-  double Q1[kMaxPer], Q2[kMaxPer];
+  load_cheb(a, tch, wch, dch);
+  double Q1[PER], Q2[PER];
 #pragma unroll
-  for (int r = 0; r < kMaxPer; ++r) Q1[r] = Q2[r] = 0.0;
+  for (int r = 0; r < PER; ++r) Q1[r] = Q2[r] = 0.0;
   for (int32_t c0 = s; c0 < e; c0 += kUpSrc) {
     __syncthreads();
     if (tid < 3 * kUpSrc) {
@@ -101,27 +136,13 @@ __global__ __launch_bounds__(256) void tree_upward_kernel(TreeArgs a) {
         const double y = d == 0 ? a.tx[m] : (d == 1 ? a.ty[m] : a.tz[m]);
         const double lo = box[d], hi = box[3 + d];
         const double half = 0.5 * (hi - lo);
-        const double t = (y - 0.5 * (lo + hi)) / half;
-        int hit = -1;
-        for (int i = 0; i < n; ++i)
-          if (t == tch[i]) hit = i;
-        double l[kTreeMaxOrder];
-        if (hit >= 0) {
-          for (int i = 0; i < n; ++i) l[i] = i == hit ? 1.0 : 0.0;
-        } else {
-          double sum = 0.0;
-          for (int i = 0; i < n; ++i) {
-            l[i] = wch[i] / (t - tch[i]);
-            sum += l[i];
-          }
-          const double is = 1.0 / sum;
-          for (int i = 0; i < n; ++i) l[i] *= is;
-        }
+        double* l = bl[j][d];
+        cheb_basis((y - 0.5 * (lo + hi)) / half, tch, wch, n, l);
+        const double ih = 1.0 / half;
         for (int i = 0; i < n; ++i) {
           double dl = 0.0;
           for (int q = 0; q < n; ++q) dl = fma(l[q], dch[q * n + i], dl);
-          bl[j][d][i] = l[i];
-          bd[j][d][i] = dl / half;
+          bd[j][d][i] = dl * ih;
         }
         if (d == 0) {
           const double w = a.ta1[m];
@@ -135,7 +156,7 @@ __global__ __launch_bounds__(256) void tree_upward_kernel(TreeArgs a) {
     __syncthreads();
     const int cnt = min(kUpSrc, (int)(e - c0));
 #pragma unroll
-    for (int r = 0; r < kMaxPer; ++r) {
+    for (int r = 0; r < PER; ++r) {
       const int p = tid + 256 * r;
       if (p < n3) {
         const int i = p / n2, jj = (p / n) % n, k = p % n;
@@ -155,11 +176,70 @@ __global__ __launch_bounds__(256) void tree_upward_kernel(TreeArgs a) {
     }
   }
 #pragma unroll
-  for (int r = 0; r < kMaxPer; ++r) {
+  for (int r = 0; r < PER; ++r) {
     const int p = tid + 256 * r;
     if (p < n3) {
       a.pq[2 * ((size_t)slot * n3 + p)] = Q1[r];
       a.pq[2 * ((size_t)slot * n3 + p) + 1] = Q2[r];
+    }
+  }
+}
+
+// Adds to the charges of the clusters mlist[off + blockIdx.x] those of their
+// children with proxies.  The parent's basis polynomials are reproduced
+// exactly by the child's interpolation, so
+//   L_p(y) = sum_q L_p(s_q^child) L_q^child(y)  and  Q_p += sum_q L_p(s_q^child) Q_q^child
+// for both charges (the gradient charges too, by differentiating the identity).
+// The tensor transfer is applied one dimension at a time.
+__global__ __launch_bounds__(256) void tree_m2m_kernel(TreeArgs a, int off) {
+  constexpr int kN3 = kTreeMaxOrder * kTreeMaxOrder * kTreeMaxOrder;
+  __shared__ double tch[kTreeMaxOrder], wch[kTreeMaxOrder];
+  __shared__ double Sm[3][kTreeMaxOrder][kTreeMaxOrder];  // Sm[d][p][q] = l_p(child point q)
+  __shared__ double A[kN3], B[kN3];
+  const int slot = a.mlist[off + blockIdx.x], tid = threadIdx.x;
+  const int n = a.order, n2 = n * n, n3 = n2 * n;
+  const double* pb = a.pbox + 6 * (size_t)slot;
+  load_cheb(a, tch, wch, nullptr);
+  for (int c = 0; c < 2; ++c) {
+    const int ch = a.kid[2 * slot + c];
+    if (ch < 0) continue;  // uniform
+    const double* cb = a.pbox + 6 * (size_t)ch;
+    __syncthreads();
+    if (tid < 3 * n) {
+      const int d = tid / n, q = tid % n;
+      const double cmid = 0.5 * (cb[d] + cb[3 + d]), chalf = 0.5 * (cb[3 + d] - cb[d]);
+      const double pmid = 0.5 * (pb[d] + pb[3 + d]), phalf = 0.5 * (pb[3 + d] - pb[d]);
+      double l[kTreeMaxOrder];
+      cheb_basis((cmid + chalf * tch[q] - pmid) / phalf, tch, wch, n, l);
+      for (int p = 0; p < n; ++p) Sm[d][p][q] = l[p];
+    }
+    for (int chg = 0; chg < 2; ++chg) {
+      __syncthreads();
+      for (int idx = tid; idx < n3; idx += 256) B[idx] = a.pq[2 * ((size_t)ch * n3 + idx) + chg];
+      __syncthreads();
+      // x: A[px][qy][qz] = sum_qx Sx[px][qx] B[qx][qy][qz]
+      for (int idx = tid; idx < n3; idx += 256) {
+        const int px = idx / n2, rest = idx % n2;
+        double v = 0.0;
+        for (int q = 0; q < n; ++q) v = fma(Sm[0][px][q], B[q * n2 + rest], v);
+        A[idx] = v;
+      }
+      __syncthreads();
+      // y: B[px][py][qz] = sum_qy Sy[py][qy] A[px][qy][qz]
+      for (int idx = tid; idx < n3; idx += 256) {
+        const int px = idx / n2, py = (idx / n) % n, qz = idx % n;
+        double v = 0.0;
+        for (int q = 0; q < n; ++q) v = fma(Sm[1][py][q], A[px * n2 + q * n + qz], v);
+        B[idx] = v;
+      }
+      __syncthreads();
+      // z, added to the parent's charges
+      for (int idx = tid; idx < n3; idx += 256) {
+        const int base = idx - idx % n, pz = idx % n;
+        double v = 0.0;
+        for (int q = 0; q < n; ++q) v = fma(Sm[2][pz][q], B[base + q], v);
+        a.pq[2 * ((size_t)slot * n3 + idx) + chg] += v;
+      }
     }
   }
 }
@@ -183,9 +263,11 @@ __device__ __forceinline__ void far_eval(double x, double y, double z, double nx
   S2 = fma(rn * iR3, fma(fma(-c.c2, te, 1.0), q2, -(1.0 - te) * q1), S2);
 }
 
-__global__ __launch_bounds__(256) void tree_batch_kernel(TreeArgs a) {
+// One work item: part of one batch's far clusters and direct ranges.
+__global__ __launch_bounds__(256) void tree_item_kernel(TreeArgs a) {
   __shared__ double sh[8][256];
-  const int b = a.border[blockIdx.x];
+  const int it = a.iorder[blockIdx.x];
+  const int b = a.ibatch[it];
   const int tid = threadIdx.x;
   const int32_t t0 = a.bstart[b], nt = a.bstart[b + 1] - t0;
   const int32_t t = t0 + min(tid, nt - 1);
@@ -194,7 +276,7 @@ __global__ __launch_bounds__(256) void tree_batch_kernel(TreeArgs a) {
   const int n3 = a.order * a.order * a.order;
   double S1 = 0.0, S2 = 0.0;
   // proxy clusters
-  for (int32_t f = a.frow[b]; f < a.frow[b + 1]; ++f) {
+  for (int32_t f = a.ifar0[it]; f < a.ifar1[it]; ++f) {
     const size_t base = (size_t)a.fcol[f] * n3;
     for (int c0 = 0; c0 < n3; c0 += 256) {
       const int cnt = min(256, n3 - c0);
@@ -216,7 +298,7 @@ __global__ __launch_bounds__(256) void tree_batch_kernel(TreeArgs a) {
   // direct ranges, pairs of N_k skipped
   int32_t p = a.xrow[t];
   const int32_t pe = a.xrow[t + 1];
-  for (int32_t r = a.nrow[b]; r < a.nrow[b + 1]; ++r) {
+  for (int32_t r = a.inear0[it]; r < a.inear1[it]; ++r) {
     const int32_t lo = a.nlo[r], hi = a.nhi[r];
     while (p < pe && a.xcol[p] < lo) ++p;
     int32_t nxt = p < pe ? a.xcol[p] : INT32_MAX;
@@ -249,16 +331,15 @@ __global__ __launch_bounds__(256) void tree_batch_kernel(TreeArgs a) {
       }
     }
   }
-  if (tid < nt) {
-    a.S[t] = S1;
-    a.S[a.M + t] = S2;
-  }
+  a.S[(size_t)it * 2 * kTreeBatch + tid] = S1;
+  a.S[(size_t)it * 2 * kTreeBatch + kTreeBatch + tid] = S2;
 }
 
 struct TreeFinishArgs {
   const double* u;
   const double* S;
   const int32_t* pos;
+  const int32_t* istart;
   const int32_t* crow;
   const int32_t* ccol;
   const double* blocks;
@@ -271,8 +352,14 @@ __global__ void tree_finish_kernel(TreeFinishArgs a) {
   const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= a.M) return;
   const int32_t M = a.M, t = a.pos[k];
-  double o1 = a.lam1 * a.u[k] + a.scale * a.S[t];
-  double o2 = a.lam2 * a.u[M + k] + a.scale * a.S[M + t];
+  const int b = t / kTreeBatch, l = t % kTreeBatch;
+  double s1 = 0.0, s2 = 0.0;
+  for (int32_t it = a.istart[b]; it < a.istart[b + 1]; ++it) {
+    s1 += a.S[(size_t)it * 2 * kTreeBatch + l];
+    s2 += a.S[(size_t)it * 2 * kTreeBatch + kTreeBatch + l];
+  }
+  double o1 = a.lam1 * a.u[k] + a.scale * s1;
+  double o2 = a.lam2 * a.u[M + k] + a.scale * s2;
   for (int32_t e = a.crow[k]; e < a.crow[k + 1]; ++e) {
     const int32_t m = a.ccol[e];
     const double* B = a.blocks + 4 * (size_t)e;
@@ -294,6 +381,9 @@ hipError_t up(T** dst, const std::vector<T>& v, size_t* bytes, hipStream_t s) {
 
 void TreeDevice::release() {
   dfree(perm); dfree(pos); dfree(bstart); dfree(border); dfree(pstart); dfree(pend);
+  dfree(dstart); dfree(dend); dfree(kid); dfree(mlist);
+  dfree(ibatch); dfree(ifar0); dfree(ifar1); dfree(inear0); dfree(inear1); dfree(istart);
+  dfree(iorder);
   dfree(frow); dfree(fcol); dfree(nrow); dfree(nlo); dfree(nhi); dfree(xrow); dfree(xcol);
   dfree(pbox); dfree(pxyz); dfree(cheb);
   dfree(tx); dfree(ty); dfree(tz); dfree(tnx); dfree(tny); dfree(tnz); dfree(tw);
@@ -308,6 +398,8 @@ hipError_t tree_upload(const TreePlan& pl, const DeviceProblem& P, const double*
   d.order = pl.order;
   d.n_batches = (int)pl.bstart.size() - 1;
   d.n_slots = (int)pl.pstart.size();
+  d.mlevel = pl.mlevel;
+  d.n_items = (int)pl.ibatch.size();
   const int n = pl.order, n3 = n * n * n;
   // Chebyshev points of the second kind, barycentric weights, differentiation matrix
   std::vector<double> cheb(2 * n + n * n);
@@ -360,6 +452,17 @@ hipError_t tree_upload(const TreePlan& pl, const DeviceProblem& P, const double*
   TUP(border, pl.border);
   TUP(pstart, pl.pstart);
   TUP(pend, pl.pend);
+  TUP(dstart, pl.dstart);
+  TUP(dend, pl.dend);
+  TUP(kid, pl.kid);
+  TUP(mlist, pl.mlist);
+  TUP(ibatch, pl.ibatch);
+  TUP(ifar0, pl.ifar0);
+  TUP(ifar1, pl.ifar1);
+  TUP(inear0, pl.inear0);
+  TUP(inear1, pl.inear1);
+  TUP(istart, pl.istart);
+  TUP(iorder, pl.iorder);
   TUP(frow, pl.frow);
   TUP(fcol, pl.fcol);
   TUP(nrow, pl.nrow);
@@ -381,8 +484,9 @@ hipError_t tree_upload(const TreePlan& pl, const DeviceProblem& P, const double*
   if (e == hipSuccess) e = dalloc(&d.ta1, (size_t)M);
   if (e == hipSuccess) e = dalloc(&d.ta2, (size_t)M);
   if (e == hipSuccess) e = dalloc(&d.pq, (size_t)d.n_slots * n3 * 2);
-  if (e == hipSuccess) e = dalloc(&d.S, 2 * (size_t)M);
-  by += (4 * (size_t)M + (size_t)d.n_slots * n3 * 2) * sizeof(double);
+  if (e == hipSuccess) e = dalloc(&d.S, (size_t)d.n_items * 2 * kTreeBatch);
+  by += (2 * (size_t)M + (size_t)d.n_items * 2 * kTreeBatch + (size_t)d.n_slots * n3 * 2) *
+        sizeof(double);
   // the host vectors above are temporaries
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   return e;
@@ -392,9 +496,24 @@ hipError_t launch_tree_sum(const TreeDevice& T, const DeviceProblem& P, const do
                            hipStream_t s) {
   const TreeArgs a = make_args(T, P, u);
   hipLaunchKernelGGL(tree_gather_kernel, dim3((unsigned)((T.M + 255) / 256)), dim3(256), 0, s, a);
-  if (T.n_slots > 0)
-    hipLaunchKernelGGL(tree_upward_kernel, dim3((unsigned)T.n_slots), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(tree_batch_kernel, dim3((unsigned)T.n_batches), dim3(256), 0, s, a);
+  if (T.n_slots > 0) {
+    const int n3 = T.order * T.order * T.order, per = (n3 + 255) / 256;
+    const dim3 g((unsigned)T.n_slots);
+    if (per <= 1)
+      hipLaunchKernelGGL(tree_p2m_kernel<1>, g, dim3(256), 0, s, a);
+    else if (per <= 2)
+      hipLaunchKernelGGL(tree_p2m_kernel<2>, g, dim3(256), 0, s, a);
+    else if (per <= 4)
+      hipLaunchKernelGGL(tree_p2m_kernel<4>, g, dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL(tree_p2m_kernel<8>, g, dim3(256), 0, s, a);
+    for (size_t hh = 1; hh + 1 < T.mlevel.size(); ++hh) {
+      const int off = T.mlevel[hh], cnt = T.mlevel[hh + 1] - off;
+      if (cnt > 0)
+        hipLaunchKernelGGL(tree_m2m_kernel, dim3((unsigned)cnt), dim3(256), 0, s, a, off);
+    }
+  }
+  hipLaunchKernelGGL(tree_item_kernel, dim3((unsigned)T.n_items), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -404,6 +523,7 @@ hipError_t launch_tree_finish(const TreeDevice& T, const DeviceProblem& P, const
   f.u = u;
   f.S = T.S;
   f.pos = T.pos;
+  f.istart = T.istart;
   f.crow = P.crow;
   f.ccol = P.ccol;
   f.blocks = P.blocks;

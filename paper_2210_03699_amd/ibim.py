@@ -317,10 +317,11 @@ class Problem:
 
     def tree_counts(self):
         """Work of one treecode pair sum (``ibim_tree_counts``)."""
-        out = np.zeros(5)
+        out = np.zeros(6)
         _check(self._lib.ibim_tree_counts(self._ctx, _dp(out)))
         return {"far_evals": out[0], "near_evals": out[1], "proxy_terms": out[2],
-                "batches": int(out[3]), "proxy_clusters": int(out[4])}
+                "batches": int(out[3]), "proxy_clusters": int(out[4]),
+                "transfers": int(out[5])}
 
     def solve_energy(self, tol, stream=None):
         g = self.rhs(stream=stream)

@@ -106,6 +106,6 @@ def test_tree_options_rejected():
     with pytest.raises(ibim.IbimError):
         ibim.Problem.from_workload(wl, device=0, summation=ibim.SUM_TREE, precision=ibim.MIXED)
     with pytest.raises(ibim.IbimError):
-        ibim.Problem.from_workload(wl, device=0, summation=ibim.SUM_TREE, tree_order=17)
+        ibim.Problem.from_workload(wl, device=0, summation=ibim.SUM_TREE, tree_order=13)
     with pytest.raises(ibim.IbimError):
         ibim.Server(1 << 30, summation=ibim.SUM_TREE)

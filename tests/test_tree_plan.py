@@ -9,7 +9,7 @@ from paper_2210_03699_amd import ibim
 @pytest.mark.parametrize("kw", [
     {"summation": ibim.SUM_TREE, "precision": ibim.MIXED},
     {"summation": ibim.SUM_TREE, "tree_order": 1},
-    {"summation": ibim.SUM_TREE, "tree_order": 17},
+    {"summation": ibim.SUM_TREE, "tree_order": 13},
     {"summation": ibim.SUM_TREE, "tree_theta": 0.0},
     {"summation": ibim.SUM_TREE, "tree_theta": 1.5},
     {"summation": 2},
