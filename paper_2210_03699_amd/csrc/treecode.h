@@ -27,7 +27,6 @@ struct TreeDevice {
           *inear1 = nullptr, *istart = nullptr, *iorder = nullptr;
   int n_items = 0;
   double* pbox = nullptr;  // 6 per proxy cluster: lo x, y, z, hi x, y, z
-  double* pxyz = nullptr;  // proxy points, 3 per point, order^3 points per cluster
   double* cheb = nullptr;  // Chebyshev points on [-1, 1], barycentric weights, D (order^2)
   // geometry in tree order
   double *tx = nullptr, *ty = nullptr, *tz = nullptr;

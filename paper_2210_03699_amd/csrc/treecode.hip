@@ -43,7 +43,7 @@ struct TreeArgs {
   const int32_t *perm, *pos, *bstart, *border, *pstart, *pend, *frow, *fcol, *nrow, *nlo, *nhi,
       *xrow, *xcol, *dstart, *dend, *kid, *mlist, *ibatch, *ifar0, *ifar1, *inear0, *inear1,
       *iorder;
-  const double *pbox, *pxyz, *cheb;
+  const double *pbox, *cheb;
   const double *tx, *ty, *tz, *tnx, *tny, *tnz, *tw;
   double *ta1, *ta2, *pq, *S;
   const double* u;
@@ -60,7 +60,7 @@ TreeArgs make_args(const TreeDevice& T, const DeviceProblem& P, const double* u)
   a.dstart = T.dstart; a.dend = T.dend; a.kid = T.kid; a.mlist = T.mlist;
   a.ibatch = T.ibatch; a.ifar0 = T.ifar0; a.ifar1 = T.ifar1; a.inear0 = T.inear0;
   a.inear1 = T.inear1; a.iorder = T.iorder;
-  a.pbox = T.pbox; a.pxyz = T.pxyz; a.cheb = T.cheb;
+  a.pbox = T.pbox; a.cheb = T.cheb;
   a.tx = T.tx; a.ty = T.ty; a.tz = T.tz; a.tnx = T.tnx; a.tny = T.tny; a.tnz = T.tnz;
   a.tw = T.tw;
   a.ta1 = T.ta1; a.ta2 = T.ta2; a.pq = T.pq; a.S = T.S;
@@ -244,18 +244,15 @@ __global__ __launch_bounds__(256) void tree_m2m_kernel(TreeArgs a, int off) {
   }
 }
 
-// Far field of one proxy point (sx, sy, sz) with charges (q1, q2).
-__device__ __forceinline__ void far_eval(double x, double y, double z, double nxk, double nyk,
-                                         double nzk, double sx, double sy, double sz, double q1,
-                                         double q2, const PairConsts& c, double& S1, double& S2) {
-  const double rx = x - sx, ry = y - sy, rz = z - sz;
-  const double R2 = fma(rz, rz, fma(ry, ry, rx * rx));
+// Far field of one proxy point with charges (q1, q2), given R^2 = |x - s_p|^2
+// and rn = (x - s_p).n_k (formed from per-axis terms of the proxy grid).
+__device__ __forceinline__ void far_eval(double R2, double rn, double q1, double q2,
+                                         const PairConsts& c, double& S1, double& S2) {
   const double iR = rsqrt_pos(R2);
   const double R = R2 * iR;
   const double kr = c.kappa * R;
   const double e = exp_neg(kr);
   const double te = fma(e, kr, e);
-  const double rn = fma(rz, nzk, fma(ry, nyk, rx * nxk));
   const double iR3 = iR * iR * iR;
   // FA Q1 - FB Q2
   S1 = fma(iR, fma(fma(-c.c1, e, 1.0), q1, -(1.0 - e) * q2), S1);
@@ -265,7 +262,11 @@ __device__ __forceinline__ void far_eval(double x, double y, double z, double nx
 
 // One work item: part of one batch's far clusters and direct ranges.
 __global__ __launch_bounds__(256) void tree_item_kernel(TreeArgs a) {
+  // LDS: near sources as 8 arrays of 256, or (same buffer) the charges of a
+  // proxy cluster (Q1, Q2 interleaved), as many x-planes of its grid at a
+  // time as fit; the grid axes separately
   __shared__ double sh[8][256];
+  __shared__ double ax[3][kTreeMaxOrder];
   const int it = a.iorder[blockIdx.x];
   const int b = a.ibatch[it];
   const int tid = threadIdx.x;
@@ -273,26 +274,42 @@ __global__ __launch_bounds__(256) void tree_item_kernel(TreeArgs a) {
   const int32_t t = t0 + min(tid, nt - 1);
   const double x = a.tx[t], y = a.ty[t], z = a.tz[t];
   const double nxk = a.tnx[t], nyk = a.tny[t], nzk = a.tnz[t];
-  const int n3 = a.order * a.order * a.order;
+  const int n = a.order, n2 = n * n, n3 = n2 * n;
+  // x-planes of the proxy grid whose charges fit in the LDS buffer at once
+  const int planes = max(1, 1024 / n2);
+  double* qs = &sh[0][0];
   double S1 = 0.0, S2 = 0.0;
-  // proxy clusters
+  // proxy clusters: points (X_i, Y_j, Z_k), so R^2 and r.n_k are built from
+  // per-axis terms: (x - X_i)^2 + (y - Y_j)^2 once per (i, j), plus (z - Z_k)^2
   for (int32_t f = a.ifar0[it]; f < a.ifar1[it]; ++f) {
-    const size_t base = (size_t)a.fcol[f] * n3;
-    for (int c0 = 0; c0 < n3; c0 += 256) {
-      const int cnt = min(256, n3 - c0);
+    const int slot = a.fcol[f];
+    const size_t base = (size_t)slot * n3;
+    for (int i0 = 0; i0 < n; i0 += planes) {
+      const int i1 = min(n, i0 + planes);
       __syncthreads();
-      if (tid < cnt) {
-        const size_t p = base + c0 + tid;
-        sh[0][tid] = a.pxyz[3 * p];
-        sh[1][tid] = a.pxyz[3 * p + 1];
-        sh[2][tid] = a.pxyz[3 * p + 2];
-        sh[3][tid] = a.pq[2 * p];
-        sh[4][tid] = a.pq[2 * p + 1];
+      if (i0 == 0 && tid < 3 * n) {
+        const int d = tid / n, i = tid % n;
+        const double* bx = a.pbox + 6 * (size_t)slot;
+        ax[d][i] = 0.5 * (bx[d] + bx[3 + d]) + 0.5 * (bx[3 + d] - bx[d]) * a.cheb[i];
+      }
+      for (int q = tid; q < (i1 - i0) * n2; q += 256) {
+        qs[2 * q] = a.pq[2 * (base + (size_t)i0 * n2 + q)];
+        qs[2 * q + 1] = a.pq[2 * (base + (size_t)i0 * n2 + q) + 1];
       }
       __syncthreads();
-      for (int j = 0; j < cnt; ++j)
-        far_eval(x, y, z, nxk, nyk, nzk, sh[0][j], sh[1][j], sh[2][j], sh[3][j], sh[4][j], a.pc,
-                 S1, S2);
+      for (int i = i0; i < i1; ++i) {
+        const double rx = x - ax[0][i];
+        const double rx2 = rx * rx, rxn = rx * nxk;
+        for (int j = 0; j < n; ++j) {
+          const double ry = y - ax[1][j];
+          const double axy = fma(ry, ry, rx2), bxy = fma(ry, nyk, rxn);
+          const double* q = qs + 2 * (((i - i0) * n + j) * n);
+          for (int k = 0; k < n; ++k) {
+            const double rz = z - ax[2][k];
+            far_eval(fma(rz, rz, axy), fma(rz, nzk, bxy), q[2 * k], q[2 * k + 1], a.pc, S1, S2);
+          }
+        }
+      }
     }
   }
   // direct ranges, pairs of N_k skipped
@@ -385,7 +402,7 @@ void TreeDevice::release() {
   dfree(ibatch); dfree(ifar0); dfree(ifar1); dfree(inear0); dfree(inear1); dfree(istart);
   dfree(iorder);
   dfree(frow); dfree(fcol); dfree(nrow); dfree(nlo); dfree(nhi); dfree(xrow); dfree(xcol);
-  dfree(pbox); dfree(pxyz); dfree(cheb);
+  dfree(pbox); dfree(cheb);
   dfree(tx); dfree(ty); dfree(tz); dfree(tnx); dfree(tny); dfree(tnz); dfree(tw);
   dfree(ta1); dfree(ta2); dfree(pq); dfree(S);
 }
@@ -416,23 +433,6 @@ hipError_t tree_upload(const TreePlan& pl, const DeviceProblem& P, const double*
       diag -= v;
     }
     cheb[2 * n + q * n + q] = diag;
-  }
-  std::vector<double> pxyz((size_t)d.n_slots * n3 * 3);
-  for (int sl = 0; sl < d.n_slots; ++sl) {
-    const double* b = pl.pbox.data() + 6 * (size_t)sl;
-    double mid[3], half[3];
-    for (int k = 0; k < 3; ++k) {
-      mid[k] = 0.5 * (b[k] + b[3 + k]);
-      half[k] = 0.5 * (b[3 + k] - b[k]);
-    }
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j)
-        for (int k = 0; k < n; ++k) {
-          const size_t p = (size_t)sl * n3 + (size_t)(i * n + j) * n + k;
-          pxyz[3 * p] = mid[0] + half[0] * cheb[i];
-          pxyz[3 * p + 1] = mid[1] + half[1] * cheb[j];
-          pxyz[3 * p + 2] = mid[2] + half[2] * cheb[k];
-        }
   }
   const int32_t M = pl.M;
   std::vector<double> g[7];
@@ -471,7 +471,6 @@ hipError_t tree_upload(const TreePlan& pl, const DeviceProblem& P, const double*
   TUP(xrow, pl.xrow);
   TUP(xcol, pl.xcol);
   TUP(pbox, pl.pbox);
-  TUP(pxyz, pxyz);
   TUP(cheb, cheb);
   TUP(tx, g[0]);
   TUP(ty, g[1]);

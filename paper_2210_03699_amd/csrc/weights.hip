@@ -45,15 +45,12 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock) void weights_kernel(WeightAr
   __shared__ double cos_t[kSamples], sin_t[kSamples];
   __shared__ double l11s[kWavesPerBlock][kSamples], l21s[kWavesPerBlock][kSamples];
   __shared__ double coef[kWavesPerBlock][4][kModes];
-  __shared__ int jmax_s[kWavesPerBlock];
 
   const int lane = threadIdx.x % kWave;
   const int wv = threadIdx.x / kWave;
-  for (int q = threadIdx.x; q < kSamples; q += blockDim.x) {
-    double ang = 2.0 * kPiD * q / kSamples;
-    cos_t[q] = cos(ang);
-    sin_t[q] = sin(ang);
-  }
+  // angles are multiples of pi: sincospi reduces them exactly
+  for (int q = threadIdx.x; q < kSamples; q += blockDim.x)
+    sincospi(2.0 * q / kSamples, &sin_t[q], &cos_t[q]);
   __syncthreads();
 
   // A wavefront past the last entry recomputes the last entry and discards
@@ -78,10 +75,10 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock) void weights_kernel(WeightAr
   const double c21 = a.kappa * a.kappa / (8.0 * kPiD);
 
   // 1. samples of l11, l21 at theta_p = pi p / kSamples
+#pragma unroll 1
   for (int p = lane; p < kSamples; p += kWave) {
-    // cos/sin of pi p / N from the 2 pi table: angle index p/2 on a 2N grid
-    double ang = kPiD * p / kSamples;
-    double c = cos(ang), s = sin(ang);
+    double c, s;
+    sincospi((double)p / kSamples, &s, &c);
     double v0 = (t1a * c + t1b * s) * d1;
     double v1 = (t2a * c + t2b * s) * d2;
     double vn2 = v0 * v0 + v1 * v1;
@@ -97,6 +94,7 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock) void weights_kernel(WeightAr
   if (lane < kModes) {
     const int j = lane;
     double a11 = 0.0, b11 = 0.0, a21 = 0.0, b21 = 0.0;
+#pragma unroll 1
     for (int p = 0; p < kSamples; ++p) {
       int q = (j * p) & (kSamples - 1);
       double cq = cos_t[q], sq = sin_t[q];
@@ -112,25 +110,20 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock) void weights_kernel(WeightAr
     coef[wv][3][j] = b21 * f;
   }
   __syncthreads();
-  // highest significant mode (wave-uniform)
-  if (lane == 0) {
-    double mx = 0.0;
-    for (int j = 0; j < kModes; ++j)
-      for (int c = 0; c < 4; ++c) mx = fmax(mx, fabs(coef[wv][c][j]));
-    int jm = 1;
-    for (int j = 0; j < kModes; ++j) {
-      double mj = 0.0;
-      for (int c = 0; c < 4; ++c) mj = fmax(mj, fabs(coef[wv][c][j]));
-      if (mj > 1e-18 * mx) jm = j + 1;
-    }
-    jmax_s[wv] = jm;
-  }
-  __syncthreads();
-  const int jmax = jmax_s[wv];
+  // highest significant mode (wave-uniform): lane j holds the largest
+  // coefficient of mode 2j; a mode counts if it exceeds 1e-18 of the largest
+  double mj = 0.0;
+  if (lane < kModes)
+    for (int c = 0; c < 4; ++c) mj = fmax(mj, fabs(coef[wv][c][lane]));
+  double mx = mj;
+  for (int off = kWave / 2; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, kWave));
+  const unsigned long long sig = __ballot(lane < kModes && mj > 1e-18 * mx);
+  const int jmax = sig ? 64 - __clzll((long long)sig) : 1;
 
   // 3. lattice sums, accumulated straight into the two weights
   double acc11 = 0.0, acc21 = 0.0;
   const double two_over_sqrtpi = 1.1283791670955126;
+#pragma unroll 1
   for (int idx = lane; idx < 2 * kPts; idx += kWave) {
     const int recip = idx >= kPts;
     const int q = recip ? idx - kPts : idx;
@@ -146,9 +139,7 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock) void weights_kernel(WeightAr
     } else {
       y1 = n1;
       y2 = n2;
-      double arg = -2.0 * kPiD * (n1 * al + n2 * be);
-      pr = cos(arg);
-      pi = sin(arg);
+      sincospi(-2.0 * (n1 * al + n2 * be), &pi, &pr);
       sg = -1.0;  // (-i)^k = (-1)^(k/2) for even k
     }
     const double r2 = y1 * y1 + y2 * y2;

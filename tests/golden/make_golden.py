@@ -2,12 +2,13 @@
 
 Calls only ``oracle`` and ``workloads``.  Outputs beside this script:
 ``kirkwood_R10_h0.25.json`` (Kirkwood sphere), ``ses500_h0.3.json``
-(500-atom molecule) and, with --no-solve, ``ses2000_h0.35.json`` (sampled
-rows only).  A full oracle solve at these sizes (1.2e5-1.3e5 tube nodes,
+(500-atom molecule), ``ses2000_twin_h0.7.json`` (the 2000-atom molecule on
+the coarsened h = 0.7 grid) and, with --no-solve, ``ses2000_h0.35.json``
+(sampled rows only).  A full oracle solve at these sizes (1.2e5-1.3e5 tube nodes,
 ~1.5e10 pair evaluations per operator application) takes 30-60 minutes on
 eight cores, so the results are stored instead of recomputed in every test.
 
-Usage: python tests/golden/make_golden.py [kirkwood|ses500|ses2000] [--no-solve]
+Usage: python tests/golden/make_golden.py [kirkwood|ses500|ses2000|ses2000_twin] [--no-solve]
 """
 import json
 import os
@@ -28,7 +29,7 @@ SEED_U = 78
 
 
 OUTPUT = {"kirkwood": "kirkwood_R10_h0.25.json", "ses500": "ses500_h0.3.json",
-          "ses2000": "ses2000_h0.35.json"}
+          "ses2000": "ses2000_h0.35.json", "ses2000_twin": "ses2000_twin_h0.7.json"}
 
 
 def main():

@@ -25,6 +25,7 @@ from paper_2210_03699_amd import ibim  # noqa: E402
 
 DEV = "cuda:0"
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "kirkwood_R10_h0.25.json")
+GOLDEN_TWIN = os.path.join(os.path.dirname(__file__), "golden", "ses2000_twin_h0.7.json")
 
 
 def _say(msg):
@@ -102,3 +103,25 @@ def test_mixed_full_size_energy():
     _say(f"[mixed kirkwood full] G_pol rel err {err:.2e} psi rows {ex:.2e} iters {info['iters']} "
          f"t {info['seconds']:.2f}s")
     assert err < 1e-6
+
+
+def test_mixed_twin_against_fp64_and_oracle():
+    """The 2000-atom molecule on the coarsened h = 0.7 grid: the mixed solve's
+    G_pol against the FP64 GPU solve and the stored oracle solve (1e-6)."""
+    if not os.path.exists(GOLDEN_TWIN):
+        pytest.skip("stored oracle values for the h = 0.7 twin are missing")
+    gold = json.load(open(GOLDEN_TWIN))
+    wl = workloads.by_name("ses2000_twin")
+    g = {}
+    for prec in (ibim.FP64, ibim.MIXED):
+        p = ibim.Problem.from_workload(wl, device=0, precision=prec)
+        _, info = p.solve_energy(wl.tol)
+        assert info["converged"]
+        g[prec] = info["g_pol"]
+        p.close()
+    e64 = abs(g[ibim.FP64] - gold["g_pol"]) / abs(gold["g_pol"])
+    emx = abs(g[ibim.MIXED] - gold["g_pol"]) / abs(gold["g_pol"])
+    emf = abs(g[ibim.MIXED] - g[ibim.FP64]) / abs(g[ibim.FP64])
+    _say(f"[mixed twin] M={gold['M']} G_pol FP64 vs oracle {e64:.2e}, mixed vs oracle {emx:.2e}, "
+         f"mixed vs FP64 {emf:.2e}")
+    assert e64 < 1e-10 and emx < 1e-6 and emf < 1e-6

@@ -234,7 +234,7 @@ def test_born_energy_near_closed_form():
 # --------------------------------------------------------------------------
 # full size: Kirkwood sphere R = 10, 20 charges, h = 0.25, eps = 3h
 GOLDENS = {"kirkwood": "kirkwood_R10_h0.25.json", "ses500": "ses500_h0.3.json",
-           "ses2000": "ses2000_h0.35.json"}
+           "ses2000": "ses2000_h0.35.json", "ses2000_twin": "ses2000_twin_h0.7.json"}
 
 
 @pytest.fixture(scope="module", params=list(GOLDENS))
@@ -267,6 +267,24 @@ def test_full_sampled_apply(full):
     e2 = np.max(np.abs(out[M + rows] - r2)) / np.max(np.abs(r2))
     _say(f"[{name} full] sampled apply rel err {e1:.3e} {e2:.3e}")
     assert e1 < 1e-12 and e2 < 1e-12
+
+
+def test_full_tree_sampled_apply(full):
+    """The treecode (8 points per dimension, theta 0.7) on the same rows: an
+    approximation of the exact sum, within 1e-6 of the largest entry."""
+    name, wl, prob, gold = full
+    tree = ibim.Problem.from_workload(wl, device=0, summation=ibim.SUM_TREE)
+    M = tree.M
+    rows = np.array(gold["rows"])
+    u = workloads.random_vector(2 * M, gold["u_seed"])
+    out = tree.apply(torch.from_numpy(u).to(DEV)).cpu().numpy()
+    tree.close()
+    r1 = np.array(gold["apply_rows_1"])
+    r2 = np.array(gold["apply_rows_2"])
+    e1 = np.max(np.abs(out[rows] - r1)) / np.max(np.abs(r1))
+    e2 = np.max(np.abs(out[M + rows] - r2)) / np.max(np.abs(r2))
+    _say(f"[{name} full] treecode sampled apply rel err {e1:.3e} {e2:.3e}")
+    assert e1 < 1e-6 and e2 < 1e-6
 
 
 def test_full_sampled_weights(full):

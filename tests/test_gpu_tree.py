@@ -39,6 +39,7 @@ def _rel(a, b, M):
 
 
 NEAR_CASES = {
+    "tiny_sphere": lambda: workloads.born_sphere(h=0.3, radius=0.6, eps_factor=1.5),
     "born_h0.2": lambda: workloads.born_sphere(h=0.2),
     "torus": lambda: workloads.torus_case(h=0.1),
     "ses_molecule": lambda: workloads.ses_molecule(20, 9.0, 0.35, 2.0, seed=11),
@@ -99,6 +100,20 @@ def test_tree_solve_matches_direct(kw):
     g_orc = orc.solve_energy(wl.charge_xyz, wl.charge_q, wl.tol)[1]["g_pol"]
     assert abs(g["direct"] - g_orc) <= 1e-10 * abs(g_orc)
     assert abs(g["tree"] - g_orc) <= 1e-6 * abs(g_orc)
+
+
+def test_small_problems_have_no_far_field():
+    """Below n^3 nodes no cluster can carry proxies: the treecode at its
+    defaults is the direct sum (one batch, or a few with a ragged last one)."""
+    for wl in (workloads.born_sphere(h=0.3, radius=0.6, eps_factor=1.5),
+               workloads.born_sphere(h=0.4, radius=1.0)):
+        direct = ibim.Problem.from_workload(wl, device=0)
+        tree = ibim.Problem.from_workload(wl, device=0, summation=ibim.SUM_TREE)
+        c = tree.tree_counts()
+        _say(f"[tree small] M={tree.M} counts={c}")
+        assert tree.M <= 512 and c["proxy_clusters"] == 0 and c["far_evals"] == 0
+        u = workloads.random_vector(2 * tree.M, 23)
+        assert _rel(_apply(tree, u), _apply(direct, u), tree.M) < 1e-13
 
 
 def test_tree_options_rejected():
