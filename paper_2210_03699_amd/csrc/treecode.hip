@@ -6,7 +6,7 @@
 // the pair sum is a derivative of
 //   FA = (1 - c1 e^{-kR})/R,  FB = (1 - e^{-kR})/R,  FC = (1 - c2 e^{-kR})/R
 // (times 1/(4 pi)): K11 = d/dn_y FA, K12 = FB, K21 = d/dn_x d/dn_y FB,
-// K22 = -d/dn_x FC.  Replacing F(x, y) by sum_p F(x, s_p) L_p(y) gives, for
+// K22 = d/dn_x FC.  Replacing F(x, y) by sum_p F(x, s_p) L_p(y) gives, for
 // the sources of C,
 //   sum_m K11 a1_m - K12 a2_m  ~  sum_p FA(x, s_p) Q1_p - FB(x, s_p) Q2_p,
 //   sum_m K21 a1_m - K22 a2_m  ~  sum_p d/dn_x FB(x, s_p) Q1_p - d/dn_x FC(x, s_p) Q2_p,

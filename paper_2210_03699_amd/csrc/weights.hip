@@ -30,7 +30,9 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kModes = 41;    // even modes 0, 2, ..., 80
 constexpr int kSamples = 128; // samples of l on [0, pi)
-constexpr int kLat = 8;       // lattice half-width of both sums
+// Lattice half-width of both sums.  The first omitted points lie at distance
+// >= 6.5; there Q(s, pi r^2)/r < 3e-22 even for the highest mode (s = 40.5).
+constexpr int kLat = 6;
 constexpr int kSide = 2 * kLat + 1;
 constexpr int kPts = kSide * kSide;  // includes the origin, skipped
 constexpr int kWavesPerBlock = 4;

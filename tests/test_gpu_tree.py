@@ -46,16 +46,18 @@ NEAR_CASES = {
 }
 
 
-@pytest.mark.parametrize("name", list(NEAR_CASES))
-def test_all_near_equals_direct(name):
+@pytest.mark.parametrize("name,rows", [(n, ibim.CTR2) for n in NEAR_CASES] +
+                         [("born_h0.2", ibim.KREG), ("ses_molecule", ibim.HYB)])
+def test_all_near_equals_direct(name, rows):
     wl = NEAR_CASES[name]()
-    direct = ibim.Problem.from_workload(wl, device=0)
-    tree = ibim.Problem.from_workload(wl, device=0, summation=ibim.SUM_TREE, tree_theta=1e-6)
+    direct = ibim.Problem.from_workload(wl, device=0, hybrid=rows)
+    tree = ibim.Problem.from_workload(wl, device=0, summation=ibim.SUM_TREE, tree_theta=1e-6,
+                                      hybrid=rows)
     cnt = tree.tree_counts()
     assert cnt["far_evals"] == 0 and cnt["near_evals"] == tree.M * tree.M
     u = workloads.random_vector(2 * tree.M, 21)
     err = _rel(_apply(tree, u), _apply(direct, u), tree.M)
-    _say(f"[tree all-near {name}] M={tree.M} batches={cnt['batches']} rel {err:.3e}")
+    _say(f"[tree all-near {name} rows={rows}] M={tree.M} batches={cnt['batches']} rel {err:.3e}")
     assert err < 1e-13
 
 
@@ -85,6 +87,20 @@ def test_error_falls_geometrically(kw):
     e = _rel(_apply(p, u), ref, p.M)
     _say(f"[tree order=8 theta=0.5] rel err {e:.3e}")
     assert e < errs[8] / 10 and e < 1e-7
+
+
+def test_tree_with_kreg_rows_matches_direct():
+    """K-reg rows have larger excluded sets (a tangent disc of radius 2h); the
+    treecode keeps them in its direct part and its solve stays within 1e-6."""
+    wl = workloads.kirkwood_sphere(h=0.2, radius=5.0, r_charges=3.0)
+    g = {}
+    for name, kwargs in (("direct", {}), ("tree", {"summation": ibim.SUM_TREE})):
+        p = ibim.Problem.from_workload(wl, device=0, hybrid=ibim.KREG, **kwargs)
+        _, info = p.solve_energy(wl.tol)
+        g[name] = info["g_pol"]
+        p.close()
+    _say(f"[tree kreg] G direct {g['direct']:.15e} tree {g['tree']:.15e}")
+    assert abs(g["tree"] - g["direct"]) <= 1e-6 * abs(g["direct"])
 
 
 def test_tree_solve_matches_direct(kw):
