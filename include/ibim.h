@@ -283,6 +283,29 @@ int ibim_pair_work(const ibim_ctx* ctx, double* pairs, double* flops);
  */
 int ibim_tree_counts(const ibim_ctx* ctx, double* out);
 
+/*
+ * The treecode plan of an IBIM_SUM_TREE context (host-only contexts too: the
+ * plan is built on the host with the geometry), for inspection.  Call once
+ * with counts (host, 8 int64) to learn the sizes: [0] M, [1] batches B,
+ * [2] proxy clusters C, [3] far entries F, [4] direct ranges R, [5] work
+ * items, [6] tree_order, [7] 0.  Every non-NULL host array is then filled:
+ *   perm (M)            node at each tree position (all ranges below are in
+ *                       tree positions);
+ *   bstart (B+1)        batch b holds bstart[b] .. bstart[b+1]-1;
+ *   cstart, cend (C)    range of proxy cluster c; cbox (6C) its box (lo x, y,
+ *                       z, hi x, y, z; flat sides padded to width h);
+ *   kid (2C)            children of c that carry proxies (-1: none);
+ *   dstart, dend (C)    the sources whose charges c takes directly;
+ *   frow (B+1), fcol (F) proxy clusters summed for batch b;
+ *   nrow (B+1), nlo, nhi (R) source ranges summed directly for batch b;
+ *   gap (1)             the largest distance |x_k - P_m| over m in N_k.
+ * IBIM_EINVAL for other contexts.
+ */
+int ibim_tree_plan(const ibim_ctx* ctx, int64_t* counts, int32_t* perm, int32_t* bstart,
+                   int32_t* cstart, int32_t* cend, double* cbox, int32_t* kid, int32_t* dstart,
+                   int32_t* dend, int32_t* frow, int32_t* fcol, int32_t* nrow, int32_t* nlo,
+                   int32_t* nhi, double* gap);
+
 /* ------------------------------------------------------------------------ */
 /*
  * Solve server: continuous batching of many independent problems on one GPU.

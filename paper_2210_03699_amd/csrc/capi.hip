@@ -255,6 +255,14 @@ int ctx_create_host(const double* sdf, int nx, int ny, int nz, const double orig
   }
   std::string err;
   int r = build_host_plan(sdf, nx, ny, nz, origin, h, eps_tube, o.hybrid, &c->plan, &err);
+  if (!r && o.summation == IBIM_SUM_TREE) {
+    TreeParams prm;
+    prm.order = o.tree_order;
+    prm.theta = o.tree_theta;
+    const HostPlan& pl = c->plan;
+    r = build_tree_plan(prm, pl.M, pl.px.data(), pl.py.data(), pl.pz.data(), pl.crow.data(),
+                        pl.ccol.data(), h, &c->tplan, &err);
+  }
   if (r) {
     delete c;
     return fail(r, err);
@@ -426,13 +434,7 @@ int ctx_setup_device(ibim_ctx* c, hipStream_t s) {
   c->pair = make_pair_plan(M, o.precision);
   c->sym = make_sym_plan(M, o.summation == IBIM_SUM_TREE ? 0 : kSymScratchMax);
   if (o.summation == IBIM_SUM_TREE) {
-    TreeParams prm;
-    prm.order = o.tree_order;
-    prm.theta = o.tree_theta;
-    std::string terr;
-    if (int r = build_tree_plan(prm, M, pl.px.data(), pl.py.data(), pl.pz.data(), pl.crow.data(),
-                                pl.ccol.data(), h, &c->tplan, &terr))
-      return fail(r, terr);
+    // the plan was built with the geometry (ctx_create_host)
     e = tree_upload(c->tplan, P, pl.px.data(), pl.py.data(), pl.pz.data(), pl.nx.data(),
                     pl.ny.data(), pl.nz.data(), pl.w.data(), &c->tree, s);
     if (e != hipSuccess) return bad(e, "treecode setup");
@@ -832,6 +834,43 @@ int ibim_pair_work(const ibim_ctx* ctx, double* pairs, double* flops) {
   if (!pairs || !flops) return fail(IBIM_EINVAL, "NULL output");
   *pairs = (double)ctx->P.M * (double)ctx->P.M;
   *flops = ctx->pair_flops;
+  return IBIM_OK;
+}
+
+int ibim_tree_plan(const ibim_ctx* ctx, int64_t* counts, int32_t* perm, int32_t* bstart,
+                   int32_t* cstart, int32_t* cend, double* cbox, int32_t* kid, int32_t* dstart,
+                   int32_t* dend, int32_t* frow, int32_t* fcol, int32_t* nrow, int32_t* nlo,
+                   int32_t* nhi, double* gap) {
+  if (int r = check_ctx(ctx)) return r;
+  if (ctx->opt.summation != IBIM_SUM_TREE) return fail(IBIM_EINVAL, "not a treecode context");
+  const ibim::TreePlan& t = ctx->tplan;
+  if (counts) {
+    counts[0] = t.M;
+    counts[1] = (int64_t)t.bstart.size() - 1;
+    counts[2] = (int64_t)t.pstart.size();
+    counts[3] = (int64_t)t.fcol.size();
+    counts[4] = (int64_t)t.nlo.size();
+    counts[5] = (int64_t)t.ibatch.size();
+    counts[6] = t.order;
+    counts[7] = 0;
+  }
+  auto put = [](int32_t* dst, const std::vector<int32_t>& v) {
+    if (dst && !v.empty()) std::memcpy(dst, v.data(), v.size() * sizeof(int32_t));
+  };
+  put(perm, t.perm);
+  put(bstart, t.bstart);
+  put(cstart, t.pstart);
+  put(cend, t.pend);
+  if (cbox && !t.pbox.empty()) std::memcpy(cbox, t.pbox.data(), t.pbox.size() * sizeof(double));
+  put(kid, t.kid);
+  put(dstart, t.dstart);
+  put(dend, t.dend);
+  put(frow, t.frow);
+  put(fcol, t.fcol);
+  put(nrow, t.nrow);
+  put(nlo, t.nlo);
+  put(nhi, t.nhi);
+  if (gap) *gap = t.gap;
   return IBIM_OK;
 }
 

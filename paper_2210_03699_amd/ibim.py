@@ -115,6 +115,7 @@ def load():
     lib.ibim_pair_timing_read.argtypes = [_VP, _I64, _D]
     lib.ibim_pair_work.argtypes = [_VP, _D, _D]
     lib.ibim_tree_counts.argtypes = [_VP, _D]
+    lib.ibim_tree_plan.argtypes = [_VP, _I64] + [_I32] * 4 + [_D] + [_I32] * 8 + [_D]
     lib.ibim_server_create.argtypes = [ctypes.POINTER(_Options), ctypes.c_size_t, ctypes.c_int,
                                        ctypes.c_int, _VP, ctypes.POINTER(_VP)]
     lib.ibim_server_submit.argtypes = [_VP, _D, ctypes.c_int, ctypes.c_int, ctypes.c_int, _D,
@@ -322,6 +323,32 @@ class Problem:
         return {"far_evals": out[0], "near_evals": out[1], "proxy_terms": out[2],
                 "batches": int(out[3]), "proxy_clusters": int(out[4]),
                 "transfers": int(out[5])}
+
+    def tree_plan(self):
+        """The treecode plan (``ibim_tree_plan``) as numpy arrays."""
+        cnt = np.zeros(8, dtype=np.int64)
+        nul = ctypes.POINTER(ctypes.c_int32)()
+        dnul = ctypes.POINTER(ctypes.c_double)()
+        _check(self._lib.ibim_tree_plan(self._ctx, cnt.ctypes.data_as(_I64), *([nul] * 4), dnul,
+                                        *([nul] * 8), dnul))
+        M, B, C, F, R = (int(v) for v in cnt[:5])
+        i32 = lambda n: np.zeros(max(n, 0), dtype=np.int32)
+        out = {"perm": i32(M), "bstart": i32(B + 1), "cstart": i32(C), "cend": i32(C),
+               "cbox": np.zeros(6 * C), "kid": i32(2 * C), "dstart": i32(C), "dend": i32(C),
+               "frow": i32(B + 1), "fcol": i32(F), "nrow": i32(B + 1), "nlo": i32(R),
+               "nhi": i32(R)}
+        gap = np.zeros(1)
+        p = lambda a: a.ctypes.data_as(_I32)
+        _check(self._lib.ibim_tree_plan(
+            self._ctx, cnt.ctypes.data_as(_I64), p(out["perm"]), p(out["bstart"]),
+            p(out["cstart"]), p(out["cend"]), _dp(out["cbox"]), p(out["kid"]), p(out["dstart"]),
+            p(out["dend"]), p(out["frow"]), p(out["fcol"]), p(out["nrow"]), p(out["nlo"]),
+            p(out["nhi"]), _dp(gap)))
+        out["cbox"] = out["cbox"].reshape(-1, 6)
+        out["gap"] = float(gap[0])
+        out["items"] = int(cnt[5])
+        out["order"] = int(cnt[6])
+        return out
 
     def solve_energy(self, tol, stream=None):
         g = self.rhs(stream=stream)

@@ -50,7 +50,7 @@ def large():
 def test_large_sampled_apply(large, precision, bar):
     wl, rows, u, ref1, ref2, M = large
     prob = ibim.Problem.from_workload(wl, device=0, precision=precision)
-    assert prob.M == M and M > 524288  # past the size of a 4 GiB unpacked scratch
+    assert prob.M == M and M > 524288  # an unpacked column-sum scratch would exceed 4 GiB here
     out = prob.apply(torch.from_numpy(u).to(DEV)).cpu().numpy()
     e1 = np.max(np.abs(out[rows] - ref1)) / np.max(np.abs(ref1))
     e2 = np.max(np.abs(out[M + rows] - ref2)) / np.max(np.abs(ref2))
