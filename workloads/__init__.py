@@ -213,6 +213,7 @@ def by_name(name: str) -> Workload:
     ``ses2000_twin`` the same molecule at h = 0.7 with eps = 1.5h (within the
                   re-entrant reach of the 1.4 A probe).
     ``kirkwood_h0.1`` the Kirkwood sphere at h = 0.1 (eps = 3h, M ~ 7.5e5).
+    ``kirkwood_h0.07`` the Kirkwood sphere at h = 0.07 (M ~ 1.5e6).
     """
     if name == "born":
         return born_sphere()
@@ -226,6 +227,8 @@ def by_name(name: str) -> Workload:
         return ses_molecule(2000, 40.0, 0.7, 1.5, seed=5)
     if name == "kirkwood_h0.1":
         return kirkwood_sphere(h=0.1)
+    if name == "kirkwood_h0.07":
+        return kirkwood_sphere(h=0.07)
     raise KeyError(name)
 
 
