@@ -31,7 +31,6 @@ struct TreePlan {
   std::vector<int32_t> pos;   // node -> tree position
   // batches: target ranges [bstart[b], bstart[b + 1])
   std::vector<int32_t> bstart;
-  std::vector<int32_t> border;  // batch indices, most work first
   // clusters with proxies (every cluster with more nodes than proxies, in
   // tree preorder): source range, bounding box (lo x, y, z, hi x, y, z)
   std::vector<int32_t> pstart, pend;

@@ -260,10 +260,6 @@ int build_tree_plan(const TreeParams& prm, int64_t M64, const double* px, const 
     pl.near_evals += nt * ns_near;
     work[b] = (double)far[b].size() * n3 * 0.8 + ns_near;
   }
-  pl.border.resize(nb);
-  std::iota(pl.border.begin(), pl.border.end(), 0);
-  std::stable_sort(pl.border.begin(), pl.border.end(),
-                   [&](int a, int b) { return work[a] > work[b]; });
 
   // work items: about kItems in all (at least kMinPart of work per target each)
   constexpr double kItems = 8192.0, kMinPart = 4096.0;

@@ -16,12 +16,11 @@ struct TreeDevice {
   int32_t M = 0;
   int n_batches = 0, n_slots = 0, order = 0;
   int32_t *perm = nullptr, *pos = nullptr;
-  int32_t *bstart = nullptr, *border = nullptr;
-  int32_t *pstart = nullptr, *pend = nullptr;
+  int32_t* bstart = nullptr;
   int32_t *dstart = nullptr, *dend = nullptr, *kid = nullptr, *mlist = nullptr;
   std::vector<int32_t> mlevel;  // host: clusters of height h are mlist[mlevel[h] .. mlevel[h + 1])
-  int32_t *frow = nullptr, *fcol = nullptr;
-  int32_t *nrow = nullptr, *nlo = nullptr, *nhi = nullptr;
+  int32_t* fcol = nullptr;  // proxy clusters of the work items' far entries
+  int32_t *nlo = nullptr, *nhi = nullptr;  // direct source ranges
   int32_t *xrow = nullptr, *xcol = nullptr;
   int32_t *ibatch = nullptr, *ifar0 = nullptr, *ifar1 = nullptr, *inear0 = nullptr,
           *inear1 = nullptr, *istart = nullptr, *iorder = nullptr;

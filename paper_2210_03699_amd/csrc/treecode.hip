@@ -40,9 +40,8 @@ namespace {
 constexpr int kUpSrc = 64;  // sources per round of the proxy-charge kernel
 
 struct TreeArgs {
-  const int32_t *perm, *pos, *bstart, *border, *pstart, *pend, *frow, *fcol, *nrow, *nlo, *nhi,
-      *xrow, *xcol, *dstart, *dend, *kid, *mlist, *ibatch, *ifar0, *ifar1, *inear0, *inear1,
-      *iorder;
+  const int32_t *perm, *pos, *bstart, *fcol, *nlo, *nhi, *xrow, *xcol, *dstart, *dend, *kid,
+      *mlist, *ibatch, *ifar0, *ifar1, *inear0, *inear1, *iorder;
   const double *pbox, *cheb;
   const double *tx, *ty, *tz, *tnx, *tny, *tnz, *tw;
   double *ta1, *ta2, *pq, *S;
@@ -54,9 +53,8 @@ struct TreeArgs {
 
 TreeArgs make_args(const TreeDevice& T, const DeviceProblem& P, const double* u) {
   TreeArgs a;
-  a.perm = T.perm; a.pos = T.pos; a.bstart = T.bstart; a.border = T.border;
-  a.pstart = T.pstart; a.pend = T.pend; a.frow = T.frow; a.fcol = T.fcol;
-  a.nrow = T.nrow; a.nlo = T.nlo; a.nhi = T.nhi; a.xrow = T.xrow; a.xcol = T.xcol;
+  a.perm = T.perm; a.pos = T.pos; a.bstart = T.bstart; a.fcol = T.fcol;
+  a.nlo = T.nlo; a.nhi = T.nhi; a.xrow = T.xrow; a.xcol = T.xcol;
   a.dstart = T.dstart; a.dend = T.dend; a.kid = T.kid; a.mlist = T.mlist;
   a.ibatch = T.ibatch; a.ifar0 = T.ifar0; a.ifar1 = T.ifar1; a.inear0 = T.inear0;
   a.inear1 = T.inear1; a.iorder = T.iorder;
@@ -397,11 +395,11 @@ hipError_t up(T** dst, const std::vector<T>& v, size_t* bytes, hipStream_t s) {
 }  // namespace
 
 void TreeDevice::release() {
-  dfree(perm); dfree(pos); dfree(bstart); dfree(border); dfree(pstart); dfree(pend);
+  dfree(perm); dfree(pos); dfree(bstart);
   dfree(dstart); dfree(dend); dfree(kid); dfree(mlist);
   dfree(ibatch); dfree(ifar0); dfree(ifar1); dfree(inear0); dfree(inear1); dfree(istart);
   dfree(iorder);
-  dfree(frow); dfree(fcol); dfree(nrow); dfree(nlo); dfree(nhi); dfree(xrow); dfree(xcol);
+  dfree(fcol); dfree(nlo); dfree(nhi); dfree(xrow); dfree(xcol);
   dfree(pbox); dfree(cheb);
   dfree(tx); dfree(ty); dfree(tz); dfree(tnx); dfree(tny); dfree(tnz); dfree(tw);
   dfree(ta1); dfree(ta2); dfree(pq); dfree(S);
@@ -449,9 +447,6 @@ hipError_t tree_upload(const TreePlan& pl, const DeviceProblem& P, const double*
   TUP(perm, pl.perm);
   TUP(pos, pl.pos);
   TUP(bstart, pl.bstart);
-  TUP(border, pl.border);
-  TUP(pstart, pl.pstart);
-  TUP(pend, pl.pend);
   TUP(dstart, pl.dstart);
   TUP(dend, pl.dend);
   TUP(kid, pl.kid);
@@ -463,9 +458,7 @@ hipError_t tree_upload(const TreePlan& pl, const DeviceProblem& P, const double*
   TUP(inear1, pl.inear1);
   TUP(istart, pl.istart);
   TUP(iorder, pl.iorder);
-  TUP(frow, pl.frow);
   TUP(fcol, pl.fcol);
-  TUP(nrow, pl.nrow);
   TUP(nlo, pl.nlo);
   TUP(nhi, pl.nhi);
   TUP(xrow, pl.xrow);
