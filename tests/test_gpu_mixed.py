@@ -67,6 +67,10 @@ CASES = {
     "kirkwood_small": lambda: workloads.kirkwood_sphere(h=0.3, radius=3.0, r_charges=2.0,
                                                         n_charges=5, seed=7, tol=1e-10),
     "ses_molecule": lambda: workloads.ses_molecule(20, 9.0, 0.35, 2.0, seed=11, tol=1e-10),
+    "laplace": lambda: workloads.born_sphere(h=0.25, radius=1.7, offset=(0.37, 0.11, -0.23),
+                                             kappa=0.0),
+    "strong_screening": lambda: workloads.born_sphere(h=0.25, radius=1.7,
+                                                      offset=(0.37, 0.11, -0.23), kappa=3.0),
 }
 
 

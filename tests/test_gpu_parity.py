@@ -46,6 +46,14 @@ CASES = {
     "kirkwood_small": lambda: workloads.kirkwood_sphere(h=0.3, radius=3.0, r_charges=2.0,
                                                         n_charges=5, seed=7, tol=1e-10),
     "ses_molecule": lambda: workloads.ses_molecule(20, 9.0, 0.35, 2.0, seed=11, tol=1e-10),
+    # degenerate parameters: no screening (kappa = 0, K12 and K21 vanish), no
+    # dielectric jump (eps_in = eps_out, lambda = 1), strong screening (kappa R ~ 7)
+    "laplace": lambda: workloads.born_sphere(h=0.25, radius=1.7, offset=(0.37, 0.11, -0.23),
+                                             kappa=0.0),
+    "no_jump": lambda: workloads.born_sphere(h=0.25, radius=1.7, offset=(0.37, 0.11, -0.23),
+                                             eps_in=2.0, eps_out=2.0, kappa=0.3),
+    "strong_screening": lambda: workloads.born_sphere(h=0.25, radius=1.7,
+                                                      offset=(0.37, 0.11, -0.23), kappa=3.0),
 }
 
 
@@ -77,6 +85,9 @@ def test_weights_match_oracle(pair):
         perm[s] = co["row"][k] + np.argsort(co["col"][s], kind="stable")
     assert np.array_equal(cl["col"], co["col"][perm])
     for got, ref in ((om11, co["om11"][perm]), (om21, co["om21"][perm])):
+        if np.max(np.abs(ref)) == 0.0:  # omega^(21) carries kappa^2: zero without screening
+            assert np.max(np.abs(got)) == 0.0, name
+            continue
         err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
         assert err < 1e-12, (name, err)
 
