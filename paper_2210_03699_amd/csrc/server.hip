@@ -76,6 +76,9 @@ struct ibim_server {
   size_t budget = 0, used = 0, peak = 0;
   int max_slots = 1;
   hipStream_t stream = nullptr;
+  // device setup of newly admitted requests (uploads, weights, right-hand
+  // side) runs here while the round already queued on `stream` executes
+  hipStream_t setup = nullptr;
   int grid = 0;
   int64_t next_ticket = 1;
   std::map<int64_t, std::unique_ptr<Request>> reqs;
@@ -173,7 +176,7 @@ void mark_failed(ibim_server* srv, Request* r, int code, const std::string& msg)
 
 // Device setup and the first GMRES cycle's start (r = b, V0 = b/||b||).
 int admit(ibim_server* srv, Request* r) {
-  hipStream_t s = srv->stream;
+  hipStream_t s = srv->setup;
   ibim_ctx* c = r->ctx;
   c->opt.device = srv->opt.device;
   if (int e = ctx_setup_device(c, s)) return e;
@@ -197,6 +200,8 @@ int admit(ibim_server* srv, Request* r) {
   HIP_TRY(launch_copy(r->d_b, K.tmp, N, s), "copy");
   HIP_TRY(K.normalize(K.tmp, st + 2, K.V, N, s), "normalize");
   HIP_TRY(K.init_g(st + 2, s), "init_g");
+  // the request's device state is complete before the main stream uses it
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
   r->phase = Phase::kIter;
   r->j = 0;
   r->total = 0;
@@ -247,6 +252,46 @@ int ensure_staging(T** d, T** h, size_t* cap, size_t n) {
   return IBIM_OK;
 }
 
+// Admission, first fit in submission order: requests whose host setup is
+// done and whose footprint fits the remaining budget get a slot and their
+// device setup (on the setup stream); they are appended to *fresh.
+void admit_waiting(ibim_server* srv, std::vector<Request*>* fresh) {
+  std::vector<Request*> still;
+  for (Request* r : srv->waiting) {
+    bool prepared;
+    {
+      std::lock_guard<std::mutex> lk(srv->mu);
+      prepared = r->prepared;
+    }
+    if (!prepared) {
+      still.push_back(r);
+      continue;
+    }
+    if (r->error) {
+      mark_failed(srv, r, r->error, r->error_msg);
+      continue;
+    }
+    const bool slot = !srv->free_slots.empty();
+    if (slot && srv->used + r->estimate <= srv->budget) {
+      const int e = admit(srv, r);
+      if (e) {
+        mark_failed(srv, r, e, ibim_last_error());
+        continue;
+      }
+      fresh->push_back(r);
+      const int n_active = (int)(srv->active.size() + fresh->size());
+      if (n_active > srv->st.max_active_seen) srv->st.max_active_seen = n_active;
+    } else {
+      if (srv->active.empty() && fresh->empty() && slot && r->estimate > srv->budget) {
+        mark_failed(srv, r, IBIM_ENOMEM, "request footprint exceeds the server's HBM budget");
+        continue;
+      }
+      still.push_back(r);
+    }
+  }
+  srv->waiting.swap(still);
+}
+
 int step_impl(ibim_server* srv) {
   hipStream_t s = srv->stream;
   // with no solve running, wait for a host setup rather than return idle
@@ -258,42 +303,13 @@ int step_impl(ibim_server* srv) {
       return false;
     });
   }
-  // 1. admission (first fit in submission order)
-  {
-    std::vector<Request*> still;
-    for (Request* r : srv->waiting) {
-      bool prepared;
-      {
-        std::lock_guard<std::mutex> lk(srv->mu);
-        prepared = r->prepared;
-      }
-      if (!prepared) {
-        still.push_back(r);
-        continue;
-      }
-      if (r->error) {
-        mark_failed(srv, r, r->error, r->error_msg);
-        continue;
-      }
-      const bool slot = !srv->free_slots.empty();
-      if (slot && srv->used + r->estimate <= srv->budget) {
-        const int e = admit(srv, r);
-        if (e) {
-          mark_failed(srv, r, e, ibim_last_error());
-          continue;
-        }
-        srv->active.push_back(r);
-        if ((int)srv->active.size() > srv->st.max_active_seen)
-          srv->st.max_active_seen = (int)srv->active.size();
-      } else {
-        if (srv->active.empty() && slot && r->estimate > srv->budget) {
-          mark_failed(srv, r, IBIM_ENOMEM, "request footprint exceeds the server's HBM budget");
-          continue;
-        }
-        still.push_back(r);
-      }
-    }
-    srv->waiting.swap(still);
+  std::vector<Request*> fresh;
+  const bool idle = srv->active.empty();
+  if (idle) {
+    // nothing on the device: admit first and run the new requests' first round now
+    admit_waiting(srv, &fresh);
+    srv->active.swap(fresh);
+    fresh.clear();
   }
   if (srv->active.empty()) return IBIM_OK;
 
@@ -412,6 +428,9 @@ int step_impl(ibim_server* srv) {
                          (size_t)srv->max_slots * kStatusStride * sizeof(double),
                          hipMemcpyDeviceToHost, s),
           "copy");
+  // requests that became ready are set up while the round runs; they join
+  // the next round
+  if (!idle) admit_waiting(srv, &fresh);
   HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
 
   // 4. decisions
@@ -484,6 +503,7 @@ int step_impl(ibim_server* srv) {
     }
     keep.push_back(r);
   }
+  keep.insert(keep.end(), fresh.begin(), fresh.end());
   srv->active.swap(keep);
   return IBIM_OK;
 }
@@ -527,7 +547,8 @@ int ibim_server_create(const ibim_options* opt, size_t hbm_budget_bytes, int max
     srv->grid = pair_batched_grid(o.precision);
     srv->sym_grid =
         o.precision == IBIM_MIXED ? pair_sym_mixed_batched_grid() : pair_sym_batched_grid();
-    hipError_t e = dalloc(&srv->d_counter, 2);
+    hipError_t e = hipStreamCreateWithFlags(&srv->setup, hipStreamNonBlocking);
+    if (e == hipSuccess) e = dalloc(&srv->d_counter, 2);
     if (e == hipSuccess) e = dalloc(&srv->d_status, (size_t)max_slots * kStatusStride);
     if (e == hipSuccess)
       e = hipHostMalloc((void**)&srv->h_status, (size_t)max_slots * kStatusStride * sizeof(double),
@@ -650,6 +671,10 @@ void ibim_server_destroy(ibim_server* srv) {
   srv->cv.notify_all();
   for (auto& t : srv->workers) t.join();
   DeviceScope ds(srv->opt.device);
+  if (srv->setup) {
+    (void)hipStreamSynchronize(srv->setup);
+    (void)hipStreamDestroy(srv->setup);
+  }
   for (auto& kv : srv->reqs) {
     Request* r = kv.second.get();
     if (r->ctx) ibim_destroy(r->ctx);
