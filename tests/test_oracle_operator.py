@@ -8,7 +8,8 @@ fixes, not with the oracle itself:
   layer-potential integrals (second order at fixed tube width);
 * the double-layer identity int dG0/dn_y = -1/2 on a rotated torus;
 * Born ion and Kirkwood sphere energies -> closed forms (eq. pol-energy);
-* GMRES -> dense LU of the explicitly assembled matrix.
+* GMRES -> dense LU of the explicitly assembled matrix;
+* apply -> the operator written out entry by entry on a tiny grid.
 """
 import math
 
@@ -194,3 +195,37 @@ def test_setup_rejects_bad_inputs():
         oracle.Oracle(sdf, org, 0.2, 100.0, EI, EE, KAP)  # tube reaches the grid edge
     with pytest.raises(ValueError):
         oracle.Oracle(sdf, org, -0.2, 0.4, EI, EE, KAP)
+
+
+def test_apply_equals_its_definition_on_a_tiny_grid():
+    """Brute force: the operator assembled entry by entry from eq.
+    (corr-trapz-rule-sys1/2) -- Lambda, h^3 K w off the correction sets, and the
+    correction blocks [h^2 om11, -h^3 kappa/(4 pi); h^2 om21, h^2 (eps_I/eps_E) om11]
+    times w on them -- applied to a random vector equals the oracle's apply.
+    Catches a dropped term, a sign, or a pair skipped or counted twice."""
+    wl = workloads.born_sphere(h=0.3, radius=0.6, eps_factor=1.5,
+                               offset=(0.07, -0.05, 0.11))
+    o = oracle.Oracle.from_workload(wl)
+    M, h = o.M, wl.h
+    nd, c = o.nodes(), o.corrections()
+    P, n, w = nd["P"], nd["n"], nd["w"]
+    u = workloads.random_vector(2 * M, 31)
+    a1, a2 = w * u[:M], w * u[M:]
+    lam1, lam2 = 0.5 * (1 + wl.eps_out / wl.eps_in), 0.5 * (1 + wl.eps_in / wl.eps_out)
+    out = np.concatenate([lam1 * u[:M], lam2 * u[M:]])
+    for k in range(M):
+        corr = {int(c["col"][e]): e for e in range(c["row"][k], c["row"][k + 1])}
+        assert k in corr  # a node is always in its own correction set
+        for m in range(M):
+            if m in corr:
+                e = corr[m]
+                out[k] += h * h * c["om11"][e] * a1[m] - h ** 3 * wl.kappa / (4 * math.pi) * a2[m]
+                out[M + k] += (h * h * c["om21"][e] * a1[m]
+                               + h * h * (wl.eps_in / wl.eps_out) * c["om11"][e] * a2[m])
+            else:
+                K = oracle.kernels(P[k], n[k], P[m], n[m], wl.eps_in, wl.eps_out, wl.kappa)
+                out[k] += h ** 3 * (K[0] * a1[m] - K[1] * a2[m])
+                out[M + k] += h ** 3 * (K[2] * a1[m] - K[3] * a2[m])
+    ref = o.apply(u)
+    assert M < 400
+    assert np.max(np.abs(out - ref)) <= 1e-12 * np.max(np.abs(ref))
