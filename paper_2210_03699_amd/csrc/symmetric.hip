@@ -169,8 +169,9 @@ SymPlan make_sym_plan(int32_t M, size_t max_scratch_bytes) {
   SymPlan pl;
   pl.T = (M + kT - 1) / kT;
   pl.nRB = (pl.T + kRows - 1) / kRows;
-  // column block length: enough items to fill the device several times over
-  int b = 4;
+  // column block length: the shortest that keeps the item count at or under
+  // 8192, so that small problems still spread over many compute units
+  int b = 1;
   while (b < 64) {
     const int64_t nCB = (pl.T + b - 1) / b;
     const int64_t items = (int64_t)pl.nRB * nCB / 2;
