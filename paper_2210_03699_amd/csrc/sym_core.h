@@ -15,7 +15,7 @@ namespace ibim {
 namespace sym {
 
 constexpr int kT = kPairTile;
-constexpr int kRows = kSymRows;
+constexpr int kRows = kSymRows;  // LDS row-sum slots; an item uses a.rows of them
 
 __device__ __forceinline__ bool careful_pair(const SymArgs& a, int I, int J) {
   const int64_t bit = (int64_t)I * a.T + J;
@@ -73,11 +73,12 @@ __device__ void item(const SymArgs& a, int rb, int cb, Shared<P>& sh) {
   const int wv = tid >> 6, l = tid & 63;
   const int T = a.T;
   const int32_t M = a.M;
-  const int I0 = rb * kRows;
+  const int rows = a.rows;
+  const int I0 = rb * rows;
   const int J0 = cb * a.b, J1 = min(J0 + a.b, T);
   const typename P::Consts pc = P::consts(a);
 
-  for (int i = 0; i < kRows; ++i) racc1[i][tid] = racc2[i][tid] = 0.0;
+  for (int i = 0; i < rows; ++i) racc1[i][tid] = racc2[i][tid] = 0.0;
 
   for (int J = max(J0, I0); J < J1; ++J) {
     {
@@ -86,7 +87,7 @@ __device__ void item(const SymArgs& a, int rb, int cb, Shared<P>& sh) {
       cacc[tid] = make_double2(0.0, 0.0);
     }
     __syncthreads();
-    for (int i = 0; i < kRows; ++i) {
+    for (int i = 0; i < rows; ++i) {
       const int I = I0 + i;
       if (I >= T || I > J) continue;  // uniform
       double S1 = racc1[i][tid], S2 = racc2[i][tid];
@@ -127,13 +128,13 @@ __device__ void item(const SymArgs& a, int rb, int cb, Shared<P>& sh) {
       racc2[i][tid] = S2;
     }
     // column sums of J
-    double* cp = a.colpart + sym_col_slot(rb, J) * (2 * kT);
+    double* cp = a.colpart + sym_col_slot(rb, J, rows) * (2 * kT);
     cp[tid] = a.scale * cacc[tid].x;
     cp[kT + tid] = a.scale * cacc[tid].y;
     __syncthreads();  // LDS is refilled for the next column tile
   }
   // row sums of this item's row tiles that met at least one J >= I
-  for (int i = 0; i < kRows; ++i) {
+  for (int i = 0; i < rows; ++i) {
     const int I = I0 + i;
     if (I >= T || I > J1 - 1) continue;
     double* rp = a.rowpart + ((size_t)cb * T + I) * (2 * kT);

@@ -10,28 +10,30 @@
 
 namespace ibim {
 
-constexpr int kSymRows = 4;  // row tiles per work item
+constexpr int kSymRows = 4;  // most row tiles per work item (the LDS row sums are sized for it)
 // Largest row-and-column scratch of the symmetric kernel (an eighth of the
 // 288 GB of HBM; it grows as M^2 / 2^19 doubles, so this covers M ~ 2e6).
 // Larger problems, and setups where the allocation fails, use the
 // one-directional kernel, whose scratch grows only linearly.
 constexpr size_t kSymScratchMax = size_t(32) << 30;
 
-// Column-sum slot of (row block rb, column tile J), rb <= J / kSymRows: the
-// slots of tile J follow those of tiles 0 .. J-1 (a packed lower triangle).
-__host__ __device__ inline size_t sym_col_slot(int rb, int J) {
-  const size_t q = (size_t)(J / kSymRows), r = (size_t)(J % kSymRows);
-  return kSymRows * q * (q + 1) / 2 + r * (q + 1) + (size_t)rb;
+// Column-sum slot of (row block rb, column tile J), rb <= J / rows, for row
+// blocks of `rows` tiles: the slots of tile J follow those of tiles 0 .. J-1
+// (a packed lower triangle).
+__host__ __device__ inline size_t sym_col_slot(int rb, int J, int rows) {
+  const size_t q = (size_t)(J / rows), r = (size_t)(J % rows);
+  return (size_t)rows * q * (q + 1) / 2 + r * (q + 1) + (size_t)rb;
 }
 
 // Decomposition of the upper triangle of tile pairs into work items.
 struct SymPlan {
   bool enabled = false;
   int T = 0;    // tiles of 256 nodes
-  int b = 0;    // column tiles per item
-  int nRB = 0;  // row blocks (kSymRows tiles each)
+  int b = 0;     // column tiles per item
+  int rows = 0;  // row tiles per item (1, 2 or kSymRows)
+  int nRB = 0;   // row blocks (`rows` tiles each)
   int nCB = 0;  // column blocks
-  size_t scratch_doubles = 0;  // row sums (nCB x T) + column sums (sym_col_slot(0, T)), 512 doubles each
+  size_t scratch_doubles = 0;  // row sums (nCB x T) + column sums (sym_col_slot(0, T, rows)), 512 doubles each
 };
 
 struct SymArgs {
@@ -45,10 +47,11 @@ struct SymArgs {
   int32_t M;
   int T;
   int b;
+  int rows;  // row tiles per item
   double c1, c2, kappa;
   double scale;       // h^3 / (4 pi)
   double* rowpart;    // [nCB][T][2][256]
-  double* colpart;    // [sym_col_slot(rb, J)][2][256]
+  double* colpart;    // [sym_col_slot(rb, J, rows)][2][256]
 };
 
 // Plan for M nodes; disabled when the scratch would exceed max_scratch_bytes

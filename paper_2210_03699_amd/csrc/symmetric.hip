@@ -7,7 +7,7 @@
 // dense sum costs about half the instructions of the one-directional kernel.
 //
 // Tiles are 256 nodes.  Work item (rb, cb) covers row tiles
-// I in [rb*kRows, rb*kRows + kRows) and column tiles J in [cb*b, cb*b + b),
+// I in [rb*rows, rb*rows + rows) and column tiles J in [cb*b, cb*b + b),
 // pairs I <= J only.  For each column tile J the workgroup stages J's records
 // in LDS and, for each row tile I, evaluates all 256 x 256 pairs: wave w holds
 // targets I[64w + l] (one per lane) and, in phase p, visits the 64 sources of
@@ -19,7 +19,7 @@
 // Diagonal tile pairs, pairs holding a corrected pair (either direction) and
 // pairs with the ragged last tile are evaluated one direction at a time with
 // the pairs of N_k skipped.  Row sums are written per (cb, I), column sums
-// per (rb, J) (only rb <= J / kRows occur, so those slots are packed); the
+// per (rb, J) (only rb <= J / rows occur, so those slots are packed); the
 // finishing kernel adds them in a fixed order.
 #include <hip/hip_runtime.h>
 
@@ -128,7 +128,7 @@ struct SymFinishArgs {
   const int32_t* ccol;
   const double* blocks;
   int32_t M;
-  int T, b, nCB;
+  int T, b, nCB, rows;
   double lam1, lam2;
   double* out;
 };
@@ -144,8 +144,8 @@ __global__ __launch_bounds__(256) void finish_sym_kernel(SymFinishArgs a) {
     s1 += rp[t];
     s2 += rp[kT + t];
   }
-  const size_t c0 = sym_col_slot(0, X);
-  for (int rb = 0; rb <= X / kRows; ++rb) {
+  const size_t c0 = sym_col_slot(0, X, a.rows);
+  for (int rb = 0; rb <= X / a.rows; ++rb) {
     const double* cp = a.colpart + (c0 + rb) * (2 * kT);
     s1 += cp[t];
     s2 += cp[kT + t];
@@ -168,7 +168,16 @@ __global__ __launch_bounds__(256) void finish_sym_kernel(SymFinishArgs a) {
 SymPlan make_sym_plan(int32_t M, size_t max_scratch_bytes) {
   SymPlan pl;
   pl.T = (M + kT - 1) / kT;
-  pl.nRB = (pl.T + kRows - 1) / kRows;
+  // row tiles per item: kRows (column tiles staged in LDS serve four row
+  // tiles), fewer for small problems so that they still have ~2048 items
+  int rows = kRows;
+  while (rows > 1) {
+    const int64_t nrb = (pl.T + rows - 1) / rows;
+    if (nrb * pl.T / 2 >= 2048) break;
+    rows /= 2;
+  }
+  pl.rows = rows;
+  pl.nRB = (pl.T + rows - 1) / rows;
   // column block length: the shortest that keeps the item count at or under
   // 8192, so that small problems still spread over many compute units
   int b = 1;
@@ -180,7 +189,7 @@ SymPlan make_sym_plan(int32_t M, size_t max_scratch_bytes) {
   }
   pl.b = b;
   pl.nCB = (pl.T + b - 1) / b;
-  pl.scratch_doubles = ((size_t)pl.nCB * pl.T + sym_col_slot(0, pl.T)) * 2 * kT;
+  pl.scratch_doubles = ((size_t)pl.nCB * pl.T + sym_col_slot(0, pl.T, rows)) * 2 * kT;
   pl.enabled = pl.T >= 2 && pl.scratch_doubles * 8 <= max_scratch_bytes;
   return pl;
 }
@@ -191,9 +200,9 @@ void sym_items(const SymPlan& pl, std::vector<int32_t>* items) {
   };
   std::vector<It> v;
   for (int rb = 0; rb < pl.nRB; ++rb)
-    for (int cb = (rb * kRows) / pl.b; cb < pl.nCB; ++cb) {
+    for (int cb = (rb * pl.rows) / pl.b; cb < pl.nCB; ++cb) {
       int pairs = 0;
-      for (int I = rb * kRows; I < std::min(rb * kRows + kRows, pl.T); ++I)
+      for (int I = rb * pl.rows; I < std::min(rb * pl.rows + pl.rows, pl.T); ++I)
         for (int J = cb * pl.b; J < std::min(cb * pl.b + pl.b, pl.T); ++J) pairs += I <= J;
       if (pairs > 0) v.push_back({rb, cb, pairs});
     }
@@ -237,6 +246,7 @@ SymArgs make_sym_args(const DeviceProblem& P, const SymPlan& pl, const int32_t* 
   a.M = P.M;
   a.T = pl.T;
   a.b = pl.b;
+  a.rows = pl.rows;
   a.c1 = P.eps_out / P.eps_in;
   a.c2 = P.eps_in / P.eps_out;
   a.kappa = P.kappa;
@@ -282,6 +292,7 @@ hipError_t launch_finish_sym(const DeviceProblem& P, const SymPlan& pl, const do
   f.T = pl.T;
   f.b = pl.b;
   f.nCB = pl.nCB;
+  f.rows = pl.rows;
   f.lam1 = P.lam1;
   f.lam2 = P.lam2;
   f.out = out;

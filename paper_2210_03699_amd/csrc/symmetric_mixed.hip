@@ -22,7 +22,6 @@ namespace ibim {
 namespace {
 
 constexpr int kT = kPairTile;
-constexpr int kRows = kSymRows;
 
 struct Mixed {
   struct Rec {
@@ -97,7 +96,7 @@ struct FinishArgs {
   PairConstsF c32;
   double scale;
   int32_t M;
-  int T, b, nCB;
+  int T, b, nCB, rows;
   double lam1, lam2;
   double* out;
 };
@@ -117,10 +116,10 @@ __global__ __launch_bounds__(256) void finish_sym_mixed_kernel(FinishArgs a) {
   const int T = a.T;
   const int X = k / kT, t = k % kT;
   double p1 = 0.0, p2 = 0.0;
-  const int cb0 = X / a.b, nr = a.nCB - cb0, nc = X / kRows + 1;
+  const int cb0 = X / a.b, nr = a.nCB - cb0, nc = X / a.rows + 1;
   for (int j = lane; j < nr + nc; j += 64) {
     const double* sp = j < nr ? a.rowpart + ((size_t)(cb0 + j) * T + X) * (2 * kT)
-                              : a.colpart + sym_col_slot(j - nr, X) * (2 * kT);
+                              : a.colpart + sym_col_slot(j - nr, X, a.rows) * (2 * kT);
     p1 += sp[t];
     p2 += sp[kT + t];
   }
@@ -230,6 +229,7 @@ hipError_t launch_finish_sym_mixed(const DeviceProblem& P, const SymPlan& pl,
   f.T = pl.T;
   f.b = pl.b;
   f.nCB = pl.nCB;
+  f.rows = pl.rows;
   f.lam1 = P.lam1;
   f.lam2 = P.lam2;
   f.out = out;
