@@ -115,9 +115,11 @@ __device__ __forceinline__ void pair_f32_sym(float xk, float yk, float zk, float
   const float rny = __fmaf_rn(rz, nzm, __fmaf_rn(ry, nym, rx * nxm));
   const float rnx = __fmaf_rn(rz, nzk, __fmaf_rn(ry, nyk, rx * nxk));
   const float nn = __fmaf_rn(nzk, nzm, __fmaf_rn(nyk, nym, nxk * nxm));
-  const float f1 = __fmaf_rn(-c.c1, te, 1.0f) * iR3;
-  const float f2 = __fmaf_rn(-c.c2, te, 1.0f) * iR3;
-  const float g12 = (1.0f - e) * iR;
+  // (1 - c t)/R^3 = 1/R^3 - c (t/R^3), (1 - e)/R = 1/R - e/R
+  const float t3 = te * iR3;
+  const float f1 = __fmaf_rn(-c.c1, t3, iR3);
+  const float f2 = __fmaf_rn(-c.c2, t3, iR3);
+  const float g12 = __fmaf_rn(-e, iR, iR);
   const float phi2 = 1.0f - te;
   const float q = rnx * rny;
   const float g21 = __fmaf_rn(phi2, __fmaf_rn(q * iR2, -3.0f, nn), (c.kappa2 * e) * q) * iR3;

@@ -89,10 +89,11 @@ struct Fp64 {
     const double rny = fma(rz, m.nz, fma(ry, m.ny, rx * m.nx));  // r . n_m
     const double rnx = fma(rz, f.nz, fma(ry, f.ny, rx * f.nx));  // r . n_k
     const double nn = fma(f.nz, m.nz, fma(f.ny, m.ny, f.nx * m.nx));
-    // kernel factors with 1/R^3 folded in
-    const double f1 = fma(-pc.c1, te, 1.0) * iR3;
-    const double f2 = fma(-pc.c2, te, 1.0) * iR3;
-    const double g12 = (1.0 - e) * iR;
+    // kernel factors with 1/R^3 folded in: (1 - c t)/R^3 = 1/R^3 - c (t/R^3)
+    const double t3 = te * iR3;
+    const double f1 = fma(-pc.c1, t3, iR3);
+    const double f2 = fma(-pc.c2, t3, iR3);
+    const double g12 = fma(-e, iR, iR);  // (1 - e)/R
     const double phi2 = 1.0 - te;
     const double q = rnx * rny;
     const double g21 = fma(phi2, fma(q * iR2, -3.0, nn), pc.kappa2 * e * q) * iR3;
