@@ -242,9 +242,13 @@ __global__ __launch_bounds__(256) void tree_m2m_kernel(TreeArgs a, int off) {
   }
 }
 
-// Far field of one proxy point with charges (q1, q2), given R^2 = |x - s_p|^2
-// and rn = (x - s_p).n_k (formed from per-axis terms of the proxy grid).
-__device__ __forceinline__ void far_eval(double R2, double rn, double q1, double q2,
+// Far field of one proxy point given R^2 = |x - s_p|^2 and rn = (x - s_p).n_k
+// (formed from per-axis terms of the proxy grid).  With e = e^{-kR},
+// t = e (1 + kR) and the point's charges (Q1, Q2):
+//   FA Q1 - FB Q2 = [(1 - c1 e) Q1 - (1 - e) Q2]/R = [A + e B]/R,
+//   d/dn_x FB Q1 - d/dn_x FC Q2 = (rn/R^3)[(1 - c2 t) Q2 - (1 - t) Q1] = (rn/R^3)[-A + t D],
+// A = Q1 - Q2, B = Q2 - c1 Q1, D = Q1 - c2 Q2 formed once per point.
+__device__ __forceinline__ void far_eval(double R2, double rn, double A, double B, double D,
                                          const PairConsts& c, double& S1, double& S2) {
   const double iR = rsqrt_pos(R2);
   const double R = R2 * iR;
@@ -252,17 +256,15 @@ __device__ __forceinline__ void far_eval(double R2, double rn, double q1, double
   const double e = exp_neg(kr);
   const double te = fma(e, kr, e);
   const double iR3 = iR * iR * iR;
-  // FA Q1 - FB Q2
-  S1 = fma(iR, fma(fma(-c.c1, e, 1.0), q1, -(1.0 - e) * q2), S1);
-  // d/dn_x FB Q1 - d/dn_x FC Q2, d/dn_x F = -(r.n_k)(1 - c t)/R^3
-  S2 = fma(rn * iR3, fma(fma(-c.c2, te, 1.0), q2, -(1.0 - te) * q1), S2);
+  S1 = fma(iR, fma(e, B, A), S1);
+  S2 = fma(rn * iR3, fma(te, D, -A), S2);
 }
 
 // One work item: part of one batch's far clusters and direct ranges.
 __global__ __launch_bounds__(256) void tree_item_kernel(TreeArgs a) {
-  // LDS: near sources as 8 arrays of 256, or (same buffer) the charges of a
-  // proxy cluster (Q1, Q2 interleaved), as many x-planes of its grid at a
-  // time as fit; the grid axes separately
+  // LDS: near sources as 8 arrays of 256, or (same buffer) the combined
+  // charges (A, B, D interleaved) of a proxy cluster, as many x-planes of its
+  // grid at a time as fit; the grid axes separately
   __shared__ double sh[8][256];
   __shared__ double ax[3][kTreeMaxOrder];
   const int it = a.iorder[blockIdx.x];
@@ -274,7 +276,7 @@ __global__ __launch_bounds__(256) void tree_item_kernel(TreeArgs a) {
   const double nxk = a.tnx[t], nyk = a.tny[t], nzk = a.tnz[t];
   const int n = a.order, n2 = n * n, n3 = n2 * n;
   // x-planes of the proxy grid whose charges fit in the LDS buffer at once
-  const int planes = max(1, 1024 / n2);
+  const int planes = max(1, 2048 / (3 * n2));
   double* qs = &sh[0][0];
   double S1 = 0.0, S2 = 0.0;
   // proxy clusters: points (X_i, Y_j, Z_k), so R^2 and r.n_k are built from
@@ -291,8 +293,11 @@ __global__ __launch_bounds__(256) void tree_item_kernel(TreeArgs a) {
         ax[d][i] = 0.5 * (bx[d] + bx[3 + d]) + 0.5 * (bx[3 + d] - bx[d]) * a.cheb[i];
       }
       for (int q = tid; q < (i1 - i0) * n2; q += 256) {
-        qs[2 * q] = a.pq[2 * (base + (size_t)i0 * n2 + q)];
-        qs[2 * q + 1] = a.pq[2 * (base + (size_t)i0 * n2 + q) + 1];
+        const double q1 = a.pq[2 * (base + (size_t)i0 * n2 + q)];
+        const double q2 = a.pq[2 * (base + (size_t)i0 * n2 + q) + 1];
+        qs[3 * q] = q1 - q2;
+        qs[3 * q + 1] = fma(-a.pc.c1, q1, q2);
+        qs[3 * q + 2] = fma(-a.pc.c2, q2, q1);
       }
       __syncthreads();
       for (int i = i0; i < i1; ++i) {
@@ -301,10 +306,11 @@ __global__ __launch_bounds__(256) void tree_item_kernel(TreeArgs a) {
         for (int j = 0; j < n; ++j) {
           const double ry = y - ax[1][j];
           const double axy = fma(ry, ry, rx2), bxy = fma(ry, nyk, rxn);
-          const double* q = qs + 2 * (((i - i0) * n + j) * n);
+          const double* q = qs + 3 * (((i - i0) * n + j) * n);
           for (int k = 0; k < n; ++k) {
             const double rz = z - ax[2][k];
-            far_eval(fma(rz, rz, axy), fma(rz, nzk, bxy), q[2 * k], q[2 * k + 1], a.pc, S1, S2);
+            far_eval(fma(rz, rz, axy), fma(rz, nzk, bxy), q[3 * k], q[3 * k + 1], q[3 * k + 2],
+                     a.pc, S1, S2);
           }
         }
       }
