@@ -159,6 +159,11 @@ void ibim_default_options(ibim_options* opt);
  * weights (eq. single_correction_weight, Theorem 2.1) and all per-problem
  * arrays are then built on the device on "stream".  *out receives the new
  * context (NULL on error).
+ * Device memory held by the context: O(M) geometry and corrections; for the
+ * direct pair sum, row and column partial sums of about (M/256)^2/8 x 4 KiB
+ * (0.3 GB at M = 1.2e5, 21 GB at M = 1.5e6; above 32 GiB, or if that
+ * allocation fails, a kernel with O(M) partial sums is used instead); the
+ * GMRES basis, (restart + 1) x 2M doubles, allocated at the first solve.
  */
 int ibim_setup(const double* sdf, int nx, int ny, int nz, const double origin[3], double h,
                double eps_tube, double eps_in, double eps_out, double kappa,
