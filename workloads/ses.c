@@ -71,8 +71,8 @@ static void cells_build(Cells* cl, const Ball* b, int n, double cs) {
   }
   cl->cs = cs;
   int nc = cl->n[0] * cl->n[1] * cl->n[2];
-  int* cnt = (int*)calloc(nc + 1, sizeof(int));
-  int* cid = (int*)malloc(sizeof(int) * n);
+  int* cnt = (int*)calloc((size_t)nc + 1, sizeof(int));
+  int* cid = (int*)malloc(sizeof(int) * (size_t)n);
   for (int i = 0; i < n; ++i) {
     int ci = (cell_of(cl, b[i].c, 0) * cl->n[1] + cell_of(cl, b[i].c, 1)) * cl->n[2] +
              cell_of(cl, b[i].c, 2);
@@ -81,7 +81,7 @@ static void cells_build(Cells* cl, const Ball* b, int n, double cs) {
   }
   for (int q = 0; q < nc; ++q) cnt[q + 1] += cnt[q];
   cl->start = cnt;
-  cl->idx = (int*)malloc(sizeof(int) * n);
+  cl->idx = (int*)malloc(sizeof(int) * (size_t)n);
   int* fill = (int*)calloc((size_t)nc, sizeof(int));
   for (int i = 0; i < n; ++i) cl->idx[cnt[cid[i]] + fill[cid[i]]++] = i;
   free(fill);
@@ -156,7 +156,8 @@ static int in_bubble(const GridInfo* g, const double* p) {
  */
 int ses_sdf(const double* xyz, const double* radii, int n, double probe, const double* origin,
             int nx, int ny, int nz, double h, double band, double* out) {
-  Ball* b = (Ball*)malloc(sizeof(Ball) * n);
+  if (n <= 0) return -1;
+  Ball* b = (Ball*)malloc(sizeof(Ball) * (size_t)n);
   double Rmax = 0.0;
   for (int i = 0; i < n; ++i) {
     for (int a = 0; a < 3; ++a) b[i].c[a] = xyz[3 * i + a];

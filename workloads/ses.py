@@ -94,7 +94,9 @@ def ses_grid(xyz, radii, h: float, eps_tube: float, probe=1.4, pad_nodes=4):
     band = eps_tube + (pad_nodes + 1) * h
     lib = _load()
     D = ctypes.POINTER(ctypes.c_double)
-    lib.ses_sdf(xyz.ctypes.data_as(D), radii.ctypes.data_as(D), xyz.shape[0], float(probe),
-                origin.ctypes.data_as(D), dims[0], dims[1], dims[2], float(h), float(band),
-                out.ctypes.data_as(D))
+    rc = lib.ses_sdf(xyz.ctypes.data_as(D), radii.ctypes.data_as(D), xyz.shape[0], float(probe),
+                     origin.ctypes.data_as(D), dims[0], dims[1], dims[2], float(h), float(band),
+                     out.ctypes.data_as(D))
+    if rc != 0:
+        raise ValueError("ses_sdf: needs at least one atom")
     return out, origin
