@@ -22,6 +22,7 @@
 
 #include <cstdint>
 
+#include "fastmath.h"
 #include "weights.h"
 
 namespace ibim {
@@ -36,6 +37,10 @@ constexpr int kLat = 6;
 constexpr int kSide = 2 * kLat + 1;
 constexpr int kPts = kSide * kSide;  // includes the origin, skipped
 constexpr int kWavesPerBlock = 4;
+// Reciprocals 1/(m + 3/2) of the gamma recurrences (x^s/Gamma(s+1) steps
+// from s to s + 1); indices reach kModes + the series length of step 4.
+constexpr int kRecip = 256;
+constexpr int kSeries = kRecip - kModes;
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -46,13 +51,15 @@ __device__ inline double wave_sum(double v) {
 __global__ __launch_bounds__(kWave* kWavesPerBlock) void weights_kernel(WeightArgs a) {
   __shared__ double cos_t[kSamples], sin_t[kSamples];
   __shared__ double l11s[kWavesPerBlock][kSamples], l21s[kWavesPerBlock][kSamples];
-  __shared__ double coef[kWavesPerBlock][4][kModes];
+  __shared__ double2 coef[kWavesPerBlock][kModes][2];  // (a11, b11), (a21, b21) of mode 2j
+  __shared__ double rs[kRecip];
 
   const int lane = threadIdx.x % kWave;
   const int wv = threadIdx.x / kWave;
   // angles are multiples of pi: sincospi reduces them exactly
   for (int q = threadIdx.x; q < kSamples; q += blockDim.x)
     sincospi(2.0 * q / kSamples, &sin_t[q], &cos_t[q]);
+  for (int m = threadIdx.x; m < kRecip; m += blockDim.x) rs[m] = 1.0 / (m + 1.5);
   __syncthreads();
 
   // A wavefront past the last entry recomputes the last entry and discards
@@ -106,17 +113,17 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock) void weights_kernel(WeightAr
       b21 += l21s[wv][p] * sq;
     }
     double f = (j == 0) ? 1.0 / kSamples : 2.0 / kSamples;
-    coef[wv][0][j] = a11 * f;
-    coef[wv][1][j] = b11 * f;
-    coef[wv][2][j] = a21 * f;
-    coef[wv][3][j] = b21 * f;
+    coef[wv][j][0] = make_double2(a11 * f, b11 * f);
+    coef[wv][j][1] = make_double2(a21 * f, b21 * f);
   }
   __syncthreads();
   // highest significant mode (wave-uniform): lane j holds the largest
   // coefficient of mode 2j; a mode counts if it exceeds 1e-18 of the largest
   double mj = 0.0;
-  if (lane < kModes)
-    for (int c = 0; c < 4; ++c) mj = fmax(mj, fabs(coef[wv][c][lane]));
+  if (lane < kModes) {
+    const double2 c1 = coef[wv][lane][0], c2 = coef[wv][lane][1];
+    mj = fmax(fmax(fabs(c1.x), fabs(c1.y)), fmax(fabs(c2.x), fabs(c2.y)));
+  }
   double mx = mj;
   for (int off = kWave / 2; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, kWave));
   const unsigned long long sig = __ballot(lane < kModes && mj > 1e-18 * mx);
@@ -125,6 +132,7 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock) void weights_kernel(WeightAr
   // 3. lattice sums, accumulated straight into the two weights
   double acc11 = 0.0, acc21 = 0.0;
   const double two_over_sqrtpi = 1.1283791670955126;
+  const double sqrtpi = 1.7724538509055160;
 #pragma unroll 1
   for (int idx = lane; idx < 2 * kPts; idx += kWave) {
     const int recip = idx >= kPts;
@@ -145,25 +153,25 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock) void weights_kernel(WeightAr
       sg = -1.0;  // (-i)^k = (-1)^(k/2) for even k
     }
     const double r2 = y1 * y1 + y2 * y2;
-    const double r = sqrt(r2);
+    const double ir = rsqrt_pos(r2);
+    const double r = r2 * ir;
     const double x = kPiD * r2;
-    const double sx = sqrt(x);
-    double Q = erfc(sx);                        // Q(1/2, x)
+    const double sx = sqrtpi * r;                 // sqrt(x)
+    double Q = erfc(sx);                          // Q(1/2, x)
     double term = two_over_sqrtpi * sx * exp(-x);  // x^s e^-x / Gamma(s+1), s = 1/2
-    const double ir = 1.0 / r;
     const double zr = y1 * ir, zi = y2 * ir;
-    const double z2r = zr * zr - zi * zi, z2i = 2.0 * zr * zi;
+    // e^{2i psi}, times (-i)^2 = -1 per mode step for the reciprocal sum
+    const double z2r = (zr * zr - zi * zi) * sg, z2i = 2.0 * zr * zi * sg;
     double wr = pr * ir, wi = pi * ir;  // phase * e^{ik psi} / r, k = 0
-    double s = 0.5;
     for (int j = 0; j < jmax; ++j) {
       const double cr = wr * Q, ci = wi * Q;
-      acc11 += coef[wv][0][j] * cr + coef[wv][1][j] * ci;
-      acc21 += coef[wv][2][j] * cr + coef[wv][3][j] * ci;
-      Q += term;
-      s += 1.0;
-      term *= x / s;
-      const double nr = (wr * z2r - wi * z2i) * sg;
-      const double ni = (wr * z2i + wi * z2r) * sg;
+      const double2 c1 = coef[wv][j][0], c2 = coef[wv][j][1];
+      acc11 = fma(c1.x, cr, fma(c1.y, ci, acc11));
+      acc21 = fma(c2.x, cr, fma(c2.y, ci, acc21));
+      Q += term;                 // Q(s + 1, x) = Q(s, x) + x^s e^-x / Gamma(s + 1)
+      term *= x * rs[j];         // s = j + 1/2 -> j + 3/2
+      const double nr = fma(wr, z2r, -wi * z2i);
+      const double ni = fma(wr, z2i, wi * z2r);
       wr = nr;
       wi = ni;
     }
@@ -172,27 +180,26 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock) void weights_kernel(WeightAr
   // 4. constant term and the punctured node (lane j owns mode 2j)
   const double r0 = sqrt(al * al + be * be);
   if (lane == 0) {
-    acc11 += coef[wv][0][0] * (-2.0);
-    acc21 += coef[wv][2][0] * (-2.0);
+    acc11 += coef[wv][0][0].x * (-2.0);
+    acc21 += coef[wv][0][1].x * (-2.0);
   }
   if (r0 == 0.0) {
     if (lane == 0) {  // limit of -P(1/2, pi r^2)/r; higher modes vanish
-      acc11 += coef[wv][0][0] * (-2.0);
-      acc21 += coef[wv][2][0] * (-2.0);
+      acc11 += coef[wv][0][0].x * (-2.0);
+      acc21 += coef[wv][0][1].x * (-2.0);
     }
   } else if (lane < jmax) {
+    // P(s, x0) = x0^s e^-x0 / Gamma(s + 1) * sum_l x0^l / ((s+1)...(s+l)),
+    // s = j + 1/2; |a| <= 1/sqrt(2) keeps x0 <= pi/2, so the series has
+    // converged to 1e-18 long before kSeries terms.
     const int j = lane;
     const double x0 = kPiD * r0 * r0;
-    double sj = 0.5;
-    double pref = two_over_sqrtpi * sqrt(x0) * exp(-x0);
-    for (int t = 0; t < j; ++t) {
-      pref *= x0 / (sj + 1.0);
-      sj += 1.0;
-    }
+    double pref = two_over_sqrtpi * sqrtpi * r0 * exp(-x0);
+    for (int t = 0; t < j; ++t) pref *= x0 * rs[t];
     double sum = 0.0, tt = 1.0;
-    for (int l = 0; l < 200; ++l) {
+    for (int l = 0; l < kSeries; ++l) {
       sum += tt;
-      tt *= x0 / (sj + 1.0 + l);
+      tt *= x0 * rs[j + l];
       if (tt < 1e-18 * sum) break;
     }
     const double Pv = pref * sum;
@@ -207,8 +214,9 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock) void weights_kernel(WeightAr
       zki = ni;
     }
     const double cr = -zkr * Pv / r0, ci = -zki * Pv / r0;
-    acc11 += coef[wv][0][j] * cr + coef[wv][1][j] * ci;
-    acc21 += coef[wv][2][j] * cr + coef[wv][3][j] * ci;
+    const double2 c1 = coef[wv][j][0], c2 = coef[wv][j][1];
+    acc11 += c1.x * cr + c1.y * ci;
+    acc21 += c2.x * cr + c2.y * ci;
   }
 
   const double z11 = wave_sum(acc11);
