@@ -109,18 +109,23 @@ def serve_bench(args):
     import numpy as np
 
     import workloads
-    from paper_2210_03699_amd import FP64, MIXED, REQ_DONE, REQ_FAILED, Server
+    from paper_2210_03699_amd import (FP64, MIXED, REQ_DONE, REQ_FAILED, SUM_DIRECT, SUM_TREE,
+                                      Server)
 
     mode = FP64 if args.precision == "fp64" else MIXED
+    summation = SUM_TREE if args.summation == "tree" else SUM_DIRECT
+    hs = tuple(float(v) for v in args.hs.split(","))
+    atoms = tuple(int(v) for v in args.ses_atoms.split(","))
     t = time.perf_counter()
-    reqs = workloads.serving_stream(args.requests, seed=4)
+    reqs = workloads.serving_stream(args.requests, seed=4, hs=hs, ses_atoms=atoms)
     print(f"[serve] generated {len(reqs)} requests in {time.perf_counter() - t:.1f}s",
           file=sys.stderr, flush=True)
     budget = int(args.hbm_budget_gib * (1 << 30))
 
     def run(arrivals):
         srv = Server(budget, max_slots=args.slots, host_threads=args.host_threads,
-                     precision=mode)
+                     precision=mode, summation=summation, tree_order=args.tree_order,
+                     tree_theta=args.tree_theta, tree_min_nodes=args.tree_min_nodes)
         order = np.argsort(arrivals, kind="stable")
         tickets, t_arr, t_done = {}, {}, {}
         nxt = 0
@@ -165,6 +170,7 @@ def serve_bench(args):
     lat = [r["latency"] for r in res2]
     pairs = sum(float(r["applies"]) * r["M"] * r["M"] for r in res2)
     Ms = sorted(r["M"] for r in res2)
+    n_tree = sum(1 for m in Ms if summation == SUM_TREE and m >= args.tree_min_nodes)
     out = {
         "metric": METRIC,
         "value": pairs / mk2,
@@ -180,9 +186,14 @@ def serve_bench(args):
         "data": "synthetic",
         "config": {
             "workload": f"serving_stream_{len(reqs)}", "seed": 4, "tol": 1e-6,
-            "spheres": "R~U[2,10], 1..30 charges", "ses": "50..200 atoms",
-            "h": [0.3, 0.5], "eps_tube": "2h", "slots": args.slots,
+            "spheres": "R~U[2,10], 1..30 charges", "ses": f"{atoms[0]}..{atoms[1]} atoms",
+            "h": list(hs), "eps_tube": "2h", "slots": args.slots,
             "hbm_budget_gib": args.hbm_budget_gib, "pair_kernel": args.precision,
+            "summation": args.summation,
+            **({"tree_min_nodes": args.tree_min_nodes, "tree_order": args.tree_order,
+                "tree_theta": args.tree_theta, "tree_requests": n_tree,
+                "pairs": "M^2 per application whichever summation"}
+               if summation == SUM_TREE else {}),
             "M_min": Ms[0], "M_median": Ms[len(Ms) // 2], "M_max": Ms[-1],
         },
         "solves_per_s": len(reqs) / mk2,
@@ -230,6 +241,13 @@ def main():
     ap.add_argument("--slots", type=int, default=16)
     ap.add_argument("--host-threads", type=int, default=8)
     ap.add_argument("--hbm-budget-gib", type=float, default=64.0)
+    ap.add_argument("--hs", default="0.3,0.5",
+                    help="--serve: grid spacings the stream draws from (comma list)")
+    ap.add_argument("--ses-atoms", default="50,200",
+                    help="--serve: atom-count range of the stream's molecules")
+    ap.add_argument("--tree-min-nodes", type=int, default=0,
+                    help="with --summation tree: requests below this many nodes keep the "
+                         "direct sum (and --precision)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)

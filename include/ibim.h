@@ -71,6 +71,8 @@ typedef struct {
   int summation;       /* IBIM_SUM_DIRECT (default) or IBIM_SUM_TREE, below */
   int tree_order;      /* IBIM_SUM_TREE: Chebyshev points per dimension, 2..12 (default 8) */
   double tree_theta;   /* IBIM_SUM_TREE: separation parameter, (0, 1] (default 0.7) */
+  int64_t tree_min_nodes; /* IBIM_SUM_TREE: problems with fewer tube nodes use the
+                             direct sum instead (default 0: every problem) */
 } ibim_options;
 
 /*
@@ -90,9 +92,14 @@ typedef struct {
  *                   than tree_order^3 nodes and the box gap exceeds the largest
  *                   corrected-pair distance.  An approximation: its error falls
  *                   geometrically with tree_order and with smaller tree_theta.
- *                   Float64 only (IBIM_MIXED is rejected); not accepted by the
- *                   solve server.  The corrections, GMRES and energy are those
- *                   of the direct path.
+ *                   The treecode evaluates in float64.  A problem with fewer
+ *                   than tree_min_nodes tube nodes is summed directly in the
+ *                   requested precision; IBIM_MIXED with IBIM_SUM_TREE is
+ *                   accepted only with tree_min_nodes > 0 (it then means: mixed
+ *                   direct sums below the threshold, the float64 treecode at or
+ *                   above it).  The solve server applies the same rule per
+ *                   request.  The corrections, GMRES and energy are those of
+ *                   the direct path.
  */
 #define IBIM_SUM_DIRECT 0
 #define IBIM_SUM_TREE 1
@@ -175,6 +182,14 @@ void ibim_destroy(ibim_ctx* ctx);
 
 /* Thread-local message describing the last error (never NULL). */
 const char* ibim_last_error(void);
+
+/*
+ * The options this context runs with (host, one struct): those given to
+ * ibim_setup except where IBIM_SUM_TREE was resolved for the problem's size
+ * (summation IBIM_SUM_DIRECT below tree_min_nodes; precision IBIM_FP64 when
+ * the treecode is used).
+ */
+int ibim_context_options(const ibim_ctx* ctx, ibim_options* opt);
 
 /* Number of tube nodes M (unknowns are 2M). */
 int ibim_num_nodes(const ibim_ctx* ctx, int64_t* M);
@@ -325,7 +340,9 @@ int ibim_tree_plan(const ibim_ctx* ctx, int64_t* counts, int32_t* perm, int32_t*
  *      HBM budget (a request that does not fit lets later smaller ones pass);
  *   2. ONE persistent batched pair-kernel launch covers a work list of
  *      (request, target tile, source chunk) items of every active solve; each
- *      item is computed exactly as in the single-problem kernel;
+ *      item is computed exactly as in the single-problem kernel.  Requests
+ *      that the options send to the treecode (IBIM_SUM_TREE, at least
+ *      tree_min_nodes nodes) run their treecode launches after it instead;
  *   3. per request: sparse correction, one GMRES (Arnoldi + Givens) step or a
  *      residual step, all on the device, then a single status read-back;
  *   4. finished solves compute G_pol (eq. pol-energy), keep their solution on
@@ -352,7 +369,9 @@ typedef struct {
 #define IBIM_REQ_FAILED (-1)
 
 /* opt: solver options of every request (precision, restart, max_iter,
- * check_residual, device, r_near); hbm_budget_bytes > 0; max_slots >= 1
+ * check_residual, device, r_near, hybrid, precond, summation and the
+ * treecode fields, resolved per request by its size as in ibim_setup;
+ * validated as there); hbm_budget_bytes > 0; max_slots >= 1
  * concurrent solves; host_threads >= 1 background setup threads; stream:
  * the hipStream_t every round runs on (NULL: the null stream). */
 int ibim_server_create(const ibim_options* opt, size_t hbm_budget_bytes, int max_slots,

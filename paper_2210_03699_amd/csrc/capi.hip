@@ -211,16 +211,8 @@ int ensure_krylov(ibim_ctx* c) {
   return IBIM_OK;
 }
 
-// Copies n device doubles to the pinned mirror and waits for them.
-int ctx_create_host(const double* sdf, int nx, int ny, int nz, const double origin[3], double h,
-                    double eps_tube, double eps_in, double eps_out, double kappa,
-                    const double* charge_xyz, const double* charge_q, int n_charges,
-                    const ibim_options& o, ibim_ctx** out) {
-  *out = nullptr;
-  if (!(eps_in > 0) || !(eps_out > 0) || !(kappa >= 0) || !std::isfinite(kappa))
-    return fail(IBIM_EINVAL, "eps_in, eps_out must be > 0 and kappa >= 0");
-  if (n_charges < 0 || (n_charges > 0 && (!charge_xyz || !charge_q)))
-    return fail(IBIM_EINVAL, "bad charge arrays");
+// Checks the options shared by ibim_setup and the solve server.
+int check_options(const ibim_options& o) {
   if (o.precision != IBIM_FP64 && o.precision != IBIM_MIXED)
     return fail(IBIM_EINVAL, "unknown precision mode");
   if (!(o.r_near >= 0.0) || !std::isfinite(o.r_near))
@@ -233,13 +225,31 @@ int ctx_create_host(const double* sdf, int nx, int ny, int nz, const double orig
     return fail(IBIM_EINVAL, "unknown preconditioning mode");
   if (o.summation != IBIM_SUM_DIRECT && o.summation != IBIM_SUM_TREE)
     return fail(IBIM_EINVAL, "unknown summation mode");
+  if (o.tree_min_nodes < 0) return fail(IBIM_EINVAL, "tree_min_nodes must be >= 0");
   if (o.summation == IBIM_SUM_TREE) {
-    if (o.precision != IBIM_FP64) return fail(IBIM_EINVAL, "the treecode runs in float64 only");
+    if (o.precision != IBIM_FP64 && o.tree_min_nodes == 0)
+      return fail(IBIM_EINVAL,
+                  "the treecode runs in float64 only (IBIM_MIXED needs tree_min_nodes > 0)");
     if (o.tree_order < 2 || o.tree_order > ibim::kTreeMaxOrder)
       return fail(IBIM_EINVAL, "tree_order must be in [2, 12]");
     if (!(o.tree_theta > 0.0 && o.tree_theta <= 1.0))
       return fail(IBIM_EINVAL, "tree_theta must be in (0, 1]");
   }
+  return IBIM_OK;
+}
+
+// Host part of ibim_setup: the geometry, the correction sets and, for the
+// treecode, its plan; IBIM_SUM_TREE is resolved here for the problem's size.
+int ctx_create_host(const double* sdf, int nx, int ny, int nz, const double origin[3], double h,
+                    double eps_tube, double eps_in, double eps_out, double kappa,
+                    const double* charge_xyz, const double* charge_q, int n_charges,
+                    const ibim_options& o, ibim_ctx** out) {
+  *out = nullptr;
+  if (!(eps_in > 0) || !(eps_out > 0) || !(kappa >= 0) || !std::isfinite(kappa))
+    return fail(IBIM_EINVAL, "eps_in, eps_out must be > 0 and kappa >= 0");
+  if (n_charges < 0 || (n_charges > 0 && (!charge_xyz || !charge_q)))
+    return fail(IBIM_EINVAL, "bad charge arrays");
+  if (int r = check_options(o)) return r;
   ibim_ctx* c = new (std::nothrow) ibim_ctx();
   if (!c) return fail(IBIM_ENOMEM, "host allocation failed");
   c->opt = o;
@@ -256,6 +266,13 @@ int ctx_create_host(const double* sdf, int nx, int ny, int nz, const double orig
   std::string err;
   int r = build_host_plan(sdf, nx, ny, nz, origin, h, eps_tube, o.hybrid, &c->plan, &err);
   if (!r && o.summation == IBIM_SUM_TREE) {
+    // the treecode serves problems of at least tree_min_nodes nodes, in float64
+    if ((int64_t)c->plan.M < o.tree_min_nodes)
+      c->opt.summation = IBIM_SUM_DIRECT;
+    else
+      c->opt.precision = IBIM_FP64;
+  }
+  if (!r && c->opt.summation == IBIM_SUM_TREE) {
     TreeParams prm;
     prm.order = o.tree_order;
     prm.theta = o.tree_theta;
@@ -283,7 +300,9 @@ size_t ctx_footprint_estimate(const ibim_ctx* c) {
   b += (ntile + 1) * 4 + std::min(nnz, ntile * ntile) * 4;
   b += (4 * nc + (nc > 0 ? nc : 1)) * 8;
   const SymPlan sp = make_sym_plan((int32_t)M, kSymScratchMax);
-  if (sp.enabled)
+  if (c->opt.summation == IBIM_SUM_TREE)
+    b += tree_device_bytes(c->tplan);
+  else if (sp.enabled)
     b += sp.scratch_doubles * 8 + ((size_t)sp.nRB * sp.nCB * 2 + 2) * 4 +
          (((size_t)sp.T * sp.T + 31) / 32) * 4;
   else
@@ -545,6 +564,7 @@ void ibim_default_options(ibim_options* opt) {
   opt->summation = IBIM_SUM_DIRECT;
   opt->tree_order = 8;
   opt->tree_theta = 0.7;
+  opt->tree_min_nodes = 0;
 }
 
 const char* ibim_last_error(void) { return g_last_error.c_str(); }
@@ -579,6 +599,13 @@ void ibim_destroy(ibim_ctx* ctx) {
   if (!ctx) return;
   ctx->release();
   delete ctx;
+}
+
+int ibim_context_options(const ibim_ctx* ctx, ibim_options* opt) {
+  if (int r = check_ctx(ctx)) return r;
+  if (!opt) return fail(IBIM_EINVAL, "opt is NULL");
+  *opt = ctx->opt;
+  return IBIM_OK;
 }
 
 int ibim_num_nodes(const ibim_ctx* ctx, int64_t* M) {

@@ -131,6 +131,8 @@ struct ibim_ctx {
 
 namespace ibim {
 
+// Validates options (IBIM_EINVAL with a message for the first bad field).
+int check_options(const ibim_options& o);
 // Host part of ibim_setup: validates, builds the geometry and correction sets.
 int ctx_create_host(const double* sdf, int nx, int ny, int nz, const double origin[3], double h,
                     double eps_tube, double eps_in, double eps_out, double kappa,

@@ -4,7 +4,8 @@
 // (geometry and correction sets) -> waiting for admission -> active (device
 // data, Krylov basis) -> done (G_pol and the solution kept on the host) or
 // failed.  Each round does one persistent batched pair-kernel launch over the
-// work items of every active solve, then the per-request GMRES step.  The
+// work items of every active direct-sum solve, then per request the treecode
+// launches (requests that the options send to it) and the GMRES step.  The
 // per-request sequence of kernels and their inputs are those of ibim_solve
 // and ibim_energy, so results do not depend on the mix of requests.
 #include <hip/hip_runtime.h>
@@ -318,6 +319,7 @@ int step_impl(ibim_server* srv) {
   size_t nargs = 0, nitems = 0, nsargs = 0, nswork = 0;
   for (Request* r : srv->active) {
     const ibim_ctx* c = r->ctx;
+    if (c->opt.summation == IBIM_SUM_TREE) continue;  // summed on its own in step 3
     if (c->sym.enabled) {
       ++nsargs;
       nswork += (size_t)c->n_sym_items;
@@ -333,6 +335,7 @@ int step_impl(ibim_server* srv) {
   size_t ia = 0, it = 0, isa = 0, isw = 0;
   for (Request* r : srv->active) {
     ibim_ctx* c = r->ctx;
+    if (c->opt.summation == IBIM_SUM_TREE) continue;
     const int64_t N = c->kr.n;
     const double* u = r->phase == Phase::kIter ? c->kr.V + (int64_t)r->j * N : r->d_x;
     if (c->sym.enabled) {
@@ -396,7 +399,11 @@ int step_impl(ibim_server* srv) {
     double* st = srv->d_status + (size_t)r->slot * kStatusStride;
     const double* u = r->phase == Phase::kIter ? K.V + (int64_t)r->j * N : r->d_x;
     double* out = r->phase == Phase::kIter ? K.V + (int64_t)(r->j + 1) * N : K.tmp2;
-    if (c->sym.enabled && c->opt.precision == IBIM_MIXED)
+    if (c->opt.summation == IBIM_SUM_TREE) {
+      // large requests: the treecode's own launches, queued behind the batched ones
+      HIP_TRY(launch_tree_sum(c->tree, c->P, u, s), "treecode launch");
+      HIP_TRY(launch_tree_finish(c->tree, c->P, u, out, s), "finish");
+    } else if (c->sym.enabled && c->opt.precision == IBIM_MIXED)
       HIP_TRY(launch_finish_sym_mixed(c->P, c->sym, c->d_careful, u, c->sym_scratch, out, s),
               "finish");
     else if (c->sym.enabled)
@@ -529,12 +536,7 @@ int ibim_server_create(const ibim_options* opt, size_t hbm_budget_bytes, int max
   ibim_default_options(&o);
   if (opt) o = *opt;
   if (o.device < 0) return fail(IBIM_EINVAL, "the server needs a device (options.device >= 0)");
-  if (o.precision != IBIM_FP64 && o.precision != IBIM_MIXED)
-    return fail(IBIM_EINVAL, "unknown precision mode");
-  if (o.summation != IBIM_SUM_DIRECT)
-    return fail(IBIM_EINVAL, "the server batches direct pair sums only (summation must be IBIM_SUM_DIRECT)");
-  if (o.restart < 1 || o.restart > 1000 || o.max_iter < 1)
-    return fail(IBIM_EINVAL, "restart must be in [1, 1000] and max_iter >= 1");
+  if (int r = check_options(o)) return r;
   ibim_server* srv = new (std::nothrow) ibim_server();
   if (!srv) return fail(IBIM_ENOMEM, "host allocation failed");
   srv->opt = o;

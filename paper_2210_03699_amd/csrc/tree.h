@@ -66,4 +66,8 @@ int build_tree_plan(const TreeParams& prm, int64_t M, const double* px, const do
                     const double* pz, const int64_t* crow, const int32_t* ccol, double h,
                     TreePlan* plan, std::string* err);
 
+// Device bytes that uploading the plan allocates (index arrays, permuted
+// geometry, Chebyshev tables, proxy charges and per-item partial sums).
+size_t tree_device_bytes(const TreePlan& plan);
+
 }  // namespace ibim

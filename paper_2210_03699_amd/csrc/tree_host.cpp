@@ -315,4 +315,16 @@ int build_tree_plan(const TreeParams& prm, int64_t M64, const double* px, const 
   return IBIM_OK;
 }
 
+size_t tree_device_bytes(const TreePlan& pl) {
+  const size_t n = (size_t)pl.order, n3 = n * n * n, M = (size_t)pl.M;
+  const size_t ints = pl.perm.size() + pl.pos.size() + pl.bstart.size() + pl.dstart.size() +
+                      pl.dend.size() + pl.kid.size() + pl.mlist.size() + pl.ibatch.size() +
+                      pl.ifar0.size() + pl.ifar1.size() + pl.inear0.size() + pl.inear1.size() +
+                      pl.istart.size() + pl.iorder.size() + pl.fcol.size() + pl.nlo.size() +
+                      pl.nhi.size() + pl.xrow.size() + pl.xcol.size();
+  const size_t dbls = pl.pbox.size() + (2 * n + n * n) + 9 * M + pl.pstart.size() * n3 * 2 +
+                      pl.ibatch.size() * 2 * (size_t)kTreeBatch;
+  return ints * 4 + dbls * 8;
+}
+
 }  // namespace ibim

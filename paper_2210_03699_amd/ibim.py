@@ -42,7 +42,8 @@ class _Options(ctypes.Structure):
                 ("check_residual", ctypes.c_int), ("device", ctypes.c_int),
                 ("r_near", ctypes.c_double), ("hybrid", ctypes.c_int),
                 ("precond", ctypes.c_int), ("summation", ctypes.c_int),
-                ("tree_order", ctypes.c_int), ("tree_theta", ctypes.c_double)]
+                ("tree_order", ctypes.c_int), ("tree_theta", ctypes.c_double),
+                ("tree_min_nodes", ctypes.c_int64)]
 
 
 class _SolveInfo(ctypes.Structure):
@@ -100,6 +101,7 @@ def load():
     lib.ibim_destroy.argtypes = [_VP]
     lib.ibim_destroy.restype = None
     lib.ibim_num_nodes.argtypes = [_VP, _I64]
+    lib.ibim_context_options.argtypes = [_VP, ctypes.POINTER(_Options)]
     lib.ibim_node_grid_index.argtypes = [_VP, _I64]
     lib.ibim_node_geometry.argtypes = [_VP, _D, _D, _D]
     lib.ibim_num_corrections.argtypes = [_VP, _I64]
@@ -168,7 +170,7 @@ class Problem:
     def __init__(self, sdf, origin, h, eps_tube, eps_in, eps_out, kappa, charge_xyz=None,
                  charge_q=None, precision=FP64, restart=60, max_iter=300, check_residual=True,
                  device=0, r_near=0.0, hybrid=CTR2, precond=PRECOND_DIAG, summation=SUM_DIRECT,
-                 tree_order=8, tree_theta=0.7, stream=None):
+                 tree_order=8, tree_theta=0.7, tree_min_nodes=0, stream=None):
         lib = load()
         self._lib = lib
         sdf = np.ascontiguousarray(sdf, dtype=np.float64)
@@ -193,6 +195,7 @@ class Problem:
         opt.summation = int(summation)
         opt.tree_order = int(tree_order)
         opt.tree_theta = float(tree_theta)
+        opt.tree_min_nodes = int(tree_min_nodes)
         self.device = int(device)
         self.h = float(h)
         ctx = ctypes.c_void_p()
@@ -208,6 +211,12 @@ class Problem:
         nnz = ctypes.c_int64()
         _check(lib.ibim_num_corrections(ctx, ctypes.byref(nnz)))
         self.nnz = int(nnz.value)
+        eff = _Options()
+        _check(lib.ibim_context_options(ctx, ctypes.byref(eff)))
+        #: summation and precision this problem runs with (IBIM_SUM_TREE is
+        #: resolved by size: direct below tree_min_nodes, float64 treecode above)
+        self.summation = int(eff.summation)
+        self.precision = int(eff.precision)
 
     @classmethod
     def from_workload(cls, wl, **kw):
@@ -369,7 +378,8 @@ class Server:
 
     def __init__(self, hbm_budget_bytes, max_slots=16, host_threads=4, precision=FP64,
                  restart=60, max_iter=300, check_residual=True, device=0, r_near=0.0,
-                 hybrid=CTR2, precond=PRECOND_DIAG, summation=SUM_DIRECT, stream=None):
+                 hybrid=CTR2, precond=PRECOND_DIAG, summation=SUM_DIRECT, tree_order=8,
+                 tree_theta=0.7, tree_min_nodes=0, stream=None):
         lib = load()
         self._lib = lib
         opt = _Options()
@@ -383,6 +393,9 @@ class Server:
         opt.hybrid = int(hybrid)
         opt.precond = int(precond)
         opt.summation = int(summation)
+        opt.tree_order = int(tree_order)
+        opt.tree_theta = float(tree_theta)
+        opt.tree_min_nodes = int(tree_min_nodes)
         srv = ctypes.c_void_p()
         _check(lib.ibim_server_create(ctypes.byref(opt), int(hbm_budget_bytes), int(max_slots),
                                       int(host_threads), _stream_ptr(stream), ctypes.byref(srv)))

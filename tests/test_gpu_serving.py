@@ -103,6 +103,45 @@ def test_alone_equals_mixed_equals_direct(wls, precision, restart, hybrid):
         _say(f"[serving] {n}: iters={mixed[n][2]['iters']} G={mixed[n][0]:.12e}")
 
 
+def test_tree_requests_in_the_mix(wls):
+    """With IBIM_SUM_TREE and a size threshold, requests of at least
+    tree_min_nodes nodes run the float64 treecode inside the rounds and the
+    others the batched mixed kernel.  Every result is the same bits alone, in
+    the mix and through ibim_solve with the same options, and the treecode's
+    energies are within the treecode's error of the float64 direct solve."""
+    pool = dict(wls)
+    pool["kirkwood_r6"] = workloads.kirkwood_sphere(h=0.25, radius=6.0, r_charges=4.5,
+                                                    n_charges=8, seed=3, tol=1e-8)
+    sizes = {}
+    for n, w in pool.items():
+        p = ibim.Problem.from_workload(w, device=-1)
+        sizes[n] = p.M
+        p.close()
+    thr = sorted(sizes.values())[len(sizes) // 2]
+    opt = dict(precision=ibim.MIXED, summation=ibim.SUM_TREE, tree_min_nodes=thr)
+    names = list(pool)
+    _say(f"[serving] tree threshold {thr}: sizes {sizes}")
+    mixed, stats = _serve(pool, names, **opt)
+    assert stats["finished"] == len(names) and stats["failed"] == 0
+    assert stats["bytes_in_use"] == 0
+    n_tree = 0
+    for n in names:
+        p = ibim.Problem.from_workload(pool[n], device=-1, **opt)
+        tree = p.summation == ibim.SUM_TREE
+        p.close()
+        assert tree == (sizes[n] >= thr), n
+        n_tree += tree
+        alone, _ = _serve(pool, [n], slots=1, **opt)
+        _same(alone[n], mixed[n], f"{n} alone vs mix (tree={tree})")
+        _same(_direct(pool[n], **opt), mixed[n], f"{n} ibim_solve vs server (tree={tree})")
+        assert mixed[n][2]["converged"], n
+        if tree:
+            g64 = _direct(pool[n])[0]
+            _say(f"[serving] {n}: treecode G={mixed[n][0]:.12e} direct fp64 G={g64:.12e}")
+            assert abs(mixed[n][0] - g64) <= 1e-6 * abs(g64), n
+    assert 0 < n_tree < len(names)
+
+
 def test_energy_matches_oracle(wls):
     wl = wls["kirkwood_small"]
     out, _ = _serve(wls, ["kirkwood_small", "born_h0.4"])

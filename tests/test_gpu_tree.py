@@ -138,5 +138,7 @@ def test_tree_options_rejected():
         ibim.Problem.from_workload(wl, device=0, summation=ibim.SUM_TREE, precision=ibim.MIXED)
     with pytest.raises(ibim.IbimError):
         ibim.Problem.from_workload(wl, device=0, summation=ibim.SUM_TREE, tree_order=13)
+    with pytest.raises(ibim.IbimError):  # the server validates as ibim_setup does
+        ibim.Server(1 << 30, summation=ibim.SUM_TREE, precision=ibim.MIXED)
     with pytest.raises(ibim.IbimError):
-        ibim.Server(1 << 30, summation=ibim.SUM_TREE)
+        ibim.Server(1 << 30, summation=ibim.SUM_TREE, tree_theta=0.0)

@@ -14,6 +14,7 @@ from paper_2210_03699_amd import ibim
     {"summation": ibim.SUM_TREE, "tree_theta": 0.0},
     {"summation": ibim.SUM_TREE, "tree_theta": 1.5},
     {"summation": 2},
+    {"summation": ibim.SUM_TREE, "tree_min_nodes": -1},
 ])
 def test_bad_tree_options_rejected(kw):
     wl = workloads.born_sphere(h=0.4)
@@ -26,6 +27,30 @@ def test_tree_options_accepted_on_host():
     p = ibim.Problem.from_workload(wl, device=-1, summation=ibim.SUM_TREE, tree_order=6,
                                    tree_theta=0.5)
     assert p.M > 0
+    p.close()
+
+
+def test_tree_resolved_by_size():
+    """IBIM_SUM_TREE serves problems of at least tree_min_nodes nodes, in float64;
+    smaller ones keep the direct sum in the requested precision."""
+    wl = workloads.born_sphere(h=0.4)
+    p = ibim.Problem.from_workload(wl, device=-1, summation=ibim.SUM_TREE)
+    assert (p.summation, p.precision) == (ibim.SUM_TREE, ibim.FP64)
+    M = p.M
+    p.close()
+    p = ibim.Problem.from_workload(wl, device=-1, summation=ibim.SUM_TREE, tree_min_nodes=M)
+    assert (p.summation, p.precision) == (ibim.SUM_TREE, ibim.FP64)
+    p.tree_plan()  # a treecode context has a plan
+    p.close()
+    p = ibim.Problem.from_workload(wl, device=-1, summation=ibim.SUM_TREE, tree_min_nodes=M,
+                                   precision=ibim.MIXED)
+    assert (p.summation, p.precision) == (ibim.SUM_TREE, ibim.FP64)
+    p.close()
+    p = ibim.Problem.from_workload(wl, device=-1, summation=ibim.SUM_TREE,
+                                   tree_min_nodes=M + 1, precision=ibim.MIXED)
+    assert (p.summation, p.precision) == (ibim.SUM_DIRECT, ibim.MIXED)
+    with pytest.raises(ibim.IbimError):
+        p.tree_plan()  # not a treecode context
     p.close()
 
 
