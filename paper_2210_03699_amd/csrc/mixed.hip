@@ -14,6 +14,7 @@
 // float64.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <cstdint>
@@ -199,12 +200,16 @@ struct NearArgs {
   int32_t* col;           // fill pass only
 };
 
-// One thread per row: nodes within the offset ball, closer than r_near in
-// float64, not corrected by the row (fill == false counts, true writes).
+// One wavefront per row: nodes within the offset ball, closer than r_near in
+// float64, not corrected by the row (fill == false counts, true writes).  The
+// lanes take consecutive cells of the offset cube [-W, W]^3, clipped to the
+// grid, in (di, dj, dl) order and a ballot compacts the hits, so each row's
+// list is in cell order.
 template <bool kFill>
 __global__ __launch_bounds__(256) void near_kernel(NearArgs a) {
-  const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= a.M) return;
+  const int lane = threadIdx.x & 63;
+  const int32_t k = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (k >= a.M) return;  // whole wavefronts
   const int64_t q = a.grid_index[k];
   const int i = (int)(q / ((int64_t)a.ny * a.nz));
   const int j = (int)((q / a.nz) % a.ny);
@@ -214,28 +219,42 @@ __global__ __launch_bounds__(256) void near_kernel(NearArgs a) {
   int64_t out = kFill ? a.rowptr[k] : 0;
   int32_t cnt = 0;
   const int W = a.W;
-  for (int di = -W; di <= W; ++di) {
-    const int ii = i + di;
-    if (ii < 0 || ii >= a.nx) continue;
-    for (int dj = -W; dj <= W; ++dj) {
-      const int jj = j + dj;
-      if (jj < 0 || jj >= a.ny || di * di + dj * dj > W * W) continue;
-      for (int dl = -W; dl <= W; ++dl) {
-        const int ll = l + dl;
-        if (ll < 0 || ll >= a.nz || di * di + dj * dj + dl * dl > W * W) continue;
-        const int32_t m = a.node_of[((int64_t)ii * a.ny + jj) * a.nz + ll];
-        if (m < 0) continue;
+  const int i0 = max(-W, -i), j0 = max(-W, -j), l0 = max(-W, -l);
+  const int si = min(W, a.nx - 1 - i) - i0 + 1, sj = min(W, a.ny - 1 - j) - j0 + 1,
+            sl = min(W, a.nz - 1 - l) - l0 + 1;
+  const int ncell = si * sj * sl;  // below 2^31: the grid is (host check)
+  // this lane's cell (ci, cj, cl) in the mixed radix (si, sj, sl), advanced by
+  // 64 cells per step as the digits (ai, aj, al) with carries
+  int cl = lane % sl, cj = (lane / sl) % sj, ci = lane / (sl * sj);
+  const int al = 64 % sl, aj = (64 / sl) % sj, ai = 64 / (sl * sj);
+  for (int base = 0; base < ncell; base += 64) {
+    bool hit = false;
+    int32_t m = -1;
+    const int di = i0 + ci, dj = j0 + cj, dl = l0 + cl;
+    if (base + lane < ncell && di * di + dj * dj + dl * dl <= W * W) {
+      m = a.node_of[((int64_t)(i + di) * a.ny + (j + dj)) * a.nz + (l + dl)];
+      if (m >= 0) {
         const double rx = x - a.px[m], ry = y - a.py[m], rz = z - a.pz[m];
-        if (rx * rx + ry * ry + rz * rz >= a.rn2) continue;
-        bool corrected = false;
-        for (int32_t e = c0; e < c1; ++e) corrected |= (a.ccol[e] == m);
-        if (corrected) continue;
-        if (kFill) a.col[out++] = m;
-        ++cnt;
+        if (rx * rx + ry * ry + rz * rz < a.rn2) {
+          bool corrected = false;
+          for (int32_t e = c0; e < c1; ++e) corrected |= (a.ccol[e] == m);
+          hit = !corrected;
+        }
       }
     }
+    cl += al;
+    int carry = cl >= sl;
+    cl -= carry ? sl : 0;
+    cj += aj + carry;
+    carry = cj >= sj;
+    cj -= carry ? sj : 0;
+    ci += ai + carry;
+    const unsigned long long mask = __ballot(hit);
+    if (kFill && hit) a.col[out + __popcll(mask & ((1ull << lane) - 1ull))] = m;
+    out += __popcll(mask);
+    cnt += __popcll(mask);
   }
-  if (!kFill) a.count[k] = cnt;
+  if (!kFill && lane == 0) a.count[k] = cnt;
 }
 
 }  // namespace
@@ -302,10 +321,14 @@ hipError_t build_near_list(DeviceProblem& P, const int32_t* node_of, const int64
   a.crow = P.crow;
   a.ccol = P.ccol;
   a.nx = nx; a.ny = ny; a.nz = nz;
-  a.W = (int)std::ceil((r_near + 2.0 * eps) / P.h);
+  if ((int64_t)nx * ny * nz >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  // reach in cells, capped by the grid diagonal (every grid cell is within it)
+  const double reach = std::ceil((r_near + 2.0 * eps) / P.h);
+  const double diag = std::ceil(std::sqrt((double)nx * nx + (double)ny * ny + (double)nz * nz));
+  a.W = (int)std::min(reach, diag);
   a.rn2 = r_near * r_near;
   a.M = P.M;
-  const unsigned blocks = (unsigned)((P.M + 255) / 256);
+  const unsigned blocks = (unsigned)((P.M + 3) / 4);  // four rows (wavefronts) per block
   int32_t* d_count = nullptr;
   hipError_t e = hipMalloc((void**)&d_count, sizeof(int32_t) * (size_t)P.M);
   if (e != hipSuccess) return e;
