@@ -92,14 +92,14 @@ typedef struct {
  *                   than tree_order^3 nodes and the box gap exceeds the largest
  *                   corrected-pair distance.  An approximation: its error falls
  *                   geometrically with tree_order and with smaller tree_theta.
- *                   The treecode evaluates in float64.  A problem with fewer
- *                   than tree_min_nodes tube nodes is summed directly in the
- *                   requested precision; IBIM_MIXED with IBIM_SUM_TREE is
- *                   accepted only with tree_min_nodes > 0 (it then means: mixed
- *                   direct sums below the threshold, the float64 treecode at or
- *                   above it).  The solve server applies the same rule per
- *                   request.  The corrections, GMRES and energy are those of
- *                   the direct path.
+ *                   With IBIM_FP64 all of it is float64; with IBIM_MIXED the
+ *                   target-proxy evaluations run in float32 (on float64-formed
+ *                   differences, summed in float32 over n proxies, then in
+ *                   float64) while the direct part and the proxy charges stay
+ *                   float64.  A problem with fewer than tree_min_nodes tube
+ *                   nodes is summed directly instead, in the same precision;
+ *                   the solve server applies this rule per request.  The
+ *                   corrections, GMRES and energy are those of the direct path.
  */
 #define IBIM_SUM_DIRECT 0
 #define IBIM_SUM_TREE 1
@@ -185,9 +185,8 @@ const char* ibim_last_error(void);
 
 /*
  * The options this context runs with (host, one struct): those given to
- * ibim_setup except where IBIM_SUM_TREE was resolved for the problem's size
- * (summation IBIM_SUM_DIRECT below tree_min_nodes; precision IBIM_FP64 when
- * the treecode is used).
+ * ibim_setup, with IBIM_SUM_TREE resolved for the problem's size (summation
+ * IBIM_SUM_DIRECT below tree_min_nodes).
  */
 int ibim_context_options(const ibim_ctx* ctx, ibim_options* opt);
 

@@ -227,9 +227,6 @@ int check_options(const ibim_options& o) {
     return fail(IBIM_EINVAL, "unknown summation mode");
   if (o.tree_min_nodes < 0) return fail(IBIM_EINVAL, "tree_min_nodes must be >= 0");
   if (o.summation == IBIM_SUM_TREE) {
-    if (o.precision != IBIM_FP64 && o.tree_min_nodes == 0)
-      return fail(IBIM_EINVAL,
-                  "the treecode runs in float64 only (IBIM_MIXED needs tree_min_nodes > 0)");
     if (o.tree_order < 2 || o.tree_order > ibim::kTreeMaxOrder)
       return fail(IBIM_EINVAL, "tree_order must be in [2, 12]");
     if (!(o.tree_theta > 0.0 && o.tree_theta <= 1.0))
@@ -266,11 +263,8 @@ int ctx_create_host(const double* sdf, int nx, int ny, int nz, const double orig
   std::string err;
   int r = build_host_plan(sdf, nx, ny, nz, origin, h, eps_tube, o.hybrid, &c->plan, &err);
   if (!r && o.summation == IBIM_SUM_TREE) {
-    // the treecode serves problems of at least tree_min_nodes nodes, in float64
-    if ((int64_t)c->plan.M < o.tree_min_nodes)
-      c->opt.summation = IBIM_SUM_DIRECT;
-    else
-      c->opt.precision = IBIM_FP64;
+    // the treecode serves problems of at least tree_min_nodes nodes
+    if ((int64_t)c->plan.M < o.tree_min_nodes) c->opt.summation = IBIM_SUM_DIRECT;
   }
   if (!r && c->opt.summation == IBIM_SUM_TREE) {
     TreeParams prm;
@@ -309,7 +303,7 @@ size_t ctx_footprint_estimate(const ibim_ctx* c) {
     b += (size_t)pp.nsplit * n * 8;
   // Krylov basis and GMRES scratch (as allocated by ensure_krylov)
   b += ((m + 4) * n + (m + 1) * (m + 1030) + 8 * m) * 8;
-  if (c->opt.precision == IBIM_MIXED) {
+  if (c->opt.precision == IBIM_MIXED && c->opt.summation == IBIM_SUM_DIRECT) {
     const double h = pl.h, eps = pl.eps;
     const double rn = c->opt.r_near > 0.0 ? c->opt.r_near : 4.0 * h;
     // near pairs per row: a disc of radius r_near in a slab of thickness 2 eps
@@ -410,8 +404,8 @@ int ctx_setup_device(ibim_ctx* c, hipStream_t s) {
   dfree(d_rowid); dfree(d_axis); dfree(d_alpha); dfree(d_beta); dfree(d_eta); dfree(d_tau);
   dfree(d_k1); dfree(d_k2);
   if (e != hipSuccess) return bad(e, "correction weights");
-  if (o.precision == IBIM_MIXED) {
-    // float32 geometry relative to the centroid, and the near list
+  if (o.precision == IBIM_MIXED && o.summation == IBIM_SUM_DIRECT) {
+    // float32 geometry relative to the centroid, and the near list (direct sum)
     double cen[3] = {0, 0, 0};
     for (int32_t m = 0; m < M; ++m) {
       cen[0] += pl.px[m];
@@ -457,6 +451,7 @@ int ctx_setup_device(ibim_ctx* c, hipStream_t s) {
     e = tree_upload(c->tplan, P, pl.px.data(), pl.py.data(), pl.pz.data(), pl.nx.data(),
                     pl.ny.data(), pl.nz.data(), pl.w.data(), &c->tree, s);
     if (e != hipSuccess) return bad(e, "treecode setup");
+    c->tree.mixed = o.precision == IBIM_MIXED;
     bytes += c->tree.bytes;
     const double n4 = std::pow((double)o.tree_order, 4.0);
     c->pair_flops = 60.0 * c->tplan.near_evals + 36.0 * c->tplan.far_evals +

@@ -22,7 +22,9 @@
 // one target per lane) runs through its proxy clusters and then its direct
 // source ranges, staging both in LDS; the finishing kernel adds a batch's
 // parts in a fixed order, so results are reproducible.  All arithmetic is
-// float64.
+// float64 except, in the mixed form, the target-proxy evaluations: float32
+// kernels on float64-formed differences, summed in float32 over one line of
+// n proxies and then in float64.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -260,7 +262,22 @@ __device__ __forceinline__ void far_eval(double R2, double rn, double A, double 
   S2 = fma(rn * iR3, fma(te, D, -A), S2);
 }
 
+// far_eval in float32 (the mixed form): hardware reciprocal square root and
+// base-2 exponential, every operation explicit.
+__device__ __forceinline__ void far_eval_f32(float R2, float rn, float A, float B, float D,
+                                             const PairConstsF& c, float& S1, float& S2) {
+  const float iR = __builtin_amdgcn_rsqf(R2);
+  const float R = R2 * iR;
+  const float kr = c.kappa * R;
+  const float e = exp_neg_f32(kr);
+  const float te = __fmaf_rn(e, kr, e);
+  const float iR3 = iR * iR * iR;
+  S1 = __fmaf_rn(iR, __fmaf_rn(e, B, A), S1);
+  S2 = __fmaf_rn(rn * iR3, __fmaf_rn(te, D, -A), S2);
+}
+
 // One work item: part of one batch's far clusters and direct ranges.
+template <bool kMixed>
 __global__ __launch_bounds__(256) void tree_item_kernel(TreeArgs a) {
   // LDS: near sources as 8 arrays of 256, or (same buffer) the combined
   // charges (A, B, D interleaved) of a proxy cluster, as many x-planes of its
@@ -276,9 +293,13 @@ __global__ __launch_bounds__(256) void tree_item_kernel(TreeArgs a) {
   const double nxk = a.tnx[t], nyk = a.tny[t], nzk = a.tnz[t];
   const int n = a.order, n2 = n * n, n3 = n2 * n;
   // x-planes of the proxy grid whose charges fit in the LDS buffer at once
-  const int planes = max(1, 2048 / (3 * n2));
+  const int planes = max(1, (kMixed ? 4096 : 2048) / (3 * n2));
   double* qs = &sh[0][0];
+  float* qf = reinterpret_cast<float*>(&sh[0][0]);
   double S1 = 0.0, S2 = 0.0;
+  const PairConstsF pcf{(float)a.pc.c1, (float)a.pc.c2, (float)a.pc.kappa, (float)a.pc.kappa2};
+  const float nxf = (float)nxk, nyf = (float)nyk, nzf = (float)nzk;
+  float rzf[kTreeMaxOrder];  // mixed form: z - Z_k of the current cluster
   // proxy clusters: points (X_i, Y_j, Z_k), so R^2 and r.n_k are built from
   // per-axis terms: (x - X_i)^2 + (y - Y_j)^2 once per (i, j), plus (z - Z_k)^2
   for (int32_t f = a.ifar0[it]; f < a.ifar1[it]; ++f) {
@@ -295,22 +316,53 @@ __global__ __launch_bounds__(256) void tree_item_kernel(TreeArgs a) {
       for (int q = tid; q < (i1 - i0) * n2; q += 256) {
         const double q1 = a.pq[2 * (base + (size_t)i0 * n2 + q)];
         const double q2 = a.pq[2 * (base + (size_t)i0 * n2 + q) + 1];
-        qs[3 * q] = q1 - q2;
-        qs[3 * q + 1] = fma(-a.pc.c1, q1, q2);
-        qs[3 * q + 2] = fma(-a.pc.c2, q2, q1);
+        if (kMixed) {
+          qf[3 * q] = (float)(q1 - q2);
+          qf[3 * q + 1] = (float)fma(-a.pc.c1, q1, q2);
+          qf[3 * q + 2] = (float)fma(-a.pc.c2, q2, q1);
+        } else {
+          qs[3 * q] = q1 - q2;
+          qs[3 * q + 1] = fma(-a.pc.c1, q1, q2);
+          qs[3 * q + 2] = fma(-a.pc.c2, q2, q1);
+        }
       }
       __syncthreads();
-      for (int i = i0; i < i1; ++i) {
-        const double rx = x - ax[0][i];
-        const double rx2 = rx * rx, rxn = rx * nxk;
-        for (int j = 0; j < n; ++j) {
-          const double ry = y - ax[1][j];
-          const double axy = fma(ry, ry, rx2), bxy = fma(ry, nyk, rxn);
-          const double* q = qs + 3 * (((i - i0) * n + j) * n);
-          for (int k = 0; k < n; ++k) {
-            const double rz = z - ax[2][k];
-            far_eval(fma(rz, rz, axy), fma(rz, nzk, bxy), q[3 * k], q[3 * k + 1], q[3 * k + 2],
-                     a.pc, S1, S2);
+      if (kMixed) {
+        if (i0 == 0) {
+#pragma unroll
+          for (int k = 0; k < kTreeMaxOrder; ++k) rzf[k] = k < n ? (float)(z - ax[2][k]) : 0.0f;
+        }
+        for (int i = i0; i < i1; ++i) {
+          const float rx = (float)(x - ax[0][i]);
+          const float rx2 = rx * rx, rxn = rx * nxf;
+          for (int j = 0; j < n; ++j) {
+            const float ry = (float)(y - ax[1][j]);
+            const float axy = __fmaf_rn(ry, ry, rx2), bxy = __fmaf_rn(ry, nyf, rxn);
+            const float* q = qf + 3 * (((i - i0) * n + j) * n);
+            float s1 = 0.0f, s2 = 0.0f;
+#pragma unroll
+            for (int k = 0; k < kTreeMaxOrder; ++k) {
+              if (k < n)
+                far_eval_f32(__fmaf_rn(rzf[k], rzf[k], axy), __fmaf_rn(rzf[k], nzf, bxy),
+                             q[3 * k], q[3 * k + 1], q[3 * k + 2], pcf, s1, s2);
+            }
+            S1 += (double)s1;
+            S2 += (double)s2;
+          }
+        }
+      } else {
+        for (int i = i0; i < i1; ++i) {
+          const double rx = x - ax[0][i];
+          const double rx2 = rx * rx, rxn = rx * nxk;
+          for (int j = 0; j < n; ++j) {
+            const double ry = y - ax[1][j];
+            const double axy = fma(ry, ry, rx2), bxy = fma(ry, nyk, rxn);
+            const double* q = qs + 3 * (((i - i0) * n + j) * n);
+            for (int k = 0; k < n; ++k) {
+              const double rz = z - ax[2][k];
+              far_eval(fma(rz, rz, axy), fma(rz, nzk, bxy), q[3 * k], q[3 * k + 1],
+                       q[3 * k + 2], a.pc, S1, S2);
+            }
           }
         }
       }
@@ -511,7 +563,10 @@ hipError_t launch_tree_sum(const TreeDevice& T, const DeviceProblem& P, const do
         hipLaunchKernelGGL(tree_m2m_kernel, dim3((unsigned)cnt), dim3(256), 0, s, a, off);
     }
   }
-  hipLaunchKernelGGL(tree_item_kernel, dim3((unsigned)T.n_items), dim3(256), 0, s, a);
+  if (T.mixed)
+    hipLaunchKernelGGL(tree_item_kernel<true>, dim3((unsigned)T.n_items), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(tree_item_kernel<false>, dim3((unsigned)T.n_items), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

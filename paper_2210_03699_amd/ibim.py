@@ -214,7 +214,7 @@ class Problem:
         eff = _Options()
         _check(lib.ibim_context_options(ctx, ctypes.byref(eff)))
         #: summation and precision this problem runs with (IBIM_SUM_TREE is
-        #: resolved by size: direct below tree_min_nodes, float64 treecode above)
+        #: resolved by size: direct below tree_min_nodes, the treecode above)
         self.summation = int(eff.summation)
         self.precision = int(eff.precision)
 

@@ -6,7 +6,8 @@ Section 2.5); its reference is the exact sum:
   pair directly and must equal the direct path to rounding (1e-13);
 * against the FP64 oracle's operator, the error falls geometrically as the
   number of Chebyshev points grows and as theta shrinks;
-* solves: G_pol within 1e-6 of the direct FP64 solve (the mixed form's bar).
+* solves: G_pol within 1e-6 of the direct FP64 solve (the mixed form's bar),
+  also with the far field in float32 (IBIM_MIXED).
 """
 import sys
 
@@ -89,6 +90,25 @@ def test_error_falls_geometrically(kw):
     assert e < errs[8] / 10 and e < 1e-7
 
 
+def test_mixed_far_field(kw):
+    """IBIM_MIXED evaluates the target-proxy terms in float32: its error against
+    the oracle stays at the treecode's own level; with no far field (tiny theta)
+    nothing is float32 and the result is the float64 direct sum."""
+    wl, u, ref, orc = kw
+    errs = {}
+    for prec in (ibim.FP64, ibim.MIXED):
+        p = ibim.Problem.from_workload(wl, device=0, summation=ibim.SUM_TREE, precision=prec)
+        errs[prec] = _rel(_apply(p, u), ref, p.M)
+        p.close()
+    _say(f"[tree mixed far field] rel err fp64 {errs[ibim.FP64]:.3e} mixed {errs[ibim.MIXED]:.3e}")
+    assert errs[ibim.MIXED] < 1e-6 and errs[ibim.MIXED] < 3 * errs[ibim.FP64]
+    direct = ibim.Problem.from_workload(wl, device=0)
+    near = ibim.Problem.from_workload(wl, device=0, summation=ibim.SUM_TREE, tree_theta=1e-6,
+                                      precision=ibim.MIXED)
+    assert near.tree_counts()["far_evals"] == 0
+    assert _rel(_apply(near, u), _apply(direct, u), near.M) < 1e-13
+
+
 def test_tree_with_kreg_rows_matches_direct():
     """K-reg rows have larger excluded sets (a tangent disc of radius 2h); the
     treecode keeps them in its direct part and its solve stays within 1e-6."""
@@ -106,7 +126,8 @@ def test_tree_with_kreg_rows_matches_direct():
 def test_tree_solve_matches_direct(kw):
     wl, u, ref, orc = kw
     g = {}
-    for name, kwargs in (("direct", {}), ("tree", {"summation": ibim.SUM_TREE})):
+    for name, kwargs in (("direct", {}), ("tree", {"summation": ibim.SUM_TREE}),
+                         ("tree_mixed", {"summation": ibim.SUM_TREE, "precision": ibim.MIXED})):
         p = ibim.Problem.from_workload(wl, device=0, **kwargs)
         _, info = p.solve_energy(wl.tol)
         assert info["converged"]
@@ -116,6 +137,7 @@ def test_tree_solve_matches_direct(kw):
     g_orc = orc.solve_energy(wl.charge_xyz, wl.charge_q, wl.tol)[1]["g_pol"]
     assert abs(g["direct"] - g_orc) <= 1e-10 * abs(g_orc)
     assert abs(g["tree"] - g_orc) <= 1e-6 * abs(g_orc)
+    assert abs(g["tree_mixed"] - g_orc) <= 1e-6 * abs(g_orc)
 
 
 def test_small_problems_have_no_far_field():
@@ -135,10 +157,10 @@ def test_small_problems_have_no_far_field():
 def test_tree_options_rejected():
     wl = workloads.born_sphere(h=0.4)
     with pytest.raises(ibim.IbimError):
-        ibim.Problem.from_workload(wl, device=0, summation=ibim.SUM_TREE, precision=ibim.MIXED)
-    with pytest.raises(ibim.IbimError):
         ibim.Problem.from_workload(wl, device=0, summation=ibim.SUM_TREE, tree_order=13)
+    with pytest.raises(ibim.IbimError):
+        ibim.Problem.from_workload(wl, device=0, summation=ibim.SUM_TREE, tree_min_nodes=-1)
     with pytest.raises(ibim.IbimError):  # the server validates as ibim_setup does
-        ibim.Server(1 << 30, summation=ibim.SUM_TREE, precision=ibim.MIXED)
+        ibim.Server(1 << 30, summation=ibim.SUM_TREE, tree_order=1)
     with pytest.raises(ibim.IbimError):
         ibim.Server(1 << 30, summation=ibim.SUM_TREE, tree_theta=0.0)
