@@ -5,7 +5,7 @@ the largest molecular workload the method is aimed at).
 At these sizes the symmetric pair kernel keeps a column-sum scratch of 5 to
 21 GB (it grows as M^2); the check is that its packed layout and the
 finishing kernels read back exactly what the work items wrote.  Sampled rows
-of ``apply`` (float64, mixed, treecode) are compared with the oracle's rows
+of ``apply`` (float64, mixed, treecode in float64 and mixed) are compared with the oracle's rows
 (computed here, weights only at the sampled rows); the solves are compared
 with each other and with the Kirkwood series (discretisation error).
 """
@@ -48,7 +48,8 @@ def large(request):
 
 
 MODES = {"fp64": ({"precision": ibim.FP64}, 1e-12), "mixed": ({"precision": ibim.MIXED}, 1e-6),
-         "tree": ({"summation": ibim.SUM_TREE}, 1e-6)}
+         "tree": ({"summation": ibim.SUM_TREE}, 1e-6),
+         "tree_mixed": ({"summation": ibim.SUM_TREE, "precision": ibim.MIXED}, 1e-6)}
 
 
 @pytest.mark.parametrize("mode", list(MODES))
@@ -68,7 +69,7 @@ def test_large_sampled_apply(large, mode):
 def test_large_solves(large):
     h, wl, rows, u, ref1, ref2, M = large
     # float64 direct at h = 0.1 only (8 applications of 2.8 s each at h = 0.07)
-    modes = ("fp64", "mixed", "tree") if h == 0.1 else ("mixed", "tree")
+    modes = ("fp64", "mixed", "tree", "tree_mixed") if h == 0.1 else ("mixed", "tree", "tree_mixed")
     g = {}
     for mode in modes:
         prob = ibim.Problem.from_workload(wl, device=0, **MODES[mode][0])

@@ -280,11 +280,13 @@ def test_full_sampled_apply(full):
     assert e1 < 1e-12 and e2 < 1e-12
 
 
-def test_full_tree_sampled_apply(full):
-    """The treecode (8 points per dimension, theta 0.7) on the same rows: an
-    approximation of the exact sum, within 1e-6 of the largest entry."""
+@pytest.mark.parametrize("precision", [ibim.FP64, ibim.MIXED])
+def test_full_tree_sampled_apply(full, precision):
+    """The treecode (8 points per dimension, theta 0.7; far field in float32 for
+    the mixed form) on the same rows: an approximation of the exact sum,
+    within 1e-6 of the largest entry."""
     name, wl, prob, gold = full
-    tree = ibim.Problem.from_workload(wl, device=0, summation=ibim.SUM_TREE)
+    tree = ibim.Problem.from_workload(wl, device=0, summation=ibim.SUM_TREE, precision=precision)
     M = tree.M
     rows = np.array(gold["rows"])
     u = workloads.random_vector(2 * M, gold["u_seed"])
@@ -294,7 +296,7 @@ def test_full_tree_sampled_apply(full):
     r2 = np.array(gold["apply_rows_2"])
     e1 = np.max(np.abs(out[rows] - r1)) / np.max(np.abs(r1))
     e2 = np.max(np.abs(out[M + rows] - r2)) / np.max(np.abs(r2))
-    _say(f"[{name} full] treecode sampled apply rel err {e1:.3e} {e2:.3e}")
+    _say(f"[{name} full] treecode (precision {precision}) sampled apply rel err {e1:.3e} {e2:.3e}")
     assert e1 < 1e-6 and e2 < 1e-6
 
 
