@@ -40,4 +40,29 @@ struct Krylov {
   hipError_t backsolve(int n, hipStream_t s);
 };
 
+// One Arnoldi + Givens step of many independent solves, one launch per stage
+// for all of them: solve q orthogonalises w = V_{j+1} (holding A V_j on
+// entry) against V_0..V_j twice (classical Gram-Schmidt, as the single-solve
+// sequence dots/sub/dots/sub), normalises it and applies the Givens step.
+// Every solve gets exactly the blocks and reduction order of the
+// single-solve launchers, so its bits do not depend on the batch.
+struct KrylovStepArgs {
+  const double* V;  // basis of the solve; w = V + (j + 1) n
+  double *H, *cs, *sn, *g, *hcol, *hcol2, *scal, *partial;  // its Krylov workspace
+  double* status;   // out: |g_{j+1}|, H(j+1, j)
+  int64_t n;
+  int m, j;
+  // filled by krylov_step_batched: dot-product blocks of n, and this solve's
+  // first block in the launches over V (nblk (j+1) blocks), over w alone
+  // (nblk), the reductions (j + 1) and the row launches (ceil(n / 256))
+  int nblk, rows_per;
+  int64_t dot0, dotw0, red0, vec0;
+};
+
+// steps: pinned host array of count entries (the block fields are filled
+// here); d_steps: device array of count entries, written on stream s from
+// steps, which must stay unchanged until s has passed this point.
+hipError_t krylov_step_batched(KrylovStepArgs* steps, int count, KrylovStepArgs* d_steps,
+                               hipStream_t s);
+
 }  // namespace ibim

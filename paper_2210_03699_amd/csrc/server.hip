@@ -101,6 +101,9 @@ struct ibim_server {
   int32_t* d_swork = nullptr;
   int32_t* h_swork = nullptr;
   size_t swork_cap = 0;
+  KrylovStepArgs* d_steps = nullptr;  // batched GMRES step of the solves in Arnoldi phase
+  KrylovStepArgs* h_steps = nullptr;
+  size_t steps_cap = 0;
   int sym_grid = 0;
   int* d_counter = nullptr;  // two counters: one-directional and symmetric launches
   double* d_status = nullptr;  // 8 doubles per slot
@@ -391,7 +394,12 @@ int step_impl(ibim_server* srv) {
   srv->st.rounds++;
   srv->st.batched_items += (int64_t)(nitems + nswork);
 
-  // 3. per request: correction, then one GMRES or residual step
+  // 3. per request: correction, then one GMRES or residual step; the GMRES
+  // (Arnoldi + Givens) steps of all solves run batched after the loop
+  if (int e = ensure_staging(&srv->d_steps, &srv->h_steps, &srv->steps_cap,
+                             srv->active.size()))
+    return e;
+  int nsteps = 0;
   for (Request* r : srv->active) {
     ibim_ctx* c = r->ctx;
     Krylov& K = c->kr;
@@ -416,21 +424,27 @@ int step_impl(ibim_server* srv) {
       HIP_TRY(launch_row_scaling(c, out, out, s), "row scaling");
     r->applies++;
     if (r->phase == Phase::kIter) {
-      const int j = r->j;
-      HIP_TRY(K.dots(K.V, N, j + 1, out, N, K.hcol, 0, s), "dots");
-      HIP_TRY(K.sub(K.V, N, j + 1, K.hcol, out, N, s), "sub");
-      HIP_TRY(K.dots(K.V, N, j + 1, out, N, K.hcol2, 0, s), "dots");
-      HIP_TRY(K.sub(K.V, N, j + 1, K.hcol2, out, N, s), "sub");
-      HIP_TRY(K.dots(out, N, 1, out, N, K.scal, 0, s), "dots");
-      HIP_TRY(K.normalize(out, K.scal, out, N, s), "normalize");
-      HIP_TRY(K.givens(j, s), "givens");
-      HIP_TRY(hipMemcpyAsync(st, K.status, 2 * sizeof(double), hipMemcpyDeviceToDevice, s),
-              "copy");
+      // as ibim_solve's dots/sub/dots/sub/dots/normalize/givens on out = V_{j+1}
+      KrylovStepArgs& a = srv->h_steps[nsteps++];
+      a.V = K.V;
+      a.H = K.H;
+      a.cs = K.cs;
+      a.sn = K.sn;
+      a.g = K.g;
+      a.hcol = K.hcol;
+      a.hcol2 = K.hcol2;
+      a.scal = K.scal;
+      a.partial = K.partial;
+      a.status = st;  // straight into the request's status slot
+      a.n = N;
+      a.m = K.m;
+      a.j = r->j;
     } else {
       HIP_TRY(K.residual(r->d_b, K.tmp2, K.tmp, N, s), "residual");
       HIP_TRY(K.dots(K.tmp, N, 1, K.tmp, N, st + 3, 0, s), "dots");
     }
   }
+  HIP_TRY(krylov_step_batched(srv->h_steps, nsteps, srv->d_steps, s), "batched GMRES step");
   HIP_TRY(hipMemcpyAsync(srv->h_status, srv->d_status,
                          (size_t)srv->max_slots * kStatusStride * sizeof(double),
                          hipMemcpyDeviceToHost, s),
@@ -688,8 +702,10 @@ void ibim_server_destroy(ibim_server* srv) {
   dfree(srv->d_items);
   dfree(srv->d_sargs);
   dfree(srv->d_swork);
+  dfree(srv->d_steps);
   if (srv->h_sargs) (void)hipHostFree(srv->h_sargs);
   if (srv->h_swork) (void)hipHostFree(srv->h_swork);
+  if (srv->h_steps) (void)hipHostFree(srv->h_steps);
   dfree(srv->d_counter);
   dfree(srv->d_status);
   if (srv->h_args) (void)hipHostFree(srv->h_args);
