@@ -104,6 +104,12 @@ struct ibim_server {
   KrylovStepArgs* d_steps = nullptr;  // batched GMRES step of the solves in Arnoldi phase
   KrylovStepArgs* h_steps = nullptr;
   size_t steps_cap = 0;
+  SymFinishArgs* d_fin = nullptr;  // batched finishing launches (float64, mixed)
+  SymFinishArgs* h_fin = nullptr;
+  size_t fin_cap = 0;
+  SymMixedFinishArgs* d_finm = nullptr;
+  SymMixedFinishArgs* h_finm = nullptr;
+  size_t finm_cap = 0;
   int sym_grid = 0;
   int* d_counter = nullptr;  // two counters: one-directional and symmetric launches
   double* d_status = nullptr;  // 8 doubles per slot
@@ -394,35 +400,49 @@ int step_impl(ibim_server* srv) {
   srv->st.rounds++;
   srv->st.batched_items += (int64_t)(nitems + nswork);
 
-  // 3. per request: correction, then one GMRES or residual step; the GMRES
-  // (Arnoldi + Givens) steps of all solves run batched after the loop
-  if (int e = ensure_staging(&srv->d_steps, &srv->h_steps, &srv->steps_cap,
-                             srv->active.size()))
-    return e;
-  int nsteps = 0;
+  // 3. per request: correction (+ row scaling), then one GMRES or residual
+  // step.  The finishing kernels of the requests on the symmetric kernels run
+  // as one launch per precision, and the GMRES (Arnoldi + Givens) steps of all
+  // solves as one launch per stage.
+  const size_t na = srv->active.size();
+  if (int e = ensure_staging(&srv->d_steps, &srv->h_steps, &srv->steps_cap, na)) return e;
+  if (int e = ensure_staging(&srv->d_fin, &srv->h_fin, &srv->fin_cap, na)) return e;
+  if (int e = ensure_staging(&srv->d_finm, &srv->h_finm, &srv->finm_cap, na)) return e;
+  const bool unscale = srv->opt.precond == IBIM_PRECOND_DIAG;
+  int nsteps = 0, nfin = 0, nfinm = 0;
+  for (Request* r : srv->active) {
+    ibim_ctx* c = r->ctx;
+    Krylov& K = c->kr;
+    const int64_t N = K.n;
+    const double* u = r->phase == Phase::kIter ? K.V + (int64_t)r->j * N : r->d_x;
+    double* out = r->phase == Phase::kIter ? K.V + (int64_t)(r->j + 1) * N : K.tmp2;
+    r->applies++;
+    if (c->opt.summation == IBIM_SUM_DIRECT && c->sym.enabled) {
+      if (c->opt.precision == IBIM_MIXED)
+        srv->h_finm[nfinm++] =
+            make_finish_sym_mixed_args(c->P, c->sym, c->d_careful, u, c->sym_scratch, out);
+      else
+        srv->h_fin[nfin++] = make_finish_sym_args(c->P, c->sym, u, c->sym_scratch, out);
+      continue;
+    }
+    if (c->opt.summation == IBIM_SUM_TREE) {
+      // large requests: the treecode's own launches, queued behind the batched ones
+      HIP_TRY(launch_tree_sum(c->tree, c->P, u, s), "treecode launch");
+      HIP_TRY(launch_tree_finish(c->tree, c->P, u, out, s), "finish");
+    } else if (c->opt.precision == IBIM_MIXED) {
+      HIP_TRY(launch_finish_mixed(c->P, c->pair, u, c->partial, out, s), "finish");
+    } else {
+      HIP_TRY(launch_finish(c->P, c->pair, c->opt.precision, u, c->partial, out, s), "finish");
+    }
+    if (unscale) HIP_TRY(launch_row_scaling(c, out, out, s), "row scaling");
+  }
+  HIP_TRY(launch_finish_sym_batched(srv->h_fin, nfin, srv->d_fin, unscale, s), "finish");
+  HIP_TRY(launch_finish_sym_mixed_batched(srv->h_finm, nfinm, srv->d_finm, unscale, s), "finish");
   for (Request* r : srv->active) {
     ibim_ctx* c = r->ctx;
     Krylov& K = c->kr;
     const int64_t N = K.n;
     double* st = srv->d_status + (size_t)r->slot * kStatusStride;
-    const double* u = r->phase == Phase::kIter ? K.V + (int64_t)r->j * N : r->d_x;
-    double* out = r->phase == Phase::kIter ? K.V + (int64_t)(r->j + 1) * N : K.tmp2;
-    if (c->opt.summation == IBIM_SUM_TREE) {
-      // large requests: the treecode's own launches, queued behind the batched ones
-      HIP_TRY(launch_tree_sum(c->tree, c->P, u, s), "treecode launch");
-      HIP_TRY(launch_tree_finish(c->tree, c->P, u, out, s), "finish");
-    } else if (c->sym.enabled && c->opt.precision == IBIM_MIXED)
-      HIP_TRY(launch_finish_sym_mixed(c->P, c->sym, c->d_careful, u, c->sym_scratch, out, s),
-              "finish");
-    else if (c->sym.enabled)
-      HIP_TRY(launch_finish_sym(c->P, c->sym, u, c->sym_scratch, out, s), "finish");
-    else if (c->opt.precision == IBIM_MIXED)
-      HIP_TRY(launch_finish_mixed(c->P, c->pair, u, c->partial, out, s), "finish");
-    else
-      HIP_TRY(launch_finish(c->P, c->pair, c->opt.precision, u, c->partial, out, s), "finish");
-    if (c->opt.precond == IBIM_PRECOND_DIAG)
-      HIP_TRY(launch_row_scaling(c, out, out, s), "row scaling");
-    r->applies++;
     if (r->phase == Phase::kIter) {
       // as ibim_solve's dots/sub/dots/sub/dots/normalize/givens on out = V_{j+1}
       KrylovStepArgs& a = srv->h_steps[nsteps++];
@@ -703,6 +723,10 @@ void ibim_server_destroy(ibim_server* srv) {
   dfree(srv->d_sargs);
   dfree(srv->d_swork);
   dfree(srv->d_steps);
+  dfree(srv->d_fin);
+  dfree(srv->d_finm);
+  if (srv->h_fin) (void)hipHostFree(srv->h_fin);
+  if (srv->h_finm) (void)hipHostFree(srv->h_finm);
   if (srv->h_sargs) (void)hipHostFree(srv->h_sargs);
   if (srv->h_swork) (void)hipHostFree(srv->h_swork);
   if (srv->h_steps) (void)hipHostFree(srv->h_steps);

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "operator.h"
+#include "pair_math.h"
 
 namespace ibim {
 
@@ -74,6 +75,31 @@ int pair_sym_batched_grid();
 hipError_t launch_finish_sym(const DeviceProblem& P, const SymPlan& pl, const double* u,
                              const double* scratch, double* out, hipStream_t stream);
 
+// Finishing kernels' arguments (one problem); blk0 is the problem's first
+// block in a batched finishing launch.
+struct SymFinishArgs {
+  const double* u;
+  const double* rowpart;
+  const double* colpart;
+  const int32_t* crow;
+  const int32_t* ccol;
+  const double* blocks;
+  int32_t M;
+  int T, b, nCB, rows;
+  double lam1, lam2;
+  double* out;
+  int64_t blk0;
+};
+SymFinishArgs make_finish_sym_args(const DeviceProblem& P, const SymPlan& pl, const double* u,
+                                   const double* scratch, double* out);
+// One launch finishing many problems (the solve server): args is a pinned
+// host array of count entries (blk0 filled here), d_args a device array it
+// is copied to on the stream.  Each problem's out is what launch_finish_sym
+// writes, divided by lambda1 (psi rows) and lambda2 (psi_n rows) when
+// unscale is set, as the row scaling of the scaled system does.
+hipError_t launch_finish_sym_batched(SymFinishArgs* args, int count, SymFinishArgs* d_args,
+                                     bool unscale, hipStream_t stream);
+
 // Mixed form (float32 pairs, float64 sums) on the same schedule, and its
 // finishing kernel, which also replaces the float32 value of every near pair
 // by its float64 value (recomputing the float32 value exactly as the pair
@@ -85,5 +111,34 @@ int pair_sym_mixed_batched_grid();
 hipError_t launch_finish_sym_mixed(const DeviceProblem& P, const SymPlan& pl,
                                    const uint32_t* careful, const double* u,
                                    const double* scratch, double* out, hipStream_t stream);
+
+struct SymMixedFinishArgs {
+  const double* u;
+  const double* rowpart;
+  const double* colpart;
+  const int32_t* crow;
+  const int32_t* ccol;
+  const double* blocks;
+  const int64_t* nrow;
+  const int32_t* ncol;
+  const double *px, *py, *pz, *nx, *ny, *nz, *w;
+  const float *fx, *fy, *fz, *fnx, *fny, *fnz;
+  const uint32_t* careful;
+  PairConsts c64;
+  PairConstsF c32;
+  double scale;
+  int32_t M;
+  int T, b, nCB, rows;
+  double lam1, lam2;
+  double* out;
+  int64_t blk0;
+};
+SymMixedFinishArgs make_finish_sym_mixed_args(const DeviceProblem& P, const SymPlan& pl,
+                                              const uint32_t* careful, const double* u,
+                                              const double* scratch, double* out);
+// As launch_finish_sym_batched, for the mixed form.
+hipError_t launch_finish_sym_mixed_batched(SymMixedFinishArgs* args, int count,
+                                           SymMixedFinishArgs* d_args, bool unscale,
+                                           hipStream_t stream);
 
 }  // namespace ibim

@@ -121,22 +121,10 @@ __global__ __launch_bounds__(256, 4) void pair_sym_batched_kernel(
   sym::batched<Fp64>(probs, work, n_work, counter, sh);
 }
 
-struct SymFinishArgs {
-  const double* u;
-  const double* rowpart;
-  const double* colpart;
-  const int32_t* crow;
-  const int32_t* ccol;
-  const double* blocks;
-  int32_t M;
-  int T, b, nCB, rows;
-  double lam1, lam2;
-  double* out;
-};
 
-__global__ __launch_bounds__(256) void finish_sym_kernel(SymFinishArgs a) {
-  const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= a.M) return;
+// Row k of one problem: partial slots, Lambda u and the sparse blocks
+// (divided by lambda when unscale is set).
+__device__ __forceinline__ void finish_sym_row(const SymFinishArgs& a, int32_t k, bool unscale) {
   const int32_t M = a.M;
   const int X = k / kT, t = k % kT;
   double s1 = 0.0, s2 = 0.0;
@@ -160,8 +148,33 @@ __global__ __launch_bounds__(256) void finish_sym_kernel(SymFinishArgs a) {
     o1 += B[0] * v1 + B[1] * v2;
     o2 += B[2] * v1 + B[3] * v2;
   }
+  if (unscale) {
+    o1 = o1 / a.lam1;
+    o2 = o2 / a.lam2;
+  }
   a.out[k] = o1;
   a.out[M + k] = o2;
+}
+
+__global__ __launch_bounds__(256) void finish_sym_kernel(SymFinishArgs a) {
+  const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= a.M) return;
+  finish_sym_row(a, k, false);
+}
+
+// Several problems: the block's problem is the last one whose blk0 <= block.
+__global__ __launch_bounds__(256) void finish_sym_batched_kernel(const SymFinishArgs* fa,
+                                                                 int count, int unscale) {
+  const int64_t blk = blockIdx.x;
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (fa[mid].blk0 <= blk) lo = mid; else hi = mid - 1;
+  }
+  const SymFinishArgs& a = fa[lo];
+  const int64_t k = (blk - a.blk0) * 256 + threadIdx.x;
+  if (k >= a.M) return;
+  finish_sym_row(a, (int32_t)k, unscale != 0);
 }
 
 }  // namespace
@@ -280,8 +293,8 @@ int pair_sym_batched_grid() {
   return cus * per;
 }
 
-hipError_t launch_finish_sym(const DeviceProblem& P, const SymPlan& pl, const double* u,
-                             const double* scratch, double* out, hipStream_t stream) {
+SymFinishArgs make_finish_sym_args(const DeviceProblem& P, const SymPlan& pl, const double* u,
+                                   const double* scratch, double* out) {
   SymFinishArgs f;
   f.u = u;
   f.rowpart = scratch;
@@ -297,8 +310,31 @@ hipError_t launch_finish_sym(const DeviceProblem& P, const SymPlan& pl, const do
   f.lam1 = P.lam1;
   f.lam2 = P.lam2;
   f.out = out;
+  f.blk0 = 0;
+  return f;
+}
+
+hipError_t launch_finish_sym(const DeviceProblem& P, const SymPlan& pl, const double* u,
+                             const double* scratch, double* out, hipStream_t stream) {
+  const SymFinishArgs f = make_finish_sym_args(P, pl, u, scratch, out);
   const unsigned blocks = (unsigned)((P.M + 255) / 256);
   hipLaunchKernelGGL(finish_sym_kernel, dim3(blocks), dim3(256), 0, stream, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish_sym_batched(SymFinishArgs* args, int count, SymFinishArgs* d_args,
+                                     bool unscale, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  int64_t blk = 0;
+  for (int q = 0; q < count; ++q) {
+    args[q].blk0 = blk;
+    blk += (args[q].M + 255) / 256;
+  }
+  hipError_t e = hipMemcpyAsync(d_args, args, sizeof(SymFinishArgs) * (size_t)count,
+                                hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(finish_sym_batched_kernel, dim3((unsigned)blk), dim3(256), 0, stream, d_args,
+                     count, unscale ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -80,26 +80,6 @@ __global__ __launch_bounds__(256, 4) void pair_sym_mixed_batched_kernel(
   sym::batched<Mixed>(probs, work, n_work, counter, sh);
 }
 
-struct FinishArgs {
-  const double* u;
-  const double* rowpart;
-  const double* colpart;
-  const int32_t* crow;
-  const int32_t* ccol;
-  const double* blocks;
-  const int64_t* nrow;
-  const int32_t* ncol;
-  const double *px, *py, *pz, *nx, *ny, *nz, *w;
-  const float *fx, *fy, *fz, *fnx, *fny, *fnz;
-  const uint32_t* careful;
-  PairConsts c64;
-  PairConstsF c32;
-  double scale;
-  int32_t M;
-  int T, b, nCB, rows;
-  double lam1, lam2;
-  double* out;
-};
 
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -108,10 +88,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // One wave per row k: partial sums, sparse corrections and near-pair fix-ups
 // are spread over the lanes in a fixed assignment and reduced in a fixed tree.
-__global__ __launch_bounds__(256) void finish_sym_mixed_kernel(FinishArgs a) {
-  const int lane = threadIdx.x & 63;
-  const int32_t k = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (k >= a.M) return;  // uniform in the wave
+__device__ __forceinline__ void finish_sym_mixed_row(const SymMixedFinishArgs& a, int32_t k,
+                                                     int lane, bool unscale) {
   const int32_t M = a.M;
   const int T = a.T;
   const int X = k / kT, t = k % kT;
@@ -173,9 +151,37 @@ __global__ __launch_bounds__(256) void finish_sym_mixed_kernel(FinishArgs a) {
   f1 = wave_sum(f1);
   f2 = wave_sum(f2);
   if (lane == 0) {
-    a.out[k] = a.lam1 * a.u[k] + p1 + a.scale * f1;
-    a.out[M + k] = a.lam2 * a.u[M + k] + p2 + a.scale * f2;
+    double o1 = a.lam1 * a.u[k] + p1 + a.scale * f1;
+    double o2 = a.lam2 * a.u[M + k] + p2 + a.scale * f2;
+    if (unscale) {
+      o1 = o1 / a.lam1;
+      o2 = o2 / a.lam2;
+    }
+    a.out[k] = o1;
+    a.out[M + k] = o2;
   }
+}
+
+__global__ __launch_bounds__(256) void finish_sym_mixed_kernel(SymMixedFinishArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int32_t k = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (k >= a.M) return;  // uniform in the wave
+  finish_sym_mixed_row(a, k, lane, false);
+}
+
+// Several problems: the block's problem is the last one whose blk0 <= block.
+__global__ __launch_bounds__(256) void finish_sym_mixed_batched_kernel(
+    const SymMixedFinishArgs* fa, int count, int unscale) {
+  const int64_t blk = blockIdx.x;
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (fa[mid].blk0 <= blk) lo = mid; else hi = mid - 1;
+  }
+  const SymMixedFinishArgs& a = fa[lo];
+  const int64_t k = (blk - a.blk0) * 4 + (threadIdx.x >> 6);
+  if (k >= a.M) return;  // uniform in the wave
+  finish_sym_mixed_row(a, (int32_t)k, threadIdx.x & 63, unscale != 0);
 }
 
 }  // namespace
@@ -203,10 +209,10 @@ int pair_sym_mixed_batched_grid() {
   return cus * per;
 }
 
-hipError_t launch_finish_sym_mixed(const DeviceProblem& P, const SymPlan& pl,
-                                   const uint32_t* careful, const double* u,
-                                   const double* scratch, double* out, hipStream_t stream) {
-  FinishArgs f;
+SymMixedFinishArgs make_finish_sym_mixed_args(const DeviceProblem& P, const SymPlan& pl,
+                                              const uint32_t* careful, const double* u,
+                                              const double* scratch, double* out) {
+  SymMixedFinishArgs f;
   f.u = u;
   f.rowpart = scratch;
   f.colpart = scratch + (size_t)pl.nCB * pl.T * 2 * kT;
@@ -233,8 +239,33 @@ hipError_t launch_finish_sym_mixed(const DeviceProblem& P, const SymPlan& pl,
   f.lam1 = P.lam1;
   f.lam2 = P.lam2;
   f.out = out;
+  f.blk0 = 0;
+  return f;
+}
+
+hipError_t launch_finish_sym_mixed(const DeviceProblem& P, const SymPlan& pl,
+                                   const uint32_t* careful, const double* u,
+                                   const double* scratch, double* out, hipStream_t stream) {
+  const SymMixedFinishArgs f = make_finish_sym_mixed_args(P, pl, careful, u, scratch, out);
   const unsigned blocks = (unsigned)((P.M + 3) / 4);
   hipLaunchKernelGGL(finish_sym_mixed_kernel, dim3(blocks), dim3(256), 0, stream, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish_sym_mixed_batched(SymMixedFinishArgs* args, int count,
+                                           SymMixedFinishArgs* d_args, bool unscale,
+                                           hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  int64_t blk = 0;
+  for (int q = 0; q < count; ++q) {
+    args[q].blk0 = blk;
+    blk += (args[q].M + 3) / 4;
+  }
+  hipError_t e = hipMemcpyAsync(d_args, args, sizeof(SymMixedFinishArgs) * (size_t)count,
+                                hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(finish_sym_mixed_batched_kernel, dim3((unsigned)blk), dim3(256), 0, stream,
+                     d_args, count, unscale ? 1 : 0);
   return hipGetLastError();
 }
 
