@@ -37,8 +37,8 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3  # MI355X vector FP32 (counts packed float32 iss
 # counters read for a plain 256 MiB copy).  Valid only while the kernel sources
 # hash to the recorded digest; otherwise the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "fp64": ("fb00e151", 681.5e6),
-    "mixed": ("af6ba1d4", 506.0e6),
+    "fp64": ("10d64cac", 683.2e6),
+    "mixed": ("ef43987d", 504.4e6),
 }
 # stored oracle results (tests/golden/make_golden.py) per workload
 GOLDEN = {"kirkwood": "kirkwood_R10_h0.25.json", "ses500": "ses500_h0.3.json",
