@@ -121,6 +121,19 @@ struct ibim_server {
   std::deque<Request*> prep_queue;
   std::vector<std::thread> workers;
   bool stopping = false;
+  // device memory of finished or failed requests is freed on its own thread
+  // (each hipFree waits for the device), so rounds do not stall on it; the
+  // bytes still held count against the budget until they are freed
+  struct Reap {
+    ibim_ctx* ctx;
+    double *b, *x;
+    size_t bytes;
+  };
+  std::deque<Reap> reap_queue;
+  std::condition_variable reap_cv;
+  size_t reaping = 0;  // bytes queued or being freed (under mu)
+  bool reap_stop = false;
+  std::thread reaper;
 };
 
 namespace {
@@ -163,13 +176,42 @@ void worker_main(ibim_server* srv, int omp_threads) {
   }
 }
 
-void release_device(ibim_server* srv, Request* r) {
-  if (r->ctx) {
-    ibim_destroy(r->ctx);
-    r->ctx = nullptr;
+void reaper_main(ibim_server* srv) {
+  (void)hipSetDevice(srv->opt.device);
+  for (;;) {
+    ibim_server::Reap job;
+    {
+      std::unique_lock<std::mutex> lk(srv->mu);
+      srv->reap_cv.wait(lk, [&] { return srv->reap_stop || !srv->reap_queue.empty(); });
+      if (srv->reap_queue.empty()) return;  // stopping and drained
+      job = srv->reap_queue.front();
+      srv->reap_queue.pop_front();
+    }
+    ibim_destroy(job.ctx);
+    dfree(job.b);
+    dfree(job.x);
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->reaping -= job.bytes;
   }
-  dfree(r->d_b);
-  dfree(r->d_x);
+}
+
+size_t reaping_bytes(ibim_server* srv) {
+  std::lock_guard<std::mutex> lk(srv->mu);
+  return srv->reaping;
+}
+
+void release_device(ibim_server* srv, Request* r) {
+  if (r->ctx || r->d_b || r->d_x) {
+    {
+      std::lock_guard<std::mutex> lk(srv->mu);
+      srv->reap_queue.push_back(ibim_server::Reap{r->ctx, r->d_b, r->d_x, r->held});
+      srv->reaping += r->held;
+    }
+    srv->reap_cv.notify_one();
+    r->ctx = nullptr;
+    r->d_b = nullptr;
+    r->d_x = nullptr;
+  }
   srv->used -= r->held;
   r->held = 0;
   if (r->slot >= 0) srv->free_slots.push_back(r->slot);
@@ -282,7 +324,7 @@ void admit_waiting(ibim_server* srv, std::vector<Request*>* fresh) {
       continue;
     }
     const bool slot = !srv->free_slots.empty();
-    if (slot && srv->used + r->estimate <= srv->budget) {
+    if (slot && srv->used + reaping_bytes(srv) + r->estimate <= srv->budget) {
       const int e = admit(srv, r);
       if (e) {
         mark_failed(srv, r, e, ibim_last_error());
@@ -602,6 +644,7 @@ int ibim_server_create(const ibim_options* opt, size_t hbm_budget_bytes, int max
   }
   const int per = std::max(1, cores / host_threads);
   for (int t = 0; t < host_threads; ++t) srv->workers.emplace_back(worker_main, srv, per);
+  srv->reaper = std::thread(reaper_main, srv);
   *out = srv;
   return IBIM_OK;
 }
@@ -706,6 +749,12 @@ void ibim_server_destroy(ibim_server* srv) {
   }
   srv->cv.notify_all();
   for (auto& t : srv->workers) t.join();
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->reap_stop = true;
+  }
+  srv->reap_cv.notify_all();
+  if (srv->reaper.joinable()) srv->reaper.join();  // frees what is still queued first
   DeviceScope ds(srv->opt.device);
   if (srv->setup) {
     (void)hipStreamSynchronize(srv->setup);
