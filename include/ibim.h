@@ -333,10 +333,14 @@ int ibim_tree_plan(const ibim_ctx* ctx, int64_t* counts, int32_t* perm, int32_t*
  * GMRES tolerance) are queued by ibim_server_submit, which copies the inputs
  * and starts the host part of their setup on a background thread.  Each
  * ibim_server_step is one round:
- *   1. admission: prepared requests are set up on the device, in submission
- *      order, while a solve slot is free and the estimated device footprint
- *      (geometry, corrections, split partial sums, Krylov basis) fits in the
- *      HBM budget (a request that does not fit lets later smaller ones pass);
+ *   1. admission: prepared requests get a solve slot, in submission order,
+ *      while one is free and the estimated device footprint (geometry,
+ *      corrections, partial sums, Krylov basis) fits in the HBM budget (a
+ *      request that does not fit lets later smaller ones pass; memory of
+ *      finished requests counts until a background thread has freed it).
+ *      Their device setup runs on a background thread and a second stream
+ *      while rounds continue, and they join the first round after it (with
+ *      no solve running, the step sets them up itself);
  *   2. ONE persistent batched pair-kernel launch covers a work list of
  *      (request, target tile, source chunk) items of every active solve; each
  *      item is computed exactly as in the single-problem kernel.  Requests

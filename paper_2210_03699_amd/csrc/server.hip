@@ -51,7 +51,10 @@ struct Request {
   std::string error_msg;
   ibim_ctx* ctx = nullptr;
   size_t estimate = 0;
-  size_t held = 0;  // device bytes charged to the budget
+  size_t held = 0;  // device bytes charged to the budget (the estimate while admitting)
+  size_t setup_bytes = 0;  // device bytes once set up
+  int admit_error = 0;     // result of the device setup on the admission thread
+  std::string admit_msg;
   int slot = -1;
   double* d_b = nullptr;  // right-hand side
   double* d_x = nullptr;  // iterate
@@ -134,6 +137,16 @@ struct ibim_server {
   size_t reaping = 0;  // bytes queued or being freed (under mu)
   bool reap_stop = false;
   std::thread reaper;
+  // device setup of admitted requests while rounds run: the main thread
+  // reserves a slot and the estimated bytes and queues the request; the
+  // admission thread sets it up on the setup stream; the next round picks it up
+  std::deque<Request*> admit_queue;
+  std::vector<Request*> admitted;     // set up (or failed), not yet picked up
+  std::condition_variable admit_cv;   // work for the admission thread
+  std::condition_variable admitted_cv;
+  int admitting = 0;                  // queued or being set up (main thread)
+  bool admit_stop = false;
+  std::thread admitter;
 };
 
 namespace {
@@ -226,8 +239,10 @@ void mark_failed(ibim_server* srv, Request* r, int code, const std::string& msg)
   srv->st.failed++;
 }
 
-// Device setup and the first GMRES cycle's start (r = b, V0 = b/||b||).
-int admit(ibim_server* srv, Request* r) {
+// Device setup and the first GMRES cycle's start (r = b, V0 = b/||b||) on
+// the setup stream, for a request holding a reserved slot.  Touches only the
+// request and its slot, so it may run on the admission thread.
+int admit_device(ibim_server* srv, Request* r) {
   hipStream_t s = srv->setup;
   ibim_ctx* c = r->ctx;
   c->opt.device = srv->opt.device;
@@ -236,11 +251,7 @@ int admit(ibim_server* srv, Request* r) {
   const int64_t N = c->kr.n;
   HIP_TRY(dalloc(&r->d_b, (size_t)N), "right-hand side allocation");
   HIP_TRY(dalloc(&r->d_x, (size_t)N), "iterate allocation");
-  r->held = c->device_bytes + 2 * (size_t)N * 8;
-  srv->used += r->held;
-  if (srv->used > srv->peak) srv->peak = srv->used;
-  r->slot = srv->free_slots.back();
-  srv->free_slots.pop_back();
+  r->setup_bytes = c->device_bytes + 2 * (size_t)N * 8;
   r->M = c->P.M;
   double* st = srv->d_status + (size_t)r->slot * kStatusStride;
   if (int e = rhs_impl(c, r->d_b, s)) return e;
@@ -260,9 +271,61 @@ int admit(ibim_server* srv, Request* r) {
   r->applies = 0;
   r->bnorm = -1.0;
   r->t_admit = std::chrono::steady_clock::now();
+  return IBIM_OK;
+}
+
+void admitter_main(ibim_server* srv) {
+  (void)hipSetDevice(srv->opt.device);
+  for (;;) {
+    Request* r = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(srv->mu);
+      srv->admit_cv.wait(lk, [&] { return srv->admit_stop || !srv->admit_queue.empty(); });
+      if (srv->admit_stop) return;  // queued requests are released by the server's destroy
+      r = srv->admit_queue.front();
+      srv->admit_queue.pop_front();
+    }
+    const int e = admit_device(srv, r);
+    const std::string msg = e ? std::string(ibim_last_error()) : std::string();
+    {
+      std::lock_guard<std::mutex> lk(srv->mu);
+      r->admit_error = e;
+      r->admit_msg = msg;
+      srv->admitted.push_back(r);
+    }
+    srv->admitted_cv.notify_all();
+  }
+}
+
+// Main thread, after the device setup: the budget charge becomes the actual
+// bytes and the request joins *fresh, or it fails alone.
+void finish_admission(ibim_server* srv, Request* r, int e, const std::string& msg,
+                      std::vector<Request*>* fresh) {
+  if (e) {
+    mark_failed(srv, r, e, msg);
+    return;
+  }
+  srv->used = srv->used - r->held + r->setup_bytes;
+  r->held = r->setup_bytes;
+  if (srv->used > srv->peak) srv->peak = srv->used;
   r->state = IBIM_REQ_ACTIVE;
   srv->st.admitted++;
-  return IBIM_OK;
+  fresh->push_back(r);
+}
+
+// Requests whose device setup finished on the admission thread, in the
+// order they finished (wait: block until at least one is there).
+void collect_admitted(ibim_server* srv, std::vector<Request*>* fresh, bool wait) {
+  std::vector<Request*> done;
+  {
+    std::unique_lock<std::mutex> lk(srv->mu);
+    if (wait) srv->admitted_cv.wait(lk, [&] { return !srv->admitted.empty(); });
+    done.swap(srv->admitted);
+  }
+  for (Request* r : done) {
+    --srv->admitting;
+    finish_admission(srv, r, r->admit_error, r->admit_msg, fresh);
+  }
 }
 
 // Finishing a request: G_pol from psi at the charges, solution to the host.
@@ -306,8 +369,9 @@ int ensure_staging(T** d, T** h, size_t* cap, size_t n) {
 
 // Admission, first fit in submission order: requests whose host setup is
 // done and whose footprint fits the remaining budget get a slot and their
-// device setup (on the setup stream); they are appended to *fresh.
-void admit_waiting(ibim_server* srv, std::vector<Request*>* fresh) {
+// device setup on the setup stream, here (now: appended to *fresh) or on the
+// admission thread (picked up by a later round).
+void admit_waiting(ibim_server* srv, std::vector<Request*>* fresh, bool now) {
   std::vector<Request*> still;
   for (Request* r : srv->waiting) {
     bool prepared;
@@ -325,16 +389,24 @@ void admit_waiting(ibim_server* srv, std::vector<Request*>* fresh) {
     }
     const bool slot = !srv->free_slots.empty();
     if (slot && srv->used + reaping_bytes(srv) + r->estimate <= srv->budget) {
-      const int e = admit(srv, r);
-      if (e) {
-        mark_failed(srv, r, e, ibim_last_error());
-        continue;
+      r->slot = srv->free_slots.back();
+      srv->free_slots.pop_back();
+      r->held = r->estimate;  // reserved until the device setup reports its bytes
+      srv->used += r->held;
+      if (now) {
+        const int e = admit_device(srv, r);
+        finish_admission(srv, r, e, e ? std::string(ibim_last_error()) : std::string(), fresh);
+      } else {
+        {
+          std::lock_guard<std::mutex> lk(srv->mu);
+          srv->admit_queue.push_back(r);
+        }
+        ++srv->admitting;
+        srv->admit_cv.notify_one();
       }
-      fresh->push_back(r);
-      const int n_active = (int)(srv->active.size() + fresh->size());
-      if (n_active > srv->st.max_active_seen) srv->st.max_active_seen = n_active;
     } else {
-      if (srv->active.empty() && fresh->empty() && slot && r->estimate > srv->budget) {
+      if (srv->active.empty() && fresh->empty() && srv->admitting == 0 && slot &&
+          r->estimate > srv->budget) {
         mark_failed(srv, r, IBIM_ENOMEM, "request footprint exceeds the server's HBM budget");
         continue;
       }
@@ -346,8 +418,12 @@ void admit_waiting(ibim_server* srv, std::vector<Request*>* fresh) {
 
 int step_impl(ibim_server* srv) {
   hipStream_t s = srv->stream;
+  std::vector<Request*> fresh;
+  // requests set up on the admission thread join this round
+  collect_admitted(srv, &fresh, false);
+  if (srv->active.empty() && fresh.empty() && srv->admitting > 0) collect_admitted(srv, &fresh, true);
   // with no solve running, wait for a host setup rather than return idle
-  if (srv->active.empty() && !srv->waiting.empty()) {
+  if (srv->active.empty() && fresh.empty() && !srv->waiting.empty()) {
     std::unique_lock<std::mutex> lk(srv->mu);
     srv->ready_cv.wait(lk, [&] {
       for (Request* r : srv->waiting)
@@ -355,14 +431,15 @@ int step_impl(ibim_server* srv) {
       return false;
     });
   }
-  std::vector<Request*> fresh;
-  const bool idle = srv->active.empty();
+  const bool idle = srv->active.empty() && fresh.empty();
   if (idle) {
-    // nothing on the device: admit first and run the new requests' first round now
-    admit_waiting(srv, &fresh);
-    srv->active.swap(fresh);
-    fresh.clear();
+    // nothing on the device: admit here and run the new requests' first round now
+    admit_waiting(srv, &fresh, true);
   }
+  srv->active.insert(srv->active.end(), fresh.begin(), fresh.end());
+  fresh.clear();
+  if ((int)srv->active.size() > srv->st.max_active_seen)
+    srv->st.max_active_seen = (int)srv->active.size();
   if (srv->active.empty()) return IBIM_OK;
 
   // 2. batched pair launches over every active request: one for the problems
@@ -511,9 +588,9 @@ int step_impl(ibim_server* srv) {
                          (size_t)srv->max_slots * kStatusStride * sizeof(double),
                          hipMemcpyDeviceToHost, s),
           "copy");
-  // requests that became ready are set up while the round runs; they join
-  // the next round
-  if (!idle) admit_waiting(srv, &fresh);
+  // requests that became ready are set up on the admission thread while the
+  // round runs; they join a later round
+  if (!idle) admit_waiting(srv, &fresh, false);
   HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
 
   // 4. decisions
@@ -586,7 +663,6 @@ int step_impl(ibim_server* srv) {
     }
     keep.push_back(r);
   }
-  keep.insert(keep.end(), fresh.begin(), fresh.end());
   srv->active.swap(keep);
   return IBIM_OK;
 }
@@ -645,6 +721,7 @@ int ibim_server_create(const ibim_options* opt, size_t hbm_budget_bytes, int max
   const int per = std::max(1, cores / host_threads);
   for (int t = 0; t < host_threads; ++t) srv->workers.emplace_back(worker_main, srv, per);
   srv->reaper = std::thread(reaper_main, srv);
+  srv->admitter = std::thread(admitter_main, srv);
   *out = srv;
   return IBIM_OK;
 }
@@ -691,7 +768,7 @@ int ibim_server_step(ibim_server* srv, int* active, int* waiting) {
   DeviceScope ds(srv->opt.device);
   const int e = step_impl(srv);
   if (active) *active = (int)srv->active.size();
-  if (waiting) *waiting = (int)srv->waiting.size();
+  if (waiting) *waiting = (int)srv->waiting.size() + srv->admitting;
   return e;
 }
 
@@ -749,6 +826,12 @@ void ibim_server_destroy(ibim_server* srv) {
   }
   srv->cv.notify_all();
   for (auto& t : srv->workers) t.join();
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->admit_stop = true;
+  }
+  srv->admit_cv.notify_all();
+  if (srv->admitter.joinable()) srv->admitter.join();  // a setup in progress completes
   {
     std::lock_guard<std::mutex> lk(srv->mu);
     srv->reap_stop = true;
