@@ -73,6 +73,9 @@ typedef struct {
   double tree_theta;   /* IBIM_SUM_TREE: separation parameter, (0, 1] (default 0.7) */
   int64_t tree_min_nodes; /* IBIM_SUM_TREE: problems with fewer tube nodes use the
                              direct sum instead (default 0: every problem) */
+  int64_t pair_scratch_max; /* direct sum: device bytes the symmetric pair kernel may
+                               use for its partial sums (default 0: 32 GiB); a problem
+                               needing more uses the one-directional kernels */
 } ibim_options;
 
 /*

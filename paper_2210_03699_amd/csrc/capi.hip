@@ -211,6 +211,11 @@ int ensure_krylov(ibim_ctx* c) {
   return IBIM_OK;
 }
 
+// Partial-sum bytes the symmetric pair kernel may use under these options.
+static size_t sym_scratch_cap(const ibim_options& o) {
+  return o.pair_scratch_max > 0 ? (size_t)o.pair_scratch_max : kSymScratchMax;
+}
+
 // Checks the options shared by ibim_setup and the solve server.
 int check_options(const ibim_options& o) {
   if (o.precision != IBIM_FP64 && o.precision != IBIM_MIXED)
@@ -226,6 +231,7 @@ int check_options(const ibim_options& o) {
   if (o.summation != IBIM_SUM_DIRECT && o.summation != IBIM_SUM_TREE)
     return fail(IBIM_EINVAL, "unknown summation mode");
   if (o.tree_min_nodes < 0) return fail(IBIM_EINVAL, "tree_min_nodes must be >= 0");
+  if (o.pair_scratch_max < 0) return fail(IBIM_EINVAL, "pair_scratch_max must be >= 0");
   if (o.summation == IBIM_SUM_TREE) {
     if (o.tree_order < 2 || o.tree_order > ibim::kTreeMaxOrder)
       return fail(IBIM_EINVAL, "tree_order must be in [2, 12]");
@@ -293,7 +299,7 @@ size_t ctx_footprint_estimate(const ibim_ctx* c) {
   size_t b = 7 * M * 8 + (M + 1) * 4 + nnz * (4 + 6 * 8);
   b += (ntile + 1) * 4 + std::min(nnz, ntile * ntile) * 4;
   b += (4 * nc + (nc > 0 ? nc : 1)) * 8;
-  const SymPlan sp = make_sym_plan((int32_t)M, kSymScratchMax);
+  const SymPlan sp = make_sym_plan((int32_t)M, sym_scratch_cap(c->opt));
   if (c->opt.summation == IBIM_SUM_TREE)
     b += tree_device_bytes(c->tplan);
   else if (sp.enabled)
@@ -445,7 +451,7 @@ int ctx_setup_device(ibim_ctx* c, hipStream_t s) {
     bytes += ((size_t)M + 1) * 8 + (size_t)P.nnear * 4;
   }
   c->pair = make_pair_plan(M, o.precision);
-  c->sym = make_sym_plan(M, o.summation == IBIM_SUM_TREE ? 0 : kSymScratchMax);
+  c->sym = make_sym_plan(M, o.summation == IBIM_SUM_TREE ? 0 : sym_scratch_cap(o));
   if (o.summation == IBIM_SUM_TREE) {
     // the plan was built with the geometry (ctx_create_host)
     e = tree_upload(c->tplan, P, pl.px.data(), pl.py.data(), pl.pz.data(), pl.nx.data(),
@@ -560,6 +566,7 @@ void ibim_default_options(ibim_options* opt) {
   opt->tree_order = 8;
   opt->tree_theta = 0.7;
   opt->tree_min_nodes = 0;
+  opt->pair_scratch_max = 0;
 }
 
 const char* ibim_last_error(void) { return g_last_error.c_str(); }

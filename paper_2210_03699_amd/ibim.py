@@ -43,7 +43,7 @@ class _Options(ctypes.Structure):
                 ("r_near", ctypes.c_double), ("hybrid", ctypes.c_int),
                 ("precond", ctypes.c_int), ("summation", ctypes.c_int),
                 ("tree_order", ctypes.c_int), ("tree_theta", ctypes.c_double),
-                ("tree_min_nodes", ctypes.c_int64)]
+                ("tree_min_nodes", ctypes.c_int64), ("pair_scratch_max", ctypes.c_int64)]
 
 
 class _SolveInfo(ctypes.Structure):
@@ -170,7 +170,7 @@ class Problem:
     def __init__(self, sdf, origin, h, eps_tube, eps_in, eps_out, kappa, charge_xyz=None,
                  charge_q=None, precision=FP64, restart=60, max_iter=300, check_residual=True,
                  device=0, r_near=0.0, hybrid=CTR2, precond=PRECOND_DIAG, summation=SUM_DIRECT,
-                 tree_order=8, tree_theta=0.7, tree_min_nodes=0, stream=None):
+                 tree_order=8, tree_theta=0.7, tree_min_nodes=0, pair_scratch_max=0, stream=None):
         lib = load()
         self._lib = lib
         sdf = np.ascontiguousarray(sdf, dtype=np.float64)
@@ -196,6 +196,7 @@ class Problem:
         opt.tree_order = int(tree_order)
         opt.tree_theta = float(tree_theta)
         opt.tree_min_nodes = int(tree_min_nodes)
+        opt.pair_scratch_max = int(pair_scratch_max)
         self.device = int(device)
         self.h = float(h)
         ctx = ctypes.c_void_p()
@@ -379,7 +380,7 @@ class Server:
     def __init__(self, hbm_budget_bytes, max_slots=16, host_threads=4, precision=FP64,
                  restart=60, max_iter=300, check_residual=True, device=0, r_near=0.0,
                  hybrid=CTR2, precond=PRECOND_DIAG, summation=SUM_DIRECT, tree_order=8,
-                 tree_theta=0.7, tree_min_nodes=0, stream=None):
+                 tree_theta=0.7, tree_min_nodes=0, pair_scratch_max=0, stream=None):
         lib = load()
         self._lib = lib
         opt = _Options()
@@ -396,6 +397,7 @@ class Server:
         opt.tree_order = int(tree_order)
         opt.tree_theta = float(tree_theta)
         opt.tree_min_nodes = int(tree_min_nodes)
+        opt.pair_scratch_max = int(pair_scratch_max)
         srv = ctypes.c_void_p()
         _check(lib.ibim_server_create(ctypes.byref(opt), int(hbm_budget_bytes), int(max_slots),
                                       int(host_threads), _stream_ptr(stream), ctypes.byref(srv)))

@@ -136,6 +136,43 @@ def test_solve_and_energy_match_oracle(pair):
     assert abs(g_on_oracle_x - info_o["g_pol"]) <= 1e-12 * abs(info_o["g_pol"])
 
 
+# The one-directional kernels: the path of problems whose symmetric partial
+# sums would exceed the scratch cap (32 GiB by default, M above ~2e6), forced
+# here by a one-byte cap.
+ONEDIR = ["born_h0.2", "offset_sphere", "torus", "kirkwood_small", "ses_molecule"]
+
+
+@pytest.mark.parametrize("name", ONEDIR)
+@pytest.mark.parametrize("precision,bar", [(ibim.FP64, 1e-12), (ibim.MIXED, 1e-6)])
+def test_one_directional_apply_matches_oracle(name, precision, bar):
+    wl = CASES[name]()
+    prob = ibim.Problem.from_workload(wl, device=0, precision=precision, pair_scratch_max=1)
+    orc = oracle.Oracle.from_workload(wl)
+    u = workloads.random_vector(2 * prob.M, 11)
+    out = prob.apply(torch.from_numpy(u).to(DEV)).cpu().numpy()
+    err = _blockwise_rel(out, orc.apply(u), prob.M)
+    pairs, flops = prob.pair_work()
+    _say(f"[{name} one-directional precision={precision}] apply rel err {err:.3e} "
+         f"flops/pair {flops / pairs:.1f}")
+    assert flops == 60.0 * prob.M * prob.M  # the one-directional count: no shared evaluation
+    assert err < bar, (name, err)
+    prob.close()
+
+
+@pytest.mark.parametrize("name", ["kirkwood_small", "ses_molecule"])
+def test_one_directional_solve_matches_oracle(name):
+    wl = CASES[name]()
+    prob = ibim.Problem.from_workload(wl, device=0, pair_scratch_max=1)
+    orc = oracle.Oracle.from_workload(wl)
+    x, info = prob.solve_energy(1e-10)
+    _, info_o = orc.solve_energy(wl.charge_xyz, wl.charge_q, 1e-10)
+    _say(f"[{name} one-directional] iters {info['iters']} / {info_o['iters']} "
+         f"G {info['g_pol']:.15e} / {info_o['g_pol']:.15e}")
+    assert info["converged"] and abs(info["iters"] - info_o["iters"]) <= 1
+    assert abs(info["g_pol"] - info_o["g_pol"]) <= 1e-10 * abs(info_o["g_pol"])
+    prob.close()
+
+
 def test_restarted_solve_matches_oracle():
     wl = workloads.born_sphere(h=0.4)
     prob = ibim.Problem.from_workload(wl, device=0, restart=4, max_iter=200)

@@ -145,6 +145,38 @@ def test_tree_requests_in_the_mix(wls):
     assert 0 < n_tree < len(names)
 
 
+@pytest.mark.parametrize("precision", [ibim.FP64, ibim.MIXED])
+def test_one_directional_requests_in_the_mix(wls, precision):
+    """With a scratch cap that sends the larger requests to the one-directional
+    kernels, both batched pair launches run in the same rounds; every result
+    is still the same bits alone, in the mix and through ibim_solve."""
+    names = list(MIX)
+    sizes = {}
+    for n in names:
+        p = ibim.Problem.from_workload(wls[n], device=-1)
+        sizes[n] = p.M
+        p.close()
+    # the symmetric partial sums take about T^2 (1 + 1/(2 rows)) x 4 KiB for T
+    # tiles of 256 nodes: half of the largest problem's T^2 x 4 KiB sends it
+    # (and only the larger problems) to the one-directional kernels
+    cap = 4096 * (max(sizes.values()) // 256 + 1) ** 2 // 2
+    opt = dict(precision=precision, pair_scratch_max=cap)
+    onedir = {}
+    for n in names:
+        p = ibim.Problem.from_workload(wls[n], device=0, **opt)
+        pairs, flops = p.pair_work()
+        onedir[n] = flops == 60.0 * pairs  # (a one-tile problem counts 60 on either path)
+        p.close()
+    assert any(onedir.values()) and not all(onedir.values()), onedir
+    mixed, stats = _serve(wls, names, **opt)
+    _say(f"[serving one-directional cap={cap}] sizes {sizes} one-directional {onedir}")
+    assert stats["finished"] == len(names) and stats["failed"] == 0
+    for n in names:
+        alone, _ = _serve(wls, [n], slots=1, **opt)
+        _same(alone[n], mixed[n], f"{n} alone vs mix")
+        _same(_direct(wls[n], **opt), mixed[n], f"{n} ibim_solve vs server")
+
+
 def test_energy_matches_oracle(wls):
     wl = wls["kirkwood_small"]
     out, _ = _serve(wls, ["kirkwood_small", "born_h0.4"])
