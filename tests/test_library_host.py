@@ -143,3 +143,6 @@ def test_python_binding_rejects_bad_arguments():
                      device=-1, restart=0)
     with pytest.raises(ValueError):
         ibim.Problem(sdf, org, 0.2, 0.4, 1.0, 80.0, 0.1, np.zeros((2, 3)), np.ones(1), device=-1)
+    with pytest.raises(ibim.IbimError):
+        ibim.Problem(sdf, org, 0.2, 0.4, 1.0, 80.0, 0.1, np.zeros((1, 3)), np.ones(1),
+                     device=-1, pair_scratch_max=-1)
