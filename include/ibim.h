@@ -363,7 +363,8 @@ typedef struct {
   int64_t submitted, admitted, finished, failed;
   int64_t rounds;           /* ibim_server_step calls that did device work */
   int64_t batched_items;    /* pair-kernel work items over all rounds */
-  size_t bytes_in_use;      /* device bytes held by active solves */
+  size_t bytes_in_use;      /* device bytes charged to the budget: active solves, and
+                               requests being set up at their estimate */
   size_t bytes_peak;
   size_t budget_bytes;
   int active, waiting, max_active_seen;

@@ -813,7 +813,7 @@ int ibim_server_get_stats(ibim_server* srv, ibim_server_stats* st) {
   srv->st.bytes_in_use = srv->used;
   srv->st.bytes_peak = srv->peak;
   srv->st.active = (int)srv->active.size();
-  srv->st.waiting = (int)srv->waiting.size();
+  srv->st.waiting = (int)srv->waiting.size() + srv->admitting;  // as ibim_server_step
   *st = srv->st;
   return IBIM_OK;
 }
