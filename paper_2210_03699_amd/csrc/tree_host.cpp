@@ -56,28 +56,49 @@ struct Builder {
     nd.r = std::sqrt(r2);
   }
 
-  int build(int32_t s, int32_t e) {
-    Node nd;
+  // The shape depends on the counts only: a cluster of n > kTreeBatch points
+  // splits into ceil(nb/2) batches and the rest (nb batches in all).
+  static int32_t split(int32_t s, int32_t e) {
+    const int32_t nb = (e - s + kTreeBatch - 1) / kTreeBatch;
+    return s + ((nb + 1) / 2) * kTreeBatch;
+  }
+  static int count(int32_t s, int32_t e) {
+    if (e - s <= kTreeBatch) return 1;
+    const int32_t mid = split(s, e);
+    return 1 + count(s, mid) + count(mid, e);
+  }
+
+  // Node id (preorder) of [s, e) and its subtree from id on; large subtrees
+  // are built as tasks of the enclosing parallel region (disjoint ranges of
+  // perm and of nodes, so the result does not depend on the schedule).
+  void build(int32_t s, int32_t e, int id) {
+    Node& nd = nodes[id];
     nd.s = s;
     nd.e = e;
     box(nd);
-    const int id = (int)nodes.size();
-    nodes.push_back(nd);
     if (e - s > kTreeBatch) {
       int d = 0;
       for (int q = 1; q < 3; ++q)
         if (nd.hi[q] - nd.lo[q] > nd.hi[d] - nd.lo[d]) d = q;
-      const int32_t nb = (e - s + kTreeBatch - 1) / kTreeBatch;
-      const int32_t mid = s + ((nb + 1) / 2) * kTreeBatch;
+      const int32_t mid = split(s, e);
       const double* pd = p[d];
       std::nth_element(perm->begin() + s, perm->begin() + mid, perm->begin() + e,
                        [pd](int32_t a, int32_t b) { return pd[a] < pd[b] || (pd[a] == pd[b] && a < b); });
-      const int l = build(s, mid);
-      const int r = build(mid, e);
-      nodes[id].kid[0] = l;
-      nodes[id].kid[1] = r;
+      const int l = id + 1, r = id + 1 + count(s, mid);
+      nd.kid[0] = l;
+      nd.kid[1] = r;
+#pragma omp task if (mid - s > 32 * kTreeBatch) default(none) firstprivate(s, mid, l)
+      build(s, mid, l);
+      build(mid, e, r);
+#pragma omp taskwait
     }
-    return id;
+  }
+
+  void build_all(int32_t M) {
+    nodes.assign((size_t)count(0, M), Node());
+#pragma omp parallel
+#pragma omp single
+    build(0, M, 0);
   }
 };
 
@@ -122,7 +143,7 @@ int build_tree_plan(const TreeParams& prm, int64_t M64, const double* px, const 
   B.p[1] = py;
   B.p[2] = pz;
   B.perm = &pl.perm;
-  B.build(0, M);
+  B.build_all(M);
   const std::vector<Node>& nd = B.nodes;
   pl.pos.resize(M);
   for (int32_t t = 0; t < M; ++t) pl.pos[pl.perm[t]] = t;
