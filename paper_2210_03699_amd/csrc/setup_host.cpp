@@ -116,22 +116,32 @@ int build_host_plan(const double* sdf, int nx, int ny, int nz, const double orig
   plan->h = h;
   plan->eps = eps;
 
-  // Tube membership in grid scan order.
-  std::vector<int32_t> node_of(ngrid, -1);
-  int64_t M = 0;
-  for (int64_t q = 0; q < ngrid; ++q) {
-    double v = sdf[q];
-    if (std::isnan(v)) {
-      *err = "NaN in the signed distance";
-      return IBIM_EGEOM;
+  // Tube membership in grid scan order: nodes counted per chunk of the grid,
+  // then numbered from each chunk's offset (the same numbering as one scan).
+  const int64_t kChunk = 1 << 16;
+  const int64_t nchunk = (ngrid + kChunk - 1) / kChunk;
+  std::vector<int64_t> first(nchunk + 1, 0);
+  int has_nan = 0;
+#pragma omp parallel for schedule(static) reduction(| : has_nan)
+  for (int64_t c = 0; c < nchunk; ++c) {
+    const int64_t q1 = std::min(ngrid, (c + 1) * kChunk);
+    int64_t n = 0;
+    for (int64_t q = c * kChunk; q < q1; ++q) {
+      const double v = sdf[q];
+      has_nan |= std::isnan(v) ? 1 : 0;
+      n += std::fabs(v) < eps ? 1 : 0;
     }
-    if (std::fabs(v) < eps) {
-      if (M >= INT32_MAX) {
-        *err = "more than 2^31-1 tube nodes";
-        return IBIM_EINVAL;
-      }
-      node_of[q] = (int32_t)M++;
-    }
+    first[c + 1] = n;
+  }
+  if (has_nan) {
+    *err = "NaN in the signed distance";
+    return IBIM_EGEOM;
+  }
+  for (int64_t c = 0; c < nchunk; ++c) first[c + 1] += first[c];
+  const int64_t M = first[nchunk];
+  if (M > INT32_MAX) {
+    *err = "more than 2^31-1 tube nodes";
+    return IBIM_EINVAL;
   }
   if (M == 0) {
     *err = "empty tube: no grid node with |d| < eps_tube";
@@ -139,8 +149,20 @@ int build_host_plan(const double* sdf, int nx, int ny, int nz, const double orig
   }
   plan->M = M;
   plan->grid_index.resize(M);
-  for (int64_t q = 0; q < ngrid; ++q)
-    if (node_of[q] >= 0) plan->grid_index[node_of[q]] = q;
+  std::vector<int32_t> node_of(ngrid);
+#pragma omp parallel for schedule(static)
+  for (int64_t c = 0; c < nchunk; ++c) {
+    const int64_t q1 = std::min(ngrid, (c + 1) * kChunk);
+    int64_t m = first[c];
+    for (int64_t q = c * kChunk; q < q1; ++q) {
+      if (std::fabs(sdf[q]) < eps) {
+        plan->grid_index[m] = q;
+        node_of[q] = (int32_t)m++;
+      } else {
+        node_of[q] = -1;
+      }
+    }
+  }
 
   auto& G = *plan;
   G.px.resize(M); G.py.resize(M); G.pz.resize(M);

@@ -106,7 +106,8 @@ def test_alone_equals_mixed_equals_direct(wls, precision, restart, hybrid):
         _say(f"[serving] {n}: iters={mixed[n][2]['iters']} G={mixed[n][0]:.12e}")
 
 
-def test_tree_requests_in_the_mix(wls):
+@pytest.mark.parametrize("precision", [ibim.FP64, ibim.MIXED])
+def test_tree_requests_in_the_mix(wls, precision):
     """With IBIM_SUM_TREE and a size threshold, requests of at least
     tree_min_nodes nodes run the float64 treecode inside the rounds and the
     others the batched mixed kernel.  Every result is the same bits alone, in
@@ -121,7 +122,7 @@ def test_tree_requests_in_the_mix(wls):
         sizes[n] = p.M
         p.close()
     thr = sorted(sizes.values())[len(sizes) // 2]
-    opt = dict(precision=ibim.MIXED, summation=ibim.SUM_TREE, tree_min_nodes=thr)
+    opt = dict(precision=precision, summation=ibim.SUM_TREE, tree_min_nodes=thr)
     names = list(pool)
     _say(f"[serving] tree threshold {thr}: sizes {sizes}")
     mixed, stats = _serve(pool, names, **opt)
