@@ -365,7 +365,26 @@ def test_full_sampled_weights(full):
 def test_full_solve(full):
     name, wl, prob, gold = full
     if "g_pol" not in gold:
-        pytest.skip("no stored oracle solve for this workload")
+        # ses2000: an oracle solve (~46 applications of 1e11 pairs) is out of
+        # the oracle's reach here; its solve is pinned on the h = 0.7 twin.  At
+        # full size: the right-hand side on the stored rows, and the FP64 and
+        # mixed solves against each other and their explicit residuals.
+        M = prob.M
+        g = prob.rhs()
+        rows = np.array(gold["rows"])
+        gh = g.cpu().numpy()
+        assert np.max(np.abs(gh[rows] - gold["rhs_rows_1"])) < 1e-13 * np.max(np.abs(gh[:M]))
+        x, info = prob.solve_energy(wl.tol)
+        mixed = ibim.Problem.from_workload(wl, device=0, precision=ibim.MIXED)
+        xm, info_m = mixed.solve_energy(wl.tol)
+        mixed.close()
+        _say(f"[{name} full] fp64 iters={info['iters']} G={info['g_pol']:.15e}; "
+             f"mixed iters={info_m['iters']} G={info_m['g_pol']:.15e}")
+        assert info["converged"] and info_m["converged"]
+        assert info["explicit_rel_resid"] < 10 * wl.tol
+        assert info_m["explicit_rel_resid"] < 10 * wl.tol
+        assert abs(info_m["g_pol"] - info["g_pol"]) <= 1e-6 * abs(info["g_pol"])
+        return
     M = prob.M
     g = prob.rhs()
     rows = np.array(gold["rows"])
