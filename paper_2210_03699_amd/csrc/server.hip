@@ -1,13 +1,15 @@
 // Solve server: continuous batching of independent CTR-IBIM solves on one GPU.
 //
 // A request moves through: submitted -> host setup on a background thread
-// (geometry and correction sets) -> waiting for admission -> active (device
-// data, Krylov basis) -> done (G_pol and the solution kept on the host) or
-// failed.  Each round does one persistent batched pair-kernel launch over the
-// work items of every active direct-sum solve, then per request the treecode
-// launches (requests that the options send to it) and the GMRES step.  The
-// per-request sequence of kernels and their inputs are those of ibim_solve
-// and ibim_energy, so results do not depend on the mix of requests.
+// (geometry and correction sets) -> waiting for admission -> device setup on
+// the admission thread (uploads, correction weights, Krylov basis; a second
+// stream) -> active -> done (G_pol and the solution kept on the host; its
+// device memory freed on the reaper thread) or failed.  Each round does one
+// persistent batched pair-kernel launch over the work items of every active
+// direct-sum solve, the treecode launches of requests that the options send
+// to it, one batched finishing launch per precision and one launch per GMRES
+// stage for all solves.  Every request gets the blocks and reduction order of
+// ibim_solve and ibim_energy, so results do not depend on the mix of requests.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
