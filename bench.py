@@ -8,9 +8,17 @@ explicit residual check, and the polarisation energy.  The problem setup
 (signed distance on the host -> geometry, correction sets and weights on the
 device) is timed separately because it consumes host buffers.
 
+Default workload: the 2000-atom random-walk molecule (SES, 40 A box) at
+h = 0.35, eps = 2h, float64 pairs, GMRES tol 1e-6.
+
 value = pair interactions evaluated in all operator applications of the timed
 steps / wall time of those steps (one pair = the four kernels for one
-(target, source)).  Also reported: solves/s and per-solve latency.
+(target, source)).  Also reported: solves/s, per-solve latency, the dominant
+kernel's roofline (60 algorithmic flops per ordered pair against the FP64
+vector peak; the flops as evaluated and the VALU-counter flops beside it), a
+mixed-precision leg on the same problem (solves/s, G_pol and solution error
+against the FP64 solve), the oracle check of the coarsened h = 0.7 twin and
+the oracle's own rates on the host.
 
 Prints ONE JSON line.  ``--gpus`` above 1 is refused: this build runs on one
 GPU.
@@ -32,13 +40,21 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6  # MI355X vector FP64
 PEAK_FP32_VECTOR_TFLOPS = 157.3  # MI355X vector FP32 (counts packed float32 issue)
 
 
-# HBM bytes per pair-kernel launch on the Kirkwood workload, from rocprofv3
-# FETCH_SIZE and WRITE_SIZE (KiB per dispatch, scaled by 2.0 and 1.0: what the
-# counters read for a plain 256 MiB copy).  Valid only while the kernel sources
-# hash to the recorded digest; otherwise the traffic is reported as null.
-MEASURED_TRAFFIC = {
-    "fp64": ("10d64cac", 683.2e6),
-    "mixed": ("ef43987d", 504.4e6),
+FLOPS_PER_PAIR = 60  # algorithmic flops of the four kernels for one ordered pair (FMA = 2)
+
+# Counter figures of the dominant pair kernel, per (precision, workload), from
+# the rocprofv3 summaries under profiles/: HBM bytes per launch (FETCH_SIZE and
+# WRITE_SIZE, KiB per dispatch, scaled by what they read for a plain 256 MiB
+# copy: 2.0 and 1.0), VALU flops per launch (SQ_INSTS_VALU_FLOPS_FP64 or _FP32
+# x 64 lanes) and the average duration of the counted dispatches.  Valid only
+# while the kernel sources hash to the recorded digest; otherwise null.
+MEASURED_COUNTERS = {
+    ("fp64", "kirkwood"): {"digest": "10d64cac", "traffic_bytes": 683.2e6,
+                           "valu_flops": 11622290460 * 64, "ms": 18.67,
+                           "source": "profiles/pair_sym_fp64_kirkwood_R10_h0.25.md"},
+    ("mixed", "kirkwood"): {"digest": "ef43987d", "traffic_bytes": 504.4e6,
+                            "valu_flops": 7531334384 * 64, "ms": 10.06,
+                            "source": "profiles/pair_sym_mixed_kirkwood_R10_h0.25.md"},
 }
 # stored oracle results (tests/golden/make_golden.py) per workload
 GOLDEN = {"kirkwood": "kirkwood_R10_h0.25.json", "ses500": "ses500_h0.3.json",
@@ -210,12 +226,128 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_solve_baseline():
+    """One complete oracle solve (setup + GMRES + G_pol) of the Born ion, the
+    smallest configuration (sphere R = 2, h = 0.2, tol 1e-10, M = 5,020)."""
+    import oracle
+    import workloads
+
+    wl = workloads.born_sphere()
+    t = time.perf_counter()
+    orc = oracle.Oracle.from_workload(wl)
+    t_setup = time.perf_counter() - t
+    t = time.perf_counter()
+    _, info = orc.solve_energy(wl.charge_xyz, wl.charge_q, wl.tol)
+    t_solve = time.perf_counter() - t
+    return wl, {"workload": wl.name, "M": orc.M, "setup_s": t_setup, "solve_s": t_solve,
+                "solves_per_s": 1.0 / t_solve, "iters": info["iters"], "g_pol": info["g_pol"]}
+
+
+def measured_profile(precision, workload):
+    """Counter figures of the dominant pair kernel from profiles/, valid while
+    the kernel sources hash to the digest they were taken with."""
+    rec = MEASURED_COUNTERS.get((precision, workload))
+    if rec is None or kernel_digest(precision) != rec["digest"]:
+        return None
+    return rec
+
+
+def timed_solves(prob, tol, steps, warmup, label):
+    """warmup + steps complete solves (rhs, GMRES, explicit residual, G_pol)."""
+    import torch
+
+    def step():
+        g = prob.rhs()
+        x, info = prob.solve(g, tol)
+        G = prob.energy(x)  # synchronises the stream
+        return x, info, G
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    prob.pair_timing(True)
+    lat, applies, iters, x, G = [], 0, [], None, None
+    t_start = time.perf_counter()
+    for i in range(steps):
+        ts = time.perf_counter()
+        x, info, G = step()
+        lat.append(time.perf_counter() - ts)
+        applies += info["applies"]
+        iters.append(info["iters"])
+        print(f"[bench] {label} step {i}: {lat[-1] * 1e3:.1f} ms iters={info['iters']} "
+              f"G_pol={G:.12e}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    n_launch, pair_ms = prob.pair_timing_read()
+    prob.pair_timing(False)
+    return {"elapsed": elapsed, "lat": lat, "applies": applies, "iters": iters, "x": x, "G": G,
+            "pair_ms": pair_ms / max(n_launch, 1), "n_launch": n_launch}
+
+
+def block_errors(x, ref, M):
+    """Max and RMS error of the psi and psi_n blocks relative to the largest
+    entry of the reference block."""
+    out = {}
+    for name, sl in (("psi", slice(0, M)), ("psi_n", slice(M, 2 * M))):
+        d = x[sl] - ref[sl]
+        s = max(float(abs(ref[sl]).max()), 1e-300)
+        out[name] = {"max_rel": float(abs(d).max()) / s,
+                     "rms_rel": float((d * d).mean() ** 0.5) / s}
+    return out
+
+
+def twin_check(args):
+    """FP64 and mixed solves of the 2000-atom molecule on the coarsened
+    h = 0.7 grid against the stored oracle solve (G_pol, sampled solution rows)."""
+    import numpy as np
+
+    import workloads
+    from paper_2210_03699_amd import FP64, MIXED, Problem
+
+    path = os.path.join(ROOT, "tests", "golden", "ses2000_twin_h0.7.json")
+    gold = json.load(open(path))
+    wl = workloads.by_name("ses2000_twin")
+    rows = np.asarray(gold["rows"], dtype=np.int64)
+    xr1, xr2 = np.asarray(gold["x_rows_1"]), np.asarray(gold["x_rows_2"])
+    out = {"workload": wl.name, "M": gold["M"], "oracle_g_pol": gold["g_pol"],
+           "oracle_iters": gold["gmres"]["iters"]}
+    for label, mode in (("fp64", FP64), ("mixed", MIXED)):
+        prob = Problem.from_workload(wl, device=0, precision=mode)
+        x, info = prob.solve_energy(wl.tol)
+        xh = x.cpu().numpy()
+        M = prob.M
+        out[label] = {
+            "iters": info["iters"],
+            "g_pol": info["g_pol"],
+            "g_pol_rel_err_vs_oracle": abs(info["g_pol"] - gold["g_pol"]) / abs(gold["g_pol"]),
+            "psi_rows_max_rel_err_vs_oracle":
+                float(np.max(np.abs(xh[rows] - xr1)) / np.max(np.abs(xr1))),
+            "psi_n_rows_max_rel_err_vs_oracle":
+                float(np.max(np.abs(xh[M + rows] - xr2)) / np.max(np.abs(xr2))),
+        }
+        prob.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="kirkwood")
+    ap.add_argument("--workload", default="ses2000",
+                    help="named workload (workloads.by_name); default: the 2000-atom SES "
+                         "molecule at h = 0.35, the largest single-GPU configuration")
     ap.add_argument("--rows", default="ctr2", choices=["ctr2", "hyb", "kreg"],
                     help="quadrature of the rows: CTR2 everywhere, HYB-IBIM (K-reg rows at "
                          "bad nodes), or K-reg everywhere")
@@ -230,6 +362,11 @@ def main():
                          "application stands for)")
     ap.add_argument("--tree-order", type=int, default=8)
     ap.add_argument("--tree-theta", type=float, default=0.7)
+    ap.add_argument("--mixed-steps", type=int, default=5,
+                    help="timed solves of the mixed-precision leg (after one warm-up solve)")
+    ap.add_argument("--no-mixed-leg", action="store_true")
+    ap.add_argument("--no-twin", action="store_true",
+                    help="skip the oracle check on the h = 0.7 twin of the 2000-atom molecule")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile", action="store_true",
@@ -238,13 +375,13 @@ def main():
     ap.add_argument("--serve", action="store_true",
                     help="serving benchmark: a seeded stream of independent requests through "
                          "the continuous-batching server (p50/p99 latency, solves/s)")
-    ap.add_argument("--requests", type=int, default=32)
+    ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--slots", type=int, default=16)
     ap.add_argument("--host-threads", type=int, default=8)
     ap.add_argument("--hbm-budget-gib", type=float, default=64.0)
-    ap.add_argument("--hs", default="0.3,0.5",
+    ap.add_argument("--hs", default="0.2,0.3,0.5",
                     help="--serve: grid spacings the stream draws from (comma list)")
-    ap.add_argument("--ses-atoms", default="50,200",
+    ap.add_argument("--ses-atoms", default="50,2000",
                     help="--serve: atom-count range of the stream's molecules")
     ap.add_argument("--tree-min-nodes", type=int, default=0,
                     help="with --summation tree: requests below this many nodes keep the "
@@ -264,22 +401,25 @@ def main():
     from paper_2210_03699_amd import (CTR2, FP64, HYB, KREG, MIXED, PRECOND_DIAG, PRECOND_NONE,
                                       SUM_DIRECT, SUM_TREE, Problem)
 
+    t0 = time.perf_counter()
     wl = workloads.by_name(args.workload)
+    input_s = time.perf_counter() - t0
     dev = "cuda:0"
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
     mode = FP64 if args.precision == "fp64" else MIXED
     rows = {"ctr2": CTR2, "hyb": HYB, "kreg": KREG}[args.rows]
     precond = PRECOND_NONE if args.unscaled else PRECOND_DIAG
     tree = args.summation == "tree"
-    prob = Problem.from_workload(wl, device=0, precision=mode, hybrid=rows, precond=precond,
-                                 summation=SUM_TREE if tree else SUM_DIRECT,
-                                 tree_order=args.tree_order, tree_theta=args.tree_theta)
+    kw = dict(device=0, hybrid=rows, precond=precond,
+              summation=SUM_TREE if tree else SUM_DIRECT, tree_order=args.tree_order,
+              tree_theta=args.tree_theta)
+    t0 = time.perf_counter()
+    prob = Problem.from_workload(wl, precision=mode, **kw)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     M = prob.M
-    print(f"[bench] {wl.name}: M={M} nnz={prob.nnz} setup {setup_s:.2f}s", file=sys.stderr,
-          flush=True)
+    print(f"[bench] {wl.name}: M={M} nnz={prob.nnz} input {input_s:.1f}s setup {setup_s:.2f}s",
+          file=sys.stderr, flush=True)
 
     if args.profile:
         u = torch.from_numpy(workloads.random_vector(2 * M, 1)).to(dev)
@@ -292,39 +432,39 @@ def main():
         print(json.dumps({"profile": True, "M": M, "copy_bytes": src.numel() * 8}), flush=True)
         return
 
-    def step():
-        g = prob.rhs()
-        x, info = prob.solve(g, wl.tol)
-        G = prob.energy(x)  # synchronises the stream
-        return info, G
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    prob.pair_timing(True)
-    lat, applies, iters, G = [], 0, [], None
-    t_start = time.perf_counter()
-    for i in range(args.steps):
-        ts = time.perf_counter()
-        info, G = step()
-        lat.append(time.perf_counter() - ts)
-        applies += info["applies"]
-        iters.append(info["iters"])
-        print(f"[bench] step {i}: {lat[-1] * 1e3:.1f} ms iters={info['iters']} G_pol={G:.12e}",
-              file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    n_launch, pair_ms = prob.pair_timing_read()
-    prob.pair_timing(False)
-
+    r = timed_solves(prob, wl.tol, args.steps, args.warmup, args.precision)
+    elapsed, lat = r["elapsed"], r["lat"]
+    pairs = float(r["applies"]) * M * M
+    avg_pair_ms = r["pair_ms"]
     peak = PEAK_FP64_VECTOR_TFLOPS if args.precision == "fp64" else PEAK_FP32_VECTOR_TFLOPS
-    pairs = float(applies) * M * M
-    avg_pair_ms = pair_ms / max(n_launch, 1)
-    _, pair_flops = prob.pair_work()
-    achieved_tflops = pair_flops / (avg_pair_ms * 1e-3) / 1e12
-    digest, measured = MEASURED_TRAFFIC[args.precision]
-    traffic = measured if (args.workload == "kirkwood" and not tree
-                           and kernel_digest(args.precision) == digest) else None
+    _, performed_flops = prob.pair_work()
+    alg_flops = FLOPS_PER_PAIR * float(M) * M
+    achieved = alg_flops / (avg_pair_ms * 1e-3) / 1e12
+    prof = None if tree else measured_profile(args.precision, args.workload)
+    roofline = {
+        "bound": "alu",
+        "achieved": achieved,
+        "peak": peak,
+        "unit": "TFLOP/s",
+        "frac": achieved / peak,
+        "traffic": prof["traffic_bytes"] if prof else None,
+        "kernel": "pair_sym_fp64_kernel" if args.precision == "fp64" else "pair_sym_mixed_kernel",
+        "flops_per_launch": alg_flops,
+        "flop_count": f"algorithmic: {FLOPS_PER_PAIR} flops per ordered pair x M^2 ordered pairs",
+        "launch_ms": avg_pair_ms,
+        "performed": {
+            "flops_per_launch": performed_flops,
+            "achieved": performed_flops / (avg_pair_ms * 1e-3) / 1e12,
+            "frac": performed_flops / (avg_pair_ms * 1e-3) / 1e12 / peak,
+            "flop_count": "as evaluated: 68 per shared evaluation of both directions of a pair, "
+                          "60 per one-directional pair (diagonal, corrected and ragged tiles)"},
+        "valu_counter": None if prof is None else {
+            "flops_per_launch": prof["valu_flops"],
+            "launch_ms": prof["ms"],
+            "achieved": prof["valu_flops"] / (prof["ms"] * 1e-3) / 1e12,
+            "frac": prof["valu_flops"] / (prof["ms"] * 1e-3) / 1e12 / peak,
+            "source": prof["source"]},
+    }
     out = {
         "metric": METRIC,
         "value": pairs / elapsed,
@@ -348,21 +488,14 @@ def main():
         },
         "solves_per_s": args.steps / elapsed,
         "latency_ms": {"p50": percentile(lat, 50) * 1e3, "p99": percentile(lat, 99) * 1e3},
-        "gmres_iters": iters,
-        "applies_per_solve": applies / args.steps,
+        "gmres_iters": r["iters"],
+        "applies_per_solve": r["applies"] / args.steps,
         "pair_kernel_ms": avg_pair_ms,
         "pair_kernel_pairs_per_s": float(M) * M / (avg_pair_ms * 1e-3),
-        "pair_kernel_flops_per_launch": pair_flops,
+        "input_s": input_s,
         "setup_s": setup_s,
-        "g_pol": G,
-        "roofline": {
-            "bound": "alu",
-            "achieved": achieved_tflops,
-            "peak": peak,
-            "unit": "TFLOP/s",
-            "frac": achieved_tflops / peak,
-            "traffic": traffic,
-        },
+        "g_pol": r["G"],
+        "roofline": roofline,
     }
     if tree:
         tc = prob.tree_counts()
@@ -376,10 +509,63 @@ def main():
     if os.path.exists(golden):
         gold = json.load(open(golden))
         if "g_pol" in gold:
-            out["g_pol_rel_err_vs_oracle"] = abs(G - gold["g_pol"]) / abs(gold["g_pol"])
+            out["g_pol_rel_err_vs_oracle"] = abs(r["G"] - gold["g_pol"]) / abs(gold["g_pol"])
+        else:
+            # sampled operator rows of the stored oracle values (no full oracle solve)
+            grows = np.asarray(gold["rows"], dtype=np.int64)
+            u = torch.from_numpy(workloads.random_vector(2 * M, gold["u_seed"])).to(dev)
+            Au = prob.apply(u).cpu().numpy()
+            a1, a2 = np.asarray(gold["apply_rows_1"]), np.asarray(gold["apply_rows_2"])
+            out["apply_rows_rel_err_vs_oracle"] = max(
+                float(np.max(np.abs(Au[grows] - a1)) / np.max(np.abs(a1))),
+                float(np.max(np.abs(Au[M + grows] - a2)) / np.max(np.abs(a2))))
+    x64 = r["x"].cpu().numpy()
+
+    if args.precision == "fp64" and not tree and not args.no_mixed_leg:
+        # the mixed form on the same problem: speed and its error against FP64
+        prob.close()
+        del prob
+        torch.cuda.empty_cache()
+        pm = Problem.from_workload(wl, precision=MIXED, **kw)
+        rm = timed_solves(pm, wl.tol, args.mixed_steps, 1, "mixed")
+        xm = rm["x"].cpu().numpy()
+        mixed = {
+            "solves_per_s": args.mixed_steps / rm["elapsed"],
+            "ms_per_solve": rm["elapsed"] / args.mixed_steps * 1e3,
+            "speedup_vs_fp64_solves": (args.mixed_steps / rm["elapsed"]) / out["solves_per_s"],
+            "gmres_iters": rm["iters"],
+            "pair_kernel_ms": rm["pair_ms"],
+            "pair_kernel_pairs_per_s": float(M) * M / (rm["pair_ms"] * 1e-3),
+            "frac_fp32_vector_peak": FLOPS_PER_PAIR * float(M) * M / (rm["pair_ms"] * 1e-3)
+                                     / 1e12 / PEAK_FP32_VECTOR_TFLOPS,
+            "g_pol": rm["G"],
+            "g_pol_rel_err_vs_fp64": abs(rm["G"] - r["G"]) / abs(r["G"]),
+            "solution_err_vs_fp64": block_errors(xm, x64, M),
+        }
+        mp = measured_profile("mixed", args.workload)
+        if mp is not None:
+            mixed["valu_counter_fp32_tflops"] = mp["valu_flops"] / (mp["ms"] * 1e-3) / 1e12
+        out["mixed"] = mixed
+        pm.close()
+        del pm
+        torch.cuda.empty_cache()
+    if args.workload == "ses2000" and not args.no_twin:
+        print("[bench] twin h = 0.7 against the stored oracle solve", file=sys.stderr, flush=True)
+        out["twin_h0.7"] = twin_check(args)
     if not args.no_cpu_baseline:
         print("[bench] CPU baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(wl, M, args.cpu_seconds)
+        cb = cpu_baseline(wl, M, args.cpu_seconds)
+        cb["cpu_model"] = cpu_model()
+        # the oracle's solve rate on this workload, from its measured pair rate
+        cb["oracle_solve_s_estimated"] = r["applies"] / args.steps * M * M / cb["value"]
+        bwl, ob = oracle_solve_baseline()
+        # the same Born-ion solve on the GPU, for the solves/s comparison
+        pb = Problem.from_workload(bwl, device=0)
+        rb = timed_solves(pb, bwl.tol, 20, 2, "born")
+        ob["gpu_solves_per_s"] = 20 / rb["elapsed"]
+        ob["gpu_g_pol"] = rb["G"]
+        cb["oracle_solve_born"] = ob
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 

@@ -249,6 +249,15 @@ def test_warm_start():
     _say(f"[warm] cold {info['iters']} from solution {info1['iters']} from 0.9x {info2['iters']}")
     assert info2["converged"] and info2["iters"] < info["iters"]
     assert abs(G2 - G) <= 1e-9 * abs(G)
+    # against the oracle's cold solve: both to a residual of 1e-12
+    x3, info3 = prob.solve(g, 1e-12, x=0.9 * x, warm=True)
+    G3 = prob.energy(x3)
+    orc = oracle.Oracle.from_workload(wl)
+    _, info_o = orc.solve_energy(wl.charge_xyz, wl.charge_q, 1e-12)
+    e = abs(G3 - info_o["g_pol"]) / abs(info_o["g_pol"])
+    _say(f"[warm] warm-started G_pol vs oracle cold solve {e:.2e} "
+         f"(iters {info3['iters']} / {info_o['iters']})")
+    assert info3["converged"] and e <= 1e-10
 
 
 def test_zero_charges_give_the_zero_solution():

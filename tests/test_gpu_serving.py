@@ -9,6 +9,7 @@ budget, and a bad request must fail alone.  One energy is checked against
 the FP64 oracle.
 """
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -104,6 +105,53 @@ def test_alone_equals_mixed_equals_direct(wls, precision, restart, hybrid):
         if restart >= 60:
             assert mixed[n][2]["converged"]
         _say(f"[serving] {n}: iters={mixed[n][2]['iters']} G={mixed[n][0]:.12e}")
+
+
+def test_request_admitted_while_another_is_mid_solve(wls):
+    """Continuous batching, not a queue: with two slots, a request submitted
+    after the first has run several rounds is admitted while the first is
+    still in its solve, the two share rounds, and both end with the same bits
+    as when each runs alone.  The unscaled system is used so that the first
+    request needs many rounds."""
+    opt = dict(precond=ibim.PRECOND_NONE)
+    a_name, b_name = "kirkwood_small", "born_h0.4"
+    srv = ibim.Server(8 * GiB, max_slots=2, host_threads=2, **opt)
+    try:
+        ta = srv.submit_workload(wls[a_name])
+        rounds_a = 0
+        for _ in range(100000):
+            srv.step()
+            if srv.state(ta) == ibim.REQ_ACTIVE:
+                rounds_a += 1
+                if rounds_a == 3:
+                    break
+        assert srv.state(ta) == ibim.REQ_ACTIVE, "first request finished within three rounds"
+        tb = srv.submit_workload(wls[b_name])
+        # the second request's setup runs on the server's threads; give it time
+        # without stepping, so the first request cannot advance meanwhile
+        time.sleep(2.0)
+        srv.step()
+        sa, sb = srv.state(ta), srv.state(tb)
+        _say(f"[serving] after the next round: first {sa}, second {sb}")
+        assert sa == ibim.REQ_ACTIVE and sb == ibim.REQ_ACTIVE
+        shared = 1
+        while True:
+            a, w = srv.step()
+            if srv.state(ta) == ibim.REQ_ACTIVE and srv.state(tb) == ibim.REQ_ACTIVE:
+                shared += 1
+            if a == 0 and w == 0:
+                break
+        _say(f"[serving] rounds shared by both requests: {shared}")
+        out = {}
+        for n, t in ((a_name, ta), (b_name, tb)):
+            st, g, info = srv.poll(t)
+            assert st == ibim.REQ_DONE, n
+            out[n] = (g, srv.solution(t), info)
+    finally:
+        srv.close()
+    for n in (a_name, b_name):
+        alone, _ = _serve(wls, [n], slots=1, **opt)
+        _same(alone[n], out[n], f"{n} alone vs admitted mid-solve")
 
 
 @pytest.mark.parametrize("precision", [ibim.FP64, ibim.MIXED])

@@ -29,11 +29,18 @@ def _sphere_oracle(R, h, eps, kappa=KAP, ei=EI, ee=EE):
 
 
 def test_sphere_area_second_order():
+    """h^3 sum w -> 4 pi R^2 at fixed tube width: the observed order, fitted
+    over four grids, is about two (grid alignment makes single ratios erratic)."""
+    hs = (0.2, 0.15, 0.1, 0.075)
     errs = []
-    for h in (0.3, 0.15):
-        o = _sphere_oracle(2.0, h, 0.6)
+    for h in hs:
+        sdf, org = workloads.sphere_sdf(2.0, h, 0.6)
+        o = oracle.Oracle(sdf, org, h, 0.6, EI, EE, KAP, weight_rows=np.zeros(1, dtype=np.int64))
         errs.append(abs(o.area() - 16 * math.pi) / (16 * math.pi))
-    assert errs[0] < 1e-4 and errs[1] < 2e-4
+    order = np.polyfit(np.log(hs), np.log(errs), 1)[0]
+    print(f"sphere area errors {errs}, fitted order {order:.2f}")
+    assert 1.7 < order < 3.5
+    assert max(errs) < 5e-4 and errs[-1] < 5e-5
 
 
 def test_torus_area():
@@ -41,6 +48,25 @@ def test_torus_area():
     o = oracle.Oracle.from_workload(wl)
     exact = 4 * math.pi ** 2 * 1.0 * 0.5
     assert abs(o.area() - exact) / exact < 1e-3
+
+
+def test_torus_area_study_against_table_1():
+    """Area of the rotated torus (radii 1 and 1/2, the angles of Section 2.6)
+    with eps = 2h and the finite-difference Jacobian J_h, as in the torus
+    table of Section 2.6, whose relative errors lie between 9.5e-7 and 8.5e-6
+    on grids of 103 to 512 nodes per side.  The table does not state the box
+    those grids cover, so the spacing of each row, and so its exact value, is
+    unknown (parity unpinned); what is checked is that the error falls from
+    h = 0.1 into the table's range at the finest spacings here."""
+    exact = 4 * math.pi ** 2 * 1.0 * 0.5
+    errs = {}
+    for h in (0.1, 0.05, 0.025, 0.02):
+        wl = workloads.torus_case(h=h)
+        o = oracle.Oracle.from_workload(wl, weight_rows=np.zeros(1, dtype=np.int64))
+        errs[h] = abs(o.area() - exact) / exact
+    print("torus area relative errors:", errs)
+    assert errs[0.05] < errs[0.1] / 4
+    assert errs[0.025] < 1.5e-5 and errs[0.02] < 1.5e-5
 
 
 def test_sphere_geometry_exact_quantities():
