@@ -246,6 +246,26 @@ int ibim_rhs(ibim_ctx* ctx, double* g, void* stream);
 int ibim_apply(ibim_ctx* ctx, const double* u, double* out, void* stream);
 
 /*
+ * Allocation-free variant of ibim_apply, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, layout and result as ibim_apply.
+ * The partial sums of the dense pair sum go to a static device array of
+ * IBIM_NOALLOC_SCRATCH_BYTES owned by the library (one per GPU, held until
+ * the process ends) instead of context memory:
+ *   - symmetric kernels when the context's plan fits there (result
+ *     bit-identical to ibim_apply);
+ *   - otherwise the one-directional kernels when their nsplit x 2M partial
+ *     sums fit (result equal to ibim_apply within float64 rounding).
+ * Larger problems and treecode contexts fail with IBIM_EINVAL (message in
+ * ibim_last_error).  The call makes no device allocation or free.  Every call
+ * on one GPU shares that GPU's array and overwrites it: calls that overlap in
+ * time on the same GPU (other streams or threads) race and must be serialised
+ * by the caller.  Pair-kernel timing (ibim_pair_timing) skips these calls.
+ */
+#define IBIM_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int ibim_apply_noalloc(ibim_ctx* ctx, const double* u, double* out, void* stream);
+
+/*
  * Solve A x = rhs by GMRES(restart) from x0 = 0 until |g_{j+1}| <= tol ||b||
  * (Section 2.5), where b = rhs, or Lambda^-1 rhs for the row-scaled system of
  * IBIM_PRECOND_DIAG (the residuals in info refer to that system).  rhs, x:

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -40,6 +41,32 @@ int hip_fail(hipError_t e, const char* where) {
 namespace {
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Partial sums of ibim_apply_noalloc.  Each GPU the library runs on holds its
+// own copy for the life of the process; host code reaches it only through the
+// device address from hipGetSymbolAddress (taken once per device, with that
+// device current), never through the array's name.
+constexpr size_t kNoAllocScratchDoubles = (size_t)IBIM_NOALLOC_SCRATCH_BYTES / sizeof(double);
+__device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+double* g_noalloc_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `dev` (the current device).
+int noalloc_scratch(int dev, double** out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxDevices) return fail(IBIM_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_noalloc_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_noalloc_ptr[dev];
+  return IBIM_OK;
+}
 
 __global__ void rhs_kernel(const double* px, const double* py, const double* pz, const double* nx,
                            const double* ny, const double* nz, int32_t M, const double* zq,
@@ -136,10 +163,13 @@ int fetch(ibim_ctx* c, const double* d, int n, hipStream_t s, double* out) {
 
 namespace ibim {
 
-int apply_impl(ibim_ctx* c, const double* u, double* out, hipStream_t s) {
+// out = A u with the pair sum's partial sums in sym_scratch (symmetric
+// kernels, when sym_on) or in partial (one-directional kernels).
+static int apply_core(ibim_ctx* c, const double* u, double* out, hipStream_t s, bool sym_on,
+                      double* sym_scratch, double* partial, bool timed) {
   const int prec = c->opt.precision;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (c->timing) {
+  if (timed) {
     if (2 * c->tcount + 2 > c->tev.size()) {
       for (int i = 0; i < 2; ++i) {
         hipEvent_t e;
@@ -154,32 +184,37 @@ int apply_impl(ibim_ctx* c, const double* u, double* out, hipStream_t s) {
   const bool tree = c->opt.summation == IBIM_SUM_TREE;
   if (tree) {
     HIP_TRY(launch_tree_sum(c->tree, c->P, u, s), "treecode launch");
-  } else if (c->sym.enabled) {
-    const SymArgs sa =
-        make_sym_args(c->P, c->sym, c->d_sym_items, c->d_careful, u, c->sym_scratch);
+  } else if (sym_on) {
+    const SymArgs sa = make_sym_args(c->P, c->sym, c->d_sym_items, c->d_careful, u, sym_scratch);
     if (prec == IBIM_MIXED)
       HIP_TRY(launch_pair_sym_mixed(sa, c->n_sym_items, s), "pair kernel launch");
     else
       HIP_TRY(launch_pair_sym(sa, c->n_sym_items, s), "pair kernel launch");
   } else if (prec == IBIM_MIXED)
-    HIP_TRY(launch_pair_mixed(c->P, c->pair, u, c->partial, s), "pair kernel launch");
+    HIP_TRY(launch_pair_mixed(c->P, c->pair, u, partial, s), "pair kernel launch");
   else
-    HIP_TRY(launch_pair(c->P, c->pair, prec, u, c->partial, s), "pair kernel launch");
-  if (c->timing) {
+    HIP_TRY(launch_pair(c->P, c->pair, prec, u, partial, s), "pair kernel launch");
+  if (timed) {
     HIP_TRY(hipEventRecord(e1, s), "hipEventRecord");
     ++c->tcount;
   }
   if (tree)
     HIP_TRY(launch_tree_finish(c->tree, c->P, u, out, s), "finish kernel launch");
-  else if (c->sym.enabled && prec == IBIM_MIXED)
-    HIP_TRY(launch_finish_sym_mixed(c->P, c->sym, c->d_careful, u, c->sym_scratch, out, s),
+  else if (sym_on && prec == IBIM_MIXED)
+    HIP_TRY(launch_finish_sym_mixed(c->P, c->sym, c->d_careful, u, sym_scratch, out, s),
             "finish kernel launch");
-  else if (c->sym.enabled)
-    HIP_TRY(launch_finish_sym(c->P, c->sym, u, c->sym_scratch, out, s), "finish kernel launch");
+  else if (sym_on)
+    HIP_TRY(launch_finish_sym(c->P, c->sym, u, sym_scratch, out, s), "finish kernel launch");
   else if (prec == IBIM_MIXED)
-    HIP_TRY(launch_finish_mixed(c->P, c->pair, u, c->partial, out, s), "finish kernel launch");
+    HIP_TRY(launch_finish_mixed(c->P, c->pair, u, partial, out, s), "finish kernel launch");
   else
-    HIP_TRY(launch_finish(c->P, c->pair, prec, u, c->partial, out, s), "finish kernel launch");
+    HIP_TRY(launch_finish(c->P, c->pair, prec, u, partial, out, s), "finish kernel launch");
+  return IBIM_OK;
+}
+
+int apply_impl(ibim_ctx* c, const double* u, double* out, hipStream_t s) {
+  if (int r = apply_core(c, u, out, s, c->sym.enabled, c->sym_scratch, c->partial, c->timing))
+    return r;
   ++c->applies;
   return IBIM_OK;
 }
@@ -703,6 +738,31 @@ int ibim_apply(ibim_ctx* ctx, const double* u, double* out, void* stream) {
   if (!u || !out || u == out) return fail(IBIM_EINVAL, "u and out must be distinct device vectors");
   DeviceScope ds(ctx->opt.device);
   return apply_impl(ctx, u, out, as_stream(stream));
+}
+
+int ibim_apply_noalloc(ibim_ctx* ctx, const double* u, double* out, void* stream) {
+  if (int r = check_dev(ctx)) return r;
+  if (!u || !out || u == out) return fail(IBIM_EINVAL, "u and out must be distinct device vectors");
+  if (ctx->opt.summation == IBIM_SUM_TREE)
+    return fail(IBIM_EINVAL, "ibim_apply_noalloc: treecode contexts are not supported");
+  // partial sums needed by the symmetric kernels (the context's plan) and by
+  // the one-directional kernels; the first that fits the static array is used
+  const size_t cap = kNoAllocScratchDoubles;
+  const bool sym_fits = ctx->sym.enabled && ctx->sym.scratch_doubles <= cap;
+  const size_t one_way = (size_t)ctx->pair.nsplit * 2 * (size_t)ctx->P.M;
+  if (!sym_fits && one_way > cap)
+  {
+    const size_t need = ctx->sym.enabled ? std::min(ctx->sym.scratch_doubles, one_way) : one_way;
+    return fail(IBIM_EINVAL, "ibim_apply_noalloc: the partial sums need " +
+                                 std::to_string(need * 8) + " bytes, more than the " +
+                                 std::to_string(IBIM_NOALLOC_SCRATCH_BYTES) +
+                                 "-byte static scratch");
+  }
+  DeviceScope ds(ctx->opt.device);
+  if (!ds.ok) return fail(IBIM_EHIP, "hipSetDevice failed");
+  double* scr = nullptr;
+  if (int r = noalloc_scratch(ctx->opt.device, &scr)) return r;
+  return apply_core(ctx, u, out, as_stream(stream), sym_fits, scr, scr, false);
 }
 
 namespace {

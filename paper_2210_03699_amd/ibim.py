@@ -110,6 +110,7 @@ def load():
     lib.ibim_correction_weights.argtypes = [_VP, _D, _D, _VP]
     lib.ibim_rhs.argtypes = [_VP, _VP, _VP]
     lib.ibim_apply.argtypes = [_VP, _VP, _VP, _VP]
+    lib.ibim_apply_noalloc.argtypes = [_VP, _VP, _VP, _VP]
     lib.ibim_solve.argtypes = [_VP, _VP, ctypes.c_double, _VP, ctypes.POINTER(_SolveInfo), _VP]
     lib.ibim_solve_guess.argtypes = lib.ibim_solve.argtypes
     lib.ibim_energy.argtypes = [_VP, _VP, _D, _VP]
@@ -287,6 +288,14 @@ class Problem:
         out = self.new_vector() if out is None else out
         _check(self._lib.ibim_apply(self._ctx, _dev_ptr(u, 2 * self.M),
                                     _dev_ptr(out, 2 * self.M), _stream_ptr(stream)))
+        return out
+
+    def apply_noalloc(self, u, out, stream=None):
+        """``ibim_apply_noalloc``: as :meth:`apply` into a caller-supplied
+        ``out``, with the pair sum's partial sums in the library's static
+        device scratch (no device allocation)."""
+        _check(self._lib.ibim_apply_noalloc(self._ctx, _dev_ptr(u, 2 * self.M),
+                                            _dev_ptr(out, 2 * self.M), _stream_ptr(stream)))
         return out
 
     def solve(self, rhs, tol, x=None, stream=None, warm=False):
