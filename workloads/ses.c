@@ -88,10 +88,24 @@ static void cells_build(Cells* cl, const Ball* b, int n, double cs) {
   free(cid);
 }
 
-/* atoms with centre within `rad` of p (rad <= cs * reach) -> out, returns count */
-static int cells_query(const Cells* cl, const Ball* b, const double* p, double rad, int* out,
-                       int cap) {
-  int lo[3], hi[3], m = 0;
+/* growable list of indices */
+typedef struct {
+  int* v;
+  int n, cap;
+} IntBuf;
+
+static void ib_push(IntBuf* b, int i) {
+  if (b->n == b->cap) {
+    b->cap = b->cap ? 2 * b->cap : 1024;
+    b->v = (int*)realloc(b->v, sizeof(int) * (size_t)b->cap);
+  }
+  b->v[b->n++] = i;
+}
+
+/* every point with centre within `rad` of p -> out (replaced), returns count */
+static int cells_query(const Cells* cl, const Ball* b, const double* p, double rad, IntBuf* out) {
+  int lo[3], hi[3];
+  out->n = 0;
   for (int a = 0; a < 3; ++a) {
     lo[a] = (int)floor((p[a] - rad - cl->lo[a]) / cl->cs);
     hi[a] = (int)floor((p[a] + rad - cl->lo[a]) / cl->cs);
@@ -104,10 +118,10 @@ static int cells_query(const Cells* cl, const Ball* b, const double* p, double r
         int q = (x * cl->n[1] + y) * cl->n[2] + z;
         for (int t = cl->start[q]; t < cl->start[q + 1]; ++t) {
           int i = cl->idx[t];
-          if (dist3(b[i].c, p) < rad && m < cap) out[m++] = i;
+          if (dist3(b[i].c, p) < rad) ib_push(out, i);
         }
       }
-  return m;
+  return out->n;
 }
 
 typedef struct {
@@ -173,11 +187,11 @@ int ses_sdf(const double* xyz, const double* radii, int n, double probe, const d
   int ov_cap = 32 * n + 32;
   int* ov = (int*)malloc(sizeof(int) * ov_cap);
   {
-    int nb[4096];
+    IntBuf qb = {0};
     for (int i = 0; i < n; ++i) {
-      int m = cells_query(&cl, b, b[i].c, 2.0 * Rmax, nb, 4096);
+      const int m = cells_query(&cl, b, b[i].c, 2.0 * Rmax, &qb);
       for (int t = 0; t < m; ++t) {
-        int k = nb[t];
+        int k = qb.v[t];
         if (k == i || dist3(b[i].c, b[k].c) >= b[i].R + b[k].R) continue;
         if (ov_start[i + 1] + 1 > ov_cap) {
           ov_cap *= 2;
@@ -187,41 +201,50 @@ int ses_sdf(const double* xyz, const double* radii, int n, double probe, const d
       }
       if (i + 1 < n) ov_start[i + 2] = ov_start[i + 1];
     }
+    free(qb.v);
   }
   const int64_t ng = (int64_t)nx * ny * nz;
 
   /* 1. s(x) = min_i |x - c_i| - R_i (>= 0 in A), inner(x) = max_i R_i - |x - c_i| */
   double* s = (double*)malloc(sizeof(double) * ng);
   double* inner = (double*)malloc(sizeof(double) * ng);
+  int* deepest = (int*)malloc(sizeof(int) * ng); /* the ball of largest depth, -1 if none */
 #pragma omp parallel for schedule(dynamic, 4)
   for (int i = 0; i < nx; ++i) {
-    int nb[4096];
+    IntBuf qb = {0};
     for (int j = 0; j < ny; ++j)
       for (int k = 0; k < nz; ++k) {
         double x[3] = {origin[0] + i * h, origin[1] + j * h, origin[2] + k * h};
-        int m = cells_query(&cl, b, x, 2.0 * Rmax + band + probe, nb, 4096);
+        const int m = cells_query(&cl, b, x, 2.0 * Rmax + band + probe, &qb);
+        const int* nb = qb.v;
         double sm = 1e300, im = -1e300;
+        int deep = -1;
         for (int t = 0; t < m; ++t) {
           double dd = dist3(x, b[nb[t]].c) - b[nb[t]].R;
           if (dd < sm) sm = dd;
-          if (-dd > im) im = -dd;
+          if (-dd > im) {
+            im = -dd;
+            deep = nb[t];
+          }
         }
         if (m == 0) sm = 1e300;
         int64_t q = ((int64_t)i * ny + j) * nz + k;
         s[q] = sm;
         inner[q] = im;
+        deepest[q] = deep;
       }
+    free(qb.v);
   }
 
   /* 2. circles of intersecting sphere pairs */
   int ccap = 64 * n + 64, nc = 0;
   Circle* circ = (Circle*)malloc(sizeof(Circle) * ccap);
   {
-    int nb[4096];
+    IntBuf qb = {0};
     for (int i = 0; i < n; ++i) {
-      int m = cells_query(&cl, b, b[i].c, 2.0 * Rmax, nb, 4096);
+      const int m = cells_query(&cl, b, b[i].c, 2.0 * Rmax, &qb);
       for (int t = 0; t < m; ++t) {
-        int j = nb[t];
+        int j = qb.v[t];
         if (j <= i) continue;
         double D = dist3(b[i].c, b[j].c);
         if (D >= b[i].R + b[j].R || D <= fabs(b[i].R - b[j].R) || D == 0.0) continue;
@@ -242,17 +265,18 @@ int ses_sdf(const double* xyz, const double* radii, int n, double probe, const d
         C->j = j;
       }
     }
+    free(qb.v);
   }
   /* 3. exposed vertices of sphere triples */
   int vcap = 64 * n + 64, nv = 0;
   Vertex* vert = (Vertex*)malloc(sizeof(Vertex) * vcap);
   {
-    int nb[4096];
+    IntBuf qb = {0}, qb2 = {0};
     for (int ci = 0; ci < nc; ++ci) {
       const Circle* C = &circ[ci];
-      int m = cells_query(&cl, b, C->C, C->rho + Rmax, nb, 4096);
+      const int m = cells_query(&cl, b, C->C, C->rho + Rmax, &qb);
       for (int t = 0; t < m; ++t) {
-        int k = nb[t];
+        int k = qb.v[t];
         if (k <= C->j) continue; /* i < j < k once */
         /* intersect circle with sphere k: points p = C + rho (cos t e1 + sin t e2) */
         double w[3] = {b[k].c[0] - C->C[0], b[k].c[1] - C->C[1], b[k].c[2] - C->C[2]};
@@ -271,9 +295,8 @@ int ses_sdf(const double* xyz, const double* radii, int n, double probe, const d
         for (int sg = -1; sg <= 1; sg += 2) {
           double p[3];
           for (int q = 0; q < 3; ++q) p[q] = C->C[q] + C->rho * (cph * e1[q] + sg * sph * e2[q]);
-          int nb2[4096];
-          int m2 = cells_query(&fcl, b, p, Rmax, nb2, 4096);
-          if (buried(b, nb2, m2, p, C->i, C->j, k)) continue;
+          const int m2 = cells_query(&fcl, b, p, Rmax, &qb2);
+          if (buried(b, qb2.v, m2, p, C->i, C->j, k)) continue;
           if (nv >= vcap) {
             vcap *= 2;
             vert = (Vertex*)realloc(vert, sizeof(Vertex) * vcap);
@@ -286,6 +309,8 @@ int ses_sdf(const double* xyz, const double* radii, int n, double probe, const d
         }
       }
     }
+    free(qb.v);
+    free(qb2.v);
   }
   /* cell lists over circle centres and vertices (reuse the Ball layout) */
   Ball* cb = (Ball*)malloc(sizeof(Ball) * (nc > 0 ? nc : 1));
@@ -298,52 +323,126 @@ int ses_sdf(const double* xyz, const double* radii, int n, double probe, const d
     for (int a = 0; a < 3; ++a) vb[q].c[a] = vert[q].p[a];
     vb[q].R = 0.0;
   }
-  Cells ccl, vcl;
-  if (nc > 0) cells_build(&ccl, cb, nc, 0.5 * Rmax);
+  /* cells of edge Rmax for the candidate queries of step 4 (radius at most
+   * Rmax + reach_d), half that for the vertex queries */
+  Cells acl, ccl, vcl;
+  cells_build(&acl, b, n, Rmax);
+  if (nc > 0) cells_build(&ccl, cb, nc, Rmax);
   if (nv > 0) cells_build(&vcl, vb, nv, 0.5 * Rmax);
 
   /* 4. distances: pass 0 keeps every exposed candidate, pass 1 drops the
-   * candidates of enclosed solvent bubbles found after pass 0 */
+   * candidates of enclosed solvent bubbles found after pass 0.  Two exact
+   * prunings keep the candidate lists short.  (a) A point inside ball k at
+   * depth D = R_k - |x - c_k| has every point within D of it inside that
+   * ball, so a candidate nearer than the deepest ball's depth (inner[q]),
+   * less a slack far above rounding and the 1e-12 burial margin, is buried
+   * and skipped untested; so is a candidate that the burial test of that
+   * ball alone finds inside it (buried() would find that ball: the point lies
+   * on a sphere that the ball overlaps).  (b) Vertices are stored only when
+   * exposed, so the nearest vertex bounds the answer and farther candidates
+   * are skipped.
+   * Pass 1 recomputes only bubble nodes and nodes whose pass-0 candidate lies
+   * in a bubble: elsewhere the candidates before the chosen one were buried
+   * and stay so, and the chosen one stays valid. */
   const double reach_d = probe + band; /* candidates farther than this do not matter */
+  const double slack = 1e-12 * Rmax + 1e-9;
   uint8_t* bubble = NULL;
+  int64_t* chosen = (int64_t*)malloc(sizeof(int64_t) * ng); /* nearest node of the chosen candidate */
   for (int pass = 0; pass < 2; ++pass) {
   GridInfo gi = {bubble, origin, nx, ny, nz, h};
 #pragma omp parallel for schedule(dynamic, 2)
   for (int i = 0; i < nx; ++i) {
-    int* nb = (int*)malloc(sizeof(int) * 8192);
-    Cand* cand = (Cand*)malloc(sizeof(Cand) * 3 * 8192);
-    for (int j = 0; j < ny; ++j)
+    IntBuf qb = {0};
+    Cand* cand = NULL;
+    int cand_cap = 0;
+    for (int j = 0; j < ny; ++j) {
+      /* signed distance to the boundary of B (positive inside) at the
+       * previous node of this line when it is exact; it is 1-Lipschitz, so
+       * the answer here lies within h of it (pass 0 only) */
+      int prev_exact = 0;
+      double Dprev = 0.0;
       for (int k = 0; k < nz; ++k) {
         int64_t q = ((int64_t)i * ny + j) * nz + k;
+        const int nb_ok = pass == 0 && prev_exact;
+        prev_exact = 0;
+        if (pass == 1 && !bubble[q] && (chosen[q] < 0 || !bubble[chosen[q]])) continue;
+        chosen[q] = -1;
         double x[3] = {origin[0] + i * h, origin[1] + j * h, origin[2] + k * h};
         if (s[q] >= 0.0 && !(bubble && bubble[q])) {
           /* probe centre: at least r_p from the molecule */
           out[q] = -(probe + (s[q] < 1e3 ? s[q] : 1e3));
+          /* s is the exact distance to B when the nearest ball's centre lay
+           * within the radius of step 1 */
+          if (s[q] <= Rmax + band + probe) {
+            prev_exact = 1;
+            Dprev = -s[q];
+          }
           continue;
         }
         if (inner[q] - probe > band) {
           out[q] = inner[q] - probe; /* deep inside: a lower bound is enough */
           continue;
         }
-        /* every candidate (sphere patch, circle arc, vertex) within reach_d,
-         * with its distance; the nearest exposed one gives the distance */
+        double lower = inner[q] - slack;
+        double upper = 1e300;
+        if (nb_ok) {
+          if (Dprev - h - slack > lower) lower = Dprev - h - slack;
+          upper = Dprev + h + slack;
+        }
+        const int kd = deepest[q];
+        /* exposed vertices within reach_d (outside bubbles in pass 1) */
         int nk = 0;
-        int m = cells_query(&fcl, b, x, Rmax + reach_d, nb, 8192);
+        if (nv > 0) {
+          const double vrad = upper < reach_d ? upper : reach_d;
+          const int mv = cells_query(&vcl, vb, x, vrad, &qb);
+          if (mv > cand_cap) {
+            cand_cap = 2 * mv;
+            cand = (Cand*)realloc(cand, sizeof(Cand) * (size_t)cand_cap);
+          }
+          for (int t = 0; t < mv; ++t) {
+            const Vertex* V = &vert[qb.v[t]];
+            if (in_bubble(&gi, V->p)) continue;
+            Cand* K = &cand[nk++];
+            for (int a = 0; a < 3; ++a) K->p[a] = V->p[a];
+            K->dd = dist3(x, V->p);
+            K->e1 = K->e2 = -1;
+            K->vertex = 1;
+            if (K->dd < upper) upper = K->dd;
+          }
+        }
+        /* sphere patches and circle arcs within reach_d, between the bounds */
+        /* a patch or arc point within `upper` of x lies on a sphere whose
+         * centre (or on a circle whose centre) is within Rmax + upper */
+        const double qrad = Rmax + (upper < reach_d ? upper : reach_d);
+        const int m = cells_query(&acl, b, x, qrad, &qb);
+        if (nk + m > cand_cap) {
+          cand_cap = 2 * (nk + m);
+          cand = (Cand*)realloc(cand, sizeof(Cand) * (size_t)cand_cap);
+        }
         for (int t = 0; t < m; ++t) {
-          const Ball* B = &b[nb[t]];
+          const int ib = qb.v[t];
+          const Ball* B = &b[ib];
           double dxc = dist3(x, B->c);
           if (dxc == 0.0 || fabs(B->R - dxc) > reach_d) continue;
-          Cand* K = &cand[nk++];
-          K->dd = fabs(B->R - dxc);
+          const double dd = fabs(B->R - dxc);
+          if (dd < lower || dd > upper) continue;
+          Cand* K = &cand[nk];
+          K->dd = dd;
           for (int a = 0; a < 3; ++a) K->p[a] = B->c[a] + B->R * ((x[a] - B->c[a]) / dxc);
-          K->e1 = nb[t];
+          if (kd >= 0 && kd != ib && dist3(b[kd].c, K->p) < b[kd].R * (1.0 - 1e-12)) continue;
+          ++nk;
+          K->e1 = ib;
           K->e2 = -1;
           K->vertex = 0;
         }
         if (nc > 0) {
-          int mc = cells_query(&ccl, cb, x, Rmax + reach_d, nb, 8192);
+          const int mc = cells_query(&ccl, cb, x, qrad, &qb);
+          if (nk + mc > cand_cap) {
+            cand_cap = 2 * (nk + mc);
+            cand = (Cand*)realloc(cand, sizeof(Cand) * (size_t)cand_cap);
+          }
           for (int t = 0; t < mc; ++t) {
-            const Circle* C = &circ[nb[t]];
+            const Circle* C = &circ[qb.v[t]];
             double w[3] = {x[0] - C->C[0], x[1] - C->C[1], x[2] - C->C[2]};
             /* every point of the circle is at least |x - C| - rho away */
             if (sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]) - C->rho > reach_d) continue;
@@ -354,22 +453,14 @@ int ses_sdf(const double* xyz, const double* radii, int n, double probe, const d
             Cand* K = &cand[nk];
             for (int a = 0; a < 3; ++a) K->p[a] = C->C[a] + C->rho * wp[a] / L;
             K->dd = dist3(x, K->p);
-            if (K->dd > reach_d) continue;
+            if (K->dd > reach_d || K->dd < lower || K->dd > upper) continue;
+            if (kd >= 0 && kd != C->i && kd != C->j &&
+                dist3(b[kd].c, K->p) < b[kd].R * (1.0 - 1e-12))
+              continue;
             ++nk;
             K->e1 = C->i;
             K->e2 = C->j;
             K->vertex = 0;
-          }
-        }
-        if (nv > 0) {
-          int mv = cells_query(&vcl, vb, x, reach_d, nb, 8192);
-          for (int t = 0; t < mv; ++t) {
-            const Vertex* V = &vert[nb[t]];
-            Cand* K = &cand[nk++];
-            for (int a = 0; a < 3; ++a) K->p[a] = V->p[a];
-            K->dd = dist3(x, V->p);
-            K->e1 = K->e2 = -1;
-            K->vertex = 1;
           }
         }
         qsort(cand, (size_t)nk, sizeof(Cand), cand_cmp);
@@ -379,17 +470,28 @@ int ses_sdf(const double* xyz, const double* radii, int n, double probe, const d
           if (!K->vertex) {
             const int o0 = ov_start[K->e1], o1 = ov_start[K->e1 + 1];
             if (buried(b, ov + o0, o1 - o0, K->p, K->e1, K->e2, -1)) continue;
+            if (in_bubble(&gi, K->p)) continue;
           }
-          if (in_bubble(&gi, K->p)) continue;
           best = K->dd;
+          /* the nearest grid node of the chosen point (as in_bubble rounds it) */
+          const int ii = (int)floor((K->p[0] - origin[0]) / h + 0.5);
+          const int jj = (int)floor((K->p[1] - origin[1]) / h + 0.5);
+          const int kk = (int)floor((K->p[2] - origin[2]) / h + 0.5);
+          if (ii >= 0 && jj >= 0 && kk >= 0 && ii < nx && jj < ny && kk < nz)
+            chosen[q] = ((int64_t)ii * ny + jj) * nz + kk;
           break;
         }
         /* no exposed boundary point within reach_d: the distance is at least
          * reach_d (and at least the ball depth) */
         if (best > 1e299) best = inner[q] > reach_d ? inner[q] : reach_d;
         out[q] = best - probe;
+        if (best < 1e299) {
+          prev_exact = 1;
+          Dprev = best;
+        }
       }
-    free(nb);
+    }
+    free(qb.v);
     free(cand);
   }
   if (pass == 0) {
@@ -435,9 +537,11 @@ int ses_sdf(const double* xyz, const double* radii, int n, double probe, const d
   }
   }
   free(bubble);
+  free(chosen);
   free(b);
   free(s);
   free(inner);
+  free(deepest);
   free(circ);
   free(vert);
   free(cb);
@@ -446,6 +550,8 @@ int ses_sdf(const double* xyz, const double* radii, int n, double probe, const d
   free(cl.idx);
   free(fcl.start);
   free(fcl.idx);
+  free(acl.start);
+  free(acl.idx);
   free(ov_start);
   free(ov);
   if (nc > 0) {
