@@ -127,12 +127,17 @@ def test_request_admitted_while_another_is_mid_solve(wls):
                     break
         assert srv.state(ta) == ibim.REQ_ACTIVE, "first request finished within three rounds"
         tb = srv.submit_workload(wls[b_name])
-        # the second request's setup runs on the server's threads; give it time
-        # without stepping, so the first request cannot advance meanwhile
-        time.sleep(2.0)
-        srv.step()
-        sa, sb = srv.state(ta), srv.state(tb)
-        _say(f"[serving] after the next round: first {sa}, second {sb}")
+        # the second request's host setup, then its device setup, run on the
+        # server's threads (a round hands it from one to the other, and the
+        # first round after its device setup picks it up); wait for each
+        # without stepping, so the first request advances only one round per wait
+        for waited in range(1, 6):
+            time.sleep(1.0)
+            srv.step()
+            sa, sb = srv.state(ta), srv.state(tb)
+            _say(f"[serving] after {waited} wait(s): first {sa}, second {sb}")
+            if sb != ibim.REQ_WAITING:
+                break
         assert sa == ibim.REQ_ACTIVE and sb == ibim.REQ_ACTIVE
         shared = 1
         while True:
