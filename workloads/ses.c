@@ -267,6 +267,16 @@ int ses_sdf(const double* xyz, const double* radii, int n, double probe, const d
     }
     free(qb.v);
   }
+  /* circles listed under their first sphere (i < j) */
+  int* cstart = (int*)calloc((size_t)n + 1, sizeof(int));
+  int* cidx = (int*)malloc(sizeof(int) * (size_t)(nc > 0 ? nc : 1));
+  for (int q = 0; q < nc; ++q) cstart[circ[q].i + 1]++;
+  for (int i = 0; i < n; ++i) cstart[i + 1] += cstart[i];
+  {
+    int* fill = (int*)calloc((size_t)n, sizeof(int));
+    for (int q = 0; q < nc; ++q) cidx[cstart[circ[q].i] + fill[circ[q].i]++] = q;
+    free(fill);
+  }
   /* 3. exposed vertices of sphere triples */
   int vcap = 64 * n + 64, nv = 0;
   Vertex* vert = (Vertex*)malloc(sizeof(Vertex) * vcap);
@@ -312,22 +322,16 @@ int ses_sdf(const double* xyz, const double* radii, int n, double probe, const d
     free(qb.v);
     free(qb2.v);
   }
-  /* cell lists over circle centres and vertices (reuse the Ball layout) */
-  Ball* cb = (Ball*)malloc(sizeof(Ball) * (nc > 0 ? nc : 1));
-  for (int q = 0; q < nc; ++q) {
-    for (int a = 0; a < 3; ++a) cb[q].c[a] = circ[q].C[a];
-    cb[q].R = circ[q].rho;
-  }
+  /* cell list over the vertices (reuse the Ball layout) */
   Ball* vb = (Ball*)malloc(sizeof(Ball) * (nv > 0 ? nv : 1));
   for (int q = 0; q < nv; ++q) {
     for (int a = 0; a < 3; ++a) vb[q].c[a] = vert[q].p[a];
     vb[q].R = 0.0;
   }
-  /* cells of edge Rmax for the candidate queries of step 4 (radius at most
+  /* cells of edge Rmax for the sphere queries of step 4 (radius at most
    * Rmax + reach_d), half that for the vertex queries */
-  Cells acl, ccl, vcl;
+  Cells acl, vcl;
   cells_build(&acl, b, n, Rmax);
-  if (nc > 0) cells_build(&ccl, cb, nc, Rmax);
   if (nv > 0) cells_build(&vcl, vb, nv, 0.5 * Rmax);
 
   /* 4. distances: pass 0 keeps every exposed candidate, pass 1 drops the
@@ -355,6 +359,9 @@ int ses_sdf(const double* xyz, const double* radii, int n, double probe, const d
     IntBuf qb = {0};
     Cand* cand = NULL;
     int cand_cap = 0;
+    int64_t* stamp = (int64_t*)malloc(sizeof(int64_t) * (size_t)n); /* last node each sphere passed */
+    double* sdist = (double*)malloc(sizeof(double) * (size_t)n);
+    for (int a = 0; a < n; ++a) stamp[a] = -1;
     for (int j = 0; j < ny; ++j) {
       /* signed distance to the boundary of B (positive inside) at the
        * previous node of this line when it is exact; it is 1-Lipschitz, so
@@ -410,39 +417,45 @@ int ses_sdf(const double* xyz, const double* radii, int n, double probe, const d
             if (K->dd < upper) upper = K->dd;
           }
         }
-        /* sphere patches and circle arcs within reach_d, between the bounds */
-        /* a patch or arc point within `upper` of x lies on a sphere whose
-         * centre (or on a circle whose centre) is within Rmax + upper */
-        const double qrad = Rmax + (upper < reach_d ? upper : reach_d);
-        const int m = cells_query(&acl, b, x, qrad, &qb);
-        if (nk + m > cand_cap) {
-          cand_cap = 2 * (nk + m);
-          cand = (Cand*)realloc(cand, sizeof(Cand) * (size_t)cand_cap);
-        }
+        /* sphere patches and circle arcs within reach_d, between the bounds.
+         * A patch or arc point within bnd of x lies on a sphere within bnd
+         * of x (|R_i - |x - c_i|| <= bnd), whose centre is within Rmax + bnd;
+         * an arc is examined only when both of its spheres are. */
+        const double bnd = upper < reach_d ? upper : reach_d;
+        const int m = cells_query(&acl, b, x, Rmax + bnd + slack, &qb);
+        int nsel = 0;
         for (int t = 0; t < m; ++t) {
           const int ib = qb.v[t];
-          const Ball* B = &b[ib];
-          double dxc = dist3(x, B->c);
-          if (dxc == 0.0 || fabs(B->R - dxc) > reach_d) continue;
-          const double dd = fabs(B->R - dxc);
-          if (dd < lower || dd > upper) continue;
-          Cand* K = &cand[nk];
-          K->dd = dd;
-          for (int a = 0; a < 3; ++a) K->p[a] = B->c[a] + B->R * ((x[a] - B->c[a]) / dxc);
-          if (kd >= 0 && kd != ib && dist3(b[kd].c, K->p) < b[kd].R * (1.0 - 1e-12)) continue;
-          ++nk;
-          K->e1 = ib;
-          K->e2 = -1;
-          K->vertex = 0;
+          const double dxc = dist3(x, b[ib].c);
+          if (fabs(b[ib].R - dxc) > bnd + slack) continue;
+          stamp[ib] = q;  /* sphere ib passes within bnd of x */
+          qb.v[nsel] = ib;
+          sdist[nsel++] = dxc;
         }
-        if (nc > 0) {
-          const int mc = cells_query(&ccl, cb, x, qrad, &qb);
-          if (nk + mc > cand_cap) {
-            cand_cap = 2 * (nk + mc);
+        for (int t = 0; t < nsel; ++t) {
+          const int ib = qb.v[t];
+          const Ball* B = &b[ib];
+          const double dxc = sdist[t];
+          const double sd = fabs(B->R - dxc);
+          if (nk + 1 + (cstart[ib + 1] - cstart[ib]) > cand_cap) {
+            cand_cap = 2 * (nk + 1 + (cstart[ib + 1] - cstart[ib]));
             cand = (Cand*)realloc(cand, sizeof(Cand) * (size_t)cand_cap);
           }
-          for (int t = 0; t < mc; ++t) {
-            const Circle* C = &circ[qb.v[t]];
+          if (dxc != 0.0 && sd <= reach_d && sd >= lower && sd <= upper) {
+            Cand* K = &cand[nk];
+            K->dd = sd;
+            for (int a = 0; a < 3; ++a) K->p[a] = B->c[a] + B->R * ((x[a] - B->c[a]) / dxc);
+            if (!(kd >= 0 && kd != ib && dist3(b[kd].c, K->p) < b[kd].R * (1.0 - 1e-12))) {
+              ++nk;
+              K->e1 = ib;
+              K->e2 = -1;
+              K->vertex = 0;
+            }
+          }
+          /* circles on this sphere and a later one */
+          for (int u = cstart[ib]; u < cstart[ib + 1]; ++u) {
+            const Circle* C = &circ[cidx[u]];
+            if (stamp[C->j] != q) continue;
             double w[3] = {x[0] - C->C[0], x[1] - C->C[1], x[2] - C->C[2]};
             /* every point of the circle is at least |x - C| - rho away */
             if (sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]) - C->rho > reach_d) continue;
@@ -493,6 +506,8 @@ int ses_sdf(const double* xyz, const double* radii, int n, double probe, const d
     }
     free(qb.v);
     free(cand);
+    free(stamp);
+    free(sdist);
   }
   if (pass == 0) {
     /* flood fill the solvent (d < 0) from the grid boundary */
@@ -544,7 +559,6 @@ int ses_sdf(const double* xyz, const double* radii, int n, double probe, const d
   free(deepest);
   free(circ);
   free(vert);
-  free(cb);
   free(vb);
   free(cl.start);
   free(cl.idx);
@@ -554,10 +568,8 @@ int ses_sdf(const double* xyz, const double* radii, int n, double probe, const d
   free(acl.idx);
   free(ov_start);
   free(ov);
-  if (nc > 0) {
-    free(ccl.start);
-    free(ccl.idx);
-  }
+  free(cstart);
+  free(cidx);
   if (nv > 0) {
     free(vcl.start);
     free(vcl.idx);
