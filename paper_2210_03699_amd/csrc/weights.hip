@@ -15,7 +15,8 @@
 // Q, P the regularised incomplete gamma functions.  Instead of tabulating
 // basis weights and interpolating them, the GPU evaluates this for every
 // entry directly: one wavefront per entry, the lanes splitting the theta
-// samples, the Fourier modes and the lattice points.
+// samples, the Fourier modes and the lattice points.  Only the modes up to the
+// last significant one are summed, over a lattice just wide enough for it.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -31,11 +32,16 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kModes = 41;    // even modes 0, 2, ..., 80
 constexpr int kSamples = 128; // samples of l on [0, pi)
-// Lattice half-width of both sums.  The first omitted points lie at distance
-// >= 6.5; there Q(s, pi r^2)/r < 3e-22 even for the highest mode (s = 40.5).
-constexpr int kLat = 6;
-constexpr int kSide = 2 * kLat + 1;
-constexpr int kPts = kSide * kSide;  // includes the origin, skipped
+// Lattice half-width of both sums for the highest mode in use: points with
+// |n_i| > L lie at distance >= L + 1/2, where Q(s, pi r^2)/r < 3e-22 for every
+// s = j + 1/2 up to the highest significant mode j (L = 4 up to j = 4, 5 up
+// to j = 18, 6 up to j = 40).
+__device__ inline int lattice_halfwidth(int jhi) { return jhi <= 4 ? 4 : (jhi <= 18 ? 5 : 6); }
+// Modes whose coefficients (of l11, and of l21) are all below this fraction
+// of that function's largest coefficient are dropped: with
+// |omega[e^{ik psi}/|y|]| < 25 over the cell, the dropped terms total below
+// 1e-13 of the largest coefficient.
+constexpr double kModeCut = 1e-16;
 constexpr int kWavesPerBlock = 4;
 // Reciprocals 1/(m + 3/2) of the gamma recurrences (x^s/Gamma(s+1) steps
 // from s to s + 1); indices reach kModes + the series length of step 4.
@@ -48,10 +54,11 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-__global__ __launch_bounds__(kWave* kWavesPerBlock) void weights_kernel(WeightArgs a) {
+__global__ __launch_bounds__(kWave* kWavesPerBlock, 4) void weights_kernel(WeightArgs a) {
   __shared__ double cos_t[kSamples], sin_t[kSamples];
   __shared__ double l11s[kWavesPerBlock][kSamples], l21s[kWavesPerBlock][kSamples];
   __shared__ double2 coef[kWavesPerBlock][kModes][2];  // (a11, b11), (a21, b21) of mode 2j
+  __shared__ double2 sumU[kWavesPerBlock][kSamples / 2], difV[kWavesPerBlock][kSamples / 2];
   __shared__ double rs[kRecip];
 
   const int lane = threadIdx.x % kWave;
@@ -99,45 +106,75 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock) void weights_kernel(WeightAr
   __syncthreads();
 
   // 2. Fourier coefficients of the even modes: lane j owns mode k = 2j.
-  //    cos(2j theta_p) = cos(2 pi (j p mod N) / N).
+  //    Samples p and N - p pair up (cos(2 pi j (N - p)/N) = cos(2 pi j p/N),
+  //    sin changes sign), so with U_p = l_p + l_{N-p}, V_p = l_p - l_{N-p}:
+  //    sum_p l_p cos = l_0 + (-1)^j l_{N/2} + sum_{p=1}^{N/2-1} U_p cos,
+  //    sum_p l_p sin = sum_{p=1}^{N/2-1} V_p sin; cos(2 j theta_p) =
+  //    cos(2 pi (j p mod N) / N).
+  {
+    const int p = lane;  // 1 .. N/2 - 1 (lane 0 unused)
+    if (p > 0) {
+      const double x11 = l11s[wv][p], y11 = l11s[wv][kSamples - p];
+      const double x21 = l21s[wv][p], y21 = l21s[wv][kSamples - p];
+      sumU[wv][p] = make_double2(x11 + y11, x21 + y21);
+      difV[wv][p] = make_double2(x11 - y11, x21 - y21);
+    }
+  }
+  __syncthreads();
   if (lane < kModes) {
     const int j = lane;
-    double a11 = 0.0, b11 = 0.0, a21 = 0.0, b21 = 0.0;
+    const double sg = (j & 1) ? -1.0 : 1.0;
+    double a11 = l11s[wv][0] + sg * l11s[wv][kSamples / 2];
+    double a21 = l21s[wv][0] + sg * l21s[wv][kSamples / 2];
+    double b11 = 0.0, b21 = 0.0;
 #pragma unroll 1
-    for (int p = 0; p < kSamples; ++p) {
-      int q = (j * p) & (kSamples - 1);
-      double cq = cos_t[q], sq = sin_t[q];
-      a11 += l11s[wv][p] * cq;
-      b11 += l11s[wv][p] * sq;
-      a21 += l21s[wv][p] * cq;
-      b21 += l21s[wv][p] * sq;
+    for (int p = 1; p < kSamples / 2; ++p) {
+      const int q = (j * p) & (kSamples - 1);
+      const double cq = cos_t[q], sq = sin_t[q];
+      const double2 U = sumU[wv][p], V = difV[wv][p];
+      a11 = fma(U.x, cq, a11);
+      a21 = fma(U.y, cq, a21);
+      b11 = fma(V.x, sq, b11);
+      b21 = fma(V.y, sq, b21);
     }
     double f = (j == 0) ? 1.0 / kSamples : 2.0 / kSamples;
     coef[wv][j][0] = make_double2(a11 * f, b11 * f);
     coef[wv][j][1] = make_double2(a21 * f, b21 * f);
   }
   __syncthreads();
-  // highest significant mode (wave-uniform): lane j holds the largest
-  // coefficient of mode 2j; a mode counts if it exceeds 1e-18 of the largest
-  double mj = 0.0;
+  // highest significant mode (wave-uniform): a mode counts if one of its
+  // coefficients of l11 (or of l21) exceeds kModeCut of the largest
+  // coefficient of the same function (the two scales differ by ~10^3)
+  double m11 = 0.0, m21 = 0.0;
   if (lane < kModes) {
     const double2 c1 = coef[wv][lane][0], c2 = coef[wv][lane][1];
-    mj = fmax(fmax(fabs(c1.x), fabs(c1.y)), fmax(fabs(c2.x), fabs(c2.y)));
+    m11 = fmax(fabs(c1.x), fabs(c1.y));
+    m21 = fmax(fabs(c2.x), fabs(c2.y));
   }
-  double mx = mj;
-  for (int off = kWave / 2; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, kWave));
-  const unsigned long long sig = __ballot(lane < kModes && mj > 1e-18 * mx);
+  double x11 = m11, x21 = m21;
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    x11 = fmax(x11, __shfl_xor(x11, off, kWave));
+    x21 = fmax(x21, __shfl_xor(x21, off, kWave));
+  }
+  const unsigned long long sig =
+      __ballot(lane < kModes && (m11 > kModeCut * x11 || m21 > kModeCut * x21));
   const int jmax = sig ? 64 - __clzll((long long)sig) : 1;
+  const int lat = lattice_halfwidth(jmax - 1);
+  const int side = 2 * lat + 1, pts = side * side;  // pts includes the origin, skipped
+  // q / side by a float reciprocal: q < 169 and (q + 1/2)/side stays at
+  // least 1/26 away from an integer, far above the float rounding
+  const float inv_side = 1.0f / (float)side;
 
   // 3. lattice sums, accumulated straight into the two weights
   double acc11 = 0.0, acc21 = 0.0;
   const double two_over_sqrtpi = 1.1283791670955126;
   const double sqrtpi = 1.7724538509055160;
 #pragma unroll 1
-  for (int idx = lane; idx < 2 * kPts; idx += kWave) {
-    const int recip = idx >= kPts;
-    const int q = recip ? idx - kPts : idx;
-    const int n1 = q / kSide - kLat, n2 = q % kSide - kLat;
+  for (int idx = lane; idx < 2 * pts; idx += kWave) {
+    const int recip = idx >= pts;
+    const int q = recip ? idx - pts : idx;
+    const int qd = (int)(((float)q + 0.5f) * inv_side);
+    const int n1 = qd - lat, n2 = q - qd * side - lat;
     if (n1 == 0 && n2 == 0) continue;
     double y1, y2, pr, pi, sg;
     if (!recip) {
