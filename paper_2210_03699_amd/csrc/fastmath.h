@@ -48,6 +48,45 @@ IBIM_HD inline float exp_neg_f32(float x) {
 }
 
 #if defined(__HIPCC__)
+// e^{-kappa R} for finite R >= 0 in the symmetric float64 pair kernel, by
+// Tang's table-driven method (ACM TOMS 15, 1989) with a table of 64 entries:
+// y = -64 kappa R / ln 2 is split as y = n + f, n = 64 m + j integer,
+// |f| <= 1/2, so that e^{-kappa R} = 2^m 2^{j/64} 2^{f/64}.  The nearest
+// integer n comes from adding 1.5 2^52 in the fused multiply-add that forms
+// y (the low word of the sum is n), f from a second fused multiply-add, and
+// 2^{f/64} - 1 from its Taylor polynomial of degree 5 (truncation below
+// 3.6e-17 relative).  Entry j of the table, 2^{j/64}, is held by lane j of
+// the wavefront and read with ds_bpermute, so every lane must be active.
+struct ExpWave {
+  double c;     // -64 kappa / ln 2
+  int lo, hi;   // this lane's table entry 2^{lane/64}
+};
+
+__device__ inline ExpWave exp_wave_init(double kappa) {
+  ExpWave w;
+  w.c = -kappa * 92.33248261689366;  // 64 / ln 2
+  const double t = exp2((double)(threadIdx.x & 63) * 0.015625);
+  w.lo = __double2loint(t);
+  w.hi = __double2hiint(t);
+  return w;
+}
+
+__device__ __forceinline__ double exp_neg_wave(double R, const ExpWave& w) {
+  const double kShift = 6755399441055744.0;  // 1.5 2^52
+  const double s = fma(R, w.c, kShift);
+  const int n = __double2loint(s);
+  const double f = fma(R, w.c, -(s - kShift));
+  double p = fma(f, 1.2417843701716925e-12, 5.732851688640402e-10);
+  p = fma(p, f, 2.1173137155464776e-07);
+  p = fma(p, f, 5.86490495505617e-05);
+  p = fma(p, f, 0.010830424696249145);
+  p *= f;
+  const int addr = (n & 63) << 2;
+  const double T = __hiloint2double(__builtin_amdgcn_ds_bpermute(addr, w.hi),
+                                    __builtin_amdgcn_ds_bpermute(addr, w.lo));
+  return ldexp(fma(T, p, T), n >> 6);
+}
+
 // 1/sqrt(x) for finite x > 0: hardware estimate and one third-order
 // correction y (1 + e/2 + 3 e^2/8), e = 1 - x y^2.
 __device__ inline double rsqrt_pos(double x) {

@@ -111,18 +111,19 @@ __device__ __forceinline__ void pair_f32_sym(float xk, float yk, float zk, float
   const float iR3 = iR2 * iR;
   const float kr = c.kappa * R;
   const float e = exp_neg_f32(kr);
-  const float te = __fmaf_rn(e, kr, e);
   const float rny = __fmaf_rn(rz, nzm, __fmaf_rn(ry, nym, rx * nxm));
   const float rnx = __fmaf_rn(rz, nzk, __fmaf_rn(ry, nyk, rx * nxk));
   const float nn = __fmaf_rn(nzk, nzm, __fmaf_rn(nyk, nym, nxk * nxm));
-  // (1 - c t)/R^3 = 1/R^3 - c (t/R^3), (1 - e)/R = 1/R - e/R
-  const float t3 = te * iR3;
+  // t3 = e (1 + kR)/R^3, u = 1/R^3 - t3; (1 - c t)/R^3 = 1/R^3 - c t3,
+  // (1 - e)/R = 1/R - e/R, K21 = n_k.n_m u + q (k^2 e/R^3 - 3 u/R^2)
+  const float eiR3 = e * iR3;
+  const float t3 = __fmaf_rn(eiR3, kr, eiR3);
+  const float u = iR3 - t3;
   const float f1 = __fmaf_rn(-c.c1, t3, iR3);
   const float f2 = __fmaf_rn(-c.c2, t3, iR3);
   const float g12 = __fmaf_rn(-e, iR, iR);
-  const float phi2 = 1.0f - te;
   const float q = rnx * rny;
-  const float g21 = __fmaf_rn(phi2, __fmaf_rn(q * iR2, -3.0f, nn), (c.kappa2 * e) * q) * iR3;
+  const float g21 = __fmaf_rn(nn, u, q * __fmaf_rn(u * iR2, -3.0f, c.kappa2 * eiR3));
   const float g11 = rny * f1, g22 = rnx * f2;
   d1 = __fmaf_rn(g11, am1, -(g12 * am2));
   d2 = __fmaf_rn(g21, am1, g22 * am2);

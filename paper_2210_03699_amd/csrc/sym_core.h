@@ -30,7 +30,10 @@ __device__ __forceinline__ T* lds_at(T* base, unsigned byte_off) {
 template <class P>
 struct Shared {
   typename P::Lds rec;                     // records of the column tile J
-  double2 cacc[kT];                        // column sums of J (row 1, row 2)
+  // column sums of J (row 1, row 2) in two arrays of doubles: lanes add to
+  // consecutive slots, 8 bytes apart, which keeps the LDS atomics free of
+  // bank conflicts (a 16-byte stride gave 4-way conflicts)
+  double cacc1[kT], cacc2[kT];
   double racc1[kRows][kT], racc2[kRows][kT];  // row sums, lane-private slots
 };
 
@@ -66,7 +69,8 @@ __device__ __forceinline__ void one_way(const SymArgs& a, const typename P::Cons
 // One work item (rb, cb).  Called by all 256 threads of the workgroup.
 template <class P>
 __device__ void item(const SymArgs& a, int rb, int cb, Shared<P>& sh) {
-  double2* const cacc = sh.cacc;
+  double* const cacc1 = sh.cacc1;
+  double* const cacc2 = sh.cacc2;
   auto& racc1 = sh.racc1;
   auto& racc2 = sh.racc2;
   const int tid = threadIdx.x;
@@ -84,7 +88,8 @@ __device__ void item(const SymArgs& a, int rb, int cb, Shared<P>& sh) {
     {
       const int32_t m = J * kT + tid;
       if (m < M) P::store(sh.rec, tid, P::load(a, m));
-      cacc[tid] = make_double2(0.0, 0.0);
+      cacc1[tid] = 0.0;
+      cacc2[tid] = 0.0;
     }
     __syncthreads();
     for (int i = 0; i < rows; ++i) {
@@ -101,8 +106,8 @@ __device__ void item(const SymArgs& a, int rb, int cb, Shared<P>& sh) {
           // row J from the sources of I (uniform global loads)
           double c1 = 0.0, c2 = 0.0;
           one_way<P>(a, pc, J, I, [&](int j) { return P::load(a, I * kT + j); }, c1, c2);
-          cacc[tid].x += c1;
-          cacc[tid].y += c2;
+          cacc1[tid] += c1;
+          cacc2[tid] += c2;
         }
         __syncthreads();
         continue;
@@ -118,9 +123,9 @@ __device__ void item(const SymArgs& a, int rb, int cb, Shared<P>& sh) {
           x16 += 16u;
           double C1, C2;
           P::both(f, P::at(sh.rec, off), pc, S1, S2, C1, C2);
-          double2* c = lds_at(cacc, off);
-          atomicAdd(&c->x, C1);
-          atomicAdd(&c->y, C2);
+          const unsigned off8 = off >> 1;  // the same slot in an array of doubles
+          atomicAdd(lds_at(cacc1, off8), C1);
+          atomicAdd(lds_at(cacc2, off8), C2);
         }
         __syncthreads();
       }
@@ -129,8 +134,8 @@ __device__ void item(const SymArgs& a, int rb, int cb, Shared<P>& sh) {
     }
     // column sums of J
     double* cp = a.colpart + sym_col_slot(rb, J, rows) * (2 * kT);
-    cp[tid] = a.scale * cacc[tid].x;
-    cp[kT + tid] = a.scale * cacc[tid].y;
+    cp[tid] = a.scale * cacc1[tid];
+    cp[kT + tid] = a.scale * cacc2[tid];
     __syncthreads();  // LDS is refilled for the next column tile
   }
   // row sums of this item's row tiles that met at least one J >= I

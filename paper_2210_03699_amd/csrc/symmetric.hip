@@ -48,9 +48,12 @@ struct Fp64 {
   struct Lds {
     double2 A[kT], B[kT], C[kT], D[kT];  // (px,py) (pz,nx) (ny,nz) (a1,a2)
   };
-  using Consts = PairConsts;
+  struct Consts {
+    PairConsts k;  // one-directional evaluations
+    ExpWave ew;    // table exponential of the symmetric evaluation
+  };
   static __device__ __forceinline__ Consts consts(const SymArgs& a) {
-    return PairConsts{a.c1, a.c2, a.kappa, a.kappa * a.kappa};
+    return Consts{PairConsts{a.c1, a.c2, a.kappa, a.kappa * a.kappa}, exp_wave_init(a.kappa)};
   }
   static __device__ __forceinline__ Rec load(const SymArgs& a, int32_t m) {
     const double wm = a.w[m];
@@ -71,10 +74,13 @@ struct Fp64 {
   static __device__ __forceinline__ void one(const Rec& t, const Rec& r, const Consts& pc,
                                              double& d1, double& d2) {
     pair_f64<false>(t.px, t.py, t.pz, t.nx, t.ny, t.nz, r.px, r.py, r.pz, r.nx, r.ny, r.nz, r.a1,
-                    r.a2, pc, d1, d2);
+                    r.a2, pc.k, d1, d2);
   }
   // Both directions of the pair (fixed f, rotating m): k <- m added to
-  // (S1, S2), m <- k returned in (C1, C2).
+  // (S1, S2), m <- k returned in (C1, C2).  With u = (1 - e(1 + kR))/R^3 and
+  // t3 = e(1 + kR)/R^3 the kernel factors are (1 - c t)/R^3 = 1/R^3 - c t3
+  // and K21 R^3 / R^3 = n_k.n_m u + q (k^2 e/R^3 - 3 u/R^2).  Called with all
+  // 64 lanes of the wavefront active (the exponential reads other lanes).
   static __device__ __forceinline__ void both(const Rec& f, const Rec& m, const Consts& pc,
                                               double& S1, double& S2, double& C1, double& C2) {
     const double rx = f.px - m.px, ry = f.py - m.py, rz = f.pz - m.pz;  // r = x_k - P_m
@@ -83,20 +89,19 @@ struct Fp64 {
     const double R = R2s * iR;
     const double iR2 = iR * iR;
     const double iR3 = iR2 * iR;
-    const double kr = pc.kappa * R;
-    const double e = exp_neg(kr);
-    const double te = fma(e, kr, e);
+    const double e = exp_neg_wave(R, pc.ew);
+    const double kr = pc.k.kappa * R;
     const double rny = fma(rz, m.nz, fma(ry, m.ny, rx * m.nx));  // r . n_m
     const double rnx = fma(rz, f.nz, fma(ry, f.ny, rx * f.nx));  // r . n_k
     const double nn = fma(f.nz, m.nz, fma(f.ny, m.ny, f.nx * m.nx));
-    // kernel factors with 1/R^3 folded in: (1 - c t)/R^3 = 1/R^3 - c (t/R^3)
-    const double t3 = te * iR3;
-    const double f1 = fma(-pc.c1, t3, iR3);
-    const double f2 = fma(-pc.c2, t3, iR3);
+    const double eiR3 = e * iR3;
+    const double t3 = fma(eiR3, kr, eiR3);
+    const double u = iR3 - t3;
+    const double f1 = fma(-pc.k.c1, t3, iR3);
+    const double f2 = fma(-pc.k.c2, t3, iR3);
     const double g12 = fma(-e, iR, iR);  // (1 - e)/R
-    const double phi2 = 1.0 - te;
     const double q = rnx * rny;
-    const double g21 = fma(phi2, fma(q * iR2, -3.0, nn), pc.kappa2 * e * q) * iR3;
+    const double g21 = fma(nn, u, q * fma(u * iR2, -3.0, pc.k.kappa2 * eiR3));
     // k <- m
     const double g11 = rny * f1, g22 = rnx * f2;
     S1 = fma(g11, m.a1, fma(-g12, m.a2, S1));
