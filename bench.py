@@ -133,9 +133,15 @@ def serve_bench(args):
     hs = tuple(float(v) for v in args.hs.split(","))
     atoms = tuple(int(v) for v in args.ses_atoms.split(","))
     t = time.perf_counter()
-    reqs = workloads.serving_stream(args.requests, seed=4, hs=hs, ses_atoms=atoms)
-    print(f"[serve] generated {len(reqs)} requests in {time.perf_counter() - t:.1f}s",
-          file=sys.stderr, flush=True)
+    def progress(i, wl):
+        if i % 16 == 15 or i + 1 == args.requests:
+            print(f"[serve] made {i + 1}/{args.requests} requests "
+                  f"({time.perf_counter() - t:.0f}s)", file=sys.stderr, flush=True)
+
+    reqs = workloads.serving_stream(args.requests, seed=4, hs=hs, ses_atoms=atoms,
+                                    progress=progress)
+    t_gen = time.perf_counter() - t
+    print(f"[serve] generated {len(reqs)} requests in {t_gen:.1f}s", file=sys.stderr, flush=True)
     budget = int(args.hbm_budget_gib * (1 << 30))
 
     def run(arrivals):
@@ -146,7 +152,12 @@ def serve_bench(args):
         tickets, t_arr, t_done = {}, {}, {}
         nxt = 0
         t0 = time.perf_counter()
+        t_report = t0
         while nxt < len(order) or len(t_done) < len(order):
+            if time.perf_counter() - t_report > 15.0:
+                t_report = time.perf_counter()
+                print(f"[serve] {t_report - t0:.0f}s: {nxt} submitted, {len(t_done)} done",
+                      file=sys.stderr, flush=True)
             now = time.perf_counter() - t0
             while nxt < len(order) and arrivals[order[nxt]] <= now:
                 i = int(order[nxt])
@@ -211,6 +222,10 @@ def serve_bench(args):
                 "pairs": "M^2 per application whichever summation"}
                if summation == SUM_TREE else {}),
             "M_min": Ms[0], "M_median": Ms[len(Ms) // 2], "M_max": Ms[-1],
+            "M_p10_p90": [percentile(Ms, 10), percentile(Ms, 90)],
+            "requests_by_h": {str(hh): sum(1 for w in reqs if w.h == hh) for hh in hs},
+            "ses_requests": sum(1 for w in reqs if w.meta.get("geometry") == "ses"),
+            "input_generation_s": t_gen,
         },
         "solves_per_s": len(reqs) / mk2,
         "capacity_solves_per_s": capacity,
@@ -222,6 +237,10 @@ def serve_bench(args):
         "rounds": st2["rounds"],
         "max_active": st2["max_active_seen"],
         "bytes_peak": st2["bytes_peak"],
+        # admission passes that held a set-up request back (closed batch, Poisson run)
+        "held_for_slot": [st["held_for_slot"], st2["held_for_slot"]],
+        "held_for_budget": [st["held_for_budget"], st2["held_for_budget"]],
+        "bytes_peak_closed_batch": st["bytes_peak"],
     }
     print(json.dumps(out), flush=True)
 
@@ -340,6 +359,49 @@ def twin_check(args):
     return out
 
 
+def rnear_sweep(args):
+    """Mixed form: G_pol and surface-potential error against the stored oracle
+    solves and time per solve, for near radii r_near = 1h, 2h, 3h, 4h (and the
+    FP64 solve for reference), on the 500-atom molecule and the 2000-atom
+    molecule's h = 0.7 twin."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2210_03699_amd import FP64, MIXED, Problem
+
+    out = {"metric": "mixed-form error and time per solve against r_near", "cases": []}
+    for name, gname in (("ses500", "ses500_h0.3.json"), ("ses2000_twin", "ses2000_twin_h0.7.json")):
+        gold = json.load(open(os.path.join(ROOT, "tests", "golden", gname)))
+        wl = workloads.by_name(name)
+        rows = np.asarray(gold["rows"], dtype=np.int64)
+        xr1, xr2 = np.asarray(gold["x_rows_1"]), np.asarray(gold["x_rows_2"])
+        for f in (0.0, 1.0, 2.0, 3.0, 4.0):
+            prec = FP64 if f == 0.0 else MIXED
+            t0 = time.perf_counter()
+            prob = Problem.from_workload(wl, device=0, precision=prec, r_near=f * wl.h)
+            torch.cuda.synchronize()
+            t_setup = time.perf_counter() - t0
+            times = []
+            for rep in range(3):
+                t0 = time.perf_counter()
+                x, info = prob.solve_energy(wl.tol)
+                times.append(time.perf_counter() - t0)
+            xh = x.cpu().numpy()
+            M = prob.M
+            rec = {"workload": wl.name, "M": M, "precision": "fp64" if f == 0.0 else "mixed",
+                   "r_near_over_h": f, "setup_s": t_setup, "solve_s": min(times),
+                   "iters": info["iters"],
+                   "g_pol_rel_err_vs_oracle": abs(info["g_pol"] - gold["g_pol"]) / abs(gold["g_pol"]),
+                   "psi_rows_max_rel_err": float(np.max(np.abs(xh[rows] - xr1)) / np.max(np.abs(xr1))),
+                   "psi_n_rows_max_rel_err":
+                       float(np.max(np.abs(xh[M + rows] - xr2)) / np.max(np.abs(xr2)))}
+            print(f"[rnear] {json.dumps(rec)}", file=sys.stderr, flush=True)
+            out["cases"].append(rec)
+            prob.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -372,6 +434,9 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: 3 operator applications and one plain "
                          "256 MiB device copy (the reference for the HBM byte counters)")
+    ap.add_argument("--rnear-sweep", action="store_true",
+                    help="mixed form: error against the stored oracle solves and time per solve "
+                         "for r_near = h, 2h, 3h, 4h on the 500-atom molecule and the h = 0.7 twin")
     ap.add_argument("--serve", action="store_true",
                     help="serving benchmark: a seeded stream of independent requests through "
                          "the continuous-batching server (p50/p99 latency, solves/s)")
@@ -392,6 +457,9 @@ def main():
         sys.exit(2)
     if args.serve:
         serve_bench(args)
+        return
+    if args.rnear_sweep:
+        rnear_sweep(args)
         return
 
     import numpy as np

@@ -65,7 +65,7 @@ typedef struct {
   int device;          /* HIP device ordinal; -1 = host-only context (setup
                           and inspection only, no device memory) */
   double r_near;       /* IBIM_MIXED: pairs closer than r_near (Angstrom) are
-                          re-evaluated in float64 (default 0 = 4 h) */
+                          re-evaluated in float64 (default 0 = 2 h) */
   int hybrid;          /* IBIM_CTR2 (default), IBIM_HYB or IBIM_KREG, below */
   int precond;         /* IBIM_PRECOND_DIAG (default) or IBIM_PRECOND_NONE, below */
   int summation;       /* IBIM_SUM_DIRECT (default) or IBIM_SUM_TREE, below */
@@ -388,6 +388,14 @@ typedef struct {
   size_t bytes_peak;
   size_t budget_bytes;
   int active, waiting, max_active_seen;
+  /* admission passes (one per request and round) that held a set-up request
+   * back: for want of a free slot, or because its footprint estimate did not
+   * fit the budget left */
+  int64_t held_for_slot, held_for_budget;
+  /* largest amount by which an admitted request's device bytes (at the peak
+   * of its setup, or after it) exceeded the footprint estimate it was
+   * admitted on; 0 while every estimate was an upper bound */
+  size_t estimate_shortfall;
 } ibim_server_stats;
 
 #define IBIM_REQ_WAITING 0 /* preparing on the host or queued for admission */

@@ -276,6 +276,49 @@ int check_options(const ibim_options& o) {
   return IBIM_OK;
 }
 
+// Near radius of the mixed form (default 2h: the smallest measured radius
+// whose surface-potential error stays near the larger radii's, with G_pol
+// about 100 times inside the 1e-6 bar at every radius from h to 4h).
+static double near_radius(const ibim_options& o, double h) {
+  return o.r_near > 0.0 ? o.r_near : 2.0 * h;
+}
+
+// Upper bound on the mixed near list: for every row, the tube nodes in the
+// cube of half-width ceil((r_near + 2 eps)/h) cells around its grid node
+// (clipped to the grid) that build_near_list scans, counted with 3-D prefix
+// sums of the tube indicator.
+static int64_t near_list_bound(const HostPlan& pl, int nx, int ny, int nz, double r_near) {
+  const int64_t sx = (int64_t)(ny + 1) * (nz + 1), sy = nz + 1;
+  std::vector<int32_t> S((size_t)(nx + 1) * sx, 0);
+  for (int64_t m = 0; m < pl.M; ++m) {
+    const int64_t q = pl.grid_index[m];
+    const int i = (int)(q / ((int64_t)ny * nz)), j = (int)((q / nz) % ny), k = (int)(q % nz);
+    S[(i + 1) * sx + (j + 1) * sy + (k + 1)] = 1;
+  }
+  for (int i = 1; i <= nx; ++i)
+    for (int j = 1; j <= ny; ++j)
+      for (int k = 1; k <= nz; ++k) {
+        const int64_t c = i * sx + j * sy + k;
+        S[c] += S[c - sx] + S[c - sy] + S[c - 1] - S[c - sx - sy] - S[c - sx - 1] - S[c - sy - 1] +
+                S[c - sx - sy - 1];
+      }
+  const double reach = std::ceil((r_near + 2.0 * pl.eps) / pl.h);
+  const double diag = std::ceil(std::sqrt((double)nx * nx + (double)ny * ny + (double)nz * nz));
+  const int W = (int)std::min(reach, diag);
+  int64_t total = 0;
+  for (int64_t m = 0; m < pl.M; ++m) {
+    const int64_t q = pl.grid_index[m];
+    const int i = (int)(q / ((int64_t)ny * nz)), j = (int)((q / nz) % ny), k = (int)(q % nz);
+    const int64_t i0 = std::max(i - W, 0), i1 = std::min(i + W, nx - 1) + 1;
+    const int64_t j0 = std::max(j - W, 0), j1 = std::min(j + W, ny - 1) + 1;
+    const int64_t k0 = std::max(k - W, 0), k1 = std::min(k + W, nz - 1) + 1;
+    auto at = [&](int64_t a, int64_t b, int64_t c) { return (int64_t)S[a * sx + b * sy + c]; };
+    total += at(i1, j1, k1) - at(i0, j1, k1) - at(i1, j0, k1) - at(i1, j1, k0) + at(i0, j0, k1) +
+             at(i0, j1, k0) + at(i1, j0, k0) - at(i0, j0, k0);
+  }
+  return total;
+}
+
 // Host part of ibim_setup: the geometry, the correction sets and, for the
 // treecode, its plan; IBIM_SUM_TREE is resolved here for the problem's size.
 int ctx_create_host(const double* sdf, int nx, int ny, int nz, const double origin[3], double h,
@@ -319,6 +362,8 @@ int ctx_create_host(const double* sdf, int nx, int ny, int nz, const double orig
     delete c;
     return fail(r, err);
   }
+  if (c->opt.precision == IBIM_MIXED && c->opt.summation == IBIM_SUM_DIRECT)
+    c->near_bound = near_list_bound(c->plan, nx, ny, nz, near_radius(c->opt, h));
   *out = c;
   return IBIM_OK;
 }
@@ -344,14 +389,17 @@ size_t ctx_footprint_estimate(const ibim_ctx* c) {
     b += (size_t)pp.nsplit * n * 8;
   // Krylov basis and GMRES scratch (as allocated by ensure_krylov)
   b += ((m + 4) * n + (m + 1) * (m + 1030) + 8 * m) * 8;
+  // temporaries of the device setup (freed before it returns, but held at
+  // its peak): the weights' per-entry inputs, then (mixed direct form) the
+  // grid-to-node map, node grid indices and the near-list row counts
+  size_t tmp = nnz * (4 + 1 + 3 * 8) + 8 * M * 8;
   if (c->opt.precision == IBIM_MIXED && c->opt.summation == IBIM_SUM_DIRECT) {
-    const double h = pl.h, eps = pl.eps;
-    const double rn = c->opt.r_near > 0.0 ? c->opt.r_near : 4.0 * h;
-    // near pairs per row: a disc of radius r_near in a slab of thickness 2 eps
-    const double per_row = 3.14159265358979 * rn * rn * 2.0 * eps / (h * h * h) * 1.3 + 16.0;
-    b += 6 * M * 4 + (M + 1) * 8 + (size_t)(per_row * (double)M) * 4;
+    const size_t grid = (size_t)c->nx * c->ny * c->nz;
+    tmp = std::max(tmp, grid * 4 + M * 8 + M * 4);
+    // float32 geometry, near-list rows and (bounded) entries
+    b += 6 * M * 4 + (M + 1) * 8 + (size_t)c->near_bound * 4;
   }
-  return b;
+  return b + tmp;
 }
 
 int ctx_setup_device(ibim_ctx* c, hipStream_t s) {
@@ -406,6 +454,9 @@ int ctx_setup_device(ibim_ctx* c, hipStream_t s) {
   int8_t* d_axis = nullptr;
   double *d_alpha = nullptr, *d_beta = nullptr, *d_eta = nullptr, *d_tau = nullptr;
   double *d_k1 = nullptr, *d_k2 = nullptr;
+  // the weights' per-entry inputs and outputs are alive beside everything
+  // uploaded so far
+  size_t peak = bytes + (size_t)nnz * (4 + 1 + 3 * 8) + 8 * (size_t)M * 8 + 6 * (size_t)nnz * 8;
   hipError_t e = upload(&d_rowid, pl.crowid.data(), pl.crowid.size(), s);
   if (e == hipSuccess) e = upload(&d_axis, pl.caxis.data(), pl.caxis.size(), s);
   if (e == hipSuccess) e = upload(&d_alpha, pl.calpha.data(), pl.calpha.size(), s);
@@ -477,12 +528,15 @@ int ctx_setup_device(ibim_ctx* c, hipStream_t s) {
       if (e == hipSuccess) e = upload(&d_gidx, pl.grid_index.data(), pl.grid_index.size(), s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
     }
-    const double r_near = o.r_near > 0.0 ? o.r_near : 4.0 * h;
+    const double r_near = near_radius(o, h);
     if (e == hipSuccess)
       e = build_near_list(P, d_node_of, d_gidx, nx, ny, nz, r_near, eps_tube, s);
     dfree(d_node_of);
     dfree(d_gidx);
     if (e != hipSuccess) return bad(e, "mixed-precision setup");
+    // grid-to-node map and node indices beside the near list (or its counts)
+    peak = std::max(peak, bytes + (size_t)nx * ny * nz * 4 + (size_t)M * 8 +
+                              std::max((size_t)M * 4, ((size_t)M + 1) * 8 + (size_t)P.nnear * 4));
     bytes += ((size_t)M + 1) * 8 + (size_t)P.nnear * 4;
   }
   c->pair = make_pair_plan(M, o.precision);
@@ -537,6 +591,7 @@ int ctx_setup_device(ibim_ctx* c, hipStream_t s) {
   if (e == hipSuccess) e = dalloc(&c->d_psi, (size_t)(n_charges > 0 ? n_charges : 1));
   if (e != hipSuccess) return bad(e, "setup");
   c->device_bytes = bytes;
+  c->setup_peak_bytes = std::max(peak, bytes);
   return IBIM_OK;
 }
 

@@ -106,7 +106,11 @@ struct ibim_ctx {
   bool on_device() const { return opt.device >= 0 && device_ready; }
   bool device_ready = false;
   int nx = 0, ny = 0, nz = 0;  // grid dimensions (kept for the near list)
+  // mixed direct form: an upper bound on the near-list entries (tube nodes in
+  // the cube each row's near search scans), from ctx_create_host
+  int64_t near_bound = 0;
   size_t device_bytes = 0;     // device memory held by the context
+  size_t setup_peak_bytes = 0; // largest device memory during its setup (temporaries included)
 
   void release() {
     if (!on_device()) return;
@@ -140,8 +144,9 @@ int ctx_create_host(const double* sdf, int nx, int ny, int nz, const double orig
                     const ibim_options& o, ibim_ctx** out);
 // Device part: uploads, correction weights, mixed-precision data, scratch.
 int ctx_setup_device(ibim_ctx* c, hipStream_t s);
-// Device bytes a context will hold once set up with a Krylov basis (an
-// estimate of the near list for the mixed form).
+// Device bytes a context will hold once set up with a Krylov basis, plus the
+// peak of its setup temporaries: an upper bound (the near list of the mixed
+// form is bounded by the tube nodes its search scans).
 size_t ctx_footprint_estimate(const ibim_ctx* c);
 
 int apply_impl(ibim_ctx* c, const double* u, double* out, hipStream_t s);

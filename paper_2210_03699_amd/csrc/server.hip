@@ -254,6 +254,13 @@ int admit_device(ibim_server* srv, Request* r) {
   HIP_TRY(dalloc(&r->d_b, (size_t)N), "right-hand side allocation");
   HIP_TRY(dalloc(&r->d_x, (size_t)N), "iterate allocation");
   r->setup_bytes = c->device_bytes + 2 * (size_t)N * 8;
+  {
+    const size_t top = std::max(c->setup_peak_bytes, r->setup_bytes);
+    if (top > r->estimate) {
+      std::lock_guard<std::mutex> lk(srv->mu);
+      srv->st.estimate_shortfall = std::max(srv->st.estimate_shortfall, top - r->estimate);
+    }
+  }
   r->M = c->P.M;
   double* st = srv->d_status + (size_t)r->slot * kStatusStride;
   if (int e = rhs_impl(c, r->d_b, s)) return e;
@@ -412,6 +419,8 @@ void admit_waiting(ibim_server* srv, std::vector<Request*>* fresh, bool now) {
         mark_failed(srv, r, IBIM_ENOMEM, "request footprint exceeds the server's HBM budget");
         continue;
       }
+      if (slot) ++srv->st.held_for_budget;
+      else ++srv->st.held_for_slot;
       still.push_back(r);
     }
   }
@@ -816,7 +825,11 @@ int ibim_server_get_stats(ibim_server* srv, ibim_server_stats* st) {
   srv->st.bytes_peak = srv->peak;
   srv->st.active = (int)srv->active.size();
   srv->st.waiting = (int)srv->waiting.size() + srv->admitting;  // as ibim_server_step
-  *st = srv->st;
+  {
+    // estimate_shortfall is written by the admission thread
+    std::lock_guard<std::mutex> lk(srv->mu);
+    *st = srv->st;
+  }
   return IBIM_OK;
 }
 

@@ -58,7 +58,9 @@ class _ServerStats(ctypes.Structure):
                 ("rounds", ctypes.c_int64), ("batched_items", ctypes.c_int64),
                 ("bytes_in_use", ctypes.c_size_t), ("bytes_peak", ctypes.c_size_t),
                 ("budget_bytes", ctypes.c_size_t), ("active", ctypes.c_int),
-                ("waiting", ctypes.c_int), ("max_active_seen", ctypes.c_int)]
+                ("waiting", ctypes.c_int), ("max_active_seen", ctypes.c_int),
+                ("held_for_slot", ctypes.c_int64), ("held_for_budget", ctypes.c_int64),
+                ("estimate_shortfall", ctypes.c_size_t)]
 
 
 REQ_WAITING, REQ_ACTIVE, REQ_DONE, REQ_FAILED = 0, 1, 2, -1

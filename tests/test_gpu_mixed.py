@@ -4,7 +4,7 @@
   kernel is replaced by its float64 value in the finishing pass; the result
   must equal the float64 operator to float64 rounding.  This holds only if the
   two float32 evaluations of each pair agree bit for bit.
-* With the default r_near = 4h the operator, the solution and G_pol are
+* With the default r_near = 2h the operator, the solution and G_pol are
   compared with the float64 oracle; the stated bar for G_pol is 1e-6
   relative, and the measured errors are printed.
 """

@@ -160,6 +160,22 @@ def test_request_admitted_while_another_is_mid_solve(wls):
 
 
 @pytest.mark.parametrize("precision", [ibim.FP64, ibim.MIXED])
+def test_footprint_estimates_bound_the_device_bytes(wls, precision):
+    """Admission reserves each request's footprint estimate; it must bound the
+    device bytes the request holds at the peak of its setup (temporaries
+    included) and after it, for molecules of the serving stream's kind (the
+    mixed near list included) and spheres."""
+    pool = dict(wls)
+    pool["ses_60_h0.5"] = workloads.ses_molecule(60, 12.0, 0.5, 2.0, seed=21, tol=1e-6)
+    pool["ses_150_h0.3"] = workloads.ses_molecule(150, 17.0, 0.3, 2.0, seed=22, tol=1e-6)
+    _, stats = _serve(pool, list(pool), precision=precision)
+    _say(f"[serving] precision={precision}: estimate shortfall {stats['estimate_shortfall']} B, "
+         f"peak {stats['bytes_peak']} B")
+    assert stats["finished"] == len(pool) and stats["failed"] == 0
+    assert stats["estimate_shortfall"] == 0
+
+
+@pytest.mark.parametrize("precision", [ibim.FP64, ibim.MIXED])
 def test_tree_requests_in_the_mix(wls, precision):
     """With IBIM_SUM_TREE and a size threshold, requests of at least
     tree_min_nodes nodes run the float64 treecode inside the rounds and the

@@ -232,14 +232,15 @@ def by_name(name: str) -> Workload:
     raise KeyError(name)
 
 
-def serving_stream(n_requests=32, seed=4, sphere_radius=(2.0, 10.0), max_charges=30,
-                   ses_atoms=(50, 200), hs=(0.3, 0.5), tol=1e-6) -> list:
+def serving_stream(n_requests=256, seed=4, sphere_radius=(2.0, 10.0), max_charges=30,
+                   ses_atoms=(50, 2000), hs=(0.2, 0.3, 0.5), tol=1e-6, progress=None) -> list:
     """Seeded mix of solve requests for the serving benchmark.
 
     Half spheres (radius uniform in ``sphere_radius``, 1..``max_charges``
     charges in r <= 0.8 R), half random-walk SES molecules (atom count uniform
     in ``ses_atoms``, box scaled as 25 A * (n/500)^(1/3)); grid spacing drawn
-    from ``hs``, tube half-width 2h, GMRES tolerance ``tol``.
+    from ``hs``, tube half-width 2h, GMRES tolerance ``tol``.  ``progress``,
+    if given, is called with (index, workload) after each request is made.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []
@@ -256,6 +257,8 @@ def serving_stream(n_requests=32, seed=4, sphere_radius=(2.0, 10.0), max_charges
             box = 25.0 * (n / 500.0) ** (1.0 / 3.0)
             wl = ses_molecule(n, box, h, 2.0, seed=sub_seed, tol=tol)
         out.append(wl)
+        if progress is not None:
+            progress(i, wl)
     return out
 
 
