@@ -142,7 +142,7 @@ __device__ void item(const SymArgs& a, int rb, int cb, Shared<P>& sh) {
   for (int i = 0; i < rows; ++i) {
     const int I = I0 + i;
     if (I >= T || I > J1 - 1) continue;
-    double* rp = a.rowpart + ((size_t)cb * T + I) * (2 * kT);
+    double* rp = a.rowpart + sym_row_slot(cb, I, a.b, (T + a.b - 1) / a.b) * (2 * kT);
     rp[tid] = a.scale * racc1[i][tid];
     rp[kT + tid] = a.scale * racc2[i][tid];
   }

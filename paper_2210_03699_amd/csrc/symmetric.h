@@ -26,6 +26,20 @@ __host__ __device__ inline size_t sym_col_slot(int rb, int J, int rows) {
   return (size_t)rows * q * (q + 1) / 2 + r * (q + 1) + (size_t)rb;
 }
 
+// Row-sum slot of (column block cb, row tile X), cb >= X / b, for column
+// blocks of b tiles: the slots of tile X follow those of tiles 0 .. X-1,
+// which hold nCB - floor(X'/b) slots each (a packed upper triangle).
+__host__ __device__ inline size_t sym_row_slot(int cb, int X, int b, int nCB) {
+  const int64_t q = X / b, r = X % b;
+  const int64_t before = (int64_t)X * nCB - (b * q * (q - 1) / 2 + q * r);
+  return (size_t)(before + (cb - q));
+}
+// Row-sum slots of all T tiles.
+__host__ __device__ inline size_t sym_row_slots_total(int T, int b, int nCB) {
+  const int64_t q = T / b, r = T % b;
+  return (size_t)((int64_t)T * nCB - (b * q * (q - 1) / 2 + q * r));
+}
+
 // Decomposition of the upper triangle of tile pairs into work items.
 struct SymPlan {
   bool enabled = false;
@@ -34,7 +48,7 @@ struct SymPlan {
   int rows = 0;  // row tiles per item (1, 2 or kSymRows)
   int nRB = 0;   // row blocks (`rows` tiles each)
   int nCB = 0;  // column blocks
-  size_t scratch_doubles = 0;  // row sums (nCB x T) + column sums (sym_col_slot(0, T, rows)), 512 doubles each
+  size_t scratch_doubles = 0;  // row sums (sym_row_slots_total) + column sums (sym_col_slot(0, T, rows)), 512 doubles each
 };
 
 struct SymArgs {
@@ -51,7 +65,7 @@ struct SymArgs {
   int rows;  // row tiles per item
   double c1, c2, kappa;
   double scale;       // h^3 / (4 pi)
-  double* rowpart;    // [nCB][T][2][256]
+  double* rowpart;    // [sym_row_slot(cb, I, b, nCB)][2][256]
   double* colpart;    // [sym_col_slot(rb, J, rows)][2][256]
 };
 

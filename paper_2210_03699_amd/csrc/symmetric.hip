@@ -134,7 +134,7 @@ __device__ __forceinline__ void finish_sym_row(const SymFinishArgs& a, int32_t k
   const int X = k / kT, t = k % kT;
   double s1 = 0.0, s2 = 0.0;
   for (int cb = X / a.b; cb < a.nCB; ++cb) {
-    const double* rp = a.rowpart + ((size_t)cb * a.T + X) * (2 * kT);
+    const double* rp = a.rowpart + sym_row_slot(cb, X, a.b, a.nCB) * (2 * kT);
     s1 += rp[t];
     s2 += rp[kT + t];
   }
@@ -208,7 +208,8 @@ SymPlan make_sym_plan(int32_t M, size_t max_scratch_bytes) {
   }
   pl.b = b;
   pl.nCB = (pl.T + b - 1) / b;
-  pl.scratch_doubles = ((size_t)pl.nCB * pl.T + sym_col_slot(0, pl.T, rows)) * 2 * kT;
+  pl.scratch_doubles =
+      (sym_row_slots_total(pl.T, b, pl.nCB) + sym_col_slot(0, pl.T, rows)) * 2 * kT;
   pl.enabled = pl.T >= 2 && pl.scratch_doubles * 8 <= max_scratch_bytes;
   return pl;
 }
@@ -271,7 +272,7 @@ SymArgs make_sym_args(const DeviceProblem& P, const SymPlan& pl, const int32_t* 
   a.kappa = P.kappa;
   a.scale = P.h * P.h * P.h / (4.0 * kPiD);
   a.rowpart = scratch;
-  a.colpart = scratch + (size_t)pl.nCB * pl.T * 2 * kT;
+  a.colpart = scratch + sym_row_slots_total(pl.T, pl.b, pl.nCB) * 2 * kT;
   return a;
 }
 
@@ -303,7 +304,7 @@ SymFinishArgs make_finish_sym_args(const DeviceProblem& P, const SymPlan& pl, co
   SymFinishArgs f;
   f.u = u;
   f.rowpart = scratch;
-  f.colpart = scratch + (size_t)pl.nCB * pl.T * 2 * kT;
+  f.colpart = scratch + sym_row_slots_total(pl.T, pl.b, pl.nCB) * 2 * kT;
   f.crow = P.crow;
   f.ccol = P.ccol;
   f.blocks = P.blocks;

@@ -96,7 +96,7 @@ __device__ __forceinline__ void finish_sym_mixed_row(const SymMixedFinishArgs& a
   double p1 = 0.0, p2 = 0.0;
   const int cb0 = X / a.b, nr = a.nCB - cb0, nc = X / a.rows + 1;
   for (int j = lane; j < nr + nc; j += 64) {
-    const double* sp = j < nr ? a.rowpart + ((size_t)(cb0 + j) * T + X) * (2 * kT)
+    const double* sp = j < nr ? a.rowpart + sym_row_slot(cb0 + j, X, a.b, a.nCB) * (2 * kT)
                               : a.colpart + sym_col_slot(j - nr, X, a.rows) * (2 * kT);
     p1 += sp[t];
     p2 += sp[kT + t];
@@ -215,7 +215,7 @@ SymMixedFinishArgs make_finish_sym_mixed_args(const DeviceProblem& P, const SymP
   SymMixedFinishArgs f;
   f.u = u;
   f.rowpart = scratch;
-  f.colpart = scratch + (size_t)pl.nCB * pl.T * 2 * kT;
+  f.colpart = scratch + sym_row_slots_total(pl.T, pl.b, pl.nCB) * 2 * kT;
   f.crow = P.crow;
   f.ccol = P.ccol;
   f.blocks = P.blocks;

@@ -2,8 +2,8 @@
 20 charges) at h = 0.1 (M = 754,301) and h = 0.07 (M = 1,540,232, the size of
 the largest molecular workload the method is aimed at).
 
-At these sizes the symmetric pair kernel keeps a column-sum scratch of 5 to
-21 GB (it grows as M^2); the check is that its packed layout and the
+At these sizes the symmetric pair kernel keeps a row- and column-sum scratch of 4.75 to
+19.7 GB (it grows as M^2); the check is that its packed layout and the
 finishing kernels read back exactly what the work items wrote.  Sampled rows
 of ``apply`` (float64, mixed, treecode in float64 and mixed) are compared with the oracle's rows
 (computed here, weights only at the sampled rows); the solves are compared
