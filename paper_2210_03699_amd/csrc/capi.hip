@@ -251,6 +251,16 @@ static size_t sym_scratch_cap(const ibim_options& o) {
   return o.pair_scratch_max > 0 ? (size_t)o.pair_scratch_max : kSymScratchMax;
 }
 
+// The symmetric plan of a context: none for the treecode, none past the
+// scratch cap, and none in float64 when kappa times the largest pair
+// distance exceeds what the kernel's table exponential accepts.
+static SymPlan sym_plan_for(const ibim_ctx* c) {
+  const ibim_options& o = c->opt;
+  SymPlan sp = make_sym_plan(c->plan.M, o.summation == IBIM_SUM_TREE ? 0 : sym_scratch_cap(o));
+  if (o.precision == IBIM_FP64 && c->kappa * c->node_span > kSymMaxKappaR) sp.enabled = false;
+  return sp;
+}
+
 // Checks the options shared by ibim_setup and the solve server.
 int check_options(const ibim_options& o) {
   if (o.precision != IBIM_FP64 && o.precision != IBIM_MIXED)
@@ -364,6 +374,19 @@ int ctx_create_host(const double* sdf, int nx, int ny, int nz, const double orig
   }
   if (c->opt.precision == IBIM_MIXED && c->opt.summation == IBIM_SUM_DIRECT)
     c->near_bound = near_list_bound(c->plan, nx, ny, nz, near_radius(c->opt, h));
+  {
+    const HostPlan& pl = c->plan;
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int32_t m = 0; m < pl.M; ++m) {
+      const double p[3] = {pl.px[m], pl.py[m], pl.pz[m]};
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = m == 0 ? p[d] : std::min(lo[d], p[d]);
+        hi[d] = m == 0 ? p[d] : std::max(hi[d], p[d]);
+      }
+    }
+    c->node_span = std::sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                             (hi[2] - lo[2]) * (hi[2] - lo[2]));
+  }
   *out = c;
   return IBIM_OK;
 }
@@ -379,7 +402,7 @@ size_t ctx_footprint_estimate(const ibim_ctx* c) {
   size_t b = 7 * M * 8 + (M + 1) * 4 + nnz * (4 + 6 * 8);
   b += (ntile + 1) * 4 + std::min(nnz, ntile * ntile) * 4;
   b += (4 * nc + (nc > 0 ? nc : 1)) * 8;
-  const SymPlan sp = make_sym_plan((int32_t)M, sym_scratch_cap(c->opt));
+  const SymPlan sp = sym_plan_for(c);
   if (c->opt.summation == IBIM_SUM_TREE)
     b += tree_device_bytes(c->tplan);
   else if (sp.enabled)
@@ -540,7 +563,7 @@ int ctx_setup_device(ibim_ctx* c, hipStream_t s) {
     bytes += ((size_t)M + 1) * 8 + (size_t)P.nnear * 4;
   }
   c->pair = make_pair_plan(M, o.precision);
-  c->sym = make_sym_plan(M, o.summation == IBIM_SUM_TREE ? 0 : sym_scratch_cap(o));
+  c->sym = sym_plan_for(c);
   if (o.summation == IBIM_SUM_TREE) {
     // the plan was built with the geometry (ctx_create_host)
     e = tree_upload(c->tplan, P, pl.px.data(), pl.py.data(), pl.pz.data(), pl.nx.data(),

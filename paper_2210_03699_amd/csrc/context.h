@@ -109,6 +109,7 @@ struct ibim_ctx {
   // mixed direct form: an upper bound on the near-list entries (tube nodes in
   // the cube each row's near search scans), from ctx_create_host
   int64_t near_bound = 0;
+  double node_span = 0;        // diagonal of the nodes' bounding box (largest pair distance)
   size_t device_bytes = 0;     // device memory held by the context
   size_t setup_peak_bytes = 0; // largest device memory during its setup (temporaries included)
 

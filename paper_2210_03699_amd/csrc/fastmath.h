@@ -57,34 +57,39 @@ IBIM_HD inline float exp_neg_f32(float x) {
 // 2^{f/64} - 1 from its Taylor polynomial of degree 5 (truncation below
 // 3.6e-17 relative).  Entry j of the table, 2^{j/64}, is held by lane j of
 // the wavefront and read with ds_bpermute, so every lane must be active.
+// ds_bpermute selects lane (address / 4) mod 64 and ignores the higher
+// address bits, so the address is n * 4 with no masking.  The factor 2^m
+// goes into the exponent field: lane j keeps its entry's high word minus
+// j * 2^14, and adding n * 2^14 = m * 2^20 + j * 2^14 (mod 2^32) to the
+// permuted word leaves the entry's high word plus m * 2^20.  This holds while
+// 2^m 2^{j/64} stays a normal number: kappa R <= 708 (callers check it).
 struct ExpWave {
   double c;     // -64 kappa / ln 2
-  int lo, hi;   // this lane's table entry 2^{lane/64}
+  int lo, hi;   // this lane's entry 2^{lane/64}: low word, high word - lane * 2^14
 };
-
 __device__ inline ExpWave exp_wave_init(double kappa) {
   ExpWave w;
   w.c = -kappa * 92.33248261689366;  // 64 / ln 2
-  const double t = exp2((double)(threadIdx.x & 63) * 0.015625);
+  const int lane = (int)(threadIdx.x & 63);
+  const double t = exp2((double)lane * 0.015625);
   w.lo = __double2loint(t);
-  w.hi = __double2hiint(t);
+  w.hi = (int)((unsigned)__double2hiint(t) - ((unsigned)lane << 14));
   return w;
 }
-
 __device__ __forceinline__ double exp_neg_wave(double R, const ExpWave& w) {
   const double kShift = 6755399441055744.0;  // 1.5 2^52
   const double s = fma(R, w.c, kShift);
-  const int n = __double2loint(s);
+  const unsigned n = (unsigned)__double2loint(s);
   const double f = fma(R, w.c, -(s - kShift));
   double p = fma(f, 1.2417843701716925e-12, 5.732851688640402e-10);
   p = fma(p, f, 2.1173137155464776e-07);
   p = fma(p, f, 5.86490495505617e-05);
   p = fma(p, f, 0.010830424696249145);
   p *= f;
-  const int addr = (n & 63) << 2;
-  const double T = __hiloint2double(__builtin_amdgcn_ds_bpermute(addr, w.hi),
-                                    __builtin_amdgcn_ds_bpermute(addr, w.lo));
-  return ldexp(fma(T, p, T), n >> 6);
+  const int addr = (int)(n << 2);
+  const unsigned hi = (unsigned)__builtin_amdgcn_ds_bpermute(addr, w.hi) + (n << 14);
+  const double T = __hiloint2double((int)hi, __builtin_amdgcn_ds_bpermute(addr, w.lo));
+  return fma(T, p, T);
 }
 
 // 1/sqrt(x) for finite x > 0: hardware estimate and one third-order

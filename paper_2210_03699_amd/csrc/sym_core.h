@@ -16,6 +16,17 @@ namespace sym {
 
 constexpr int kT = kPairTile;
 constexpr int kRows = kSymRows;  // LDS row-sum slots; an item uses a.rows of them
+// The staged column tile is held as four sub-blocks of 64 sources, each
+// followed by copies of its first kWrap sources, so that a lane sweeping a
+// sub-block from a rotated start reads kWrap consecutive slots from one base
+// address (LDS immediate offsets) without wrapping; the column sums have the
+// same layout, and the sums in the copies are folded back at the end.
+constexpr int kWrap = 8;
+constexpr int kSlot = 64 + kWrap;  // slots per sub-block
+constexpr int kSlots = 4 * kSlot;  // slots per staged tile
+
+// LDS slot of source j of the staged tile.
+__device__ __forceinline__ int slot(int j) { return (j >> 6) * kSlot + (j & 63); }
 
 __device__ __forceinline__ bool careful_pair(const SymArgs& a, int I, int J) {
   const int64_t bit = (int64_t)I * a.T + J;
@@ -33,7 +44,7 @@ struct Shared {
   // column sums of J (row 1, row 2) in two arrays of doubles: lanes add to
   // consecutive slots, 8 bytes apart, which keeps the LDS atomics free of
   // bank conflicts (a 16-byte stride gave 4-way conflicts)
-  double cacc1[kT], cacc2[kT];
+  double cacc1[kSlots], cacc2[kSlots];
   double racc1[kRows][kT], racc2[kRows][kT];  // row sums, lane-private slots
 };
 
@@ -85,11 +96,17 @@ __device__ void item(const SymArgs& a, int rb, int cb, Shared<P>& sh) {
   for (int i = 0; i < rows; ++i) racc1[i][tid] = racc2[i][tid] = 0.0;
 
   for (int J = max(J0, I0); J < J1; ++J) {
+    const int my = slot(tid);
+    const bool wraps = l < kWrap;  // this source also has a copy after its sub-block
     {
       const int32_t m = J * kT + tid;
-      if (m < M) P::store(sh.rec, tid, P::load(a, m));
-      cacc1[tid] = 0.0;
-      cacc2[tid] = 0.0;
+      if (m < M) {
+        const typename P::Rec r = P::load(a, m);
+        P::store(sh.rec, my, r);
+        if (wraps) P::store(sh.rec, my + 64, r);
+      }
+      cacc1[my] = cacc2[my] = 0.0;
+      if (wraps) cacc1[my + 64] = cacc2[my + 64] = 0.0;
     }
     __syncthreads();
     for (int i = 0; i < rows; ++i) {
@@ -99,43 +116,52 @@ __device__ void item(const SymArgs& a, int rb, int cb, Shared<P>& sh) {
       const bool slow = I == J || careful_pair(a, I, J) || (J == T - 1 && M % kT != 0);
       if (slow) {
         // row I from the sources of J (LDS broadcasts)
-        one_way<P>(a, pc, I, J, [&](int j) { return P::at(sh.rec, (unsigned)j << 4); }, S1, S2);
+        one_way<P>(a, pc, I, J, [&](int j) { return P::at(sh.rec, (unsigned)slot(j) << 4); }, S1,
+                   S2);
         racc1[i][tid] = S1;
         racc2[i][tid] = S2;
         if (I != J) {
           // row J from the sources of I (uniform global loads)
           double c1 = 0.0, c2 = 0.0;
           one_way<P>(a, pc, J, I, [&](int j) { return P::load(a, I * kT + j); }, c1, c2);
-          cacc1[tid] += c1;
-          cacc2[tid] += c2;
+          cacc1[my] += c1;
+          cacc2[my] += c2;
         }
         __syncthreads();
         continue;
       }
       const typename P::Rec f = P::load(a, I * kT + tid);
       for (int ph = 0; ph < 4; ++ph) {
-        // byte offsets into the 16-byte-record arrays: sub-block | ((l + s) mod 64) * 16
-        const unsigned sb16 = (unsigned)(((wv + ph) & 3) * 64) << 4;
-        unsigned x16 = (unsigned)l << 4;
-#pragma unroll 2
-        for (int s = 0; s < 64; ++s) {
-          const unsigned off = (x16 & 1008u) | sb16;
-          x16 += 16u;
-          double C1, C2;
-          P::both(f, P::at(sh.rec, off), pc, S1, S2, C1, C2);
+        // byte offset of sub-block (wv + ph) mod 4 in the 16-byte-record arrays
+        const unsigned sb16 = (unsigned)(((wv + ph) & 3) * kSlot) << 4;
+#pragma unroll 1
+        for (int s0 = 0; s0 < 64; s0 += kWrap) {
+          // this lane takes sources (l + s0 + k) mod 64, k < kWrap, from
+          // consecutive slots (the copies after the sub-block cover the wrap)
+          const unsigned off = ((((unsigned)l + (unsigned)s0) & 63u) << 4) + sb16;
           const unsigned off8 = off >> 1;  // the same slot in an array of doubles
-          atomicAdd(lds_at(cacc1, off8), C1);
-          atomicAdd(lds_at(cacc2, off8), C2);
+#pragma unroll
+          for (int k = 0; k < kWrap; ++k) {
+            double C1, C2;
+            P::both(f, P::at(sh.rec, off + 16u * k), pc, S1, S2, C1, C2);
+            atomicAdd(lds_at(cacc1, off8 + 8u * k), C1);
+            atomicAdd(lds_at(cacc2, off8 + 8u * k), C2);
+          }
         }
         __syncthreads();
       }
       racc1[i][tid] = S1;
       racc2[i][tid] = S2;
     }
-    // column sums of J
+    // column sums of J (this thread's slot and, for the first kWrap sources
+    // of a sub-block, the copy slot; every add to them has completed)
+    if (wraps) {
+      cacc1[my] += cacc1[my + 64];
+      cacc2[my] += cacc2[my + 64];
+    }
     double* cp = a.colpart + sym_col_slot(rb, J, rows) * (2 * kT);
-    cp[tid] = a.scale * cacc1[tid];
-    cp[kT + tid] = a.scale * cacc2[tid];
+    cp[tid] = a.scale * cacc1[my];
+    cp[kT + tid] = a.scale * cacc2[my];
     __syncthreads();  // LDS is refilled for the next column tile
   }
   // row sums of this item's row tiles that met at least one J >= I

@@ -17,6 +17,11 @@ constexpr int kSymRows = 4;  // most row tiles per work item (the LDS row sums a
 // Larger problems, and setups where the allocation fails, use the
 // one-directional kernel, whose scratch grows only linearly.
 constexpr size_t kSymScratchMax = size_t(32) << 30;
+// Largest kappa R the float64 symmetric kernel's table exponential accepts
+// (2^{-kappa R log2 e} must stay a normal number); problems whose largest
+// pair distance (the diagonal of their nodes' bounding box) times kappa is
+// larger use the one-directional float64 kernel.
+constexpr double kSymMaxKappaR = 708.0;
 
 // Column-sum slot of (row block rb, column tile J), rb <= J / rows, for row
 // blocks of `rows` tiles: the slots of tile J follow those of tiles 0 .. J-1

@@ -11,7 +11,9 @@
 // pairs I <= J only.  For each column tile J the workgroup stages J's records
 // in LDS and, for each row tile I, evaluates all 256 x 256 pairs: wave w holds
 // targets I[64w + l] (one per lane) and, in phase p, visits the 64 sources of
-// sub-block (w + p) mod 4 in the rotated order l, l+1, ... (mod 64).  The
+// sub-block (w + p) mod 4 in the rotated order l, l+1, ... (mod 64), eight
+// at a time from one LDS base address (each sub-block is followed by copies
+// of its first eight records, so the eight never wrap).  The
 // row sums of a tile pair stay in registers and are kept across the item in
 // lane-private LDS slots; the column sums of J go to an LDS accumulator,
 // which in any phase each wave updates in its own sub-block and each lane at
@@ -46,7 +48,8 @@ struct Fp64 {
     double px, py, pz, nx, ny, nz, a1, a2;
   };
   struct Lds {
-    double2 A[kT], B[kT], C[kT], D[kT];  // (px,py) (pz,nx) (ny,nz) (a1,a2)
+    // (px,py) (pz,nx) (ny,nz) (a1,a2) per LDS slot (sym::slot)
+    double2 A[sym::kSlots], B[sym::kSlots], C[sym::kSlots], D[sym::kSlots];
   };
   struct Consts {
     PairConsts k;  // one-directional evaluations

@@ -28,7 +28,7 @@ struct Mixed {
     float px, py, pz, nx, ny, nz, a1, a2;
   };
   struct Lds {
-    float4 A[kT], B[kT];  // (px,py,pz,nx) (ny,nz,a1,a2)
+    float4 A[sym::kSlots], B[sym::kSlots];  // (px,py,pz,nx) (ny,nz,a1,a2) per LDS slot
   };
   using Consts = PairConstsF;
   static __device__ __forceinline__ Consts consts(const SymArgs& a) {

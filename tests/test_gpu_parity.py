@@ -173,6 +173,31 @@ def test_one_directional_solve_matches_oracle(name):
     prob.close()
 
 
+@pytest.mark.parametrize("kappa, symmetric", [(100.0, True), (150.0, False)])
+def test_extreme_screening_apply_matches_oracle(kappa, symmetric):
+    """The float64 symmetric kernel's table exponential takes kappa R up to 708
+    (e^{-kappa R} a normal number); a problem whose kappa times its nodes'
+    bounding-box diagonal exceeds that is served by the one-directional
+    kernel.  On a sphere of radius 1.7 the diagonal is about 5.9, so kappa =
+    100 stays symmetric (kappa R up to ~590, e^{-kappa R} ~ 1e-256) and
+    kappa = 150 switches."""
+    wl = workloads.born_sphere(h=0.25, radius=1.7, offset=(0.37, 0.11, -0.23), kappa=kappa)
+    prob = ibim.Problem.from_workload(wl, device=0)
+    orc = oracle.Oracle.from_workload(wl)
+    p, _, _ = prob.node_geometry()
+    span = float(np.linalg.norm(p.max(axis=0) - p.min(axis=0)))
+    assert (kappa * span <= 708.0) == symmetric, (kappa, span)
+    u = workloads.random_vector(2 * prob.M, 12)
+    out = prob.apply(torch.from_numpy(u).to(DEV)).cpu().numpy()
+    err = _blockwise_rel(out, orc.apply(u), prob.M)
+    pairs, flops = prob.pair_work()
+    _say(f"[kappa={kappa}] kappa*span {kappa * span:.1f} apply rel err {err:.3e} "
+         f"flops/pair {flops / pairs:.1f}")
+    assert (flops < 60.0 * prob.M * prob.M) == symmetric
+    assert err < 1e-12, err
+    prob.close()
+
+
 def test_restarted_solve_matches_oracle():
     wl = workloads.born_sphere(h=0.4)
     prob = ibim.Problem.from_workload(wl, device=0, restart=4, max_iter=200)
