@@ -77,6 +77,41 @@ __device__ __forceinline__ void one_way(const SymArgs& a, const typename P::Cons
   }
 }
 
+// The shared evaluations of NR row tiles (this lane's targets f[r]) against
+// the staged column tile: four phases, wave w on sub-block (w + p) mod 4 in
+// phase p, each lane sweeping the 64 sources from a rotated start, kWrap at a
+// time from consecutive slots.  Row sums stay in S1, S2; the column sums of
+// all NR targets for one source go to its slot with one LDS atomic.
+template <class P, int NR>
+__device__ __forceinline__ void sweep(Shared<P>& sh, const typename P::Consts& pc,
+                                      const typename P::Rec (&f)[NR], double (&S1)[NR],
+                                      double (&S2)[NR]) {
+  const int tid = threadIdx.x;
+  const int wv = tid >> 6, l = tid & 63;
+  for (int ph = 0; ph < 4; ++ph) {
+    // byte offset of sub-block (wv + ph) mod 4 in the 16-byte-record arrays
+    const unsigned sb16 = (unsigned)(((wv + ph) & 3) * kSlot) << 4;
+#pragma unroll 1
+    for (int s0 = 0; s0 < 64; s0 += kWrap) {
+      // this lane takes sources (l + s0 + k) mod 64, k < kWrap, from
+      // consecutive slots (the copies after the sub-block cover the wrap)
+      const unsigned off = ((((unsigned)l + (unsigned)s0) & 63u) << 4) + sb16;
+      const unsigned off8 = off >> 1;  // the same slot in an array of doubles
+#pragma unroll
+      for (int k = 0; k < kWrap; ++k) {
+        const typename P::Rec m = P::at(sh.rec, off + 16u * k);
+        double C1, C2;
+        P::template both<false>(f[0], m, pc, S1[0], S2[0], C1, C2);
+#pragma unroll
+        for (int r = 1; r < NR; ++r) P::template both<true>(f[r], m, pc, S1[r], S2[r], C1, C2);
+        atomicAdd(lds_at(sh.cacc1, off8 + 8u * k), C1);
+        atomicAdd(lds_at(sh.cacc2, off8 + 8u * k), C2);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // One work item (rb, cb).  Called by all 256 threads of the workgroup.
 template <class P>
 __device__ void item(const SymArgs& a, int rb, int cb, Shared<P>& sh) {
@@ -85,7 +120,7 @@ __device__ void item(const SymArgs& a, int rb, int cb, Shared<P>& sh) {
   auto& racc1 = sh.racc1;
   auto& racc2 = sh.racc2;
   const int tid = threadIdx.x;
-  const int wv = tid >> 6, l = tid & 63;
+  const int l = tid & 63;
   const int T = a.T;
   const int32_t M = a.M;
   const int rows = a.rows;
@@ -109,12 +144,31 @@ __device__ void item(const SymArgs& a, int rb, int cb, Shared<P>& sh) {
       if (wraps) cacc1[my + 64] = cacc2[my + 64] = 0.0;
     }
     __syncthreads();
-    for (int i = 0; i < rows; ++i) {
+    auto slow = [&](int I) {
+      return I == J || careful_pair(a, I, J) || (J == T - 1 && M % kT != 0);
+    };
+    for (int i = 0; i < rows;) {
       const int I = I0 + i;
-      if (I >= T || I > J) continue;  // uniform
-      double S1 = racc1[i][tid], S2 = racc2[i][tid];
-      const bool slow = I == J || careful_pair(a, I, J) || (J == T - 1 && M % kT != 0);
-      if (slow) {
+      if (I >= T || I > J) {  // uniform
+        ++i;
+        continue;
+      }
+      if (!slow(I) && i + 1 < rows && I + 1 < J && !slow(I + 1)) {
+        // two row tiles against the staged sources: one LDS read and one
+        // column-sum atomic serve two evaluations
+        const typename P::Rec f[2] = {P::load(a, I * kT + tid), P::load(a, (I + 1) * kT + tid)};
+        double S1[2] = {racc1[i][tid], racc1[i + 1][tid]};
+        double S2[2] = {racc2[i][tid], racc2[i + 1][tid]};
+        sweep<P, 2>(sh, pc, f, S1, S2);
+        racc1[i][tid] = S1[0];
+        racc2[i][tid] = S2[0];
+        racc1[i + 1][tid] = S1[1];
+        racc2[i + 1][tid] = S2[1];
+        i += 2;
+        continue;
+      }
+      if (slow(I)) {
+        double S1 = racc1[i][tid], S2 = racc2[i][tid];
         // row I from the sources of J (LDS broadcasts)
         one_way<P>(a, pc, I, J, [&](int j) { return P::at(sh.rec, (unsigned)slot(j) << 4); }, S1,
                    S2);
@@ -128,30 +182,15 @@ __device__ void item(const SymArgs& a, int rb, int cb, Shared<P>& sh) {
           cacc2[my] += c2;
         }
         __syncthreads();
+        ++i;
         continue;
       }
-      const typename P::Rec f = P::load(a, I * kT + tid);
-      for (int ph = 0; ph < 4; ++ph) {
-        // byte offset of sub-block (wv + ph) mod 4 in the 16-byte-record arrays
-        const unsigned sb16 = (unsigned)(((wv + ph) & 3) * kSlot) << 4;
-#pragma unroll 1
-        for (int s0 = 0; s0 < 64; s0 += kWrap) {
-          // this lane takes sources (l + s0 + k) mod 64, k < kWrap, from
-          // consecutive slots (the copies after the sub-block cover the wrap)
-          const unsigned off = ((((unsigned)l + (unsigned)s0) & 63u) << 4) + sb16;
-          const unsigned off8 = off >> 1;  // the same slot in an array of doubles
-#pragma unroll
-          for (int k = 0; k < kWrap; ++k) {
-            double C1, C2;
-            P::both(f, P::at(sh.rec, off + 16u * k), pc, S1, S2, C1, C2);
-            atomicAdd(lds_at(cacc1, off8 + 8u * k), C1);
-            atomicAdd(lds_at(cacc2, off8 + 8u * k), C2);
-          }
-        }
-        __syncthreads();
-      }
-      racc1[i][tid] = S1;
-      racc2[i][tid] = S2;
+      const typename P::Rec f[1] = {P::load(a, I * kT + tid)};
+      double S1[1] = {racc1[i][tid]}, S2[1] = {racc2[i][tid]};
+      sweep<P, 1>(sh, pc, f, S1, S2);
+      racc1[i][tid] = S1[0];
+      racc2[i][tid] = S2[0];
+      ++i;
     }
     // column sums of J (this thread's slot and, for the first kWrap sources
     // of a sub-block, the copy slot; every add to them has completed)

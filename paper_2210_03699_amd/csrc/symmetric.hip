@@ -80,10 +80,12 @@ struct Fp64 {
                     r.a2, pc.k, d1, d2);
   }
   // Both directions of the pair (fixed f, rotating m): k <- m added to
-  // (S1, S2), m <- k returned in (C1, C2).  With u = (1 - e(1 + kR))/R^3 and
-  // t3 = e(1 + kR)/R^3 the kernel factors are (1 - c t)/R^3 = 1/R^3 - c t3
-  // and K21 R^3 / R^3 = n_k.n_m u + q (k^2 e/R^3 - 3 u/R^2).  Called with all
-  // 64 lanes of the wavefront active (the exponential reads other lanes).
+  // (S1, S2), m <- k returned in (C1, C2), or added to them when kAcc.  With
+  // u = (1 - e(1 + kR))/R^3 and t3 = e(1 + kR)/R^3 the kernel factors are
+  // (1 - c t)/R^3 = 1/R^3 - c t3 and K21 R^3 / R^3 = n_k.n_m u + q (k^2 e/R^3
+  // - 3 u/R^2).  Called with all 64 lanes of the wavefront active (the
+  // exponential reads other lanes).
+  template <bool kAcc = false>
   static __device__ __forceinline__ void both(const Rec& f, const Rec& m, const Consts& pc,
                                               double& S1, double& S2, double& C1, double& C2) {
     const double rx = f.px - m.px, ry = f.py - m.py, rz = f.pz - m.pz;  // r = x_k - P_m
@@ -111,8 +113,13 @@ struct Fp64 {
     S2 = fma(g21, m.a1, fma(g22, m.a2, S2));
     // m <- k: r.n_k and r.n_m swap roles with a sign change
     const double h11 = -rnx * f1, h22 = -rny * f2;
-    C1 = fma(h11, f.a1, -g12 * f.a2);
-    C2 = fma(g21, f.a1, h22 * f.a2);
+    if (kAcc) {
+      C1 = fma(h11, f.a1, fma(-g12, f.a2, C1));
+      C2 = fma(g21, f.a1, fma(h22, f.a2, C2));
+    } else {
+      C1 = fma(h11, f.a1, -g12 * f.a2);
+      C2 = fma(g21, f.a1, h22 * f.a2);
+    }
   }
 };
 
@@ -122,7 +129,7 @@ __global__ __launch_bounds__(256) void pair_sym_fp64_kernel(SymArgs a) {
   sym::item<Fp64>(a, it.x, it.y, sh);
 }
 
-__global__ __launch_bounds__(256, 4) void pair_sym_batched_kernel(
+__global__ __launch_bounds__(256, 3) void pair_sym_batched_kernel(
     const SymArgs* __restrict__ probs, const int32_t* __restrict__ work, int n_work,
     int* counter) {
   __shared__ sym::Shared<Fp64> sh;

@@ -55,6 +55,8 @@ struct Mixed {
     d1 = (double)e1;
     d2 = (double)e2;
   }
+  // (C1, C2) returned, or added to when kAcc
+  template <bool kAcc = false>
   static __device__ __forceinline__ void both(const Rec& f, const Rec& m, const Consts& pc,
                                               double& S1, double& S2, double& C1, double& C2) {
     float d1, d2, c1, c2;
@@ -62,8 +64,8 @@ struct Mixed {
                  m.nz, m.a1, m.a2, pc, d1, d2, c1, c2);
     S1 += (double)d1;
     S2 += (double)d2;
-    C1 = (double)c1;
-    C2 = (double)c2;
+    C1 = kAcc ? C1 + (double)c1 : (double)c1;
+    C2 = kAcc ? C2 + (double)c2 : (double)c2;
   }
 };
 
