@@ -49,12 +49,14 @@ FLOPS_PER_PAIR = 60  # algorithmic flops of the four kernels for one ordered pai
 # x 64 lanes) and the average duration of the counted dispatches.  Valid only
 # while the kernel sources hash to the recorded digest; otherwise null.
 MEASURED_COUNTERS = {
-    ("fp64", "kirkwood"): {"digest": "10d64cac", "traffic_bytes": 683.2e6,
-                           "valu_flops": 11622290460 * 64, "ms": 18.67,
-                           "source": "profiles/pair_sym_fp64_kirkwood_R10_h0.25.md"},
-    ("mixed", "kirkwood"): {"digest": "ef43987d", "traffic_bytes": 504.4e6,
-                            "valu_flops": 7531334384 * 64, "ms": 10.06,
-                            "source": "profiles/pair_sym_mixed_kirkwood_R10_h0.25.md"},
+    ("fp64", "ses2000"): {"digest": "0de79bec",
+                          "traffic_bytes": 2019257 * 1024 * 2.0 + 893624 * 1024,
+                          "valu_flops": 73414326688 * 64, "ms": 109.64,
+                          "source": "profiles/pair_sym_fp64_ses2000_h0.35.md"},
+    ("mixed", "ses2000"): {"digest": "6c3f0de5",
+                           "traffic_bytes": 1060630 * 1024 * 2.0 + 893624 * 1024,
+                           "valu_flops": 52012951568 * 64, "ms": 60.26,
+                           "source": "profiles/pair_sym_mixed_ses2000_h0.35.md"},
 }
 # stored oracle results (tests/golden/make_golden.py) per workload
 GOLDEN = {"kirkwood": "kirkwood_R10_h0.25.json", "ses500": "ses500_h0.3.json",
@@ -392,8 +394,10 @@ def rnear_sweep(args):
             rec = {"workload": wl.name, "M": M, "precision": "fp64" if f == 0.0 else "mixed",
                    "r_near_over_h": f, "setup_s": t_setup, "solve_s": min(times),
                    "iters": info["iters"],
-                   "g_pol_rel_err_vs_oracle": abs(info["g_pol"] - gold["g_pol"]) / abs(gold["g_pol"]),
-                   "psi_rows_max_rel_err": float(np.max(np.abs(xh[rows] - xr1)) / np.max(np.abs(xr1))),
+                   "g_pol_rel_err_vs_oracle":
+                       abs(info["g_pol"] - gold["g_pol"]) / abs(gold["g_pol"]),
+                   "psi_rows_max_rel_err":
+                       float(np.max(np.abs(xh[rows] - xr1)) / np.max(np.abs(xr1))),
                    "psi_n_rows_max_rel_err":
                        float(np.max(np.abs(xh[M + rows] - xr2)) / np.max(np.abs(xr2)))}
             print(f"[rnear] {json.dumps(rec)}", file=sys.stderr, flush=True)
@@ -613,6 +617,7 @@ def main():
         mp = measured_profile("mixed", args.workload)
         if mp is not None:
             mixed["valu_counter_fp32_tflops"] = mp["valu_flops"] / (mp["ms"] * 1e-3) / 1e12
+            mixed["traffic"] = mp["traffic_bytes"]
         out["mixed"] = mixed
         pm.close()
         del pm

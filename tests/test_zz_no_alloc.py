@@ -56,11 +56,14 @@ def test_noalloc_equals_apply_two_calls(precision):
 
 
 def test_noalloc_one_directional_when_symmetric_sums_do_not_fit():
-    """M = 120,414: the symmetric partial sums (~340 MB) exceed the 256 MiB
-    array, the one-directional ones (~77 MB) fit; then a smaller problem."""
-    for name, wl in (("kirkwood", workloads.kirkwood_sphere()),
+    """Kirkwood sphere at h = 0.2 (M = 188,926): the symmetric partial sums
+    (354 MB) exceed the 256 MiB array, the one-directional ones (73 MB) fit;
+    then a smaller problem (symmetric sums)."""
+    for name, wl in (("kirkwood", workloads.kirkwood_sphere(h=0.2)),
                      ("born", workloads.born_sphere(h=0.3))):
         prob = ibim.Problem.from_workload(wl, device=0)
+        if name == "kirkwood":
+            assert prob.M > 180000, prob.M  # past the size the static array holds symmetric sums for
         u = torch.from_numpy(workloads.random_vector(2 * prob.M, 22)).to(DEV)
         ref = prob.apply(u).cpu().numpy()
         out = torch.full((2 * prob.M,), float("nan"), dtype=torch.float64, device=DEV)
