@@ -65,7 +65,9 @@ typedef struct {
   int device;          /* HIP device ordinal; -1 = host-only context (setup
                           and inspection only, no device memory) */
   double r_near;       /* IBIM_MIXED: pairs closer than r_near (Angstrom) are
-                          re-evaluated in float64 (default 0 = 2 h) */
+                          evaluated in float64 (direct sum: re-evaluated in
+                          the finishing kernel; treecode: in its direct
+                          part) (default 0 = 2 h) */
   int hybrid;          /* IBIM_CTR2 (default), IBIM_HYB or IBIM_KREG, below */
   int precond;         /* IBIM_PRECOND_DIAG (default) or IBIM_PRECOND_NONE, below */
   int summation;       /* IBIM_SUM_DIRECT (default) or IBIM_SUM_TREE, below */
@@ -98,7 +100,9 @@ typedef struct {
  *                   With IBIM_FP64 all of it is float64; with IBIM_MIXED the
  *                   target-proxy evaluations run in float32 (on float64-formed
  *                   differences, summed in float32 over n proxies, then in
- *                   float64) while the direct part and the proxy charges stay
+ *                   float64), and so do the direct pairs at distance r_near
+ *                   or more (float64-formed differences, float64 sums); direct
+ *                   pairs nearer than r_near and the proxy charges stay
  *                   float64.  A problem with fewer than tree_min_nodes tube
  *                   nodes is summed directly instead, in the same precision;
  *                   the solve server applies this rule per request.  The

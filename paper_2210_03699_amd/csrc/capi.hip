@@ -570,6 +570,7 @@ int ctx_setup_device(ibim_ctx* c, hipStream_t s) {
                     pl.ny.data(), pl.nz.data(), pl.w.data(), &c->tree, s);
     if (e != hipSuccess) return bad(e, "treecode setup");
     c->tree.mixed = o.precision == IBIM_MIXED;
+    c->tree.rnear = near_radius(o, h);
     bytes += c->tree.bytes;
     const double n4 = std::pow((double)o.tree_order, 4.0);
     c->pair_flops = 60.0 * c->tplan.near_evals + 36.0 * c->tplan.far_evals +

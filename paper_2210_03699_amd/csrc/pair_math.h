@@ -62,14 +62,13 @@ __device__ __forceinline__ void pair_f64(double x, double y, double z, double nx
   }
 }
 
-// float32, every operation explicit (fused multiply-adds written out), so
-// that every kernel including this header computes bit-identical values
-// when its translation unit is compiled without automatic contraction.
-__device__ __forceinline__ void pair_f32(float x, float y, float z, float nxk, float nyk,
-                                         float nzk, float px, float py, float pz, float nxm,
-                                         float nym, float nzm, float a1, float a2,
-                                         const PairConstsF& c, float& d1, float& d2) {
-  const float rx = x - px, ry = y - py, rz = z - pz;
+// float32 from the difference r = x - P(y_m), every operation explicit
+// (fused multiply-adds written out), so that every kernel including this
+// header computes bit-identical values when its translation unit is compiled
+// without automatic contraction.
+__device__ __forceinline__ void pair_f32_r(float rx, float ry, float rz, float nxk, float nyk,
+                                           float nzk, float nxm, float nym, float nzm, float a1,
+                                           float a2, const PairConstsF& c, float& d1, float& d2) {
   const float R2 = __fmaf_rn(rz, rz, __fmaf_rn(ry, ry, rx * rx));
   const float iR = __builtin_amdgcn_rsqf(R2);
   const float R = R2 * iR;
@@ -91,6 +90,14 @@ __device__ __forceinline__ void pair_f32(float x, float y, float z, float nxk, f
   const float g22 = rnx * __fmaf_rn(-c.c2, te, 1.0f);
   d1 = __fmaf_rn(g11, A1, -(g12 * A2));
   d2 = __fmaf_rn(g21, A1, g22 * A2);
+}
+
+// float32 from the two points (pair_f32_r of their difference).
+__device__ __forceinline__ void pair_f32(float x, float y, float z, float nxk, float nyk,
+                                         float nzk, float px, float py, float pz, float nxm,
+                                         float nym, float nzm, float a1, float a2,
+                                         const PairConstsF& c, float& d1, float& d2) {
+  pair_f32_r(x - px, y - py, z - pz, nxk, nyk, nzk, nxm, nym, nzm, a1, a2, c, d1, d2);
 }
 
 // float32, both directions of one pair for the symmetric kernel: fixed node f

@@ -26,6 +26,7 @@ struct TreeDevice {
           *inear1 = nullptr, *istart = nullptr, *iorder = nullptr;
   int n_items = 0;
   bool mixed = false;      // target-proxy evaluations in float32 (IBIM_MIXED)
+  double rnear = 0.0;      // mixed form: direct pairs nearer than this stay float64
   double* pbox = nullptr;  // 6 per proxy cluster: lo x, y, z, hi x, y, z
   double* cheb = nullptr;  // Chebyshev points on [-1, 1], barycentric weights, D (order^2)
   // geometry in tree order

@@ -22,9 +22,12 @@
 // one target per lane) runs through its proxy clusters and then its direct
 // source ranges, staging both in LDS; the finishing kernel adds a batch's
 // parts in a fixed order, so results are reproducible.  All arithmetic is
-// float64 except, in the mixed form, the target-proxy evaluations: float32
+// float64 except, in the mixed form, the target-proxy evaluations (float32
 // kernels on float64-formed differences, summed in float32 over one line of
-// n proxies and then in float64.
+// n proxies and then in float64) and the direct pairs at distance r_near or
+// more (float32 kernels on float64-formed differences, summed in float64);
+// direct pairs nearer than r_near, where the float32 kernels lose accuracy,
+// stay float64.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -51,6 +54,7 @@ struct TreeArgs {
   PairConsts pc;
   int32_t M;
   int order;
+  float rnear2;  // mixed form: direct pairs with float32 R^2 below this stay float64
 };
 
 TreeArgs make_args(const TreeDevice& T, const DeviceProblem& P, const double* u) {
@@ -68,6 +72,7 @@ TreeArgs make_args(const TreeDevice& T, const DeviceProblem& P, const double* u)
   a.pc = PairConsts{P.eps_out / P.eps_in, P.eps_in / P.eps_out, P.kappa, P.kappa * P.kappa};
   a.M = T.M;
   a.order = T.order;
+  a.rnear2 = (float)(T.rnear * T.rnear);
   return a;
 }
 
@@ -283,6 +288,7 @@ __global__ __launch_bounds__(256) void tree_item_kernel(TreeArgs a) {
   // charges (A, B, D interleaved) of a proxy cluster, as many x-planes of its
   // grid at a time as fit; the grid axes separately
   __shared__ double sh[8][256];
+  __shared__ float shf[kMixed ? 5 : 1][256];  // mixed form: n_m, a1, a2 of the near sources
   __shared__ double ax[3][kTreeMaxOrder];
   const int it = a.iorder[blockIdx.x];
   const int b = a.ibatch[it];
@@ -388,12 +394,37 @@ __global__ __launch_bounds__(256) void tree_item_kernel(TreeArgs a) {
         sh[5][tid] = a.tnz[m];
         sh[6][tid] = a.ta1[m];
         sh[7][tid] = a.ta2[m];
+        if (kMixed) {
+          shf[0][tid] = (float)a.tnx[m];
+          shf[1][tid] = (float)a.tny[m];
+          shf[2][tid] = (float)a.tnz[m];
+          shf[3][tid] = (float)a.ta1[m];
+          shf[4][tid] = (float)a.ta2[m];
+        }
       }
       __syncthreads();
       for (int j = 0; j < cnt; ++j) {
         double d1, d2;
-        pair_f64<false>(x, y, z, nxk, nyk, nzk, sh[0][j], sh[1][j], sh[2][j], sh[3][j], sh[4][j],
-                        sh[5][j], sh[6][j], sh[7][j], a.pc, d1, d2);
+        if (kMixed) {
+          const float rx = (float)(x - sh[0][j]), ry = (float)(y - sh[1][j]),
+                      rz = (float)(z - sh[2][j]);
+          float e1, e2;
+          pair_f32_r(rx, ry, rz, nxf, nyf, nzf, shf[0][j], shf[1][j], shf[2][j], shf[3][j],
+                     shf[4][j], pcf, e1, e2);
+          d1 = (double)e1;
+          d2 = (double)e2;
+          const bool near = __fmaf_rn(rz, rz, __fmaf_rn(ry, ry, rx * rx)) < a.rnear2;
+          if (__any(near)) {  // wave-uniform: the float64 pair for the lanes that need it
+            double g1, g2;
+            pair_f64<false>(x, y, z, nxk, nyk, nzk, sh[0][j], sh[1][j], sh[2][j], sh[3][j],
+                            sh[4][j], sh[5][j], sh[6][j], sh[7][j], a.pc, g1, g2);
+            d1 = near ? g1 : d1;
+            d2 = near ? g2 : d2;
+          }
+        } else {
+          pair_f64<false>(x, y, z, nxk, nyk, nzk, sh[0][j], sh[1][j], sh[2][j], sh[3][j],
+                          sh[4][j], sh[5][j], sh[6][j], sh[7][j], a.pc, d1, d2);
+        }
         const bool ex = c0 + j == nxt;
         if (ex) {
           ++p;

@@ -91,9 +91,11 @@ def test_error_falls_geometrically(kw):
 
 
 def test_mixed_far_field(kw):
-    """IBIM_MIXED evaluates the target-proxy terms in float32: its error against
-    the oracle stays at the treecode's own level; with no far field (tiny theta)
-    nothing is float32 and the result is the float64 direct sum."""
+    """IBIM_MIXED evaluates the target-proxy terms and the direct pairs at
+    distance r_near or more in float32: its error against the oracle stays at
+    the treecode's own level.  With no far field (tiny theta) only the direct
+    part is left: with r_near covering every pair it is the float64 direct sum,
+    with the default r_near = 2h it is within the mixed form's error of it."""
     wl, u, ref, orc = kw
     errs = {}
     for prec in (ibim.FP64, ibim.MIXED):
@@ -102,11 +104,15 @@ def test_mixed_far_field(kw):
         p.close()
     _say(f"[tree mixed far field] rel err fp64 {errs[ibim.FP64]:.3e} mixed {errs[ibim.MIXED]:.3e}")
     assert errs[ibim.MIXED] < 1e-6 and errs[ibim.MIXED] < 3 * errs[ibim.FP64]
-    direct = ibim.Problem.from_workload(wl, device=0)
-    near = ibim.Problem.from_workload(wl, device=0, summation=ibim.SUM_TREE, tree_theta=1e-6,
-                                      precision=ibim.MIXED)
-    assert near.tree_counts()["far_evals"] == 0
-    assert _rel(_apply(near, u), _apply(direct, u), near.M) < 1e-13
+    direct = _apply(ibim.Problem.from_workload(wl, device=0), u)
+    for r_near, bar in ((1e30, 1e-13), (0.0, 1e-6)):
+        near = ibim.Problem.from_workload(wl, device=0, summation=ibim.SUM_TREE, tree_theta=1e-6,
+                                          precision=ibim.MIXED, r_near=r_near)
+        assert near.tree_counts()["far_evals"] == 0
+        e = _rel(_apply(near, u), direct, near.M)
+        _say(f"[tree mixed, direct part only, r_near={r_near:g}] rel err vs float64 {e:.3e}")
+        assert e < bar
+        near.close()
 
 
 def test_tree_with_kreg_rows_matches_direct():
