@@ -15,7 +15,6 @@ namespace ibim {
 namespace sym {
 
 constexpr int kT = kPairTile;
-constexpr int kRows = kSymRows;  // LDS row-sum slots; an item uses a.rows of them
 // The staged column tile is held as four sub-blocks of 64 sources, each
 // followed by copies of its first kWrap sources, so that a lane sweeping a
 // sub-block from a rotated start reads kWrap consecutive slots from one base
@@ -24,6 +23,10 @@ constexpr int kRows = kSymRows;  // LDS row-sum slots; an item uses a.rows of th
 constexpr int kWrap = 8;
 constexpr int kSlot = 64 + kWrap;  // slots per sub-block
 constexpr int kSlots = 4 * kSlot;  // slots per staged tile
+
+// Items of up to this many row tiles keep their row sums in LDS between
+// column tiles; larger items carry them in their scratch slots.
+constexpr int kLdsRows = 4;
 
 // LDS slot of source j of the staged tile.
 __device__ __forceinline__ int slot(int j) { return (j >> 6) * kSlot + (j & 63); }
@@ -45,7 +48,8 @@ struct Shared {
   // consecutive slots, 8 bytes apart, which keeps the LDS atomics free of
   // bank conflicts (a 16-byte stride gave 4-way conflicts)
   double cacc1[kSlots], cacc2[kSlots];
-  double racc1[kRows][kT], racc2[kRows][kT];  // row sums, lane-private slots
+  // row sums of items of at most kLdsRows row tiles, lane-private
+  double racc1[kLdsRows][kT], racc2[kLdsRows][kT];
 };
 
 // Sums over the sources of tile Y for the target of this lane in tile X
@@ -113,12 +117,15 @@ __device__ __forceinline__ void sweep(Shared<P>& sh, const typename P::Consts& p
 }
 
 // One work item (rb, cb).  Called by all 256 threads of the workgroup.
+// The row sums of row tile I start at zero at the first column tile that
+// meets I (J = max(J0, I)) and are carried to the next one in LDS (items of
+// at most kLdsRows row tiles) or in the tile's (cb, I) slot of the row
+// partial sums, read and written back by the thread that owns the row; the
+// slot receives them scaled by h^3/(4 pi) at the last visit (J = J1 - 1).
 template <class P>
 __device__ void item(const SymArgs& a, int rb, int cb, Shared<P>& sh) {
   double* const cacc1 = sh.cacc1;
   double* const cacc2 = sh.cacc2;
-  auto& racc1 = sh.racc1;
-  auto& racc2 = sh.racc2;
   const int tid = threadIdx.x;
   const int l = tid & 63;
   const int T = a.T;
@@ -126,9 +133,37 @@ __device__ void item(const SymArgs& a, int rb, int cb, Shared<P>& sh) {
   const int rows = a.rows;
   const int I0 = rb * rows;
   const int J0 = cb * a.b, J1 = min(J0 + a.b, T);
+  const int nCB = (T + a.b - 1) / a.b;
+  const bool in_lds = rows <= kLdsRows;  // uniform
   const typename P::Consts pc = P::consts(a);
-
-  for (int i = 0; i < rows; ++i) racc1[i][tid] = racc2[i][tid] = 0.0;
+  auto row_sums = [&](int I) { return a.rowpart + sym_row_slot(cb, I, a.b, nCB) * (2 * kT); };
+  auto row_load = [&](int i, int J, double& S1, double& S2) {
+    const int I = I0 + i;
+    if (J == max(J0, I)) {
+      S1 = S2 = 0.0;
+    } else if (in_lds) {
+      S1 = sh.racc1[i][tid];
+      S2 = sh.racc2[i][tid];
+    } else {
+      const double* rp = row_sums(I);
+      S1 = rp[tid];
+      S2 = rp[kT + tid];
+    }
+  };
+  auto row_store = [&](int i, int J, double S1, double S2) {
+    const int I = I0 + i;
+    const bool last = J == J1 - 1;
+    if (in_lds) {
+      sh.racc1[i][tid] = S1;
+      sh.racc2[i][tid] = S2;
+    }
+    if (last || !in_lds) {
+      double* rp = row_sums(I);
+      const double f = last ? a.scale : 1.0;
+      rp[tid] = f * S1;
+      rp[kT + tid] = f * S2;
+    }
+  };
 
   for (int J = max(J0, I0); J < J1; ++J) {
     const int my = slot(tid);
@@ -149,31 +184,27 @@ __device__ void item(const SymArgs& a, int rb, int cb, Shared<P>& sh) {
     };
     for (int i = 0; i < rows;) {
       const int I = I0 + i;
-      if (I >= T || I > J) {  // uniform
-        ++i;
-        continue;
-      }
+      if (I >= T || I > J) break;  // uniform; so are the later row tiles
       if (!slow(I) && i + 1 < rows && I + 1 < J && !slow(I + 1)) {
         // two row tiles against the staged sources: one LDS read and one
         // column-sum atomic serve two evaluations
         const typename P::Rec f[2] = {P::load(a, I * kT + tid), P::load(a, (I + 1) * kT + tid)};
-        double S1[2] = {racc1[i][tid], racc1[i + 1][tid]};
-        double S2[2] = {racc2[i][tid], racc2[i + 1][tid]};
+        double S1[2], S2[2];
+        row_load(i, J, S1[0], S2[0]);
+        row_load(i + 1, J, S1[1], S2[1]);
         sweep<P, 2>(sh, pc, f, S1, S2);
-        racc1[i][tid] = S1[0];
-        racc2[i][tid] = S2[0];
-        racc1[i + 1][tid] = S1[1];
-        racc2[i + 1][tid] = S2[1];
+        row_store(i, J, S1[0], S2[0]);
+        row_store(i + 1, J, S1[1], S2[1]);
         i += 2;
         continue;
       }
       if (slow(I)) {
-        double S1 = racc1[i][tid], S2 = racc2[i][tid];
+        double S1, S2;
+        row_load(i, J, S1, S2);
         // row I from the sources of J (LDS broadcasts)
         one_way<P>(a, pc, I, J, [&](int j) { return P::at(sh.rec, (unsigned)slot(j) << 4); }, S1,
                    S2);
-        racc1[i][tid] = S1;
-        racc2[i][tid] = S2;
+        row_store(i, J, S1, S2);
         if (I != J) {
           // row J from the sources of I (uniform global loads)
           double c1 = 0.0, c2 = 0.0;
@@ -186,10 +217,10 @@ __device__ void item(const SymArgs& a, int rb, int cb, Shared<P>& sh) {
         continue;
       }
       const typename P::Rec f[1] = {P::load(a, I * kT + tid)};
-      double S1[1] = {racc1[i][tid]}, S2[1] = {racc2[i][tid]};
+      double S1[1], S2[1];
+      row_load(i, J, S1[0], S2[0]);
       sweep<P, 1>(sh, pc, f, S1, S2);
-      racc1[i][tid] = S1[0];
-      racc2[i][tid] = S2[0];
+      row_store(i, J, S1[0], S2[0]);
       ++i;
     }
     // column sums of J (this thread's slot and, for the first kWrap sources
@@ -202,14 +233,6 @@ __device__ void item(const SymArgs& a, int rb, int cb, Shared<P>& sh) {
     cp[tid] = a.scale * cacc1[my];
     cp[kT + tid] = a.scale * cacc2[my];
     __syncthreads();  // LDS is refilled for the next column tile
-  }
-  // row sums of this item's row tiles that met at least one J >= I
-  for (int i = 0; i < rows; ++i) {
-    const int I = I0 + i;
-    if (I >= T || I > J1 - 1) continue;
-    double* rp = a.rowpart + sym_row_slot(cb, I, a.b, (T + a.b - 1) / a.b) * (2 * kT);
-    rp[tid] = a.scale * racc1[i][tid];
-    rp[kT + tid] = a.scale * racc2[i][tid];
   }
 }
 

@@ -11,9 +11,9 @@
 
 namespace ibim {
 
-constexpr int kSymRows = 4;  // most row tiles per work item (the LDS row sums are sized for it)
 // Largest row-and-column scratch of the symmetric kernel (an eighth of the
-// 288 GB of HBM; it grows as M^2 / 2^19 doubles, so this covers M ~ 2e6).
+// 288 GB of HBM; it grows as M^2 / rows, and with the row tiles per item of
+// make_sym_plan this covers M ~ 6.5e6).
 // Larger problems, and setups where the allocation fails, use the
 // one-directional kernel, whose scratch grows only linearly.
 constexpr size_t kSymScratchMax = size_t(32) << 30;
@@ -50,7 +50,7 @@ struct SymPlan {
   bool enabled = false;
   int T = 0;    // tiles of 256 nodes
   int b = 0;     // column tiles per item
-  int rows = 0;  // row tiles per item (1, 2 or kSymRows)
+  int rows = 0;  // row tiles per item (1 to 64, see make_sym_plan)
   int nRB = 0;   // row blocks (`rows` tiles each)
   int nCB = 0;  // column blocks
   size_t scratch_doubles = 0;  // row sums (sym_row_slots_total) + column sums (sym_col_slot(0, T, rows)), 512 doubles each

@@ -9,15 +9,17 @@
 // Tiles are 256 nodes.  Work item (rb, cb) covers row tiles
 // I in [rb*rows, rb*rows + rows) and column tiles J in [cb*b, cb*b + b),
 // pairs I <= J only.  For each column tile J the workgroup stages J's records
-// in LDS and, for each row tile I, evaluates all 256 x 256 pairs: wave w holds
-// targets I[64w + l] (one per lane) and, in phase p, visits the 64 sources of
-// sub-block (w + p) mod 4 in the rotated order l, l+1, ... (mod 64), eight
-// at a time from one LDS base address (each sub-block is followed by copies
-// of its first eight records, so the eight never wrap).  The
-// row sums of a tile pair stay in registers and are kept across the item in
-// lane-private LDS slots; the column sums of J go to an LDS accumulator,
-// which in any phase each wave updates in its own sub-block and each lane at
-// its own slot, so every slot is summed in a fixed order.
+// in LDS and, for each row tile I (two at a time where both are plain tile
+// pairs), evaluates all 256 x 256 pairs: wave w holds targets I[64w + l]
+// (one per lane) and, in phase p, visits the 64 sources of sub-block
+// (w + p) mod 4 in the rotated order l, l+1, ... (mod 64), eight at a time
+// from one LDS base address (each sub-block is followed by copies of its
+// first eight records, so the eight never wrap).  The row sums of a tile
+// pair stay in registers and are carried across the item in lane-private
+// LDS slots (items of up to four row tiles) or in their (cb, I) scratch
+// slots; the column sums of J go to an LDS accumulator, which in any phase
+// each wave updates in its own sub-block and each lane at its own slot, so
+// every slot is summed in a fixed order.
 // Diagonal tile pairs, pairs holding a corrected pair (either direction) and
 // pairs with the ragged last tile are evaluated one direction at a time with
 // the pairs of N_k skipped.  Row sums are written per (cb, I), column sums
@@ -40,7 +42,6 @@ namespace ibim {
 namespace {
 
 constexpr int kT = kPairTile;
-constexpr int kRows = kSymRows;
 
 // float64 arithmetic: records of 8 doubles, LDS as four double2 arrays.
 struct Fp64 {
@@ -197,9 +198,13 @@ __global__ __launch_bounds__(256) void finish_sym_batched_kernel(const SymFinish
 SymPlan make_sym_plan(int32_t M, size_t max_scratch_bytes) {
   SymPlan pl;
   pl.T = (M + kT - 1) / kT;
-  // row tiles per item: kRows (column tiles staged in LDS serve four row
-  // tiles), fewer for small problems so that they still have ~2048 items
-  int rows = kRows;
+  // row tiles per item: a column tile staged in LDS serves `rows` row
+  // tiles, and the column partial sums take about T^2 / (2 rows) slots of 4
+  // KiB: 4 row tiles up to T = 2048 (M = 524,288), then doubled while T
+  // exceeds 512 x rows, up to 64, which keeps the scratch under 32 GiB to
+  // M ~ 5e6; fewer for small problems so that they still have ~2048 items
+  int rows = 4;
+  while (rows < 64 && rows * 512 < pl.T) rows *= 2;
   while (rows > 1) {
     const int64_t nrb = (pl.T + rows - 1) / rows;
     if (nrb * pl.T / 2 >= 2048) break;
@@ -208,12 +213,17 @@ SymPlan make_sym_plan(int32_t M, size_t max_scratch_bytes) {
   pl.rows = rows;
   pl.nRB = (pl.T + rows - 1) / rows;
   // column block length: the shortest that keeps the item count at or under
-  // 8192, so that small problems still spread over many compute units
+  // 8192, so that small problems still spread over many compute units, and
+  // under 2048 per row tile of an item up to 32768 for larger items (items
+  // of more row tiles are longer, and a launch needs many of them to end
+  // evenly); at most 128 tiles: the row partial sums take about T^2 / (2 b)
+  // slots
+  const int64_t max_items = std::min<int64_t>(32768, std::max<int64_t>(8192, 2048 * rows));
   int b = 1;
-  while (b < 64) {
+  while (b < 128) {
     const int64_t nCB = (pl.T + b - 1) / b;
     const int64_t items = (int64_t)pl.nRB * nCB / 2;
-    if (items <= 8192) break;
+    if (items <= max_items) break;
     b *= 2;
   }
   pl.b = b;

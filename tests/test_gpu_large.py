@@ -2,9 +2,11 @@
 20 charges) at h = 0.1 (M = 754,301) and h = 0.07 (M = 1,540,232, the size of
 the largest molecular workload the method is aimed at).
 
-At these sizes the symmetric pair kernel keeps a row- and column-sum scratch of 4.75 to
-19.7 GB (it grows as M^2); the check is that its packed layout and the
-finishing kernels read back exactly what the work items wrote.  Sampled rows
+At these sizes the symmetric pair kernel spans 8 and 16 row tiles per work item
+and keeps a row- and column-sum scratch of 2.5 and 5.8 GB (it grows as
+M^2 / rows); the check is that its packed layout, the row sums carried in
+their slots from one column tile to the next, and the finishing kernels
+read back exactly what the work items wrote.  Sampled rows
 of ``apply`` (float64, mixed, treecode in float64 and mixed) are compared with the oracle's rows
 (computed here, weights only at the sampled rows); the solves are compared
 with each other and with the Kirkwood series (discretisation error).
