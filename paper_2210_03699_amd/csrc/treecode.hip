@@ -281,8 +281,10 @@ __device__ __forceinline__ void far_eval_f32(float R2, float rn, float A, float 
   S2 = __fmaf_rn(rn * iR3, __fmaf_rn(te, D, -A), S2);
 }
 
-// One work item: part of one batch's far clusters and direct ranges.
-template <bool kMixed>
+// One work item: part of one batch's far clusters and direct ranges.  kN is
+// the order when it is fixed at compile time (the float64 form at the
+// default order 8: 3-4% faster), else 0.
+template <bool kMixed, int kN>
 __global__ __launch_bounds__(256) void tree_item_kernel(TreeArgs a) {
   // LDS: near sources as 8 arrays of 256, or (same buffer) the combined
   // charges (A, B, D interleaved) of a proxy cluster, as many x-planes of its
@@ -297,7 +299,7 @@ __global__ __launch_bounds__(256) void tree_item_kernel(TreeArgs a) {
   const int32_t t = t0 + min(tid, nt - 1);
   const double x = a.tx[t], y = a.ty[t], z = a.tz[t];
   const double nxk = a.tnx[t], nyk = a.tny[t], nzk = a.tnz[t];
-  const int n = a.order, n2 = n * n, n3 = n2 * n;
+  const int n = kN > 0 ? kN : a.order, n2 = n * n, n3 = n2 * n;
   // x-planes of the proxy grid whose charges fit in the LDS buffer at once
   const int planes = max(1, (kMixed ? 4096 : 2048) / (3 * n2));
   double* qs = &sh[0][0];
@@ -347,8 +349,8 @@ __global__ __launch_bounds__(256) void tree_item_kernel(TreeArgs a) {
             const float* q = qf + 3 * (((i - i0) * n + j) * n);
             float s1 = 0.0f, s2 = 0.0f;
 #pragma unroll
-            for (int k = 0; k < kTreeMaxOrder; ++k) {
-              if (k < n)
+            for (int k = 0; k < (kN > 0 ? kN : kTreeMaxOrder); ++k) {
+              if (kN > 0 || k < n)
                 far_eval_f32(__fmaf_rn(rzf[k], rzf[k], axy), __fmaf_rn(rzf[k], nzf, bxy),
                              q[3 * k], q[3 * k + 1], q[3 * k + 2], pcf, s1, s2);
             }
@@ -594,10 +596,17 @@ hipError_t launch_tree_sum(const TreeDevice& T, const DeviceProblem& P, const do
         hipLaunchKernelGGL(tree_m2m_kernel, dim3((unsigned)cnt), dim3(256), 0, s, a, off);
     }
   }
-  if (T.mixed)
-    hipLaunchKernelGGL(tree_item_kernel<true>, dim3((unsigned)T.n_items), dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL(tree_item_kernel<false>, dim3((unsigned)T.n_items), dim3(256), 0, s, a);
+  const dim3 gi((unsigned)T.n_items);
+  if (T.mixed) {
+    // the float32 far field is faster with the order left to run time (86
+    // against 102 VGPRs, one more wave per SIMD)
+    hipLaunchKernelGGL((tree_item_kernel<true, 0>), gi, dim3(256), 0, s, a);
+  } else {
+    if (T.order == 8)
+      hipLaunchKernelGGL((tree_item_kernel<false, 8>), gi, dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((tree_item_kernel<false, 0>), gi, dim3(256), 0, s, a);
+  }
   return hipGetLastError();
 }
 
