@@ -89,7 +89,12 @@ struct ibim_server {
   int64_t next_ticket = 1;
   std::map<int64_t, std::unique_ptr<Request>> reqs;
   std::vector<Request*> waiting;  // submission order
-  std::vector<Request*> active;
+  std::vector<Request*> active;       // direct-sum solves: one round per step on `stream`
+  std::vector<Request*> tree_active;  // treecode solves: rounds on `tstream`
+  std::vector<Request*> tree_round;   // the treecode solves of the round in flight
+  bool tree_busy = false;             // a treecode round is in flight (tevent marks its end)
+  hipStream_t tstream = nullptr;
+  hipEvent_t tevent = nullptr;
   std::vector<int> free_slots;
   ibim_server_stats st{};
   // device buffers of the batched launch and of the per-round status
@@ -109,6 +114,9 @@ struct ibim_server {
   KrylovStepArgs* d_steps = nullptr;  // batched GMRES step of the solves in Arnoldi phase
   KrylovStepArgs* h_steps = nullptr;
   size_t steps_cap = 0;
+  KrylovStepArgs* d_tsteps = nullptr;  // the same for the treecode rounds
+  KrylovStepArgs* h_tsteps = nullptr;
+  size_t tsteps_cap = 0;
   SymFinishArgs* d_fin = nullptr;  // batched finishing launches (float64, mixed)
   SymFinishArgs* h_fin = nullptr;
   size_t fin_cap = 0;
@@ -117,8 +125,9 @@ struct ibim_server {
   size_t finm_cap = 0;
   int sym_grid = 0;
   int* d_counter = nullptr;  // two counters: one-directional and symmetric launches
-  double* d_status = nullptr;  // 8 doubles per slot
-  double* h_status = nullptr;  // pinned
+  double* d_status = nullptr;   // 8 doubles per slot
+  double* h_status = nullptr;   // pinned, copied at the end of each direct round
+  double* h_tstatus = nullptr;  // pinned, copied at the end of each treecode round
   // background host setup
   std::mutex mu;
   std::condition_variable cv;        // work for the setup threads
@@ -337,9 +346,9 @@ void collect_admitted(ibim_server* srv, std::vector<Request*>* fresh, bool wait)
   }
 }
 
-// Finishing a request: G_pol from psi at the charges, solution to the host.
-int finish_request(ibim_server* srv, Request* r) {
-  hipStream_t s = srv->stream;
+// Finishing a request: G_pol from psi at the charges, solution to the host,
+// on the stream its rounds ran on.
+int finish_request(ibim_server* srv, Request* r, hipStream_t s) {
   ibim_ctx* c = r->ctx;
   const int nc = (int)c->q.size();
   std::vector<double> psi(nc > 0 ? nc : 1);
@@ -414,7 +423,8 @@ void admit_waiting(ibim_server* srv, std::vector<Request*>* fresh, bool now) {
         srv->admit_cv.notify_one();
       }
     } else {
-      if (srv->active.empty() && fresh->empty() && srv->admitting == 0 && slot &&
+      if (srv->active.empty() && srv->tree_active.empty() && fresh->empty() &&
+          srv->admitting == 0 && slot &&
           r->estimate > srv->budget) {
         mark_failed(srv, r, IBIM_ENOMEM, "request footprint exceeds the server's HBM budget");
         continue;
@@ -427,120 +437,24 @@ void admit_waiting(ibim_server* srv, std::vector<Request*>* fresh, bool now) {
   srv->waiting.swap(still);
 }
 
-int step_impl(ibim_server* srv) {
-  hipStream_t s = srv->stream;
-  std::vector<Request*> fresh;
-  // requests set up on the admission thread join this round
-  collect_admitted(srv, &fresh, false);
-  if (srv->active.empty() && fresh.empty() && srv->admitting > 0) collect_admitted(srv, &fresh, true);
-  // with no solve running, wait for a host setup rather than return idle
-  if (srv->active.empty() && fresh.empty() && !srv->waiting.empty()) {
-    std::unique_lock<std::mutex> lk(srv->mu);
-    srv->ready_cv.wait(lk, [&] {
-      for (Request* r : srv->waiting)
-        if (r->prepared) return true;
-      return false;
-    });
+// Step 3 of a round for `reqs` (all on the treecode, or none) on stream s:
+// correction (+ row scaling), then one GMRES or residual step each, and the
+// status slots copied to the pinned host buffer hstat.  The finishing
+// kernels of the requests on the symmetric kernels run as one launch per
+// precision, and the GMRES (Arnoldi + Givens) steps of all solves as one
+// launch per stage, from the staging buffers passed in.
+int finish_and_step(ibim_server* srv, const std::vector<Request*>& reqs, hipStream_t s,
+                    bool tree, KrylovStepArgs** d_steps, KrylovStepArgs** h_steps,
+                    size_t* steps_cap, double* hstat) {
+  const size_t na = reqs.size();
+  if (int e = ensure_staging(d_steps, h_steps, steps_cap, na)) return e;
+  if (!tree) {
+    if (int e = ensure_staging(&srv->d_fin, &srv->h_fin, &srv->fin_cap, na)) return e;
+    if (int e = ensure_staging(&srv->d_finm, &srv->h_finm, &srv->finm_cap, na)) return e;
   }
-  const bool idle = srv->active.empty() && fresh.empty();
-  if (idle) {
-    // nothing on the device: admit here and run the new requests' first round now
-    admit_waiting(srv, &fresh, true);
-  }
-  srv->active.insert(srv->active.end(), fresh.begin(), fresh.end());
-  fresh.clear();
-  if ((int)srv->active.size() > srv->st.max_active_seen)
-    srv->st.max_active_seen = (int)srv->active.size();
-  if (srv->active.empty()) return IBIM_OK;
-
-  // 2. batched pair launches over every active request: one for the problems
-  // on the one-directional kernels, one for those on the symmetric kernel
-  size_t nargs = 0, nitems = 0, nsargs = 0, nswork = 0;
-  for (Request* r : srv->active) {
-    const ibim_ctx* c = r->ctx;
-    if (c->opt.summation == IBIM_SUM_TREE) continue;  // summed on its own in step 3
-    if (c->sym.enabled) {
-      ++nsargs;
-      nswork += (size_t)c->n_sym_items;
-    } else {
-      ++nargs;
-      nitems += (size_t)c->pair.ntile * (size_t)c->pair.nsplit;
-    }
-  }
-  if (int e = ensure_staging(&srv->d_args, &srv->h_args, &srv->args_cap, nargs)) return e;
-  if (int e = ensure_staging(&srv->d_items, &srv->h_items, &srv->items_cap, 3 * nitems)) return e;
-  if (int e = ensure_staging(&srv->d_sargs, &srv->h_sargs, &srv->sargs_cap, nsargs)) return e;
-  if (int e = ensure_staging(&srv->d_swork, &srv->h_swork, &srv->swork_cap, 2 * nswork)) return e;
-  size_t ia = 0, it = 0, isa = 0, isw = 0;
-  for (Request* r : srv->active) {
-    ibim_ctx* c = r->ctx;
-    if (c->opt.summation == IBIM_SUM_TREE) continue;
-    const int64_t N = c->kr.n;
-    const double* u = r->phase == Phase::kIter ? c->kr.V + (int64_t)r->j * N : r->d_x;
-    if (c->sym.enabled) {
-      srv->h_sargs[isa] =
-          make_sym_args(c->P, c->sym, c->d_sym_items, c->d_careful, u, c->sym_scratch);
-      for (int q = 0; q < c->n_sym_items; ++q) {
-        srv->h_swork[2 * isw] = (int32_t)isa;
-        srv->h_swork[2 * isw + 1] = q;
-        ++isw;
-      }
-      ++isa;
-    } else {
-      srv->h_args[ia] = make_pair_args(c->P, c->pair, u, c->partial);
-      for (int t = 0; t < c->pair.ntile; ++t)
-        for (int sp = 0; sp < c->pair.nsplit; ++sp) {
-          srv->h_items[3 * it] = (int32_t)ia;
-          srv->h_items[3 * it + 1] = t;
-          srv->h_items[3 * it + 2] = sp;
-          ++it;
-        }
-      ++ia;
-    }
-  }
-  hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, s, srv->d_counter, 2);
-  HIP_TRY(hipGetLastError(), "zero");
-  if (nitems > 0) {
-    HIP_TRY(hipMemcpyAsync(srv->d_args, srv->h_args, nargs * sizeof(PairArgs),
-                           hipMemcpyHostToDevice, s),
-            "copy");
-    HIP_TRY(hipMemcpyAsync(srv->d_items, srv->h_items, 3 * nitems * sizeof(int32_t),
-                           hipMemcpyHostToDevice, s),
-            "copy");
-    HIP_TRY(launch_pair_batched(srv->opt.precision, srv->d_args, srv->d_items, (int)nitems,
-                                srv->d_counter, srv->grid, s),
-            "batched pair launch");
-  }
-  if (nswork > 0) {
-    HIP_TRY(hipMemcpyAsync(srv->d_sargs, srv->h_sargs, nsargs * sizeof(SymArgs),
-                           hipMemcpyHostToDevice, s),
-            "copy");
-    HIP_TRY(hipMemcpyAsync(srv->d_swork, srv->h_swork, 2 * nswork * sizeof(int32_t),
-                           hipMemcpyHostToDevice, s),
-            "copy");
-    if (srv->opt.precision == IBIM_MIXED)
-      HIP_TRY(launch_pair_sym_mixed_batched(srv->d_sargs, srv->d_swork, (int)nswork,
-                                            srv->d_counter + 1, srv->sym_grid, s),
-              "batched symmetric pair launch");
-    else
-      HIP_TRY(launch_pair_sym_batched(srv->d_sargs, srv->d_swork, (int)nswork,
-                                      srv->d_counter + 1, srv->sym_grid, s),
-              "batched symmetric pair launch");
-  }
-  srv->st.rounds++;
-  srv->st.batched_items += (int64_t)(nitems + nswork);
-
-  // 3. per request: correction (+ row scaling), then one GMRES or residual
-  // step.  The finishing kernels of the requests on the symmetric kernels run
-  // as one launch per precision, and the GMRES (Arnoldi + Givens) steps of all
-  // solves as one launch per stage.
-  const size_t na = srv->active.size();
-  if (int e = ensure_staging(&srv->d_steps, &srv->h_steps, &srv->steps_cap, na)) return e;
-  if (int e = ensure_staging(&srv->d_fin, &srv->h_fin, &srv->fin_cap, na)) return e;
-  if (int e = ensure_staging(&srv->d_finm, &srv->h_finm, &srv->finm_cap, na)) return e;
   const bool unscale = srv->opt.precond == IBIM_PRECOND_DIAG;
   int nsteps = 0, nfin = 0, nfinm = 0;
-  for (Request* r : srv->active) {
+  for (Request* r : reqs) {
     ibim_ctx* c = r->ctx;
     Krylov& K = c->kr;
     const int64_t N = K.n;
@@ -556,7 +470,6 @@ int step_impl(ibim_server* srv) {
       continue;
     }
     if (c->opt.summation == IBIM_SUM_TREE) {
-      // large requests: the treecode's own launches, queued behind the batched ones
       HIP_TRY(launch_tree_sum(c->tree, c->P, u, s), "treecode launch");
       HIP_TRY(launch_tree_finish(c->tree, c->P, u, out, s), "finish");
     } else if (c->opt.precision == IBIM_MIXED) {
@@ -566,16 +479,19 @@ int step_impl(ibim_server* srv) {
     }
     if (unscale) HIP_TRY(launch_row_scaling(c, out, out, s), "row scaling");
   }
-  HIP_TRY(launch_finish_sym_batched(srv->h_fin, nfin, srv->d_fin, unscale, s), "finish");
-  HIP_TRY(launch_finish_sym_mixed_batched(srv->h_finm, nfinm, srv->d_finm, unscale, s), "finish");
-  for (Request* r : srv->active) {
+  if (!tree) {
+    HIP_TRY(launch_finish_sym_batched(srv->h_fin, nfin, srv->d_fin, unscale, s), "finish");
+    HIP_TRY(launch_finish_sym_mixed_batched(srv->h_finm, nfinm, srv->d_finm, unscale, s),
+            "finish");
+  }
+  for (Request* r : reqs) {
     ibim_ctx* c = r->ctx;
     Krylov& K = c->kr;
     const int64_t N = K.n;
     double* st = srv->d_status + (size_t)r->slot * kStatusStride;
     if (r->phase == Phase::kIter) {
       // as ibim_solve's dots/sub/dots/sub/dots/normalize/givens on out = V_{j+1}
-      KrylovStepArgs& a = srv->h_steps[nsteps++];
+      KrylovStepArgs& a = (*h_steps)[nsteps++];
       a.V = K.V;
       a.H = K.H;
       a.cs = K.cs;
@@ -594,23 +510,24 @@ int step_impl(ibim_server* srv) {
       HIP_TRY(K.dots(K.tmp, N, 1, K.tmp, N, st + 3, 0, s), "dots");
     }
   }
-  HIP_TRY(krylov_step_batched(srv->h_steps, nsteps, srv->d_steps, s), "batched GMRES step");
-  HIP_TRY(hipMemcpyAsync(srv->h_status, srv->d_status,
+  HIP_TRY(krylov_step_batched(*h_steps, nsteps, *d_steps, s), "batched GMRES step");
+  HIP_TRY(hipMemcpyAsync(hstat, srv->d_status,
                          (size_t)srv->max_slots * kStatusStride * sizeof(double),
                          hipMemcpyDeviceToHost, s),
           "copy");
-  // requests that became ready are set up on the admission thread while the
-  // round runs; they join a later round
-  if (!idle) admit_waiting(srv, &fresh, false);
-  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  return IBIM_OK;
+}
 
-  // 4. decisions
-  std::vector<Request*> keep;
-  for (Request* r : srv->active) {
+// Step 4 for `reqs` once their round has completed: the GMRES decisions from
+// their status slots in hstat, follow-up work on stream s (the stream their
+// round ran on).  Requests still solving are appended to *keep.
+int decide(ibim_server* srv, const std::vector<Request*>& reqs, hipStream_t s,
+           const double* hstat, std::vector<Request*>* keep) {
+  for (Request* r : reqs) {
     ibim_ctx* c = r->ctx;
     Krylov& K = c->kr;
     const int64_t N = K.n;
-    const double* hs = srv->h_status + (size_t)r->slot * kStatusStride;
+    const double* hs = hstat + (size_t)r->slot * kStatusStride;
     double* st = srv->d_status + (size_t)r->slot * kStatusStride;
     if (r->bnorm < 0.0) r->bnorm = std::sqrt(hs[2]);
     bool done = false;
@@ -669,11 +586,161 @@ int step_impl(ibim_server* srv) {
       continue;
     }
     if (done) {
-      if (int e = finish_request(srv, r)) mark_failed(srv, r, e, ibim_last_error());
+      if (int e = finish_request(srv, r, s)) mark_failed(srv, r, e, ibim_last_error());
       continue;
     }
-    keep.push_back(r);
+    keep->push_back(r);
   }
+  return IBIM_OK;
+}
+
+bool on_tree(const Request* r) { return r->ctx->opt.summation == IBIM_SUM_TREE; }
+
+int step_impl(ibim_server* srv) {
+  hipStream_t s = srv->stream;
+  std::vector<Request*> fresh;
+  // requests set up on the admission thread join this round
+  collect_admitted(srv, &fresh, false);
+  const bool none = srv->active.empty() && srv->tree_active.empty();
+  if (none && fresh.empty() && srv->admitting > 0) collect_admitted(srv, &fresh, true);
+  // with no solve running, wait for a host setup rather than return idle
+  if (none && fresh.empty() && !srv->waiting.empty()) {
+    std::unique_lock<std::mutex> lk(srv->mu);
+    srv->ready_cv.wait(lk, [&] {
+      for (Request* r : srv->waiting)
+        if (r->prepared) return true;
+      return false;
+    });
+  }
+  const bool idle = none && fresh.empty();
+  if (idle) {
+    // nothing on the device: admit here and run the new requests' first round now
+    admit_waiting(srv, &fresh, true);
+  }
+  for (Request* r : fresh) (on_tree(r) ? srv->tree_active : srv->active).push_back(r);
+  fresh.clear();
+  const int n_active = (int)(srv->active.size() + srv->tree_active.size());
+  if (n_active > srv->st.max_active_seen) srv->st.max_active_seen = n_active;
+  if (n_active == 0) return IBIM_OK;
+
+  // the treecode solves run their own rounds on a second stream, the next one
+  // launched when the previous has completed, so that the direct solves'
+  // rounds do not wait for their long launches
+  if (srv->tree_busy) {
+    hipError_t q = hipEventQuery(srv->tevent);
+    if (q == hipErrorNotReady && srv->active.empty()) q = hipEventSynchronize(srv->tevent);
+    if (q == hipSuccess) {
+      srv->tree_busy = false;
+      std::vector<Request*> next;
+      if (int e = decide(srv, srv->tree_round, srv->tstream, srv->h_tstatus, &next)) return e;
+      // then the treecode solves admitted while the round ran
+      for (Request* r : srv->tree_active)
+        if (std::find(srv->tree_round.begin(), srv->tree_round.end(), r) == srv->tree_round.end())
+          next.push_back(r);
+      srv->tree_active.swap(next);
+      srv->tree_round.clear();
+    } else if (q != hipErrorNotReady) {
+      return hip_fail(q, "treecode round");
+    }
+  }
+  if (!srv->tree_busy && !srv->tree_active.empty()) {
+    srv->tree_round = srv->tree_active;
+    if (int e = finish_and_step(srv, srv->tree_round, srv->tstream, true, &srv->d_tsteps,
+                                &srv->h_tsteps, &srv->tsteps_cap, srv->h_tstatus))
+      return e;
+    HIP_TRY(hipEventRecord(srv->tevent, srv->tstream), "event");
+    srv->tree_busy = true;
+  }
+  if (srv->active.empty()) {
+    if (!idle) admit_waiting(srv, &fresh, false);
+    return IBIM_OK;
+  }
+
+  // the direct solves' round: batched pair launches over all of them, one for
+  // the problems on the one-directional kernels, one for those on the
+  // symmetric kernel
+  size_t nargs = 0, nitems = 0, nsargs = 0, nswork = 0;
+  for (Request* r : srv->active) {
+    const ibim_ctx* c = r->ctx;
+    if (c->sym.enabled) {
+      ++nsargs;
+      nswork += (size_t)c->n_sym_items;
+    } else {
+      ++nargs;
+      nitems += (size_t)c->pair.ntile * (size_t)c->pair.nsplit;
+    }
+  }
+  if (int e = ensure_staging(&srv->d_args, &srv->h_args, &srv->args_cap, nargs)) return e;
+  if (int e = ensure_staging(&srv->d_items, &srv->h_items, &srv->items_cap, 3 * nitems)) return e;
+  if (int e = ensure_staging(&srv->d_sargs, &srv->h_sargs, &srv->sargs_cap, nsargs)) return e;
+  if (int e = ensure_staging(&srv->d_swork, &srv->h_swork, &srv->swork_cap, 2 * nswork)) return e;
+  size_t ia = 0, it = 0, isa = 0, isw = 0;
+  for (Request* r : srv->active) {
+    ibim_ctx* c = r->ctx;
+    const int64_t N = c->kr.n;
+    const double* u = r->phase == Phase::kIter ? c->kr.V + (int64_t)r->j * N : r->d_x;
+    if (c->sym.enabled) {
+      srv->h_sargs[isa] =
+          make_sym_args(c->P, c->sym, c->d_sym_items, c->d_careful, u, c->sym_scratch);
+      for (int q = 0; q < c->n_sym_items; ++q) {
+        srv->h_swork[2 * isw] = (int32_t)isa;
+        srv->h_swork[2 * isw + 1] = q;
+        ++isw;
+      }
+      ++isa;
+    } else {
+      srv->h_args[ia] = make_pair_args(c->P, c->pair, u, c->partial);
+      for (int t = 0; t < c->pair.ntile; ++t)
+        for (int sp = 0; sp < c->pair.nsplit; ++sp) {
+          srv->h_items[3 * it] = (int32_t)ia;
+          srv->h_items[3 * it + 1] = t;
+          srv->h_items[3 * it + 2] = sp;
+          ++it;
+        }
+      ++ia;
+    }
+  }
+  hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, s, srv->d_counter, 2);
+  HIP_TRY(hipGetLastError(), "zero");
+  if (nitems > 0) {
+    HIP_TRY(hipMemcpyAsync(srv->d_args, srv->h_args, nargs * sizeof(PairArgs),
+                           hipMemcpyHostToDevice, s),
+            "copy");
+    HIP_TRY(hipMemcpyAsync(srv->d_items, srv->h_items, 3 * nitems * sizeof(int32_t),
+                           hipMemcpyHostToDevice, s),
+            "copy");
+    HIP_TRY(launch_pair_batched(srv->opt.precision, srv->d_args, srv->d_items, (int)nitems,
+                                srv->d_counter, srv->grid, s),
+            "batched pair launch");
+  }
+  if (nswork > 0) {
+    HIP_TRY(hipMemcpyAsync(srv->d_sargs, srv->h_sargs, nsargs * sizeof(SymArgs),
+                           hipMemcpyHostToDevice, s),
+            "copy");
+    HIP_TRY(hipMemcpyAsync(srv->d_swork, srv->h_swork, 2 * nswork * sizeof(int32_t),
+                           hipMemcpyHostToDevice, s),
+            "copy");
+    if (srv->opt.precision == IBIM_MIXED)
+      HIP_TRY(launch_pair_sym_mixed_batched(srv->d_sargs, srv->d_swork, (int)nswork,
+                                            srv->d_counter + 1, srv->sym_grid, s),
+              "batched symmetric pair launch");
+    else
+      HIP_TRY(launch_pair_sym_batched(srv->d_sargs, srv->d_swork, (int)nswork,
+                                      srv->d_counter + 1, srv->sym_grid, s),
+              "batched symmetric pair launch");
+  }
+  srv->st.rounds++;
+  srv->st.batched_items += (int64_t)(nitems + nswork);
+
+  if (int e = finish_and_step(srv, srv->active, s, false, &srv->d_steps, &srv->h_steps,
+                              &srv->steps_cap, srv->h_status))
+    return e;
+  // requests that became ready are set up on the admission thread while the
+  // round runs; they join a later round
+  if (!idle) admit_waiting(srv, &fresh, false);
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  std::vector<Request*> keep;
+  if (int e = decide(srv, srv->active, s, srv->h_status, &keep)) return e;
   srv->active.swap(keep);
   return IBIM_OK;
 }
@@ -713,11 +780,16 @@ int ibim_server_create(const ibim_options* opt, size_t hbm_budget_bytes, int max
     srv->sym_grid =
         o.precision == IBIM_MIXED ? pair_sym_mixed_batched_grid() : pair_sym_batched_grid();
     hipError_t e = hipStreamCreateWithFlags(&srv->setup, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&srv->tstream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&srv->tevent, hipEventDisableTiming);
     if (e == hipSuccess) e = dalloc(&srv->d_counter, 2);
     if (e == hipSuccess) e = dalloc(&srv->d_status, (size_t)max_slots * kStatusStride);
     if (e == hipSuccess)
       e = hipHostMalloc((void**)&srv->h_status, (size_t)max_slots * kStatusStride * sizeof(double),
                         hipHostMallocDefault);
+    if (e == hipSuccess)
+      e = hipHostMalloc((void**)&srv->h_tstatus,
+                        (size_t)max_slots * kStatusStride * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) {
       ibim_server_destroy(srv);
       return hip_fail(e, "server allocation");
@@ -778,7 +850,7 @@ int ibim_server_step(ibim_server* srv, int* active, int* waiting) {
   if (!srv) return fail(IBIM_EINVAL, "NULL server");
   DeviceScope ds(srv->opt.device);
   const int e = step_impl(srv);
-  if (active) *active = (int)srv->active.size();
+  if (active) *active = (int)(srv->active.size() + srv->tree_active.size());
   if (waiting) *waiting = (int)srv->waiting.size() + srv->admitting;
   return e;
 }
@@ -823,7 +895,7 @@ int ibim_server_get_stats(ibim_server* srv, ibim_server_stats* st) {
   if (!srv || !st) return fail(IBIM_EINVAL, "NULL argument");
   srv->st.bytes_in_use = srv->used;
   srv->st.bytes_peak = srv->peak;
-  srv->st.active = (int)srv->active.size();
+  srv->st.active = (int)(srv->active.size() + srv->tree_active.size());
   srv->st.waiting = (int)srv->waiting.size() + srv->admitting;  // as ibim_server_step
   {
     // estimate_shortfall is written by the admission thread
@@ -858,6 +930,11 @@ void ibim_server_destroy(ibim_server* srv) {
     (void)hipStreamSynchronize(srv->setup);
     (void)hipStreamDestroy(srv->setup);
   }
+  if (srv->tstream) {
+    (void)hipStreamSynchronize(srv->tstream);  // a treecode round still in flight
+    (void)hipStreamDestroy(srv->tstream);
+  }
+  if (srv->tevent) (void)hipEventDestroy(srv->tevent);
   for (auto& kv : srv->reqs) {
     Request* r = kv.second.get();
     if (r->ctx) ibim_destroy(r->ctx);
@@ -870,6 +947,9 @@ void ibim_server_destroy(ibim_server* srv) {
   dfree(srv->d_sargs);
   dfree(srv->d_swork);
   dfree(srv->d_steps);
+  dfree(srv->d_tsteps);
+  if (srv->h_tsteps) (void)hipHostFree(srv->h_tsteps);
+  if (srv->h_tstatus) (void)hipHostFree(srv->h_tstatus);
   dfree(srv->d_fin);
   dfree(srv->d_finm);
   if (srv->h_fin) (void)hipHostFree(srv->h_fin);
