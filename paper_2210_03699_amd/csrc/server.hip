@@ -2,13 +2,15 @@
 //
 // A request moves through: submitted -> host setup on a background thread
 // (geometry and correction sets) -> waiting for admission -> device setup on
-// the admission thread (uploads, correction weights, Krylov basis; a second
-// stream) -> active -> done (G_pol and the solution kept on the host; its
-// device memory freed on the reaper thread) or failed.  Each round does one
-// persistent batched pair-kernel launch over the work items of every active
-// direct-sum solve, the treecode launches of requests that the options send
-// to it, one batched finishing launch per precision and one launch per GMRES
-// stage for all solves.  Every request gets the blocks and reduction order of
+// one of two admission threads (uploads, correction weights, Krylov basis; a
+// stream each) -> active -> done (G_pol and the solution kept on the host;
+// its device memory freed on the reaper thread) or failed.  Each round of
+// the direct-sum solves does one persistent batched pair-kernel launch over
+// the work items of all of them, one batched finishing launch per precision
+// and one launch per GMRES stage; the solves that the options send to the
+// treecode run their rounds (their own launches, then one launch per GMRES
+// stage) on a second stream, each round started when the previous one has
+// completed.  Every request gets the blocks and reduction order of
 // ibim_solve and ibim_energy, so results do not depend on the mix of requests.
 #include <hip/hip_runtime.h>
 
@@ -83,8 +85,10 @@ struct ibim_server {
   int max_slots = 1;
   hipStream_t stream = nullptr;
   // device setup of newly admitted requests (uploads, weights, right-hand
-  // side) runs here while the round already queued on `stream` executes
-  hipStream_t setup = nullptr;
+  // side) runs on these streams, one per admission thread, while the rounds
+  // execute
+  static constexpr int kAdmitters = 2;
+  hipStream_t setup[kAdmitters] = {};
   int grid = 0;
   int64_t next_ticket = 1;
   std::map<int64_t, std::unique_ptr<Request>> reqs;
@@ -153,11 +157,11 @@ struct ibim_server {
   // admission thread sets it up on the setup stream; the next round picks it up
   std::deque<Request*> admit_queue;
   std::vector<Request*> admitted;     // set up (or failed), not yet picked up
-  std::condition_variable admit_cv;   // work for the admission thread
+  std::condition_variable admit_cv;   // work for the admission threads
   std::condition_variable admitted_cv;
   int admitting = 0;                  // queued or being set up (main thread)
   bool admit_stop = false;
-  std::thread admitter;
+  std::thread admitter[kAdmitters];
 };
 
 namespace {
@@ -253,8 +257,7 @@ void mark_failed(ibim_server* srv, Request* r, int code, const std::string& msg)
 // Device setup and the first GMRES cycle's start (r = b, V0 = b/||b||) on
 // the setup stream, for a request holding a reserved slot.  Touches only the
 // request and its slot, so it may run on the admission thread.
-int admit_device(ibim_server* srv, Request* r) {
-  hipStream_t s = srv->setup;
+int admit_device(ibim_server* srv, Request* r, hipStream_t s) {
   ibim_ctx* c = r->ctx;
   c->opt.device = srv->opt.device;
   if (int e = ctx_setup_device(c, s)) return e;
@@ -292,7 +295,7 @@ int admit_device(ibim_server* srv, Request* r) {
   return IBIM_OK;
 }
 
-void admitter_main(ibim_server* srv) {
+void admitter_main(ibim_server* srv, int idx) {
   (void)hipSetDevice(srv->opt.device);
   for (;;) {
     Request* r = nullptr;
@@ -303,7 +306,7 @@ void admitter_main(ibim_server* srv) {
       r = srv->admit_queue.front();
       srv->admit_queue.pop_front();
     }
-    const int e = admit_device(srv, r);
+    const int e = admit_device(srv, r, srv->setup[idx]);
     const std::string msg = e ? std::string(ibim_last_error()) : std::string();
     {
       std::lock_guard<std::mutex> lk(srv->mu);
@@ -412,7 +415,7 @@ void admit_waiting(ibim_server* srv, std::vector<Request*>* fresh, bool now) {
       r->held = r->estimate;  // reserved until the device setup reports its bytes
       srv->used += r->held;
       if (now) {
-        const int e = admit_device(srv, r);
+        const int e = admit_device(srv, r, srv->setup[0]);
         finish_admission(srv, r, e, e ? std::string(ibim_last_error()) : std::string(), fresh);
       } else {
         {
@@ -779,7 +782,9 @@ int ibim_server_create(const ibim_options* opt, size_t hbm_budget_bytes, int max
     srv->grid = pair_batched_grid(o.precision);
     srv->sym_grid =
         o.precision == IBIM_MIXED ? pair_sym_mixed_batched_grid() : pair_sym_batched_grid();
-    hipError_t e = hipStreamCreateWithFlags(&srv->setup, hipStreamNonBlocking);
+    hipError_t e = hipSuccess;
+    for (int t = 0; t < ibim_server::kAdmitters && e == hipSuccess; ++t)
+      e = hipStreamCreateWithFlags(&srv->setup[t], hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&srv->tstream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&srv->tevent, hipEventDisableTiming);
     if (e == hipSuccess) e = dalloc(&srv->d_counter, 2);
@@ -804,7 +809,8 @@ int ibim_server_create(const ibim_options* opt, size_t hbm_budget_bytes, int max
   const int per = std::max(1, cores / host_threads);
   for (int t = 0; t < host_threads; ++t) srv->workers.emplace_back(worker_main, srv, per);
   srv->reaper = std::thread(reaper_main, srv);
-  srv->admitter = std::thread(admitter_main, srv);
+  for (int t = 0; t < ibim_server::kAdmitters; ++t)
+    srv->admitter[t] = std::thread(admitter_main, srv, t);
   *out = srv;
   return IBIM_OK;
 }
@@ -918,7 +924,8 @@ void ibim_server_destroy(ibim_server* srv) {
     srv->admit_stop = true;
   }
   srv->admit_cv.notify_all();
-  if (srv->admitter.joinable()) srv->admitter.join();  // a setup in progress completes
+  for (auto& t : srv->admitter)
+    if (t.joinable()) t.join();  // setups in progress complete
   {
     std::lock_guard<std::mutex> lk(srv->mu);
     srv->reap_stop = true;
@@ -926,9 +933,10 @@ void ibim_server_destroy(ibim_server* srv) {
   srv->reap_cv.notify_all();
   if (srv->reaper.joinable()) srv->reaper.join();  // frees what is still queued first
   DeviceScope ds(srv->opt.device);
-  if (srv->setup) {
-    (void)hipStreamSynchronize(srv->setup);
-    (void)hipStreamDestroy(srv->setup);
+  for (hipStream_t st : srv->setup) {
+    if (!st) continue;
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
   }
   if (srv->tstream) {
     (void)hipStreamSynchronize(srv->tstream);  // a treecode round still in flight
