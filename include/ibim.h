@@ -359,20 +359,23 @@ int ibim_tree_plan(const ibim_ctx* ctx, int64_t* counts, int32_t* perm, int32_t*
  * Requests (a signed-distance grid and charges, as for ibim_setup, plus a
  * GMRES tolerance) are queued by ibim_server_submit, which copies the inputs
  * and starts the host part of their setup on a background thread.  Each
- * ibim_server_step is one round:
+ * ibim_server_step is one round of the direct-sum solves:
  *   1. admission: prepared requests get a solve slot, in submission order,
  *      while one is free and the estimated device footprint (geometry,
  *      corrections, partial sums, Krylov basis) fits in the HBM budget (a
  *      request that does not fit lets later smaller ones pass; memory of
  *      finished requests counts until a background thread has freed it).
- *      Their device setup runs on a background thread and a second stream
- *      while rounds continue, and they join the first round after it (with
- *      no solve running, the step sets them up itself);
+ *      Their device setup runs on one of two background threads, each with a
+ *      stream of its own, while rounds continue, and they join the first
+ *      round after it (with no solve running, the step sets them up itself);
  *   2. ONE persistent batched pair-kernel launch covers a work list of
  *      (request, target tile, source chunk) items of every active solve; each
  *      item is computed exactly as in the single-problem kernel.  Requests
  *      that the options send to the treecode (IBIM_SUM_TREE, at least
- *      tree_min_nodes nodes) run their treecode launches after it instead;
+ *      tree_min_nodes nodes) run rounds of their own instead (their treecode
+ *      launches, then steps 3 and 4) on a second stream: a step starts the
+ *      next such round once the previous one has completed, and waits for
+ *      it only when no direct-sum solve is active;
  *   3. per request: sparse correction, one GMRES (Arnoldi + Givens) step or a
  *      residual step, all on the device, then a single status read-back;
  *   4. finished solves compute G_pol (eq. pol-energy), keep their solution on
@@ -385,7 +388,7 @@ typedef struct ibim_server ibim_server;
 
 typedef struct {
   int64_t submitted, admitted, finished, failed;
-  int64_t rounds;           /* ibim_server_step calls that did device work */
+  int64_t rounds;           /* rounds of the direct-sum solves */
   int64_t batched_items;    /* pair-kernel work items over all rounds */
   size_t bytes_in_use;      /* device bytes charged to the budget: active solves, and
                                requests being set up at their estimate */
@@ -412,7 +415,9 @@ typedef struct {
  * treecode fields, resolved per request by its size as in ibim_setup;
  * validated as there); hbm_budget_bytes > 0; max_slots >= 1
  * concurrent solves; host_threads >= 1 background setup threads; stream:
- * the hipStream_t every round runs on (NULL: the null stream). */
+ * the hipStream_t the direct-sum solves' rounds run on (NULL: the null
+ * stream); the treecode solves' rounds and the device setups use streams the
+ * server creates. */
 int ibim_server_create(const ibim_options* opt, size_t hbm_budget_bytes, int max_slots,
                        int host_threads, void* stream, ibim_server** out);
 /* Inputs as in ibim_setup (host, copied); tol > 0.  *ticket identifies the

@@ -92,7 +92,7 @@ def test_alone_equals_mixed_equals_direct(wls, precision, restart, hybrid):
     _say(f"[serving] rounds={stats['rounds']} max_active={stats['max_active_seen']} "
          f"items={stats['batched_items']}")
     assert stats["finished"] == len(names) and stats["failed"] == 0
-    # requests are set up on the admission thread while rounds run, so a small
+    # requests are set up on the admission threads while rounds run, so a small
     # one may finish before the last joins: the mix shares rounds, not
     # necessarily all at once
     assert stats["max_active_seen"] >= 2
@@ -178,8 +178,9 @@ def test_footprint_estimates_bound_the_device_bytes(wls, precision):
 @pytest.mark.parametrize("precision", [ibim.FP64, ibim.MIXED])
 def test_tree_requests_in_the_mix(wls, precision):
     """With IBIM_SUM_TREE and a size threshold, requests of at least
-    tree_min_nodes nodes run the float64 treecode inside the rounds and the
-    others the batched mixed kernel.  Every result is the same bits alone, in
+    tree_min_nodes nodes run the treecode in rounds of their own (a second
+    stream, concurrent with the direct solves' rounds) and the others the
+    batched direct kernel.  Every result is the same bits alone, in
     the mix and through ibim_solve with the same options, and the treecode's
     energies are within the treecode's error of the float64 direct solve."""
     pool = dict(wls)
