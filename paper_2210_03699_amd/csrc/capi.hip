@@ -590,7 +590,10 @@ int ctx_setup_device(ibim_ctx* c, hipStream_t s) {
     std::vector<uint32_t> bits;
     sym_careful_bits(c->sym.T, xrow, xtile, &bits);
     c->n_sym_items = (int)(items.size() / 2);
-    // flops: 68 per shared evaluation, 60 per one-way pair (diagonal, careful, ragged)
+    // flops: 68 per shared evaluation (66 in float64 in Debye units), 60 per
+    // one-way pair (diagonal, careful, ragged)
+    const double shared =
+        o.precision == IBIM_FP64 && sym_debye_units(c->kappa) ? 66.0 : 68.0;
     const int T = c->sym.T;
     auto nodes = [&](int X) { return (double)std::min(kPairTile, M - X * kPairTile); };
     double fl = 0.0;
@@ -599,7 +602,7 @@ int ctx_setup_device(ibim_ctx* c, hipStream_t s) {
       for (int J = I + 1; J < T; ++J) {
         const size_t bI = (size_t)I * T + J;
         const bool slow = ((bits[bI >> 5] >> (bI & 31)) & 1u) || (J == T - 1 && M % kPairTile);
-        fl += slow ? 120.0 * nodes(I) * nodes(J) : 68.0 * nodes(I) * nodes(J);
+        fl += (slow ? 120.0 : shared) * nodes(I) * nodes(J);
       }
     }
     c->pair_flops = fl;

@@ -41,9 +41,9 @@ __device__ __forceinline__ T* lds_at(T* base, unsigned byte_off) {
   return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off);
 }
 
-template <class P>
-struct Shared {
-  typename P::Lds rec;                     // records of the column tile J
+template <class L>
+struct SharedL {
+  L rec;                                   // records of the column tile J
   // column sums of J (row 1, row 2) in two arrays of doubles: lanes add to
   // consecutive slots, 8 bytes apart, which keeps the LDS atomics free of
   // bank conflicts (a 16-byte stride gave 4-way conflicts)
@@ -51,6 +51,9 @@ struct Shared {
   // row sums of items of at most kLdsRows row tiles, lane-private
   double racc1[kLdsRows][kT], racc2[kLdsRows][kT];
 };
+// LDS of a policy P (policies with one record layout share one type)
+template <class P>
+using Shared = SharedL<typename P::Lds>;
 
 // Sums over the sources of tile Y for the target of this lane in tile X
 // (k = X*256 + tid), pairs of N_k skipped.  src(j) returns source j of Y.
@@ -121,7 +124,8 @@ __device__ __forceinline__ void sweep(Shared<P>& sh, const typename P::Consts& p
 // meets I (J = max(J0, I)) and are carried to the next one in LDS (items of
 // at most kLdsRows row tiles) or in the tile's (cb, I) slot of the row
 // partial sums, read and written back by the thread that owns the row; the
-// slot receives them scaled by h^3/(4 pi) at the last visit (J = J1 - 1).
+// slot receives them scaled by h^3/(4 pi) at the last visit (J = J1 - 1),
+// the second row by P::scale2 (h^3/(4 pi) times the policy's unit factor).
 template <class P>
 __device__ void item(const SymArgs& a, int rb, int cb, Shared<P>& sh) {
   double* const cacc1 = sh.cacc1;
@@ -159,9 +163,8 @@ __device__ void item(const SymArgs& a, int rb, int cb, Shared<P>& sh) {
     }
     if (last || !in_lds) {
       double* rp = row_sums(I);
-      const double f = last ? a.scale : 1.0;
-      rp[tid] = f * S1;
-      rp[kT + tid] = f * S2;
+      rp[tid] = (last ? a.scale : 1.0) * S1;
+      rp[kT + tid] = (last ? P::scale2(a) : 1.0) * S2;
     }
   };
 
@@ -231,15 +234,16 @@ __device__ void item(const SymArgs& a, int rb, int cb, Shared<P>& sh) {
     }
     double* cp = a.colpart + sym_col_slot(rb, J, rows) * (2 * kT);
     cp[tid] = a.scale * cacc1[my];
-    cp[kT + tid] = a.scale * cacc2[my];
+    cp[kT + tid] = P::scale2(a) * cacc2[my];
     __syncthreads();  // LDS is refilled for the next column tile
   }
 }
 
-// Persistent loop over (problem, item) entries taken from *counter.
-template <class P>
+// Persistent loop over (problem, item) entries taken from *counter; body(a,
+// rb, cb) runs one item with all threads of the workgroup.
+template <class Body>
 __device__ void batched(const SymArgs* __restrict__ probs, const int32_t* __restrict__ work,
-                        int n_work, int* counter, Shared<P>& sh) {
+                        int n_work, int* counter, const Body& body) {
   __shared__ int next;
   for (;;) {
     if (threadIdx.x == 0) next = atomicAdd(counter, 1);
@@ -252,7 +256,7 @@ __device__ void batched(const SymArgs* __restrict__ probs, const int32_t* __rest
     const int ii = __builtin_amdgcn_readfirstlane(work[2 * it + 1]);
     const SymArgs a = probs[pi];
     const int2 it2 = a.items[ii];
-    item<P>(a, __builtin_amdgcn_readfirstlane(it2.x), __builtin_amdgcn_readfirstlane(it2.y), sh);
+    body(a, __builtin_amdgcn_readfirstlane(it2.x), __builtin_amdgcn_readfirstlane(it2.y));
     __syncthreads();  // LDS is reused by the next entry
   }
 }

@@ -22,6 +22,11 @@ constexpr size_t kSymScratchMax = size_t(32) << 30;
 // pair distance (the diagonal of their nodes' bounding box) times kappa is
 // larger use the one-directional float64 kernel.
 constexpr double kSymMaxKappaR = 708.0;
+// The float64 symmetric kernel evaluates pairs in units of the Debye length
+// 1/kappa when kappa is above this (below it R^-3 in those units could
+// overflow); otherwise kappa enters every pair.
+constexpr double kSymUnitMinKappa = 1e-30;
+__host__ __device__ inline bool sym_debye_units(double kappa) { return kappa > kSymUnitMinKappa; }
 
 // Column-sum slot of (row block rb, column tile J), rb <= J / rows, for row
 // blocks of `rows` tiles: the slots of tile J follow those of tiles 0 .. J-1

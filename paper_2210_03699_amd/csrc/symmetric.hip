@@ -44,23 +44,45 @@ namespace {
 constexpr int kT = kPairTile;
 
 // float64 arithmetic: records of 8 doubles, LDS as four double2 arrays.
+// With kUnit (kappa > 0) lengths are measured in units of the Debye length
+// 1/kappa: a record holds kappa P_m, kappa^2 w_m u1_m and kappa w_m u2_m.  In
+// the dimensionless distance rho = kappa R the Yukawa factors read e^{-rho},
+// 1 + rho and (for K21) a plain e^{-rho}/rho^3, which saves the two
+// multiplications by kappa and kappa^2 of every pair; each kernel is a
+// power of kappa times its dimensionless form, so the first sums come out
+// unchanged and the second divided by kappa, which scale2 puts back when the
+// partial sums are written.  Without kUnit (kappa = 0 or negligible) the
+// records hold P_m, w_m u1_m and w_m u2_m and kappa enters each pair.
+struct Fp64Rec {
+  double px, py, pz, nx, ny, nz, a1, a2;
+};
+struct Fp64Lds {
+  // (px,py) (pz,nx) (ny,nz) (a1,a2) per LDS slot (sym::slot)
+  double2 A[sym::kSlots], B[sym::kSlots], C[sym::kSlots], D[sym::kSlots];
+};
+template <bool kUnit>
 struct Fp64 {
-  struct Rec {
-    double px, py, pz, nx, ny, nz, a1, a2;
-  };
-  struct Lds {
-    // (px,py) (pz,nx) (ny,nz) (a1,a2) per LDS slot (sym::slot)
-    double2 A[sym::kSlots], B[sym::kSlots], C[sym::kSlots], D[sym::kSlots];
-  };
+  using Rec = Fp64Rec;
+  using Lds = Fp64Lds;
   struct Consts {
     PairConsts k;  // one-directional evaluations
     ExpWave ew;    // table exponential of the symmetric evaluation
   };
   static __device__ __forceinline__ Consts consts(const SymArgs& a) {
-    return Consts{PairConsts{a.c1, a.c2, a.kappa, a.kappa * a.kappa}, exp_wave_init(a.kappa)};
+    const double kap = kUnit ? 1.0 : a.kappa;
+    return Consts{PairConsts{a.c1, a.c2, kap, kap * kap}, exp_wave_init(kap)};
+  }
+  // multiplier of the second row of partial sums at write-out
+  static __device__ __forceinline__ double scale2(const SymArgs& a) {
+    return kUnit ? a.scale * a.kappa : a.scale;
   }
   static __device__ __forceinline__ Rec load(const SymArgs& a, int32_t m) {
     const double wm = a.w[m];
+    if (kUnit) {
+      const double k = a.kappa, wk = wm * k;
+      return Rec{k * a.px[m], k * a.py[m], k * a.pz[m], a.nx[m], a.ny[m], a.nz[m],
+                 (wk * k) * a.u[m], wk * a.u[a.M + m]};
+    }
     return Rec{a.px[m], a.py[m], a.pz[m], a.nx[m], a.ny[m], a.nz[m], wm * a.u[m],
                wm * a.u[a.M + m]};
   }
@@ -84,8 +106,8 @@ struct Fp64 {
   // (S1, S2), m <- k returned in (C1, C2), or added to them when kAcc.  With
   // u = (1 - e(1 + kR))/R^3 and t3 = e(1 + kR)/R^3 the kernel factors are
   // (1 - c t)/R^3 = 1/R^3 - c t3 and K21 R^3 / R^3 = n_k.n_m u + q (k^2 e/R^3
-  // - 3 u/R^2).  Called with all 64 lanes of the wavefront active (the
-  // exponential reads other lanes).
+  // - 3 u/R^2) (k = 1 with kUnit).  Called with all 64 lanes of the
+  // wavefront active (the exponential reads other lanes).
   template <bool kAcc = false>
   static __device__ __forceinline__ void both(const Rec& f, const Rec& m, const Consts& pc,
                                               double& S1, double& S2, double& C1, double& C2) {
@@ -96,7 +118,7 @@ struct Fp64 {
     const double iR2 = iR * iR;
     const double iR3 = iR2 * iR;
     const double e = exp_neg_wave(R, pc.ew);
-    const double kr = pc.k.kappa * R;
+    const double kr = kUnit ? R : pc.k.kappa * R;
     const double rny = fma(rz, m.nz, fma(ry, m.ny, rx * m.nx));  // r . n_m
     const double rnx = fma(rz, f.nz, fma(ry, f.ny, rx * f.nx));  // r . n_k
     const double nn = fma(f.nz, m.nz, fma(f.ny, m.ny, f.nx * m.nx));
@@ -107,7 +129,8 @@ struct Fp64 {
     const double f2 = fma(-pc.k.c2, t3, iR3);
     const double g12 = fma(-e, iR, iR);  // (1 - e)/R
     const double q = rnx * rny;
-    const double g21 = fma(nn, u, q * fma(u * iR2, -3.0, pc.k.kappa2 * eiR3));
+    const double k2e = kUnit ? eiR3 : pc.k.kappa2 * eiR3;
+    const double g21 = fma(nn, u, q * fma(u * iR2, -3.0, k2e));
     // k <- m
     const double g11 = rny * f1, g22 = rnx * f2;
     S1 = fma(g11, m.a1, fma(-g12, m.a2, S1));
@@ -124,17 +147,23 @@ struct Fp64 {
   }
 };
 
+template <bool kUnit>
 __global__ __launch_bounds__(256) void pair_sym_fp64_kernel(SymArgs a) {
-  __shared__ sym::Shared<Fp64> sh;
+  __shared__ sym::Shared<Fp64<kUnit>> sh;
   const int2 it = a.items[blockIdx.x];
-  sym::item<Fp64>(a, it.x, it.y, sh);
+  sym::item<Fp64<kUnit>>(a, it.x, it.y, sh);
 }
 
 __global__ __launch_bounds__(256, 3) void pair_sym_batched_kernel(
     const SymArgs* __restrict__ probs, const int32_t* __restrict__ work, int n_work,
     int* counter) {
-  __shared__ sym::Shared<Fp64> sh;
-  sym::batched<Fp64>(probs, work, n_work, counter, sh);
+  __shared__ sym::Shared<Fp64<true>> sh;  // one layout for both policies
+  sym::batched(probs, work, n_work, counter, [&](const SymArgs& a, int rb, int cb) {
+    if (sym_debye_units(a.kappa))
+      sym::item<Fp64<true>>(a, rb, cb, sh);
+    else
+      sym::item<Fp64<false>>(a, rb, cb, sh);
+  });
 }
 
 
@@ -297,7 +326,12 @@ SymArgs make_sym_args(const DeviceProblem& P, const SymPlan& pl, const int32_t* 
 }
 
 hipError_t launch_pair_sym(const SymArgs& a, int n_items, hipStream_t stream) {
-  hipLaunchKernelGGL(pair_sym_fp64_kernel, dim3((unsigned)n_items), dim3(256), 0, stream, a);
+  if (sym_debye_units(a.kappa))
+    hipLaunchKernelGGL(pair_sym_fp64_kernel<true>, dim3((unsigned)n_items), dim3(256), 0, stream,
+                       a);
+  else
+    hipLaunchKernelGGL(pair_sym_fp64_kernel<false>, dim3((unsigned)n_items), dim3(256), 0, stream,
+                       a);
   return hipGetLastError();
 }
 

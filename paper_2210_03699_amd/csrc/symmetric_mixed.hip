@@ -34,6 +34,7 @@ struct Mixed {
   static __device__ __forceinline__ Consts consts(const SymArgs& a) {
     return PairConstsF{(float)a.c1, (float)a.c2, (float)a.kappa, (float)(a.kappa * a.kappa)};
   }
+  static __device__ __forceinline__ double scale2(const SymArgs& a) { return a.scale; }
   static __device__ __forceinline__ Rec load(const SymArgs& a, int32_t m) {
     const double wm = a.w[m];
     return Rec{a.fx[m], a.fy[m], a.fz[m], a.fnx[m], a.fny[m], a.fnz[m], (float)(wm * a.u[m]),
@@ -79,7 +80,8 @@ __global__ __launch_bounds__(256, 4) void pair_sym_mixed_batched_kernel(
     const SymArgs* __restrict__ probs, const int32_t* __restrict__ work, int n_work,
     int* counter) {
   __shared__ sym::Shared<Mixed> sh;
-  sym::batched<Mixed>(probs, work, n_work, counter, sh);
+  sym::batched(probs, work, n_work, counter,
+               [&](const SymArgs& a, int rb, int cb) { sym::item<Mixed>(a, rb, cb, sh); });
 }
 
 
