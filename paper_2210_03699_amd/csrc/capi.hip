@@ -590,10 +590,9 @@ int ctx_setup_device(ibim_ctx* c, hipStream_t s) {
     std::vector<uint32_t> bits;
     sym_careful_bits(c->sym.T, xrow, xtile, &bits);
     c->n_sym_items = (int)(items.size() / 2);
-    // flops: 68 per shared evaluation (66 in float64 in Debye units), 60 per
-    // one-way pair (diagonal, careful, ragged)
-    const double shared =
-        o.precision == IBIM_FP64 && sym_debye_units(c->kappa) ? 66.0 : 68.0;
+    // flops: 68 per shared evaluation (66 in Debye units), 60 per one-way
+    // pair (diagonal, careful, ragged)
+    const double shared = sym_debye_units(c->kappa) ? 66.0 : 68.0;
     const int T = c->sym.T;
     auto nodes = [&](int X) { return (double)std::min(kPairTile, M - X * kPairTile); };
     double fl = 0.0;

@@ -105,6 +105,9 @@ __device__ __forceinline__ void pair_f32(float x, float y, float z, float nxk, f
 // m's amplitudes (am1, am2); (c1, c2): contribution to m from k with k's
 // amplitudes (ak1, ak2).  With r' = -r the reverse pair has r'.n_k = -r.n_m
 // and r'.n_m = -r.n_k.  Every operation explicit, as in pair_f32.
+// kUnit: lengths in units of the Debye length 1/kappa (kappa = 1 in the
+// formulas, which saves two multiplications).
+template <bool kUnit = false>
 __device__ __forceinline__ void pair_f32_sym(float xk, float yk, float zk, float nxk, float nyk,
                                              float nzk, float ak1, float ak2, float xm, float ym,
                                              float zm, float nxm, float nym, float nzm, float am1,
@@ -116,7 +119,7 @@ __device__ __forceinline__ void pair_f32_sym(float xk, float yk, float zk, float
   const float R = R2 * iR;
   const float iR2 = iR * iR;
   const float iR3 = iR2 * iR;
-  const float kr = c.kappa * R;
+  const float kr = kUnit ? R : c.kappa * R;
   const float e = exp_neg_f32(kr);
   const float rny = __fmaf_rn(rz, nzm, __fmaf_rn(ry, nym, rx * nxm));
   const float rnx = __fmaf_rn(rz, nzk, __fmaf_rn(ry, nyk, rx * nxk));
@@ -130,7 +133,8 @@ __device__ __forceinline__ void pair_f32_sym(float xk, float yk, float zk, float
   const float f2 = __fmaf_rn(-c.c2, t3, iR3);
   const float g12 = __fmaf_rn(-e, iR, iR);
   const float q = rnx * rny;
-  const float g21 = __fmaf_rn(nn, u, q * __fmaf_rn(u * iR2, -3.0f, c.kappa2 * eiR3));
+  const float k2e = kUnit ? eiR3 : c.kappa2 * eiR3;
+  const float g21 = __fmaf_rn(nn, u, q * __fmaf_rn(u * iR2, -3.0f, k2e));
   const float g11 = rny * f1, g22 = rnx * f2;
   d1 = __fmaf_rn(g11, am1, -(g12 * am2));
   d2 = __fmaf_rn(g21, am1, g22 * am2);

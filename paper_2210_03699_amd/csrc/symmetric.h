@@ -148,8 +148,7 @@ struct SymMixedFinishArgs {
   const double *px, *py, *pz, *nx, *ny, *nz, *w;
   const float *fx, *fy, *fz, *fnx, *fny, *fnz;
   const uint32_t* careful;
-  PairConsts c64;
-  PairConstsF c32;
+  PairConsts c64;  // float64 constants (the float32 ones are derived from them)
   double scale;
   int32_t M;
   int T, b, nCB, rows;

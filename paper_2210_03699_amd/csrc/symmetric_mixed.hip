@@ -1,6 +1,7 @@
 // Mixed-precision form of the symmetric pair sum: float32 pair evaluations
-// (geometry relative to the node centroid), float64 row and column sums, on
-// the schedule of symmetric.hip.  The finishing kernel adds, for every near
+// (geometry relative to the node centroid, in units of the Debye length when
+// kappa > 0, as in the float64 kernel), float64 row and column sums, on the
+// schedule of symmetric.hip.  The finishing kernel adds, for every near
 // pair (R < r_near), its float64 value minus the float32 value the pair
 // kernel summed; the latter is recomputed by the same device function with
 // the same operands (forward when the target's tile is the row tile of the
@@ -23,22 +24,51 @@ namespace {
 
 constexpr int kT = kPairTile;
 
+// Values of node m's float32 record: with kUnit (kappa > 0) in units of the
+// Debye length (positions times kappa, w u1 times kappa^2, w u2 times kappa;
+// the second row of sums then comes out divided by kappa), as in the float64
+// kernel.  The finishing kernel forms the same values with these functions.
+template <bool kUnit>
+__device__ __forceinline__ float mixed_pos(float v, double kappa) {
+  return kUnit ? (float)kappa * v : v;
+}
+template <bool kUnit>
+__device__ __forceinline__ float mixed_q1(double wm, double u, double kappa) {
+  return (float)(kUnit ? (wm * (kappa * kappa)) * u : wm * u);
+}
+template <bool kUnit>
+__device__ __forceinline__ float mixed_q2(double wm, double u, double kappa) {
+  return (float)(kUnit ? (wm * kappa) * u : wm * u);
+}
+template <bool kUnit>
+__device__ __forceinline__ PairConstsF mixed_consts(double c1, double c2, double kappa) {
+  return PairConstsF{(float)c1, (float)c2, kUnit ? 1.0f : (float)kappa,
+                     kUnit ? 1.0f : (float)(kappa * kappa)};
+}
+
+struct MixedRec {
+  float px, py, pz, nx, ny, nz, a1, a2;
+};
+struct MixedLds {
+  float4 A[sym::kSlots], B[sym::kSlots];  // (px,py,pz,nx) (ny,nz,a1,a2) per LDS slot
+};
+
+template <bool kUnit>
 struct Mixed {
-  struct Rec {
-    float px, py, pz, nx, ny, nz, a1, a2;
-  };
-  struct Lds {
-    float4 A[sym::kSlots], B[sym::kSlots];  // (px,py,pz,nx) (ny,nz,a1,a2) per LDS slot
-  };
+  using Rec = MixedRec;
+  using Lds = MixedLds;
   using Consts = PairConstsF;
   static __device__ __forceinline__ Consts consts(const SymArgs& a) {
-    return PairConstsF{(float)a.c1, (float)a.c2, (float)a.kappa, (float)(a.kappa * a.kappa)};
+    return mixed_consts<kUnit>(a.c1, a.c2, a.kappa);
   }
-  static __device__ __forceinline__ double scale2(const SymArgs& a) { return a.scale; }
+  static __device__ __forceinline__ double scale2(const SymArgs& a) {
+    return kUnit ? a.scale * a.kappa : a.scale;
+  }
   static __device__ __forceinline__ Rec load(const SymArgs& a, int32_t m) {
-    const double wm = a.w[m];
-    return Rec{a.fx[m], a.fy[m], a.fz[m], a.fnx[m], a.fny[m], a.fnz[m], (float)(wm * a.u[m]),
-               (float)(wm * a.u[a.M + m])};
+    const double wm = a.w[m], k = a.kappa;
+    return Rec{mixed_pos<kUnit>(a.fx[m], k), mixed_pos<kUnit>(a.fy[m], k),
+               mixed_pos<kUnit>(a.fz[m], k), a.fnx[m], a.fny[m], a.fnz[m],
+               mixed_q1<kUnit>(wm, a.u[m], k), mixed_q2<kUnit>(wm, a.u[a.M + m], k)};
   }
   static __device__ __forceinline__ void store(Lds& s, int i, const Rec& r) {
     s.A[i] = make_float4(r.px, r.py, r.pz, r.nx);
@@ -61,8 +91,8 @@ struct Mixed {
   static __device__ __forceinline__ void both(const Rec& f, const Rec& m, const Consts& pc,
                                               double& S1, double& S2, double& C1, double& C2) {
     float d1, d2, c1, c2;
-    pair_f32_sym(f.px, f.py, f.pz, f.nx, f.ny, f.nz, f.a1, f.a2, m.px, m.py, m.pz, m.nx, m.ny,
-                 m.nz, m.a1, m.a2, pc, d1, d2, c1, c2);
+    pair_f32_sym<kUnit>(f.px, f.py, f.pz, f.nx, f.ny, f.nz, f.a1, f.a2, m.px, m.py, m.pz, m.nx,
+                        m.ny, m.nz, m.a1, m.a2, pc, d1, d2, c1, c2);
     S1 += (double)d1;
     S2 += (double)d2;
     C1 = kAcc ? C1 + (double)c1 : (double)c1;
@@ -70,18 +100,23 @@ struct Mixed {
   }
 };
 
+template <bool kUnit>
 __global__ __launch_bounds__(256) void pair_sym_mixed_kernel(SymArgs a) {
-  __shared__ sym::Shared<Mixed> sh;
+  __shared__ sym::Shared<Mixed<kUnit>> sh;
   const int2 it = a.items[blockIdx.x];
-  sym::item<Mixed>(a, it.x, it.y, sh);
+  sym::item<Mixed<kUnit>>(a, it.x, it.y, sh);
 }
 
 __global__ __launch_bounds__(256, 4) void pair_sym_mixed_batched_kernel(
     const SymArgs* __restrict__ probs, const int32_t* __restrict__ work, int n_work,
     int* counter) {
-  __shared__ sym::Shared<Mixed> sh;
-  sym::batched(probs, work, n_work, counter,
-               [&](const SymArgs& a, int rb, int cb) { sym::item<Mixed>(a, rb, cb, sh); });
+  __shared__ sym::Shared<Mixed<true>> sh;  // one layout for both policies
+  sym::batched(probs, work, n_work, counter, [&](const SymArgs& a, int rb, int cb) {
+    if (sym_debye_units(a.kappa))
+      sym::item<Mixed<true>>(a, rb, cb, sh);
+    else
+      sym::item<Mixed<false>>(a, rb, cb, sh);
+  });
 }
 
 
@@ -92,6 +127,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // One wave per row k: partial sums, sparse corrections and near-pair fix-ups
 // are spread over the lanes in a fixed assignment and reduced in a fixed tree.
+template <bool kUnit>
 __device__ __forceinline__ void finish_sym_mixed_row(const SymMixedFinishArgs& a, int32_t k,
                                                      int lane, bool unscale) {
   const int32_t M = a.M;
@@ -115,10 +151,13 @@ __device__ __forceinline__ void finish_sym_mixed_row(const SymMixedFinishArgs& a
   // near pairs
   const double x = a.px[k], y = a.py[k], z = a.pz[k];
   const double nxk = a.nx[k], nyk = a.ny[k], nzk = a.nz[k];
-  const float fx = a.fx[k], fy = a.fy[k], fz = a.fz[k];
+  const double kap = a.c64.kappa;
+  const PairConstsF c32 = mixed_consts<kUnit>(a.c64.c1, a.c64.c2, kap);
+  const float fx = mixed_pos<kUnit>(a.fx[k], kap), fy = mixed_pos<kUnit>(a.fy[k], kap);
+  const float fz = mixed_pos<kUnit>(a.fz[k], kap);
   const float fnx = a.fnx[k], fny = a.fny[k], fnz = a.fnz[k];
   const double wk = a.w[k];
-  const float ak1 = (float)(wk * a.u[k]), ak2 = (float)(wk * a.u[M + k]);
+  const float ak1 = mixed_q1<kUnit>(wk, a.u[k], kap), ak2 = mixed_q2<kUnit>(wk, a.u[M + k], kap);
   const bool ragged = M % kT != 0;
   double f1 = 0.0, f2 = 0.0;
   for (int64_t e = a.nrow[k] + lane; e < a.nrow[k + 1]; e += 64) {
@@ -129,26 +168,28 @@ __device__ __forceinline__ void finish_sym_mixed_row(const SymMixedFinishArgs& a
     double d1, d2;
     pair_f64<false>(x, y, z, nxk, nyk, nzk, a.px[m], a.py[m], a.pz[m], a.nx[m], a.ny[m], a.nz[m],
                     a1, a2, a.c64, d1, d2);
-    const float am1 = (float)a1, am2 = (float)a2;
-    const float mx = a.fx[m], my = a.fy[m], mz = a.fz[m];
+    const float am1 = mixed_q1<kUnit>(wm, a.u[m], kap), am2 = mixed_q2<kUnit>(wm, a.u[M + m], kap);
+    const float mx = mixed_pos<kUnit>(a.fx[m], kap), my = mixed_pos<kUnit>(a.fy[m], kap);
+    const float mz = mixed_pos<kUnit>(a.fz[m], kap);
     const float mnx = a.fnx[m], mny = a.fny[m], mnz = a.fnz[m];
     float e1, e2;
     const int lo = X < Y ? X : Y, hi = X < Y ? Y : X;
     const int64_t bit = (int64_t)lo * T + hi;
     const bool careful = (a.careful[bit >> 5] >> (bit & 31)) & 1u;
     if (X == Y || careful || (ragged && hi == T - 1)) {
-      pair_f32(fx, fy, fz, fnx, fny, fnz, mx, my, mz, mnx, mny, mnz, am1, am2, a.c32, e1, e2);
+      pair_f32(fx, fy, fz, fnx, fny, fnz, mx, my, mz, mnx, mny, mnz, am1, am2, c32, e1, e2);
     } else if (X < Y) {
       float c1, c2;
-      pair_f32_sym(fx, fy, fz, fnx, fny, fnz, ak1, ak2, mx, my, mz, mnx, mny, mnz, am1, am2,
-                   a.c32, e1, e2, c1, c2);
+      pair_f32_sym<kUnit>(fx, fy, fz, fnx, fny, fnz, ak1, ak2, mx, my, mz, mnx, mny, mnz, am1,
+                          am2, c32, e1, e2, c1, c2);
     } else {
       float d1f, d2f;
-      pair_f32_sym(mx, my, mz, mnx, mny, mnz, am1, am2, fx, fy, fz, fnx, fny, fnz, ak1, ak2,
-                   a.c32, d1f, d2f, e1, e2);
+      pair_f32_sym<kUnit>(mx, my, mz, mnx, mny, mnz, am1, am2, fx, fy, fz, fnx, fny, fnz, ak1,
+                          ak2, c32, d1f, d2f, e1, e2);
     }
+    // the pair kernel's second row carries the factor kappa at write-out
     f1 += d1 - (double)e1;
-    f2 += d2 - (double)e2;
+    f2 += kUnit ? d2 - kap * (double)e2 : d2 - (double)e2;
   }
   p1 = wave_sum(p1);
   p2 = wave_sum(p2);
@@ -170,7 +211,10 @@ __global__ __launch_bounds__(256) void finish_sym_mixed_kernel(SymMixedFinishArg
   const int lane = threadIdx.x & 63;
   const int32_t k = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (k >= a.M) return;  // uniform in the wave
-  finish_sym_mixed_row(a, k, lane, false);
+  if (sym_debye_units(a.c64.kappa))
+    finish_sym_mixed_row<true>(a, k, lane, false);
+  else
+    finish_sym_mixed_row<false>(a, k, lane, false);
 }
 
 // Several problems: the block's problem is the last one whose blk0 <= block.
@@ -185,13 +229,21 @@ __global__ __launch_bounds__(256) void finish_sym_mixed_batched_kernel(
   const SymMixedFinishArgs& a = fa[lo];
   const int64_t k = (blk - a.blk0) * 4 + (threadIdx.x >> 6);
   if (k >= a.M) return;  // uniform in the wave
-  finish_sym_mixed_row(a, (int32_t)k, threadIdx.x & 63, unscale != 0);
+  if (sym_debye_units(a.c64.kappa))
+    finish_sym_mixed_row<true>(a, (int32_t)k, threadIdx.x & 63, unscale != 0);
+  else
+    finish_sym_mixed_row<false>(a, (int32_t)k, threadIdx.x & 63, unscale != 0);
 }
 
 }  // namespace
 
 hipError_t launch_pair_sym_mixed(const SymArgs& a, int n_items, hipStream_t stream) {
-  hipLaunchKernelGGL(pair_sym_mixed_kernel, dim3((unsigned)n_items), dim3(256), 0, stream, a);
+  if (sym_debye_units(a.kappa))
+    hipLaunchKernelGGL(pair_sym_mixed_kernel<true>, dim3((unsigned)n_items), dim3(256), 0, stream,
+                       a);
+  else
+    hipLaunchKernelGGL(pair_sym_mixed_kernel<false>, dim3((unsigned)n_items), dim3(256), 0,
+                       stream, a);
   return hipGetLastError();
 }
 
@@ -232,8 +284,6 @@ SymMixedFinishArgs make_finish_sym_mixed_args(const DeviceProblem& P, const SymP
   f.fnx = P.nx32; f.fny = P.ny32; f.fnz = P.nz32;
   f.careful = careful;
   f.c64 = PairConsts{P.eps_out / P.eps_in, P.eps_in / P.eps_out, P.kappa, P.kappa * P.kappa};
-  f.c32 = PairConstsF{(float)(P.eps_out / P.eps_in), (float)(P.eps_in / P.eps_out),
-                      (float)P.kappa, (float)(P.kappa * P.kappa)};
   f.scale = P.h * P.h * P.h / (4.0 * 3.14159265358979323846);
   f.M = P.M;
   f.T = pl.T;
