@@ -585,10 +585,10 @@ int ctx_setup_device(ibim_ctx* c, hipStream_t s) {
     }
   }
   if (c->sym.enabled) {
-    std::vector<int32_t> items;
-    sym_items(c->sym, &items);
     std::vector<uint32_t> bits;
     sym_careful_bits(c->sym.T, xrow, xtile, &bits);
+    std::vector<int32_t> items;
+    sym_items(c->sym, bits, M % kPairTile != 0, &items);
     c->n_sym_items = (int)(items.size() / 2);
     // flops: 68 per shared evaluation (66 in Debye units), 60 per one-way
     // pair (diagonal, careful, ragged)

@@ -82,8 +82,12 @@ struct SymArgs {
 // Plan for M nodes; disabled when the scratch would exceed max_scratch_bytes
 // (the one-directional kernel is used then).
 SymPlan make_sym_plan(int32_t M, size_t max_scratch_bytes);
-// Work items as (rb, cb) pairs, larger first.
-void sym_items(const SymPlan& pl, std::vector<int32_t>* items);
+// Work items as (rb, cb) pairs in launch order: the costliest first (those
+// holding tile pairs of the careful bit matrix, see sym_careful_bits, or of
+// the ragged last tile), then the plain ones arranged so that the items an
+// XCD runs at once (item i runs on XCD i mod 8) share row and column tiles.
+void sym_items(const SymPlan& pl, const std::vector<uint32_t>& careful, bool ragged,
+               std::vector<int32_t>* items);
 // Bit matrix of tile pairs that need the exclusion-aware evaluation.
 void sym_careful_bits(int T, const std::vector<int32_t>& xrow, const std::vector<int32_t>& xtile,
                       std::vector<uint32_t>* bits);

@@ -263,25 +263,68 @@ SymPlan make_sym_plan(int32_t M, size_t max_scratch_bytes) {
   return pl;
 }
 
-void sym_items(const SymPlan& pl, std::vector<int32_t>* items) {
+void sym_items(const SymPlan& pl, const std::vector<uint32_t>& careful, bool ragged,
+               std::vector<int32_t>* items) {
+  // Workgroups start in launch order, so the costliest items go first: a
+  // tile pair holding a corrected pair, or one with the ragged last tile, is
+  // evaluated one direction at a time with a global-memory pass for the
+  // reverse direction (weighted 4 here), a diagonal tile pair one direction
+  // only (1.25), a plain tile pair both ways at once (1).  Items of the plain
+  // full cost follow, arranged for the L2 of the XCDs: workgroup i runs on
+  // XCD i mod kXcds and each XCD has its own L2, while an item (rb, cb)
+  // stages the b column tiles of cb one after another and reloads its
+  // `rows` row tiles for each; listed in blocks of kBR row blocks x kBC
+  // column blocks, with each XCD taking a contiguous stretch of that list,
+  // the ~100 items an XCD runs at once share their row and column tiles.
+  // The cheaper (partial) items come last, costliest first.
+  constexpr int kXcds = 8, kBR = 16, kBC = 8;
+  constexpr int kPlain = 4, kDiag = 5, kSlow = 16;  // costs of a tile pair, in quarters
   struct It {
-    int rb, cb, pairs;
+    int rb, cb;
+    int64_t cost;
   };
-  std::vector<It> v;
-  for (int rb = 0; rb < pl.nRB; ++rb)
-    for (int cb = (rb * pl.rows) / pl.b; cb < pl.nCB; ++cb) {
-      int pairs = 0;
-      for (int I = rb * pl.rows; I < std::min(rb * pl.rows + pl.rows, pl.T); ++I)
-        for (int J = cb * pl.b; J < std::min(cb * pl.b + pl.b, pl.T); ++J) pairs += I <= J;
-      if (pairs > 0) v.push_back({rb, cb, pairs});
-    }
-  // larger items first (they are dispatched first), ties in index order
-  std::stable_sort(v.begin(), v.end(), [](const It& x, const It& y) { return x.pairs > y.pairs; });
+  auto cost_of = [&](int rb, int cb) {
+    int64_t c = 0;
+    for (int I = rb * pl.rows; I < std::min(rb * pl.rows + pl.rows, pl.T); ++I)
+      for (int J = std::max(I, cb * pl.b); J < std::min(cb * pl.b + pl.b, pl.T); ++J) {
+        const size_t bit = (size_t)I * pl.T + J;
+        const bool slow = ((careful[bit >> 5] >> (bit & 31)) & 1u) || (ragged && J == pl.T - 1);
+        c += I == J ? kDiag : slow ? kSlow : kPlain;
+      }
+    return c;
+  };
+  const int64_t plain_full = (int64_t)kPlain * pl.rows * pl.b;
+  std::vector<It> costly, whole, rest;
+  for (int rb0 = 0; rb0 < pl.nRB; rb0 += kBR)
+    for (int cb0 = 0; cb0 < pl.nCB; cb0 += kBC)
+      for (int rb = rb0; rb < std::min(rb0 + kBR, pl.nRB); ++rb)
+        for (int cb = std::max(cb0, (rb * pl.rows) / pl.b); cb < std::min(cb0 + kBC, pl.nCB);
+             ++cb) {
+          const int64_t c = cost_of(rb, cb);
+          if (c == 0) continue;
+          (c > plain_full ? costly : c == plain_full ? whole : rest).push_back({rb, cb, c});
+        }
+  auto by_cost = [](const It& x, const It& y) { return x.cost > y.cost; };
+  std::stable_sort(costly.begin(), costly.end(), by_cost);
+  std::stable_sort(rest.begin(), rest.end(), by_cost);
   items->clear();
-  for (const It& it : v) {
+  auto put = [&](const It& it) {
     items->push_back(it.rb);
     items->push_back(it.cb);
+  };
+  for (const It& it : costly) put(it);
+  // plain items: XCD x takes the x-th contiguous stretch, each item at the
+  // next position that runs on x (another XCD's when x has run out)
+  const size_t F = whole.size();
+  std::vector<size_t> at(kXcds + 1, 0), next(kXcds);
+  for (int x = 0; x < kXcds; ++x) at[x + 1] = at[x] + F / kXcds + ((size_t)x < F % kXcds);
+  for (int x = 0; x < kXcds; ++x) next[x] = at[x];
+  for (size_t q = 0; q < F; ++q) {
+    int x = (int)((items->size() / 2) % kXcds);
+    for (int t = 0; next[x] == at[x + 1] && t < kXcds; ++t) x = (x + 1) % kXcds;
+    put(whole[next[x]++]);
   }
+  for (const It& it : rest) put(it);
 }
 
 void sym_careful_bits(int T, const std::vector<int32_t>& xrow, const std::vector<int32_t>& xtile,
