@@ -529,7 +529,7 @@ def main():
             "achieved": performed_flops / (avg_pair_ms * 1e-3) / 1e12,
             "frac": performed_flops / (avg_pair_ms * 1e-3) / 1e12 / peak,
             "flop_count": "as evaluated: 68 per shared evaluation of both directions of a pair "
-                          "(66 with kappa > 0, in Debye units), "
+                          "(66 in Debye units), "
                           "60 per one-directional pair (diagonal, corrected and ragged tiles)"},
         "valu_counter": None if prof is None else {
             "flops_per_launch": prof["valu_flops"],

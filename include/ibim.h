@@ -311,9 +311,10 @@ int ibim_pair_timing_read(ibim_ctx* ctx, int64_t* launches, double* total_ms);
  * floating-point operations of the pair formulas (FMA counted as 2, exp and
  * rsqrt not counted): 60 per ordered pair when each pair is evaluated on its
  * own, 68 per unordered pair when both directions share one evaluation (the
- * symmetric kernels; 66 with kappa > 0, where they evaluate pairs in units
- * of the Debye length and so need no kappa factors; tile pairs holding corrected pairs and the diagonal
- * tiles are still evaluated one direction at a time).  In the mixed form
+ * symmetric kernels; 66 when they evaluate pairs in units of the Debye
+ * length and so need no kappa factors: float64 with kappa > 1e-30, the
+ * mixed form with kappa h >= 1e-6; tile pairs holding corrected pairs and
+ * the diagonal tiles are still evaluated one direction at a time).  In the mixed form
  * these are float32 operations.  For IBIM_SUM_TREE, *pairs is still M^2 (the
  * pairs the sum stands for) and *flops counts what the treecode performs: 60
  * per direct pair, 36 per target-proxy evaluation, 15 per source-proxy term

@@ -592,7 +592,9 @@ int ctx_setup_device(ibim_ctx* c, hipStream_t s) {
     c->n_sym_items = (int)(items.size() / 2);
     // flops: 68 per shared evaluation (66 in Debye units), 60 per one-way
     // pair (diagonal, careful, ragged)
-    const double shared = sym_debye_units(c->kappa) ? 66.0 : 68.0;
+    const bool unit = o.precision == IBIM_MIXED ? sym_debye_units_f32(c->kappa, P.h)
+                                                : sym_debye_units(c->kappa);
+    const double shared = unit ? 66.0 : 68.0;
     const int T = c->sym.T;
     auto nodes = [&](int X) { return (double)std::min(kPairTile, M - X * kPairTile); };
     double fl = 0.0;

@@ -22,11 +22,15 @@ constexpr size_t kSymScratchMax = size_t(32) << 30;
 // pair distance (the diagonal of their nodes' bounding box) times kappa is
 // larger use the one-directional float64 kernel.
 constexpr double kSymMaxKappaR = 708.0;
-// The float64 symmetric kernel evaluates pairs in units of the Debye length
-// 1/kappa when kappa is above this (below it R^-3 in those units could
-// overflow); otherwise kappa enters every pair.
-constexpr double kSymUnitMinKappa = 1e-30;
-__host__ __device__ inline bool sym_debye_units(double kappa) { return kappa > kSymUnitMinKappa; }
+// The symmetric kernels evaluate pairs in units of the Debye length 1/kappa
+// when kappa is large enough for those units to stay in range; otherwise
+// kappa enters every pair.  float64: kappa above 1e-30 (below it R^-3 in
+// those units could overflow).  float32 (mixed form): kappa h at least 1e-6,
+// so that kappa^2 w u and (kappa R)^-3 stay far inside the float32 range.
+__host__ __device__ inline bool sym_debye_units(double kappa) { return kappa > 1e-30; }
+__host__ __device__ inline bool sym_debye_units_f32(double kappa, double h) {
+  return kappa * h >= 1e-6;
+}
 
 // Column-sum slot of (row block rb, column tile J), rb <= J / rows, for row
 // blocks of `rows` tiles: the slots of tile J follow those of tiles 0 .. J-1
@@ -73,6 +77,7 @@ struct SymArgs {
   int T;
   int b;
   int rows;  // row tiles per item
+  int unit32;  // the mixed kernel works in Debye units (sym_debye_units_f32)
   double c1, c2, kappa;
   double scale;       // h^3 / (4 pi)
   double* rowpart;    // [sym_row_slot(cb, I, b, nCB)][2][256]
@@ -153,6 +158,7 @@ struct SymMixedFinishArgs {
   const float *fx, *fy, *fz, *fnx, *fny, *fnz;
   const uint32_t* careful;
   PairConsts c64;  // float64 constants (the float32 ones are derived from them)
+  int unit32;      // as SymArgs::unit32: the float32 values are in Debye units
   double scale;
   int32_t M;
   int T, b, nCB, rows;

@@ -362,6 +362,7 @@ SymArgs make_sym_args(const DeviceProblem& P, const SymPlan& pl, const int32_t* 
   a.c1 = P.eps_out / P.eps_in;
   a.c2 = P.eps_in / P.eps_out;
   a.kappa = P.kappa;
+  a.unit32 = sym_debye_units_f32(P.kappa, P.h) ? 1 : 0;
   a.scale = P.h * P.h * P.h / (4.0 * kPiD);
   a.rowpart = scratch;
   a.colpart = scratch + sym_row_slots_total(pl.T, pl.b, pl.nCB) * 2 * kT;

@@ -1,6 +1,6 @@
 // Mixed-precision form of the symmetric pair sum: float32 pair evaluations
 // (geometry relative to the node centroid, in units of the Debye length when
-// kappa > 0, as in the float64 kernel), float64 row and column sums, on the
+// kappa h >= 1e-6, see sym_debye_units_f32), float64 row and column sums, on the
 // schedule of symmetric.hip.  The finishing kernel adds, for every near
 // pair (R < r_near), its float64 value minus the float32 value the pair
 // kernel summed; the latter is recomputed by the same device function with
@@ -24,7 +24,7 @@ namespace {
 
 constexpr int kT = kPairTile;
 
-// Values of node m's float32 record: with kUnit (kappa > 0) in units of the
+// Values of node m's float32 record: with kUnit (SymArgs::unit32) in units of the
 // Debye length (positions times kappa, w u1 times kappa^2, w u2 times kappa;
 // the second row of sums then comes out divided by kappa), as in the float64
 // kernel.  The finishing kernel forms the same values with these functions.
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(256, 4) void pair_sym_mixed_batched_kernel(
     int* counter) {
   __shared__ sym::Shared<Mixed<true>> sh;  // one layout for both policies
   sym::batched(probs, work, n_work, counter, [&](const SymArgs& a, int rb, int cb) {
-    if (sym_debye_units(a.kappa))
+    if (a.unit32)
       sym::item<Mixed<true>>(a, rb, cb, sh);
     else
       sym::item<Mixed<false>>(a, rb, cb, sh);
@@ -211,7 +211,7 @@ __global__ __launch_bounds__(256) void finish_sym_mixed_kernel(SymMixedFinishArg
   const int lane = threadIdx.x & 63;
   const int32_t k = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (k >= a.M) return;  // uniform in the wave
-  if (sym_debye_units(a.c64.kappa))
+  if (a.unit32)
     finish_sym_mixed_row<true>(a, k, lane, false);
   else
     finish_sym_mixed_row<false>(a, k, lane, false);
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(256) void finish_sym_mixed_batched_kernel(
   const SymMixedFinishArgs& a = fa[lo];
   const int64_t k = (blk - a.blk0) * 4 + (threadIdx.x >> 6);
   if (k >= a.M) return;  // uniform in the wave
-  if (sym_debye_units(a.c64.kappa))
+  if (a.unit32)
     finish_sym_mixed_row<true>(a, (int32_t)k, threadIdx.x & 63, unscale != 0);
   else
     finish_sym_mixed_row<false>(a, (int32_t)k, threadIdx.x & 63, unscale != 0);
@@ -238,7 +238,7 @@ __global__ __launch_bounds__(256) void finish_sym_mixed_batched_kernel(
 }  // namespace
 
 hipError_t launch_pair_sym_mixed(const SymArgs& a, int n_items, hipStream_t stream) {
-  if (sym_debye_units(a.kappa))
+  if (a.unit32)
     hipLaunchKernelGGL(pair_sym_mixed_kernel<true>, dim3((unsigned)n_items), dim3(256), 0, stream,
                        a);
   else
@@ -284,6 +284,7 @@ SymMixedFinishArgs make_finish_sym_mixed_args(const DeviceProblem& P, const SymP
   f.fnx = P.nx32; f.fny = P.ny32; f.fnz = P.nz32;
   f.careful = careful;
   f.c64 = PairConsts{P.eps_out / P.eps_in, P.eps_in / P.eps_out, P.kappa, P.kappa * P.kappa};
+  f.unit32 = sym_debye_units_f32(P.kappa, P.h) ? 1 : 0;
   f.scale = P.h * P.h * P.h / (4.0 * 3.14159265358979323846);
   f.M = P.M;
   f.T = pl.T;

@@ -173,6 +173,29 @@ def test_one_directional_solve_matches_oracle(name):
     prob.close()
 
 
+@pytest.mark.parametrize("kappa", [1e-9, 1e-3])
+@pytest.mark.parametrize("precision, bar", [(ibim.FP64, 1e-12), (ibim.MIXED, 1e-6)])
+def test_weak_screening_apply_matches_oracle(kappa, precision, bar):
+    """The symmetric kernels evaluate pairs in units of the Debye length 1/kappa
+    when those units stay in range: float64 for kappa > 1e-30, float32 (the
+    mixed form) for kappa h >= 1e-6.  At h = 0.25, kappa = 1e-9 runs the
+    float64 kernel in Debye units (positions ~1e-9, kappa^2 w u ~1e-21) and the
+    mixed kernel in plain units; kappa = 1e-3 runs both in Debye units.  Each
+    is held to the oracle at its precision's bar."""
+    wl = workloads.born_sphere(h=0.25, radius=1.7, offset=(0.37, 0.11, -0.23), kappa=kappa)
+    prob = ibim.Problem.from_workload(wl, device=0, precision=precision)
+    orc = oracle.Oracle.from_workload(wl)
+    u = workloads.random_vector(2 * prob.M, 13)
+    out = prob.apply(torch.from_numpy(u).to(DEV)).cpu().numpy()
+    err = _blockwise_rel(out, orc.apply(u), prob.M)
+    pairs, flops = prob.pair_work()
+    _say(f"[kappa={kappa} precision={precision}] apply rel err {err:.3e} "
+         f"flops/pair {flops / pairs:.2f}")
+    assert np.all(np.isfinite(out))
+    assert err < bar, err
+    prob.close()
+
+
 @pytest.mark.parametrize("kappa, symmetric", [(100.0, True), (150.0, False)])
 def test_extreme_screening_apply_matches_oracle(kappa, symmetric):
     """The float64 symmetric kernel's table exponential takes kappa R up to 708
