@@ -72,7 +72,7 @@ struct SymArgs {
   const int32_t* crow;
   const int32_t* ccol;
   const uint32_t* careful;  // bit I*T + J: tile pair (I, J) holds a pair of N_k (either way)
-  const int2* items;        // (row block, column block), larger items first
+  const int2* items;        // (row block, column block) in launch order (sym_items)
   int32_t M;
   int T;
   int b;
