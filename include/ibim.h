@@ -94,8 +94,10 @@ typedef struct {
  *                   with the pairs of N_k skipped by index as in the direct
  *                   path.  A cluster is far when (r_batch + r_cluster) <
  *                   tree_theta * distance of the box centres, it holds more
- *                   than tree_order^3 nodes and the box gap exceeds the largest
- *                   corrected-pair distance.  An approximation: its error falls
+ *                   than c tree_order^3 nodes and the box gap exceeds the
+ *                   largest corrected-pair distance; c is the cost of a
+ *                   target-proxy evaluation in direct pairs: 0.44 with
+ *                   IBIM_FP64, 0.26 with IBIM_MIXED.  An approximation: its error falls
  *                   geometrically with tree_order and with smaller tree_theta.
  *                   With IBIM_FP64 all of it is float64; with IBIM_MIXED the
  *                   target-proxy evaluations run in float32 (on float64-formed

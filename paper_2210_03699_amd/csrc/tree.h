@@ -19,7 +19,16 @@ constexpr int kTreeMaxOrder = 12;
 struct TreeParams {
   int order = 8;        // Chebyshev points per dimension (degree order - 1)
   double theta = 0.7;   // separation: (r_batch + r_cluster) < theta * distance
+  // cost of one target-proxy evaluation in direct pairs: a separated
+  // cluster is summed through its order^3 proxies when it holds more than
+  // proxy_cost * order^3 nodes (kTreeProxyCost64 or kTreeProxyCost32)
+  double proxy_cost = 0.44;
 };
+// Measured VALU instructions of a target-proxy evaluation over those of a
+// direct pair (N_k skip included): float64 33 / 75, the mixed form (float32
+// proxies and direct pairs on float64-formed differences) 16 / 62.
+constexpr double kTreeProxyCost64 = 0.44;
+constexpr double kTreeProxyCost32 = 0.26;
 
 // Everything the device needs, in "tree order" (nodes permuted so that every
 // cluster and every batch is a contiguous range).
@@ -31,8 +40,9 @@ struct TreePlan {
   std::vector<int32_t> pos;   // node -> tree position
   // batches: target ranges [bstart[b], bstart[b + 1])
   std::vector<int32_t> bstart;
-  // clusters with proxies (every cluster with more nodes than proxies, in
-  // tree preorder): source range, bounding box (lo x, y, z, hi x, y, z)
+  // clusters with proxies (every cluster of more than proxy_cost * order^3
+  // nodes, in tree preorder): source range, bounding box (lo x, y, z, hi x,
+  // y, z)
   std::vector<int32_t> pstart, pend;
   std::vector<double> pbox;
   // charges of a proxy cluster: from the sources of [dstart, dend) directly

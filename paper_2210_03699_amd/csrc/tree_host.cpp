@@ -5,7 +5,8 @@
 // bounding-box side, the left part taking the nearest multiple of the batch
 // size to half the points, so every leaf (a batch of targets) holds exactly
 // kTreeBatch points except the last one.  A cluster C is approximated for a
-// batch B by its proxies when it has more points than proxies and
+// batch B by its proxies when evaluating them costs less than its points
+// (more than proxy_cost * order^3 points) and
 //   r_B + r_C < theta * d   and   d - r_B - r_C > gap,
 // d the distance of the box centres, r the half diagonals; the second
 // condition keeps every pair (k, m) with m in N_k in the direct part, where it
@@ -123,6 +124,8 @@ int build_tree_plan(const TreeParams& prm, int64_t M64, const double* px, const 
   pl = TreePlan();
   const int32_t M = (int32_t)M64;
   const int n3 = prm.order * prm.order * prm.order;
+  // clusters of more than nfar nodes carry proxies (and can be far)
+  const int nfar = (int)(prm.proxy_cost * n3);
   pl.M = M;
   pl.order = prm.order;
 
@@ -178,9 +181,9 @@ int build_tree_plan(const TreeParams& prm, int64_t M64, const double* px, const 
       const double dx = L.c[0] - C.c[0], dy = L.c[1] - C.c[1], dz = L.c[2] - C.c[2];
       const double d = std::sqrt(dx * dx + dy * dy + dz * dz);
       const bool sep = L.r + C.r < theta * d && d - L.r - C.r > pl.gap;
-      if (sep && C.e - C.s > n3) {
+      if (sep && C.e - C.s > nfar) {
         far[b].push_back(ci);
-      } else if (C.kid[0] < 0 || C.e - C.s <= n3) {
+      } else if (C.kid[0] < 0 || C.e - C.s <= nfar) {
         near[b].push_back({C.s, C.e});
       } else {
         stack.push_back(C.kid[1]);
@@ -200,12 +203,12 @@ int build_tree_plan(const TreeParams& prm, int64_t M64, const double* px, const 
     nr.swap(merged);
   }
 
-  // proxy slots: every cluster with more points than proxies, in preorder
-  // (a parent before its children)
+  // proxy slots: every cluster of more than nfar points, in preorder (a
+  // parent before its children)
   std::vector<int32_t> slot(nd.size(), -1);
   int ns = 0;
   for (size_t ci = 0; ci < nd.size(); ++ci)
-    if (nd[ci].e - nd[ci].s > n3) slot[ci] = ns++;
+    if (nd[ci].e - nd[ci].s > nfar) slot[ci] = ns++;
   pl.kid.assign(2 * (size_t)ns, -1);
   pl.dstart.resize(ns);
   pl.dend.resize(ns);
@@ -279,7 +282,7 @@ int build_tree_plan(const TreeParams& prm, int64_t M64, const double* px, const 
     pl.nrow.push_back((int32_t)pl.nlo.size());
     pl.far_evals += nt * n3 * (double)far[b].size();
     pl.near_evals += nt * ns_near;
-    work[b] = (double)far[b].size() * n3 * 0.8 + ns_near;
+    work[b] = (double)far[b].size() * n3 * prm.proxy_cost + ns_near;
   }
 
   // work items: about kItems in all (at least kMinPart of work per target each)
@@ -287,7 +290,7 @@ int build_tree_plan(const TreeParams& prm, int64_t M64, const double* px, const 
   double total = 0.0;
   for (int b = 0; b < nb; ++b) total += work[b];
   const double part = std::max(kMinPart, total / kItems);
-  const double wfar = (double)n3 * 0.8;  // a proxy evaluation costs ~0.8 direct pairs
+  const double wfar = (double)n3 * prm.proxy_cost;  // one far cluster, in direct pairs
   std::vector<double> iwork;
   pl.istart.assign(1, 0);
   for (int b = 0; b < nb; ++b) {

@@ -14,9 +14,12 @@
 // Q2_p = sum_m a2_m L_p(y_m).  The basis is evaluated in barycentric form and
 // its derivative through the differentiation matrix of the Chebyshev points
 // (l_i' = sum_q l_q D_qi, exact for polynomials of this degree).  Every
-// cluster with more nodes than proxies carries proxies; its charges come
-// from its children's proxies by the exact transfer of bbFMM's upward pass
-// (below) and directly from the sources of children without proxies.
+// cluster of more than proxy_cost * n^3 nodes (tree.h) carries proxies (a
+// target-proxy evaluation costs about a quarter of a direct pair in the
+// mixed form and under half in float64, so proxies pay off below n^3
+// nodes); its charges come from its children's proxies by the exact
+// transfer of bbFMM's upward pass (below) and directly from the sources of
+// children without proxies.
 //
 // One workgroup per work item (part of the lists of a batch of 256 targets,
 // one target per lane) runs through its proxy clusters and then its direct

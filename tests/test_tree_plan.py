@@ -63,25 +63,33 @@ PLAN_CASES = {
     "sphere_theta0.5": (lambda: workloads.kirkwood_sphere(h=0.25, radius=4.0, r_charges=2.0),
                         3, 0.5),
     "ses_hyb": (lambda: workloads.ses_molecule(60, 14.0, 0.35, 2.0, seed=11), 4, 0.8),
+    "sphere_mixed_order8": (lambda: workloads.kirkwood_sphere(h=0.25, radius=6.0, r_charges=2.0),
+                            8, 0.7),
 }
+# cost of a target-proxy evaluation in direct pairs: clusters of more than
+# this times n^3 nodes carry proxies
+PROXY_COST = {ibim.FP64: 0.44, ibim.MIXED: 0.26}
 
 
 @pytest.mark.parametrize("name", list(PLAN_CASES))
 def test_tree_plan_invariants(name):
     """The plan the treecode runs: every batch sees every source exactly once
     (far clusters and direct ranges), far clusters pass the separation test
-    recomputed from the node positions, every pair of N_k is in the direct
+    recomputed from the node positions, clusters with proxies hold more nodes
+    than c n^3 (c the cost of a target-proxy evaluation in direct pairs: 0.44
+    float64, 0.26 mixed), every pair of N_k is in the direct
     part, and each cluster's charges come from its children and its own
     direct sources without overlap."""
     make, order, theta = PLAN_CASES[name]
     wl = make()
     hyb = ibim.HYB if name == "ses_hyb" else ibim.CTR2
+    prec = ibim.MIXED if "mixed" in name else ibim.FP64
     p = ibim.Problem.from_workload(wl, device=-1, summation=ibim.SUM_TREE, tree_order=order,
-                                   tree_theta=theta, hybrid=hyb)
+                                   tree_theta=theta, hybrid=hyb, precision=prec)
     t = p.tree_plan()
     P, _, _ = p.node_geometry()
     c = p.corrections()
-    M, n3 = p.M, order ** 3
+    M, nfar = p.M, int(PROXY_COST[prec] * order ** 3)
     perm, bst = t["perm"], t["bstart"]
     assert np.array_equal(np.sort(perm), np.arange(M))
     pos = np.empty(M, np.int64)
@@ -104,7 +112,7 @@ def test_tree_plan_invariants(name):
             cover[s:e] += 1
             cc, rc = _box(Pt[s:e])
             d = np.linalg.norm(cb - cc)
-            assert e - s > n3 and rb + rc < theta * d and d - rb - rc > t["gap"]
+            assert e - s > nfar and rb + rc < theta * d and d - rb - rc > t["gap"]
             far_total += 1
         near = np.zeros(M, bool)
         for r in range(t["nrow"][b], t["nrow"][b + 1]):
@@ -116,6 +124,7 @@ def test_tree_plan_invariants(name):
             assert np.all(near[pos[c["col"][c["row"][k]:c["row"][k + 1]]]])
     assert far_total > 0  # the cases are large enough to have a far field
     for i, (s, e) in enumerate(cl):
+        assert e - s > nfar
         cover = np.zeros(e - s, np.int32)
         cover[t["dstart"][i] - s:t["dend"][i] - s] += 1
         for q in t["kid"][2 * i:2 * i + 2]:
