@@ -334,6 +334,18 @@ int ibim_pair_work(const ibim_ctx* ctx, double* pairs, double* flops);
 int ibim_tree_counts(const ibim_ctx* ctx, double* out);
 
 /*
+ * Two-way pairs of the treecode plan (IBIM_SUM_TREE contexts, host-only ones
+ * too; IBIM_EINVAL for others).  With IBIM_MIXED, two leaves (batches of
+ * targets, which are also the finest source clusters) that are near each
+ * other both ways and hold no pair of N_k either way are taken out of both
+ * batches' direct ranges (ibim_tree_plan's nlo, nhi) and evaluated once for
+ * both directions; the float64 form has none.  *n (host) receives their
+ * number; lower, upper (host, n int32 each, or NULL) the batches b < b' of
+ * each pair, in order of b, then b'.
+ */
+int ibim_tree_pairs(const ibim_ctx* ctx, int64_t* n, int32_t* lower, int32_t* upper);
+
+/*
  * The treecode plan of an IBIM_SUM_TREE context (host-only contexts too: the
  * plan is built on the host with the geometry), for inspection.  Call once
  * with counts (host, 8 int64) to learn the sizes: [0] M, [1] batches B,

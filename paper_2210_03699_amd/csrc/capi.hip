@@ -365,6 +365,7 @@ int ctx_create_host(const double* sdf, int nx, int ny, int nz, const double orig
     prm.order = o.tree_order;
     prm.theta = o.tree_theta;
     prm.proxy_cost = o.precision == IBIM_MIXED ? kTreeProxyCost32 : kTreeProxyCost64;
+    prm.two_way = o.precision == IBIM_MIXED;
     const HostPlan& pl = c->plan;
     r = build_tree_plan(prm, pl.M, pl.px.data(), pl.py.data(), pl.pz.data(), pl.crow.data(),
                         pl.ccol.data(), h, &c->tplan, &err);
@@ -1044,6 +1045,17 @@ int ibim_tree_plan(const ibim_ctx* ctx, int64_t* counts, int32_t* perm, int32_t*
   put(nlo, t.nlo);
   put(nhi, t.nhi);
   if (gap) *gap = t.gap;
+  return IBIM_OK;
+}
+
+int ibim_tree_pairs(const ibim_ctx* ctx, int64_t* n, int32_t* lower, int32_t* upper) {
+  if (int r = check_ctx(ctx)) return r;
+  if (!n) return fail(IBIM_EINVAL, "NULL count");
+  if (ctx->opt.summation != IBIM_SUM_TREE) return fail(IBIM_EINVAL, "not a treecode context");
+  const ibim::TreePlan& t = ctx->tplan;
+  *n = (int64_t)t.pcol.size();
+  if (lower && !t.pown.empty()) std::memcpy(lower, t.pown.data(), t.pown.size() * sizeof(int32_t));
+  if (upper && !t.pcol.empty()) std::memcpy(upper, t.pcol.data(), t.pcol.size() * sizeof(int32_t));
   return IBIM_OK;
 }
 

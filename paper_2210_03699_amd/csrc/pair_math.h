@@ -107,14 +107,14 @@ __device__ __forceinline__ void pair_f32(float x, float y, float z, float nxk, f
 // and r'.n_m = -r.n_k.  Every operation explicit, as in pair_f32.
 // kUnit: lengths in units of the Debye length 1/kappa (kappa = 1 in the
 // formulas, which saves two multiplications).
+// pair_f32_sym_r takes the difference r = x_k - P_m and its R2 = |r|^2
+// (formed as pair_f32_sym forms them) from the caller.
 template <bool kUnit = false>
-__device__ __forceinline__ void pair_f32_sym(float xk, float yk, float zk, float nxk, float nyk,
-                                             float nzk, float ak1, float ak2, float xm, float ym,
-                                             float zm, float nxm, float nym, float nzm, float am1,
-                                             float am2, const PairConstsF& c, float& d1,
-                                             float& d2, float& c1, float& c2) {
-  const float rx = xk - xm, ry = yk - ym, rz = zk - zm;
-  const float R2 = __fmaf_rn(rz, rz, __fmaf_rn(ry, ry, rx * rx));
+__device__ __forceinline__ void pair_f32_sym_r(float rx, float ry, float rz, float R2, float nxk,
+                                               float nyk, float nzk, float ak1, float ak2,
+                                               float nxm, float nym, float nzm, float am1,
+                                               float am2, const PairConstsF& c, float& d1,
+                                               float& d2, float& c1, float& c2) {
   const float iR = __builtin_amdgcn_rsqf(R2);
   const float R = R2 * iR;
   const float iR2 = iR * iR;
@@ -141,6 +141,18 @@ __device__ __forceinline__ void pair_f32_sym(float xk, float yk, float zk, float
   const float h11 = -rnx * f1, h22 = -rny * f2;
   c1 = __fmaf_rn(h11, ak1, -(g12 * ak2));
   c2 = __fmaf_rn(g21, ak1, h22 * ak2);
+}
+
+template <bool kUnit = false>
+__device__ __forceinline__ void pair_f32_sym(float xk, float yk, float zk, float nxk, float nyk,
+                                             float nzk, float ak1, float ak2, float xm, float ym,
+                                             float zm, float nxm, float nym, float nzm, float am1,
+                                             float am2, const PairConstsF& c, float& d1,
+                                             float& d2, float& c1, float& c2) {
+  const float rx = xk - xm, ry = yk - ym, rz = zk - zm;
+  const float R2 = __fmaf_rn(rz, rz, __fmaf_rn(ry, ry, rx * rx));
+  pair_f32_sym_r<kUnit>(rx, ry, rz, R2, nxk, nyk, nzk, ak1, ak2, nxm, nym, nzm, am1, am2, c, d1,
+                        d2, c1, c2);
 }
 
 }  // namespace ibim

@@ -23,6 +23,8 @@ struct TreeParams {
   // cluster is summed through its order^3 proxies when it holds more than
   // proxy_cost * order^3 nodes (kTreeProxyCost64 or kTreeProxyCost32)
   double proxy_cost = 0.44;
+  // near pairs of leaves evaluated once for both directions (two_way)
+  bool two_way = false;
 };
 // Measured VALU instructions of a target-proxy evaluation over those of a
 // direct pair (N_k skip included): float64 33 / 75, the mixed form (float32
@@ -52,9 +54,17 @@ struct TreePlan {
   // above the leaves, mlevel[h] .. mlevel[h + 1] being height h
   std::vector<int32_t> dstart, dend, kid;
   std::vector<int32_t> mlist, mlevel;
-  // per batch: proxy clusters (far) and merged source ranges (near), CSR
+  // per batch: proxy clusters (far) and merged source ranges (near,
+  // summed one direction at a time), CSR
   std::vector<int32_t> frow, fcol;
   std::vector<int32_t> nrow, nlo, nhi;
+  // two-way pairs of leaves (two_way plans): batches b < b' that are near
+  // each other both ways and hold no pair of N_k either way.  Pair q (batch
+  // b = pown[q]'s list prow[b] .. prow[b + 1], ascending b' = pcol[q]) is
+  // evaluated once for both directions; its row sums (for b) and column sums
+  // (for b') go to slot q, and batch b' finds its slots in incol[inrow[b'] ..
+  // inrow[b' + 1]] (ascending)
+  std::vector<int32_t> prow, pcol, pown, inrow, incol;
   // work items: a batch's lists cut into parts of similar work, so that the
   // device has many more workgroups than compute units; item i covers the
   // far entries [ifar0, ifar1) and near ranges [inear0, inear1) of batch
@@ -65,7 +75,7 @@ struct TreePlan {
   std::vector<int32_t> xrow, xcol;
   double gap = 0.0;         // largest |x_k - P_m| over m in N_k
   double far_evals = 0.0;   // target-proxy evaluations per application
-  double near_evals = 0.0;  // direct pair evaluations per application
+  double near_evals = 0.0;  // direct pair evaluations per application (ordered pairs)
   double proxy_evals = 0.0; // source-proxy terms of the direct proxy charges
   double m2m_links = 0.0;   // child-to-parent proxy transfers
 };

@@ -203,6 +203,57 @@ int build_tree_plan(const TreeParams& prm, int64_t M64, const double* px, const 
     nr.swap(merged);
   }
 
+  // two-way pairs: leaves b < b' near each other both ways (their near
+  // ranges cover each other) with no pair of N_k between them either way are
+  // taken out of both batches' near ranges and evaluated once for both
+  // directions in b's work items
+  std::vector<std::vector<int32_t>> pairs(nb);
+  if (prm.two_way) {
+    auto leaves_of = [&](const std::vector<std::pair<int32_t, int32_t>>& rs) {
+      std::vector<int32_t> v;
+      for (const auto& r : rs)
+        for (int32_t q = r.first / kTreeBatch; q * kTreeBatch < r.second; ++q) v.push_back(q);
+      return v;  // ascending: the ranges are sorted and disjoint
+    };
+    std::vector<std::vector<int32_t>> nl(nb), careful(nb);
+    for (int b = 0; b < nb; ++b) nl[b] = leaves_of(near[b]);
+    for (int32_t k = 0; k < M; ++k)
+      for (int64_t e = crow[k]; e < crow[k + 1]; ++e) {
+        const int32_t bk = pl.pos[k] / kTreeBatch, bm = pl.pos[ccol[e]] / kTreeBatch;
+        if (bk != bm) careful[std::min(bk, bm)].push_back(std::max(bk, bm));
+      }
+    for (auto& c : careful) {
+      std::sort(c.begin(), c.end());
+      c.erase(std::unique(c.begin(), c.end()), c.end());
+    }
+    auto has = [](const std::vector<int32_t>& v, int32_t x) {
+      return std::binary_search(v.begin(), v.end(), x);
+    };
+    for (int b = 0; b < nb; ++b)
+      for (int32_t q : nl[b])
+        if (q > b && has(nl[q], b) && !has(careful[b], q)) pairs[b].push_back(q);
+    // near ranges without the two-way partners (either side), merged again
+    std::vector<std::vector<int32_t>> drop(nb);
+    for (int b = 0; b < nb; ++b)
+      for (int32_t q : pairs[b]) {
+        drop[b].push_back(q);
+        drop[q].push_back(b);
+      }
+    for (int b = 0; b < nb; ++b) {
+      std::sort(drop[b].begin(), drop[b].end());
+      std::vector<std::pair<int32_t, int32_t>> rs;
+      for (int32_t q : nl[b]) {
+        if (has(drop[b], q)) continue;
+        const int32_t s = q * kTreeBatch, e = std::min(M, s + kTreeBatch);
+        if (!rs.empty() && rs.back().second == s)
+          rs.back().second = e;
+        else
+          rs.push_back({s, e});
+      }
+      near[b].swap(rs);
+    }
+  }
+
   // proxy slots: every cluster of more than nfar points, in preorder (a
   // parent before its children)
   std::vector<int32_t> slot(nd.size(), -1);
@@ -268,9 +319,12 @@ int build_tree_plan(const TreeParams& prm, int64_t M64, const double* px, const 
 
   pl.frow.assign(1, 0);
   pl.nrow.assign(1, 0);
+  pl.prow.assign(1, 0);
   std::vector<double> work(nb);
+  auto batch_size = [&](int b) { return (double)(pl.bstart[b + 1] - pl.bstart[b]); };
+  std::vector<std::vector<int32_t>> incoming(nb);
   for (int b = 0; b < nb; ++b) {
-    const double nt = pl.bstart[b + 1] - pl.bstart[b];
+    const double nt = batch_size(b);
     for (int ci : far[b]) pl.fcol.push_back(slot[ci]);
     pl.frow.push_back((int32_t)pl.fcol.size());
     double ns_near = 0.0;
@@ -280,9 +334,22 @@ int build_tree_plan(const TreeParams& prm, int64_t M64, const double* px, const 
       ns_near += r.second - r.first;
     }
     pl.nrow.push_back((int32_t)pl.nlo.size());
+    double ns_pair = 0.0;
+    for (int32_t q : pairs[b]) {
+      incoming[q].push_back((int32_t)pl.pcol.size());
+      pl.pcol.push_back(q);
+      pl.pown.push_back(b);
+      ns_pair += batch_size(q);
+    }
+    pl.prow.push_back((int32_t)pl.pcol.size());
     pl.far_evals += nt * n3 * (double)far[b].size();
-    pl.near_evals += nt * ns_near;
+    pl.near_evals += nt * ns_near + 2.0 * nt * ns_pair;
     work[b] = (double)far[b].size() * n3 * prm.proxy_cost + ns_near;
+  }
+  pl.inrow.assign(1, 0);
+  for (int b = 0; b < nb; ++b) {
+    pl.incol.insert(pl.incol.end(), incoming[b].begin(), incoming[b].end());
+    pl.inrow.push_back((int32_t)pl.incol.size());
   }
 
   // work items: about kItems in all (at least kMinPart of work per target each)
@@ -345,9 +412,11 @@ size_t tree_device_bytes(const TreePlan& pl) {
                       pl.dend.size() + pl.kid.size() + pl.mlist.size() + pl.ibatch.size() +
                       pl.ifar0.size() + pl.ifar1.size() + pl.inear0.size() + pl.inear1.size() +
                       pl.istart.size() + pl.iorder.size() + pl.fcol.size() + pl.nlo.size() +
-                      pl.nhi.size() + pl.xrow.size() + pl.xcol.size();
+                      pl.nhi.size() + pl.xrow.size() + pl.xcol.size() + pl.prow.size() +
+                      pl.pcol.size() + pl.pown.size() + pl.inrow.size() + pl.incol.size();
+  // work-item partial sums, and row and column sums of the two-way pairs
   const size_t dbls = pl.pbox.size() + (2 * n + n * n) + 9 * M + pl.pstart.size() * n3 * 2 +
-                      pl.ibatch.size() * 2 * (size_t)kTreeBatch;
+                      (pl.ibatch.size() + 2 * pl.pcol.size()) * 2 * (size_t)kTreeBatch;
   return ints * 4 + dbls * 8;
 }
 

@@ -24,7 +24,9 @@ struct TreeDevice {
   int32_t *xrow = nullptr, *xcol = nullptr;
   int32_t *ibatch = nullptr, *ifar0 = nullptr, *ifar1 = nullptr, *inear0 = nullptr,
           *inear1 = nullptr, *istart = nullptr, *iorder = nullptr;
-  int n_items = 0;
+  // two-way pairs (TreePlan::prow, pcol, pown, inrow, incol)
+  int32_t *prow = nullptr, *pcol = nullptr, *pown = nullptr, *inrow = nullptr, *incol = nullptr;
+  int n_items = 0, n_pairs = 0;
   bool mixed = false;      // target-proxy evaluations in float32 (IBIM_MIXED)
   double rnear = 0.0;      // mixed form: direct pairs nearer than this stay float64
   double* pbox = nullptr;  // 6 per proxy cluster: lo x, y, z, hi x, y, z
@@ -36,6 +38,7 @@ struct TreeDevice {
   double *ta1 = nullptr, *ta2 = nullptr;  // w u1, w u2 in tree order
   double* pq = nullptr;                   // proxy charges (Q1, Q2) per point
   double* S = nullptr;                    // per work item: 2 x 256 partial sums
+  double *rowS = nullptr, *colS = nullptr;  // per two-way pair: 2 x 256 row, column sums
   size_t bytes = 0;
 
   void release();

@@ -49,10 +49,10 @@ constexpr int kUpSrc = 64;  // sources per round of the proxy-charge kernel
 
 struct TreeArgs {
   const int32_t *perm, *pos, *bstart, *fcol, *nlo, *nhi, *xrow, *xcol, *dstart, *dend, *kid,
-      *mlist, *ibatch, *ifar0, *ifar1, *inear0, *inear1, *iorder;
+      *mlist, *ibatch, *ifar0, *ifar1, *inear0, *inear1, *iorder, *pcol, *pown;
   const double *pbox, *cheb;
   const double *tx, *ty, *tz, *tnx, *tny, *tnz, *tw;
-  double *ta1, *ta2, *pq, *S;
+  double *ta1, *ta2, *pq, *S, *rowS, *colS;
   const double* u;
   PairConsts pc;
   int32_t M;
@@ -66,11 +66,11 @@ TreeArgs make_args(const TreeDevice& T, const DeviceProblem& P, const double* u)
   a.nlo = T.nlo; a.nhi = T.nhi; a.xrow = T.xrow; a.xcol = T.xcol;
   a.dstart = T.dstart; a.dend = T.dend; a.kid = T.kid; a.mlist = T.mlist;
   a.ibatch = T.ibatch; a.ifar0 = T.ifar0; a.ifar1 = T.ifar1; a.inear0 = T.inear0;
-  a.inear1 = T.inear1; a.iorder = T.iorder;
+  a.inear1 = T.inear1; a.iorder = T.iorder; a.pcol = T.pcol; a.pown = T.pown;
   a.pbox = T.pbox; a.cheb = T.cheb;
   a.tx = T.tx; a.ty = T.ty; a.tz = T.tz; a.tnx = T.tnx; a.tny = T.tny; a.tnz = T.tnz;
   a.tw = T.tw;
-  a.ta1 = T.ta1; a.ta2 = T.ta2; a.pq = T.pq; a.S = T.S;
+  a.ta1 = T.ta1; a.ta2 = T.ta2; a.pq = T.pq; a.S = T.S; a.rowS = T.rowS; a.colS = T.colS;
   a.u = u;
   a.pc = PairConsts{P.eps_out / P.eps_in, P.eps_in / P.eps_out, P.kappa, P.kappa * P.kappa};
   a.M = T.M;
@@ -444,11 +444,104 @@ __global__ __launch_bounds__(256) void tree_item_kernel(TreeArgs a) {
   a.S[(size_t)it * 2 * kTreeBatch + kTreeBatch + tid] = S2;
 }
 
+// Two-way pairs of leaves (mixed form), one workgroup each: the targets of
+// batch b = pown[q] (one per lane) against the sources of batch b' =
+// pcol[q], both directions from one float32 evaluation on float64-formed
+// differences (float64 for the lanes whose pair is nearer than r_near; the
+// pairs hold no pair of N_k).  Row sums go to rowS[q].  The sources are
+// swept as in the symmetric direct kernel: in phase p wave w takes the 64
+// sources of sub-block (w + p) mod 4, lane l source (l + s) mod 64 at step
+// s, so each source's column sum in LDS receives one add per step from one
+// lane, in a fixed order; colS[q] takes them at the end.
+// b < b', so b is never the ragged last batch.
+__global__ __launch_bounds__(256) void tree_pair_kernel(TreeArgs a) {
+  __shared__ double sh[8][256];
+  __shared__ float shf[5][256];
+  __shared__ double cs1[256], cs2[256];
+  const int q = blockIdx.x;
+  const int b = a.pown[q], b2 = a.pcol[q];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int32_t t0 = a.bstart[b], nt = a.bstart[b + 1] - t0;
+  const int32_t t = t0 + min(tid, nt - 1);
+  const bool valid = tid < nt;
+  const double x = a.tx[t], y = a.ty[t], z = a.tz[t];
+  const double nxk = a.tnx[t], nyk = a.tny[t], nzk = a.tnz[t];
+  const float nxf = (float)nxk, nyf = (float)nyk, nzf = (float)nzk;
+  const double ak1d = a.ta1[t], ak2d = a.ta2[t];
+  const float ak1 = (float)ak1d, ak2 = (float)ak2d;
+  const PairConstsF pcf{(float)a.pc.c1, (float)a.pc.c2, (float)a.pc.kappa, (float)a.pc.kappa2};
+  const int32_t c0 = a.bstart[b2];
+  const int cnt = a.bstart[b2 + 1] - c0;
+  if (tid < cnt) {
+    const int32_t m = c0 + tid;
+    sh[0][tid] = a.tx[m];
+    sh[1][tid] = a.ty[m];
+    sh[2][tid] = a.tz[m];
+    sh[3][tid] = a.tnx[m];
+    sh[4][tid] = a.tny[m];
+    sh[5][tid] = a.tnz[m];
+    sh[6][tid] = a.ta1[m];
+    sh[7][tid] = a.ta2[m];
+    shf[0][tid] = (float)a.tnx[m];
+    shf[1][tid] = (float)a.tny[m];
+    shf[2][tid] = (float)a.tnz[m];
+    shf[3][tid] = (float)a.ta1[m];
+    shf[4][tid] = (float)a.ta2[m];
+  }
+  cs1[tid] = cs2[tid] = 0.0;
+  __syncthreads();
+  double S1 = 0.0, S2 = 0.0;
+  for (int ph = 0; ph < 4; ++ph) {
+    const int sb = ((wv + ph) & 3) * 64;
+    for (int st = 0; st < 64; ++st) {
+      const int j = sb + ((lane + st) & 63);
+      const bool live = j < cnt;  // sources past a ragged partner batch do not exist
+      const int jj = live ? j : 0;
+      const float rx = (float)(x - sh[0][jj]), ry = (float)(y - sh[1][jj]),
+                  rz = (float)(z - sh[2][jj]);
+      const float R2 = __fmaf_rn(rz, rz, __fmaf_rn(ry, ry, rx * rx));
+      float e1, e2, f1, f2;
+      pair_f32_sym_r(rx, ry, rz, R2, nxf, nyf, nzf, ak1, ak2, shf[0][jj], shf[1][jj],
+                     shf[2][jj], shf[3][jj], shf[4][jj], pcf, e1, e2, f1, f2);
+      double d1 = (double)e1, d2 = (double)e2, g1 = (double)f1, g2 = (double)f2;
+      const bool near = R2 < a.rnear2;
+      if (__any(near)) {  // wave-uniform: the float64 pair both ways for the lanes that need it
+        double h1, h2, k1, k2;
+        pair_f64<false>(x, y, z, nxk, nyk, nzk, sh[0][jj], sh[1][jj], sh[2][jj], sh[3][jj],
+                        sh[4][jj], sh[5][jj], sh[6][jj], sh[7][jj], a.pc, h1, h2);
+        pair_f64<false>(sh[0][jj], sh[1][jj], sh[2][jj], sh[3][jj], sh[4][jj], sh[5][jj], x, y,
+                        z, nxk, nyk, nzk, ak1d, ak2d, a.pc, k1, k2);
+        d1 = near ? h1 : d1;
+        d2 = near ? h2 : d2;
+        g1 = near ? k1 : g1;
+        g2 = near ? k2 : g2;
+      }
+      if (live) {
+        S1 += d1;
+        S2 += d2;
+        if (valid) {  // one lane per source and step: the adds to a slot come in step order
+          atomicAdd(&cs1[j], g1);
+          atomicAdd(&cs2[j], g2);
+        }
+      }
+    }
+    __syncthreads();  // the next phase's sub-block was this phase's of another wave
+  }
+  a.rowS[(size_t)q * 2 * kTreeBatch + tid] = S1;
+  a.rowS[(size_t)q * 2 * kTreeBatch + kTreeBatch + tid] = S2;
+  if (tid < cnt) {
+    a.colS[(size_t)q * 2 * kTreeBatch + tid] = cs1[tid];
+    a.colS[(size_t)q * 2 * kTreeBatch + kTreeBatch + tid] = cs2[tid];
+  }
+}
+
 struct TreeFinishArgs {
   const double* u;
   const double* S;
+  const double *rowS, *colS;
   const int32_t* pos;
   const int32_t* istart;
+  const int32_t *prow, *inrow, *incol;
   const int32_t* crow;
   const int32_t* ccol;
   const double* blocks;
@@ -466,6 +559,17 @@ __global__ void tree_finish_kernel(TreeFinishArgs a) {
   for (int32_t it = a.istart[b]; it < a.istart[b + 1]; ++it) {
     s1 += a.S[(size_t)it * 2 * kTreeBatch + l];
     s2 += a.S[(size_t)it * 2 * kTreeBatch + kTreeBatch + l];
+  }
+  // two-way pairs: row sums of this batch's own pairs, column sums of those
+  // of lower batches with it
+  for (int32_t q = a.prow[b]; q < a.prow[b + 1]; ++q) {
+    s1 += a.rowS[(size_t)q * 2 * kTreeBatch + l];
+    s2 += a.rowS[(size_t)q * 2 * kTreeBatch + kTreeBatch + l];
+  }
+  for (int32_t i = a.inrow[b]; i < a.inrow[b + 1]; ++i) {
+    const double* c = a.colS + (size_t)a.incol[i] * 2 * kTreeBatch;
+    s1 += c[l];
+    s2 += c[kTreeBatch + l];
   }
   double o1 = a.lam1 * a.u[k] + a.scale * s1;
   double o2 = a.lam2 * a.u[M + k] + a.scale * s2;
@@ -492,7 +596,8 @@ void TreeDevice::release() {
   dfree(perm); dfree(pos); dfree(bstart);
   dfree(dstart); dfree(dend); dfree(kid); dfree(mlist);
   dfree(ibatch); dfree(ifar0); dfree(ifar1); dfree(inear0); dfree(inear1); dfree(istart);
-  dfree(iorder);
+  dfree(iorder); dfree(prow); dfree(pcol); dfree(pown); dfree(inrow); dfree(incol);
+  dfree(rowS); dfree(colS);
   dfree(fcol); dfree(nlo); dfree(nhi); dfree(xrow); dfree(xcol);
   dfree(pbox); dfree(cheb);
   dfree(tx); dfree(ty); dfree(tz); dfree(tnx); dfree(tny); dfree(tnz); dfree(tw);
@@ -509,6 +614,7 @@ hipError_t tree_upload(const TreePlan& pl, const DeviceProblem& P, const double*
   d.n_slots = (int)pl.pstart.size();
   d.mlevel = pl.mlevel;
   d.n_items = (int)pl.ibatch.size();
+  d.n_pairs = (int)pl.pcol.size();
   const int n = pl.order, n3 = n * n * n;
   // Chebyshev points of the second kind, barycentric weights, differentiation matrix
   std::vector<double> cheb(2 * n + n * n);
@@ -552,6 +658,11 @@ hipError_t tree_upload(const TreePlan& pl, const DeviceProblem& P, const double*
   TUP(inear1, pl.inear1);
   TUP(istart, pl.istart);
   TUP(iorder, pl.iorder);
+  TUP(prow, pl.prow);
+  TUP(pcol, pl.pcol);
+  TUP(pown, pl.pown);
+  TUP(inrow, pl.inrow);
+  TUP(incol, pl.incol);
   TUP(fcol, pl.fcol);
   TUP(nlo, pl.nlo);
   TUP(nhi, pl.nhi);
@@ -571,7 +682,10 @@ hipError_t tree_upload(const TreePlan& pl, const DeviceProblem& P, const double*
   if (e == hipSuccess) e = dalloc(&d.ta2, (size_t)M);
   if (e == hipSuccess) e = dalloc(&d.pq, (size_t)d.n_slots * n3 * 2);
   if (e == hipSuccess) e = dalloc(&d.S, (size_t)d.n_items * 2 * kTreeBatch);
-  by += (2 * (size_t)M + (size_t)d.n_items * 2 * kTreeBatch + (size_t)d.n_slots * n3 * 2) *
+  if (e == hipSuccess) e = dalloc(&d.rowS, (size_t)d.n_pairs * 2 * kTreeBatch);
+  if (e == hipSuccess) e = dalloc(&d.colS, (size_t)d.n_pairs * 2 * kTreeBatch);
+  by += (2 * (size_t)M + ((size_t)d.n_items + 2 * (size_t)d.n_pairs) * 2 * kTreeBatch +
+         (size_t)d.n_slots * n3 * 2) *
         sizeof(double);
   // the host vectors above are temporaries
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -604,6 +718,8 @@ hipError_t launch_tree_sum(const TreeDevice& T, const DeviceProblem& P, const do
     // the float32 far field is faster with the order left to run time (86
     // against 102 VGPRs, one more wave per SIMD)
     hipLaunchKernelGGL((tree_item_kernel<true, 0>), gi, dim3(256), 0, s, a);
+    if (T.n_pairs > 0)
+      hipLaunchKernelGGL(tree_pair_kernel, dim3((unsigned)T.n_pairs), dim3(256), 0, s, a);
   } else {
     if (T.order == 8)
       hipLaunchKernelGGL((tree_item_kernel<false, 8>), gi, dim3(256), 0, s, a);
@@ -618,8 +734,13 @@ hipError_t launch_tree_finish(const TreeDevice& T, const DeviceProblem& P, const
   TreeFinishArgs f;
   f.u = u;
   f.S = T.S;
+  f.rowS = T.rowS;
+  f.colS = T.colS;
   f.pos = T.pos;
   f.istart = T.istart;
+  f.prow = T.prow;
+  f.inrow = T.inrow;
+  f.incol = T.incol;
   f.crow = P.crow;
   f.ccol = P.ccol;
   f.blocks = P.blocks;

@@ -121,6 +121,7 @@ def load():
     lib.ibim_pair_work.argtypes = [_VP, _D, _D]
     lib.ibim_tree_counts.argtypes = [_VP, _D]
     lib.ibim_tree_plan.argtypes = [_VP, _I64] + [_I32] * 4 + [_D] + [_I32] * 8 + [_D]
+    lib.ibim_tree_pairs.argtypes = [_VP, _I64, _I32, _I32]
     lib.ibim_server_create.argtypes = [ctypes.POINTER(_Options), ctypes.c_size_t, ctypes.c_int,
                                        ctypes.c_int, _VP, ctypes.POINTER(_VP)]
     lib.ibim_server_submit.argtypes = [_VP, _D, ctypes.c_int, ctypes.c_int, ctypes.c_int, _D,
@@ -344,6 +345,17 @@ class Problem:
         return {"far_evals": out[0], "near_evals": out[1], "proxy_terms": out[2],
                 "batches": int(out[3]), "proxy_clusters": int(out[4]),
                 "transfers": int(out[5])}
+
+    def tree_pairs(self):
+        """Two-way pairs of the treecode plan (``ibim_tree_pairs``): (lower, upper) batches."""
+        n = np.zeros(1, dtype=np.int64)
+        nul = ctypes.POINTER(ctypes.c_int32)()
+        _check(self._lib.ibim_tree_pairs(self._ctx, n.ctypes.data_as(_I64), nul, nul))
+        lo = np.zeros(int(n[0]), dtype=np.int32)
+        hi = np.zeros(int(n[0]), dtype=np.int32)
+        _check(self._lib.ibim_tree_pairs(self._ctx, n.ctypes.data_as(_I64),
+                                         lo.ctypes.data_as(_I32), hi.ctypes.data_as(_I32)))
+        return lo, hi
 
     def tree_plan(self):
         """The treecode plan (``ibim_tree_plan``) as numpy arrays."""

@@ -74,10 +74,12 @@ PROXY_COST = {ibim.FP64: 0.44, ibim.MIXED: 0.26}
 @pytest.mark.parametrize("name", list(PLAN_CASES))
 def test_tree_plan_invariants(name):
     """The plan the treecode runs: every batch sees every source exactly once
-    (far clusters and direct ranges), far clusters pass the separation test
-    recomputed from the node positions, clusters with proxies hold more nodes
-    than c n^3 (c the cost of a target-proxy evaluation in direct pairs: 0.44
-    float64, 0.26 mixed), every pair of N_k is in the direct
+    (far clusters, direct ranges and, in the mixed form, two-way pairs of
+    leaves, evaluated once for both batches), far clusters pass the separation
+    test recomputed from the node positions, clusters with proxies hold more
+    nodes than c n^3 (c the cost of a target-proxy evaluation in direct pairs:
+    0.44 float64, 0.26 mixed), two-way pairs are leaves that are near each
+    other and hold no pair of N_k, every pair of N_k is in the direct
     part, and each cluster's charges come from its children and its own
     direct sources without overlap."""
     make, order, theta = PLAN_CASES[name]
@@ -103,6 +105,22 @@ def test_tree_plan_invariants(name):
     dist = np.linalg.norm(P[rows] - P[c["col"]], axis=1)
     assert abs(t["gap"] - dist.max()) <= 1e-8 * dist.max() + 1e-8 * wl.h
     cl = [(t["cstart"][i], t["cend"][i]) for i in range(len(t["cstart"]))]
+    lo, hi = p.tree_pairs()
+    if prec == ibim.FP64:
+        assert len(lo) == 0
+    else:
+        assert len(lo) > 0  # the case is large enough to have two-way pairs
+    assert np.all(lo < hi)
+    assert np.all(np.diff(lo.astype(np.int64) * B + hi) > 0)  # ordered, no repeats
+    partners = [[] for _ in range(B)]
+    for b1, b2 in zip(lo, hi):
+        partners[b1].append(b2)
+        partners[b2].append(b1)
+    # batches holding a pair of N_k between them (either way)
+    bt = pos // 256
+    careful = set(zip(bt[rows], bt[c["col"]]))
+    for b1, b2 in zip(lo, hi):
+        assert (b1, b2) not in careful and (b2, b1) not in careful
     far_total = 0
     for b in range(B):
         cover = np.zeros(M, np.int32)
@@ -118,6 +136,9 @@ def test_tree_plan_invariants(name):
         for r in range(t["nrow"][b], t["nrow"][b + 1]):
             cover[t["nlo"][r]:t["nhi"][r]] += 1
             near[t["nlo"][r]:t["nhi"][r]] = True
+        for q in partners[b]:
+            cover[bst[q]:bst[q + 1]] += 1
+            near[bst[q]:bst[q + 1]] = True
         assert np.all(cover == 1), b
         for tt in range(bst[b], bst[b + 1]):
             k = perm[tt]
