@@ -539,7 +539,7 @@ struct TreeFinishArgs {
   const double* u;
   const double* S;
   const double *rowS, *colS;
-  const int32_t* pos;
+  const int32_t* perm;
   const int32_t* istart;
   const int32_t *prow, *inrow, *incol;
   const int32_t* crow;
@@ -550,10 +550,12 @@ struct TreeFinishArgs {
   double* out;
 };
 
+// One thread per tree position (so that the partial sums of a batch are
+// read coalesced), writing its node's row.
 __global__ void tree_finish_kernel(TreeFinishArgs a) {
-  const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= a.M) return;
-  const int32_t M = a.M, t = a.pos[k];
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.M) return;
+  const int32_t M = a.M, k = a.perm[t];
   const int b = t / kTreeBatch, l = t % kTreeBatch;
   double s1 = 0.0, s2 = 0.0;
   for (int32_t it = a.istart[b]; it < a.istart[b + 1]; ++it) {
@@ -736,7 +738,7 @@ hipError_t launch_tree_finish(const TreeDevice& T, const DeviceProblem& P, const
   f.S = T.S;
   f.rowS = T.rowS;
   f.colS = T.colS;
-  f.pos = T.pos;
+  f.perm = T.perm;
   f.istart = T.istart;
   f.prow = T.prow;
   f.inrow = T.inrow;
