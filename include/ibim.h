@@ -335,11 +335,11 @@ int ibim_tree_counts(const ibim_ctx* ctx, double* out);
 
 /*
  * Two-way pairs of the treecode plan (IBIM_SUM_TREE contexts, host-only ones
- * too; IBIM_EINVAL for others).  With IBIM_MIXED, two leaves (batches of
- * targets, which are also the finest source clusters) that are near each
- * other both ways and hold no pair of N_k either way are taken out of both
- * batches' direct ranges (ibim_tree_plan's nlo, nhi) and evaluated once for
- * both directions; the float64 form has none.  *n (host) receives their
+ * too; IBIM_EINVAL for others).  Two leaves (batches of targets, which are
+ * also the finest source clusters) that are near each other both ways and
+ * hold no pair of N_k either way are taken out of both batches' direct
+ * ranges (ibim_tree_plan's nlo, nhi) and evaluated once for both
+ * directions.  *n (host) receives their
  * number; lower, upper (host, n int32 each, or NULL) the batches b < b' of
  * each pair, in order of b, then b'.
  */

@@ -365,7 +365,7 @@ int ctx_create_host(const double* sdf, int nx, int ny, int nz, const double orig
     prm.order = o.tree_order;
     prm.theta = o.tree_theta;
     prm.proxy_cost = o.precision == IBIM_MIXED ? kTreeProxyCost32 : kTreeProxyCost64;
-    prm.two_way = o.precision == IBIM_MIXED;
+    prm.two_way = true;
     const HostPlan& pl = c->plan;
     r = build_tree_plan(prm, pl.M, pl.px.data(), pl.py.data(), pl.pz.data(), pl.crow.data(),
                         pl.ccol.data(), h, &c->tplan, &err);

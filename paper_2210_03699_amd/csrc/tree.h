@@ -23,8 +23,8 @@ struct TreeParams {
   // cluster is summed through its order^3 proxies when it holds more than
   // proxy_cost * order^3 nodes (kTreeProxyCost64 or kTreeProxyCost32)
   double proxy_cost = 0.44;
-  // near pairs of leaves evaluated once for both directions (two_way)
-  bool two_way = false;
+  // near pairs of leaves evaluated once for both directions
+  bool two_way = true;
 };
 // Measured VALU instructions of a target-proxy evaluation over those of a
 // direct pair (N_k skip included): float64 33 / 75, the mixed form (float32

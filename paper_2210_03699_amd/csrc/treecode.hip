@@ -444,19 +444,20 @@ __global__ __launch_bounds__(256) void tree_item_kernel(TreeArgs a) {
   a.S[(size_t)it * 2 * kTreeBatch + kTreeBatch + tid] = S2;
 }
 
-// Two-way pairs of leaves (mixed form), one workgroup each: the targets of
-// batch b = pown[q] (one per lane) against the sources of batch b' =
-// pcol[q], both directions from one float32 evaluation on float64-formed
-// differences (float64 for the lanes whose pair is nearer than r_near; the
-// pairs hold no pair of N_k).  Row sums go to rowS[q].  The sources are
+// Two-way pairs of leaves, one workgroup each: the targets of batch b =
+// pown[q] (one per lane) against the sources of batch b' = pcol[q], both
+// directions from one evaluation (the pairs hold no pair of N_k): float64,
+// or in the mixed form float32 on float64-formed differences (float64 for
+// the lanes whose pair is nearer than r_near).  Row sums go to rowS[q].  The sources are
 // swept as in the symmetric direct kernel: in phase p wave w takes the 64
 // sources of sub-block (w + p) mod 4, lane l source (l + s) mod 64 at step
 // s, so each source's column sum in LDS receives one add per step from one
 // lane, in a fixed order; colS[q] takes them at the end.
 // b < b', so b is never the ragged last batch.
+template <bool kMixed>
 __global__ __launch_bounds__(256) void tree_pair_kernel(TreeArgs a) {
   __shared__ double sh[8][256];
-  __shared__ float shf[5][256];
+  __shared__ float shf[kMixed ? 5 : 1][256];
   __shared__ double cs1[256], cs2[256];
   const int q = blockIdx.x;
   const int b = a.pown[q], b2 = a.pcol[q];
@@ -482,11 +483,13 @@ __global__ __launch_bounds__(256) void tree_pair_kernel(TreeArgs a) {
     sh[5][tid] = a.tnz[m];
     sh[6][tid] = a.ta1[m];
     sh[7][tid] = a.ta2[m];
-    shf[0][tid] = (float)a.tnx[m];
-    shf[1][tid] = (float)a.tny[m];
-    shf[2][tid] = (float)a.tnz[m];
-    shf[3][tid] = (float)a.ta1[m];
-    shf[4][tid] = (float)a.ta2[m];
+    if (kMixed) {
+      shf[0][tid] = (float)a.tnx[m];
+      shf[1][tid] = (float)a.tny[m];
+      shf[2][tid] = (float)a.tnz[m];
+      shf[3][tid] = (float)a.ta1[m];
+      shf[4][tid] = (float)a.ta2[m];
+    }
   }
   cs1[tid] = cs2[tid] = 0.0;
   __syncthreads();
@@ -497,15 +500,26 @@ __global__ __launch_bounds__(256) void tree_pair_kernel(TreeArgs a) {
       const int j = sb + ((lane + st) & 63);
       const bool live = j < cnt;  // sources past a ragged partner batch do not exist
       const int jj = live ? j : 0;
+      double d1, d2, g1, g2;
+      if (!kMixed) {
+        pair_f64_sym_r(x - sh[0][jj], y - sh[1][jj], z - sh[2][jj], nxk, nyk, nzk, ak1d, ak2d,
+                       sh[3][jj], sh[4][jj], sh[5][jj], sh[6][jj], sh[7][jj], a.pc, d1, d2, g1,
+                       g2);
+      }
       const float rx = (float)(x - sh[0][jj]), ry = (float)(y - sh[1][jj]),
                   rz = (float)(z - sh[2][jj]);
       const float R2 = __fmaf_rn(rz, rz, __fmaf_rn(ry, ry, rx * rx));
-      float e1, e2, f1, f2;
-      pair_f32_sym_r(rx, ry, rz, R2, nxf, nyf, nzf, ak1, ak2, shf[0][jj], shf[1][jj],
-                     shf[2][jj], shf[3][jj], shf[4][jj], pcf, e1, e2, f1, f2);
-      double d1 = (double)e1, d2 = (double)e2, g1 = (double)f1, g2 = (double)f2;
-      const bool near = R2 < a.rnear2;
-      if (__any(near)) {  // wave-uniform: the float64 pair both ways for the lanes that need it
+      if (kMixed) {
+        float e1, e2, f1, f2;
+        pair_f32_sym_r(rx, ry, rz, R2, nxf, nyf, nzf, ak1, ak2, shf[0][jj], shf[1][jj],
+                       shf[2][jj], shf[3][jj], shf[4][jj], pcf, e1, e2, f1, f2);
+        d1 = (double)e1;
+        d2 = (double)e2;
+        g1 = (double)f1;
+        g2 = (double)f2;
+      }
+      const bool near = kMixed && R2 < a.rnear2;
+      if (kMixed && __any(near)) {  // wave-uniform: the float64 pair both ways where needed
         double h1, h2, k1, k2;
         pair_f64<false>(x, y, z, nxk, nyk, nzk, sh[0][jj], sh[1][jj], sh[2][jj], sh[3][jj],
                         sh[4][jj], sh[5][jj], sh[6][jj], sh[7][jj], a.pc, h1, h2);
@@ -721,12 +735,14 @@ hipError_t launch_tree_sum(const TreeDevice& T, const DeviceProblem& P, const do
     // against 102 VGPRs, one more wave per SIMD)
     hipLaunchKernelGGL((tree_item_kernel<true, 0>), gi, dim3(256), 0, s, a);
     if (T.n_pairs > 0)
-      hipLaunchKernelGGL(tree_pair_kernel, dim3((unsigned)T.n_pairs), dim3(256), 0, s, a);
+      hipLaunchKernelGGL(tree_pair_kernel<true>, dim3((unsigned)T.n_pairs), dim3(256), 0, s, a);
   } else {
     if (T.order == 8)
       hipLaunchKernelGGL((tree_item_kernel<false, 8>), gi, dim3(256), 0, s, a);
     else
       hipLaunchKernelGGL((tree_item_kernel<false, 0>), gi, dim3(256), 0, s, a);
+    if (T.n_pairs > 0)
+      hipLaunchKernelGGL(tree_pair_kernel<false>, dim3((unsigned)T.n_pairs), dim3(256), 0, s, a);
   }
   return hipGetLastError();
 }

@@ -74,8 +74,8 @@ PROXY_COST = {ibim.FP64: 0.44, ibim.MIXED: 0.26}
 @pytest.mark.parametrize("name", list(PLAN_CASES))
 def test_tree_plan_invariants(name):
     """The plan the treecode runs: every batch sees every source exactly once
-    (far clusters, direct ranges and, in the mixed form, two-way pairs of
-    leaves, evaluated once for both batches), far clusters pass the separation
+    (far clusters, direct ranges and two-way pairs of leaves, evaluated once
+    for both batches), far clusters pass the separation
     test recomputed from the node positions, clusters with proxies hold more
     nodes than c n^3 (c the cost of a target-proxy evaluation in direct pairs:
     0.44 float64, 0.26 mixed), two-way pairs are leaves that are near each
@@ -106,10 +106,7 @@ def test_tree_plan_invariants(name):
     assert abs(t["gap"] - dist.max()) <= 1e-8 * dist.max() + 1e-8 * wl.h
     cl = [(t["cstart"][i], t["cend"][i]) for i in range(len(t["cstart"]))]
     lo, hi = p.tree_pairs()
-    if prec == ibim.FP64:
-        assert len(lo) == 0
-    else:
-        assert len(lo) > 0  # the case is large enough to have two-way pairs
+    assert len(lo) > 0  # the cases are large enough to have two-way pairs
     assert np.all(lo < hi)
     assert np.all(np.diff(lo.astype(np.int64) * B + hi) > 0)  # ordered, no repeats
     partners = [[] for _ in range(B)]
