@@ -62,44 +62,6 @@ __device__ __forceinline__ void pair_f64(double x, double y, double z, double nx
   }
 }
 
-// float64, both directions of one pair from the difference r = x_k - P_m:
-// (d1, d2) the contribution to k from m with m's amplitudes (am1, am2),
-// (c1, c2) the one to m from k with k's (ak1, ak2); the reverse pair has
-// r' = -r, so r'.n_k = -r.n_m and r'.n_m = -r.n_k, and R, the exponential,
-// n_k.n_m and q = (r.n_k)(r.n_m) are shared.  With u = (1 - e(1 + kR))/R^3
-// and t3 = e(1 + kR)/R^3 the kernel factors are 1/R^3 - c t3 and
-// K21 = n_k.n_m u + q (k^2 e/R^3 - 3 u/R^2).
-__device__ __forceinline__ void pair_f64_sym_r(double rx, double ry, double rz, double nxk,
-                                               double nyk, double nzk, double ak1, double ak2,
-                                               double nxm, double nym, double nzm, double am1,
-                                               double am2, const PairConsts& c, double& d1,
-                                               double& d2, double& c1, double& c2) {
-  const double R2 = fma(rz, rz, fma(ry, ry, rx * rx));
-  const double iR = rsqrt_pos(R2);
-  const double R = R2 * iR;
-  const double iR2 = iR * iR;
-  const double iR3 = iR2 * iR;
-  const double kr = c.kappa * R;
-  const double e = exp_neg(kr);
-  const double rny = fma(rz, nzm, fma(ry, nym, rx * nxm));
-  const double rnx = fma(rz, nzk, fma(ry, nyk, rx * nxk));
-  const double nn = fma(nzk, nzm, fma(nyk, nym, nxk * nxm));
-  const double eiR3 = e * iR3;
-  const double t3 = fma(eiR3, kr, eiR3);
-  const double u = iR3 - t3;
-  const double f1 = fma(-c.c1, t3, iR3);
-  const double f2 = fma(-c.c2, t3, iR3);
-  const double g12 = fma(-e, iR, iR);  // (1 - e)/R
-  const double q = rnx * rny;
-  const double g21 = fma(nn, u, q * fma(u * iR2, -3.0, c.kappa2 * eiR3));
-  const double g11 = rny * f1, g22 = rnx * f2;
-  d1 = fma(g11, am1, -g12 * am2);
-  d2 = fma(g21, am1, g22 * am2);
-  const double h11 = -rnx * f1, h22 = -rny * f2;
-  c1 = fma(h11, ak1, -g12 * ak2);
-  c2 = fma(g21, ak1, h22 * ak2);
-}
-
 // float32 from the difference r = x - P(y_m), every operation explicit
 // (fused multiply-adds written out), so that every kernel including this
 // header computes bit-identical values when its translation unit is compiled
