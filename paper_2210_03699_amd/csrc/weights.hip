@@ -36,7 +36,8 @@ constexpr int kSamples = 128; // samples of l on [0, pi)
 // |n_i| > L lie at distance >= L + 1/2, where Q(s, pi r^2)/r < 3e-22 for every
 // s = j + 1/2 up to the highest significant mode j (L = 4 up to j = 4, 5 up
 // to j = 18, 6 up to j = 40).
-__device__ inline int lattice_halfwidth(int jhi) { return jhi <= 4 ? 4 : (jhi <= 18 ? 5 : 6); }
+constexpr int kLatMax = 6;
+__device__ inline int lattice_halfwidth(int jhi) { return jhi <= 4 ? 4 : (jhi <= 18 ? 5 : kLatMax); }
 // Modes whose coefficients (of l11, and of l21) are all below this fraction
 // of that function's largest coefficient are dropped: with
 // |omega[e^{ik psi}/|y|]| < 25 over the cell, the dropped terms total below
@@ -54,18 +55,60 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Side of the widest lattice.
+constexpr int kLatSide = 2 * kLatMax + 1;
+
+// The reciprocal-lattice terms that do not depend on the entry, per point m
+// of the widest lattice ((m1 + kLatMax) * kLatSide + m2 + kLatMax):
+// [0] = (Q(1/2, pi|m|^2), x^(1/2) e^-x / Gamma(3/2) at x = pi|m|^2),
+// [1] = (x, 1/|m|), [2] = -e^{2i psi(m)} (the factor (-i)^2 of a mode step).
+// Only the phase e^{-2 pi i m.a} remains per entry.  Filled before every
+// weights launch on the same stream; the values never change, so launches
+// on other streams that read it meanwhile see the same bits.
+__device__ double2 recip_terms[kLatSide * kLatSide][3];
+
+__global__ void recip_terms_kernel() {
+  const int t = threadIdx.x;
+  if (t >= kLatSide * kLatSide) return;
+  const int n1 = t / kLatSide - kLatMax, n2 = t % kLatSide - kLatMax;
+  if (n1 == 0 && n2 == 0) {
+    recip_terms[t][0] = make_double2(0.0, 0.0);
+    recip_terms[t][1] = make_double2(0.0, 0.0);
+    recip_terms[t][2] = make_double2(0.0, 0.0);
+    return;
+  }
+  const double y1 = n1, y2 = n2;
+  const double r2 = y1 * y1 + y2 * y2;
+  const double ir = rsqrt_pos(r2);
+  const double r = r2 * ir;
+  const double x = kPiD * r2;
+  const double sx = 1.7724538509055160 * r;  // sqrt(x)
+  const double zr = y1 * ir, zi = y2 * ir;
+  recip_terms[t][0] = make_double2(erfc(sx), 1.1283791670955126 * sx * exp(-x));
+  recip_terms[t][1] = make_double2(x, ir);
+  recip_terms[t][2] = make_double2(-(zr * zr - zi * zi), -(2.0 * zr * zi));
+}
+
 __global__ __launch_bounds__(kWave* kWavesPerBlock, 4) void weights_kernel(WeightArgs a) {
-  __shared__ double cos_t[kSamples], sin_t[kSamples];
+  // (cos, sin) of pi q / kSamples, q < 2 kSamples: the sample angles and,
+  // at even q, the angles 2 pi m / kSamples of the transform
+  __shared__ double2 cs_t[2 * kSamples];
   __shared__ double l11s[kWavesPerBlock][kSamples], l21s[kWavesPerBlock][kSamples];
   __shared__ double2 coef[kWavesPerBlock][kModes][2];  // (a11, b11), (a21, b21) of mode 2j
-  __shared__ double2 sumU[kWavesPerBlock][kSamples / 2], difV[kWavesPerBlock][kSamples / 2];
+  // folded samples of step 2: [parity of j][p][0] = (A of l11, of l21),
+  // [..][1] = (B of l11, of l21); mid = (U_h, V_h) at p = kSamples / 4
+  __shared__ double2 fold[kWavesPerBlock][2][kSamples / 4][2];
+  __shared__ double2 mid[kWavesPerBlock][2];
   __shared__ double rs[kRecip];
 
   const int lane = threadIdx.x % kWave;
   const int wv = threadIdx.x / kWave;
   // angles are multiples of pi: sincospi reduces them exactly
-  for (int q = threadIdx.x; q < kSamples; q += blockDim.x)
-    sincospi(2.0 * q / kSamples, &sin_t[q], &cos_t[q]);
+  for (int q = threadIdx.x; q < 2 * kSamples; q += blockDim.x) {
+    double sq, cq;
+    sincospi((double)q / kSamples, &sq, &cq);
+    cs_t[q] = make_double2(cq, sq);
+  }
   for (int m = threadIdx.x; m < kRecip; m += blockDim.x) rs[m] = 1.0 / (m + 1.5);
   __syncthreads();
 
@@ -93,8 +136,7 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 4) void weights_kernel(Weigh
   // 1. samples of l11, l21 at theta_p = pi p / kSamples
 #pragma unroll 1
   for (int p = lane; p < kSamples; p += kWave) {
-    double c, s;
-    sincospi((double)p / kSamples, &s, &c);
+    const double c = cs_t[p].x, s = cs_t[p].y;
     double v0 = (t1a * c + t1b * s) * d1;
     double v1 = (t2a * c + t2b * s) * d2;
     double vn2 = v0 * v0 + v1 * v1;
@@ -105,19 +147,37 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 4) void weights_kernel(Weigh
   }
   __syncthreads();
 
-  // 2. Fourier coefficients of the even modes: lane j owns mode k = 2j.
-  //    Samples p and N - p pair up (cos(2 pi j (N - p)/N) = cos(2 pi j p/N),
-  //    sin changes sign), so with U_p = l_p + l_{N-p}, V_p = l_p - l_{N-p}:
-  //    sum_p l_p cos = l_0 + (-1)^j l_{N/2} + sum_{p=1}^{N/2-1} U_p cos,
-  //    sum_p l_p sin = sum_{p=1}^{N/2-1} V_p sin; cos(2 j theta_p) =
-  //    cos(2 pi (j p mod N) / N).
+  // 2. Fourier coefficients of the even modes: lane j owns mode k = 2j, whose
+  //    basis functions at theta_p are cos and sin of 2 pi j p / N (N = kSamples).
+  //    Samples p and N - p pair up (cos equal, sin of opposite sign): with
+  //    U_p = l_p + l_{N-p}, V_p = l_p - l_{N-p},
+  //      sum_p l_p cos = l_0 + (-1)^j l_{N/2} + sum_{p=1}^{N/2-1} U_p cos,
+  //      sum_p l_p sin = sum_{p=1}^{N/2-1} V_p sin.
+  //    Then p and N/2 - p pair up as well: the angle of N/2 - p is pi j minus
+  //    that of p, so with s = (-1)^j its cos is s cos and its sin is -s sin:
+  //      sum cos = U_{N/4} cos(pi j / 2) + sum_{p=1}^{N/4-1} (U_p + s U_{N/2-p}) cos,
+  //      sum sin = V_{N/4} sin(pi j / 2) + sum_{p=1}^{N/4-1} (V_p - s V_{N/2-p}) sin.
+  //    The folded sums A = U_p + s U_{N/2-p}, B = V_p - s V_{N/2-p} are formed
+  //    once for both signs (lane p), and the angle 2 pi j p / N is entry
+  //    2 j p mod 2N of the table.
   {
-    const int p = lane;  // 1 .. N/2 - 1 (lane 0 unused)
-    if (p > 0) {
-      const double x11 = l11s[wv][p], y11 = l11s[wv][kSamples - p];
-      const double x21 = l21s[wv][p], y21 = l21s[wv][kSamples - p];
-      sumU[wv][p] = make_double2(x11 + y11, x21 + y21);
-      difV[wv][p] = make_double2(x11 - y11, x21 - y21);
+    const int p = lane;  // 1 .. N/4 - 1, and N/4 for the middle term
+    const double* L1 = l11s[wv];
+    const double* L2 = l21s[wv];
+    if (p > 0 && p < kSamples / 4) {
+      const int h = kSamples / 2;
+      const double u1 = L1[p] + L1[kSamples - p], v1 = L1[p] - L1[kSamples - p];
+      const double u2 = L2[p] + L2[kSamples - p], v2 = L2[p] - L2[kSamples - p];
+      const double w1 = L1[h - p] + L1[h + p], x1 = L1[h - p] - L1[h + p];
+      const double w2 = L2[h - p] + L2[h + p], x2 = L2[h - p] - L2[h + p];
+      fold[wv][0][p][0] = make_double2(u1 + w1, u2 + w2);
+      fold[wv][0][p][1] = make_double2(v1 - x1, v2 - x2);
+      fold[wv][1][p][0] = make_double2(u1 - w1, u2 - w2);
+      fold[wv][1][p][1] = make_double2(v1 + x1, v2 + x2);
+    } else if (p == kSamples / 4) {
+      const int q = 3 * kSamples / 4;
+      mid[wv][0] = make_double2(L1[p] + L1[q], L2[p] + L2[q]);
+      mid[wv][1] = make_double2(L1[p] - L1[q], L2[p] - L2[q]);
     }
   }
   __syncthreads();
@@ -127,15 +187,25 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 4) void weights_kernel(Weigh
     double a11 = l11s[wv][0] + sg * l11s[wv][kSamples / 2];
     double a21 = l21s[wv][0] + sg * l21s[wv][kSamples / 2];
     double b11 = 0.0, b21 = 0.0;
-#pragma unroll 1
-    for (int p = 1; p < kSamples / 2; ++p) {
-      const int q = (j * p) & (kSamples - 1);
-      const double cq = cos_t[q], sq = sin_t[q];
-      const double2 U = sumU[wv][p], V = difV[wv][p];
-      a11 = fma(U.x, cq, a11);
-      a21 = fma(U.y, cq, a21);
-      b11 = fma(V.x, sq, b11);
-      b21 = fma(V.y, sq, b21);
+    {
+      const double2 cs = cs_t[(kSamples / 2 * j) & (2 * kSamples - 1)];
+      const double2 U = mid[wv][0], V = mid[wv][1];
+      a11 = fma(U.x, cs.x, a11);
+      a21 = fma(U.y, cs.x, a21);
+      b11 = fma(V.x, cs.y, b11);
+      b21 = fma(V.y, cs.y, b21);
+    }
+    const double2(*fj)[2] = fold[wv][j & 1];
+    int q = 0;
+#pragma unroll
+    for (int p = 1; p < kSamples / 4; ++p) {
+      q = (q + 2 * j) & (2 * kSamples - 1);
+      const double2 cs = cs_t[q];
+      const double2 A = fj[p][0], B = fj[p][1];
+      a11 = fma(A.x, cs.x, a11);
+      a21 = fma(A.y, cs.x, a21);
+      b11 = fma(B.x, cs.y, b11);
+      b21 = fma(B.y, cs.y, b21);
     }
     double f = (j == 0) ? 1.0 / kSamples : 2.0 / kSamples;
     coef[wv][j][0] = make_double2(a11 * f, b11 * f);
@@ -176,29 +246,32 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 4) void weights_kernel(Weigh
     const int qd = (int)(((float)q + 0.5f) * inv_side);
     const int n1 = qd - lat, n2 = q - qd * side - lat;
     if (n1 == 0 && n2 == 0) continue;
-    double y1, y2, pr, pi, sg;
+    double Q, term, x, ir, z2r, z2i, pr, pi;
     if (!recip) {
-      y1 = n1 - al;
-      y2 = n2 - be;
+      const double y1 = n1 - al, y2 = n2 - be;
+      const double r2 = y1 * y1 + y2 * y2;
+      ir = rsqrt_pos(r2);
+      const double r = r2 * ir;
+      x = kPiD * r2;
+      const double sx = sqrtpi * r;              // sqrt(x)
+      Q = erfc(sx);                              // Q(1/2, x)
+      term = two_over_sqrtpi * sx * exp(-x);     // x^s e^-x / Gamma(s+1), s = 1/2
+      const double zr = y1 * ir, zi = y2 * ir;
+      z2r = zr * zr - zi * zi;                   // e^{2i psi}
+      z2i = 2.0 * zr * zi;
       pr = 1.0;
       pi = 0.0;
-      sg = 1.0;
     } else {
-      y1 = n1;
-      y2 = n2;
+      const double2* t = recip_terms[(n1 + kLatMax) * kLatSide + n2 + kLatMax];
+      const double2 t0 = t[0], t1 = t[1], t2 = t[2];
+      Q = t0.x;
+      term = t0.y;
+      x = t1.x;
+      ir = t1.y;
+      z2r = t2.x;  // e^{2i psi} times (-i)^2 = -1 per mode step
+      z2i = t2.y;
       sincospi(-2.0 * (n1 * al + n2 * be), &pi, &pr);
-      sg = -1.0;  // (-i)^k = (-1)^(k/2) for even k
     }
-    const double r2 = y1 * y1 + y2 * y2;
-    const double ir = rsqrt_pos(r2);
-    const double r = r2 * ir;
-    const double x = kPiD * r2;
-    const double sx = sqrtpi * r;                 // sqrt(x)
-    double Q = erfc(sx);                          // Q(1/2, x)
-    double term = two_over_sqrtpi * sx * exp(-x);  // x^s e^-x / Gamma(s+1), s = 1/2
-    const double zr = y1 * ir, zi = y2 * ir;
-    // e^{2i psi}, times (-i)^2 = -1 per mode step for the reciprocal sum
-    const double z2r = (zr * zr - zi * zi) * sg, z2i = 2.0 * zr * zi * sg;
     double wr = pr * ir, wi = pi * ir;  // phase * e^{ik psi} / r, k = 0
     for (int j = 0; j < jmax; ++j) {
       const double cr = wr * Q, ci = wi * Q;
@@ -295,6 +368,7 @@ double kreg_constant(double kappa, double tau) {
 hipError_t launch_weights(const WeightArgs& a, hipStream_t stream) {
   if (a.nnz == 0) return hipSuccess;
   const int64_t blocks = (a.nnz + kWavesPerBlock - 1) / kWavesPerBlock;
+  hipLaunchKernelGGL(recip_terms_kernel, dim3(1), dim3(192), 0, stream);
   hipLaunchKernelGGL(weights_kernel, dim3((unsigned)blocks), dim3(kWave * kWavesPerBlock), 0,
                      stream, a);
   return hipGetLastError();
