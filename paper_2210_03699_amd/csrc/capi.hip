@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -25,6 +26,63 @@ using namespace ibim;
 namespace ibim {
 
 thread_local std::string g_last_error = "no error";
+
+namespace {
+thread_local DeviceArena* t_arena = nullptr;
+std::mutex g_arena_mu;
+std::map<uintptr_t, size_t> g_arenas;  // live blocks: base -> size
+}  // namespace
+
+hipError_t arena_create(DeviceArena* a, size_t bytes) {
+  *a = DeviceArena{};
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes > 0 ? bytes : 1);
+  if (e != hipSuccess) return e;
+  a->base = (char*)p;
+  a->size = bytes;
+  std::lock_guard<std::mutex> lk(g_arena_mu);
+  g_arenas[(uintptr_t)p] = bytes;
+  return hipSuccess;
+}
+
+void arena_release(DeviceArena* a) {
+  if (!a->base) return;
+  {
+    std::lock_guard<std::mutex> lk(g_arena_mu);
+    g_arenas.erase((uintptr_t)a->base);
+  }
+  (void)hipFree(a->base);
+  *a = DeviceArena{};
+}
+
+hipError_t device_alloc(void** p, size_t bytes) {
+  DeviceArena* a = t_arena;
+  if (a && a->base) {
+    const size_t off = (a->top + 255) & ~(size_t)255;
+    if (off <= a->size && bytes <= a->size - off) {
+      *p = a->base + off;
+      a->top = off + bytes;
+      return hipSuccess;
+    }
+    a->outside += bytes;
+  }
+  return hipMalloc(p, bytes);
+}
+
+void device_free(void* p) {
+  {
+    std::lock_guard<std::mutex> lk(g_arena_mu);
+    auto it = g_arenas.upper_bound((uintptr_t)p);
+    if (it != g_arenas.begin()) {
+      --it;
+      if ((uintptr_t)p - it->first < it->second) return;  // freed with its block
+    }
+  }
+  (void)hipFree(p);
+}
+
+ArenaScope::ArenaScope(DeviceArena* a) : prev(t_arena) { t_arena = a; }
+ArenaScope::~ArenaScope() { t_arena = prev; }
 
 int fail(int code, const std::string& msg) {
   g_last_error = msg;

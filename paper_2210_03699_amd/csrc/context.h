@@ -26,11 +26,36 @@ int hip_fail(hipError_t e, const char* where);
     if (_e != hipSuccess) return ibim::hip_fail(_e, where); \
   } while (0)
 
+// Device arenas.  hipFree waits for all work on the device, so a context
+// whose arrays are freed one by one while other streams keep the device busy
+// waits that long once per array.  While an arena is installed on a thread
+// (ArenaScope), that thread's dalloc calls are carved out of one block (256-
+// byte aligned; what does not fit goes to hipMalloc), dfree leaves pointers
+// inside a live block alone, and arena_release frees the block with one
+// hipFree once nothing in it is used any more.
+struct DeviceArena {
+  char* base = nullptr;
+  size_t size = 0, top = 0;
+  size_t outside = 0;  // bytes that did not fit and came from hipMalloc
+};
+// Allocates and registers a block of `bytes` (a->base stays null on failure).
+hipError_t arena_create(DeviceArena* a, size_t bytes);
+// Unregisters the block, then frees it; a no-op without a block.
+void arena_release(DeviceArena* a);
+hipError_t device_alloc(void** p, size_t bytes);  // the thread's arena, else hipMalloc
+void device_free(void* p);                        // hipFree unless inside a live arena
+
+struct ArenaScope {
+  DeviceArena* prev;
+  explicit ArenaScope(DeviceArena* a);
+  ~ArenaScope();
+};
+
 template <class T>
 hipError_t dalloc(T** p, size_t n) {
   *p = nullptr;
   if (n == 0) n = 1;
-  return hipMalloc((void**)p, n * sizeof(T));
+  return device_alloc((void**)p, n * sizeof(T));
 }
 
 template <class T>
@@ -43,7 +68,7 @@ hipError_t upload(T** p, const T* src, size_t n, hipStream_t s) {
 
 template <class T>
 void dfree(T*& p) {
-  if (p) (void)hipFree((void*)p);
+  if (p) device_free((void*)p);
   p = nullptr;
 }
 

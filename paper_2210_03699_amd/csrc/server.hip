@@ -62,6 +62,7 @@ struct Request {
   int slot = -1;
   double* d_b = nullptr;  // right-hand side
   double* d_x = nullptr;  // iterate
+  DeviceArena arena;      // the block its device setup allocated from
   // GMRES state (the driver of ibim_solve, one step per round)
   Phase phase = Phase::kIter;
   bool final_check = false;
@@ -141,10 +142,13 @@ struct ibim_server {
   bool stopping = false;
   // device memory of finished or failed requests is freed on its own thread
   // (each hipFree waits for the device), so rounds do not stall on it; the
-  // bytes still held count against the budget until they are freed
+  // bytes still held count against the budget until they are freed.  A
+  // request's setup allocates from one block (DeviceArena), so freeing it
+  // takes one such wait, not one per array
   struct Reap {
     ibim_ctx* ctx;
     double *b, *x;
+    DeviceArena arena;
     size_t bytes;
   };
   std::deque<Reap> reap_queue;
@@ -218,6 +222,7 @@ void reaper_main(ibim_server* srv) {
     ibim_destroy(job.ctx);
     dfree(job.b);
     dfree(job.x);
+    arena_release(&job.arena);
     std::lock_guard<std::mutex> lk(srv->mu);
     srv->reaping -= job.bytes;
   }
@@ -229,16 +234,17 @@ size_t reaping_bytes(ibim_server* srv) {
 }
 
 void release_device(ibim_server* srv, Request* r) {
-  if (r->ctx || r->d_b || r->d_x) {
+  if (r->ctx || r->d_b || r->d_x || r->arena.base) {
     {
       std::lock_guard<std::mutex> lk(srv->mu);
-      srv->reap_queue.push_back(ibim_server::Reap{r->ctx, r->d_b, r->d_x, r->held});
+      srv->reap_queue.push_back(ibim_server::Reap{r->ctx, r->d_b, r->d_x, r->arena, r->held});
       srv->reaping += r->held;
     }
     srv->reap_cv.notify_one();
     r->ctx = nullptr;
     r->d_b = nullptr;
     r->d_x = nullptr;
+    r->arena = DeviceArena{};
   }
   srv->used -= r->held;
   r->held = 0;
@@ -260,12 +266,23 @@ void mark_failed(ibim_server* srv, Request* r, int code, const std::string& msg)
 int admit_device(ibim_server* srv, Request* r, hipStream_t s) {
   ibim_ctx* c = r->ctx;
   c->opt.device = srv->opt.device;
+  // the request's device arrays come from one block of its estimated
+  // footprint, freed with one hipFree when the request is reaped (without
+  // the block they come from hipMalloc one by one)
+  {
+    DeviceScope ds(srv->opt.device);
+    if (!ds.ok) return fail(IBIM_EHIP, "hipSetDevice failed");
+    if (arena_create(&r->arena, r->estimate) != hipSuccess) (void)hipGetLastError();
+  }
+  ArenaScope scope(&r->arena);
   if (int e = ctx_setup_device(c, s)) return e;
   if (int e = ensure_krylov(c)) return e;
   const int64_t N = c->kr.n;
   HIP_TRY(dalloc(&r->d_b, (size_t)N), "right-hand side allocation");
   HIP_TRY(dalloc(&r->d_x, (size_t)N), "iterate allocation");
   r->setup_bytes = c->device_bytes + 2 * (size_t)N * 8;
+  if (r->arena.base)  // the whole block is held, plus what did not fit in it
+    r->setup_bytes = std::max(r->setup_bytes, r->arena.size + r->arena.outside);
   {
     const size_t top = std::max(c->setup_peak_bytes, r->setup_bytes);
     if (top > r->estimate) {
