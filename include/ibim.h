@@ -406,8 +406,12 @@ typedef struct {
   int64_t submitted, admitted, finished, failed;
   int64_t rounds;           /* rounds of the direct-sum solves */
   int64_t batched_items;    /* pair-kernel work items over all rounds */
-  size_t bytes_in_use;      /* device bytes charged to the budget: active solves, and
-                               requests being set up at their estimate */
+  size_t bytes_in_use;      /* device bytes charged to the budget: active solves (a
+                               request's setup allocates one block of its footprint
+                               estimate, held whole until the request is released, plus
+                               what did not fit in it), and requests being set up at
+                               their estimate.  Admission also counts the bytes of
+                               released requests whose memory is not yet freed */
   size_t bytes_peak;
   size_t budget_bytes;
   int active, waiting, max_active_seen;
