@@ -20,6 +20,7 @@
 #include <cstdint>
 #include <vector>
 
+#include "device_mem.h"
 #include "operator.h"
 #include "pair_math.h"
 #include "weights.h"
@@ -330,7 +331,7 @@ hipError_t build_near_list(DeviceProblem& P, const int32_t* node_of, const int64
   a.M = P.M;
   const unsigned blocks = (unsigned)((P.M + 3) / 4);  // four rows (wavefronts) per block
   int32_t* d_count = nullptr;
-  hipError_t e = hipMalloc((void**)&d_count, sizeof(int32_t) * (size_t)P.M);
+  hipError_t e = device_alloc((void**)&d_count, sizeof(int32_t) * (size_t)P.M);
   if (e != hipSuccess) return e;
   a.count = d_count;
   hipLaunchKernelGGL(near_kernel<false>, dim3(blocks), dim3(256), 0, stream, a);
@@ -340,14 +341,14 @@ hipError_t build_near_list(DeviceProblem& P, const int32_t* node_of, const int64
     e = hipMemcpyAsync(cnt.data(), d_count, sizeof(int32_t) * (size_t)P.M, hipMemcpyDeviceToHost,
                        stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
-  (void)hipFree(d_count);
+  device_free(d_count);
   if (e != hipSuccess) return e;
   std::vector<int64_t> rowptr(P.M + 1, 0);
   for (int32_t k = 0; k < P.M; ++k) rowptr[k + 1] = rowptr[k] + cnt[k];
   P.nnear = rowptr[P.M];
-  e = hipMalloc((void**)&P.nrow, sizeof(int64_t) * (size_t)(P.M + 1));
+  e = device_alloc((void**)&P.nrow, sizeof(int64_t) * (size_t)(P.M + 1));
   if (e == hipSuccess)
-    e = hipMalloc((void**)&P.ncol, sizeof(int32_t) * (size_t)(P.nnear > 0 ? P.nnear : 1));
+    e = device_alloc((void**)&P.ncol, sizeof(int32_t) * (size_t)(P.nnear > 0 ? P.nnear : 1));
   if (e == hipSuccess)
     e = hipMemcpyAsync(P.nrow, rowptr.data(), sizeof(int64_t) * (size_t)(P.M + 1),
                        hipMemcpyHostToDevice, stream);
