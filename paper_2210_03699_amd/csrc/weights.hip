@@ -62,7 +62,8 @@ constexpr int kLatSide = 2 * kLatMax + 1;
 // of the widest lattice ((m1 + kLatMax) * kLatSide + m2 + kLatMax):
 // [0] = (Q(1/2, pi|m|^2), x^(1/2) e^-x / Gamma(3/2) at x = pi|m|^2),
 // [1] = (x, 1/|m|), [2] = -e^{2i psi(m)} (the factor (-i)^2 of a mode step).
-// Only the phase e^{-2 pi i m.a} remains per entry.  Filled before every
+// Only the phase e^{-2 pi i m.a} remains per entry (a product of per-entry
+// tables of e^{-2 pi i m1 alpha} and e^{-2 pi i m2 beta}).  Filled before every
 // weights launch on the same stream; the values never change, so launches
 // on other streams that read it meanwhile see the same bits.
 __device__ double2 recip_terms[kLatSide * kLatSide][3];
@@ -99,6 +100,9 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 4) void weights_kernel(Weigh
   // [..][1] = (B of l11, of l21); mid = (U_h, V_h) at p = kSamples / 4
   __shared__ double2 fold[kWavesPerBlock][2][kSamples / 4][2];
   __shared__ double2 mid[kWavesPerBlock][2];
+  // (cos, sin) of -2 pi n alpha and of -2 pi n beta, n = -kLatMax .. kLatMax:
+  // the phase e^{-2 pi i m.a} of reciprocal point m is a product of two
+  __shared__ double2 phase[kWavesPerBlock][2][kLatSide];
   __shared__ double rs[kRecip];
 
   const int lane = threadIdx.x % kWave;
@@ -144,6 +148,12 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 4) void weights_kernel(Weigh
     double qf = k1 * v0 * v0 + k2 * v1 * v1;
     l11s[wv][p] = c11 * qf / (vn2 * vn);
     l21s[wv][p] = c21 / vn;
+  }
+  if (lane < 2 * kLatSide) {
+    const int d = lane / kLatSide, n = lane % kLatSide - kLatMax;
+    double sp, cp;
+    sincospi(-2.0 * n * (d ? be : al), &sp, &cp);
+    phase[wv][d][n + kLatMax] = make_double2(cp, sp);
   }
   __syncthreads();
 
@@ -270,7 +280,9 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock, 4) void weights_kernel(Weigh
       ir = t1.y;
       z2r = t2.x;  // e^{2i psi} times (-i)^2 = -1 per mode step
       z2i = t2.y;
-      sincospi(-2.0 * (n1 * al + n2 * be), &pi, &pr);
+      const double2 e1 = phase[wv][0][n1 + kLatMax], e2 = phase[wv][1][n2 + kLatMax];
+      pr = e1.x * e2.x - e1.y * e2.y;
+      pi = e1.x * e2.y + e1.y * e2.x;
     }
     double wr = pr * ir, wi = pi * ir;  // phase * e^{ik psi} / r, k = 0
     for (int j = 0; j < jmax; ++j) {
